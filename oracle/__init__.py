@@ -1,0 +1,163 @@
+"""FP64 CPU reference solver (test infrastructure).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  It wraps ``mln_oracle.c`` -- a plain density-matrix
+integrator with generic Pade exponentials that shares no code with the GPU
+library -- through ctypes.  See the header of ``mln_oracle.c`` for what it
+computes and which passages of the paper each part follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mln_oracle.c")
+_LIB = os.path.join(_HERE, "_build", "libmln_oracle.so")
+_lib = None
+
+
+def build(force=True):
+    """Compile the oracle with gcc (-O3 -fopenmp, no host-specific ISA so the
+    library also runs on other x86-64 hosts)."""
+    os.makedirs(os.path.dirname(_LIB), exist_ok=True)
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O3", "-std=c99", "-fPIC", "-shared", "-fopenmp",
+                           "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        i64 = ctypes.c_int64
+        L.orc_run.restype = ctypes.c_int
+        L.orc_run.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, ctypes.c_double, dp, dp,
+                              ctypes.c_double, i64, i64, ctypes.c_double, ctypes.c_double, i64, i64,
+                              ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, ctypes.c_double,
+                              i64, dp, dp, dp, dp, ctypes.c_int]
+        L.orc_bloch.restype = ctypes.c_int
+        L.orc_bloch.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, ctypes.c_double, dp, dp,
+                                ctypes.c_double, i64, i64, ctypes.c_double, dp, dp, dp, dp, dp,
+                                ctypes.c_int]
+        L.orc_expm.restype = ctypes.c_int
+        L.orc_expm.argtypes = [ctypes.c_int, dp, dp]
+        L.orc_superop.restype = ctypes.c_int
+        L.orc_superop.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, ctypes.c_double, dp,
+                                  ctypes.c_double, dp, dp]
+        L.orc_pade_coef.restype = ctypes.c_double
+        L.orc_pade_coef.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.orc_min_eig.restype = ctypes.c_double
+        L.orc_min_eig.argtypes = [ctypes.c_int, dp]
+        L.orc_constants.restype = None
+        L.orc_constants.argtypes = [dp]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _cx(a):
+    """complex array -> contiguous interleaved float64 view"""
+    return np.ascontiguousarray(np.asarray(a, dtype=np.complex128)).view(np.float64)
+
+
+def constants():
+    out = np.zeros(4)
+    lib().orc_constants(_p(out))
+    return dict(hbar=out[0], c0=out[1], eps0=out[2], mu0=out[3])
+
+
+def expm(a):
+    a = np.asarray(a, dtype=np.complex128)
+    n = a.shape[0]
+    out = np.zeros((n, n), dtype=np.complex128)
+    rc = lib().orc_expm(n, _p(_cx(a)), _p(out.view(np.float64)))
+    if rc:
+        raise RuntimeError("oracle expm failed")
+    return out
+
+
+def pade_coef(q, k):
+    return lib().orc_pade_coef(q, k)
+
+
+def min_eig(a):
+    a = np.asarray(a, dtype=np.complex128)
+    return lib().orc_min_eig(a.shape[0], _p(_cx(a)))
+
+
+def _medium_args(med):
+    n = med.n_levels
+    nj = len(med.jumps)
+    jumps = _cx(np.array(med.jumps).reshape(nj, n, n)) if nj else None
+    rates = np.ascontiguousarray(np.array(med.jump_rates, dtype=np.float64)) if nj else None
+    relax = _cx(med.relax_superop) if med.relax_superop is not None else None
+    return n, _cx(med.h0), _cx(med.dipole), nj, jumps, rates, float(med.dephasing), relax, \
+        _cx(med.rho0)
+
+
+def superop(med, dt):
+    n, h0, mu, nj, jumps, rates, deph, relax, _ = _medium_args(med)
+    S = np.zeros((n * n, n * n), dtype=np.complex128)
+    E0 = np.zeros((n * n, n * n), dtype=np.complex128)
+    rc = lib().orc_superop(n, _p(h0), _p(mu), nj, _p(jumps), _p(rates), deph, _p(relax), dt,
+                           _p(S.view(np.float64)), _p(E0.view(np.float64)))
+    if rc:
+        raise RuntimeError("oracle superop failed")
+    return S, E0
+
+
+def run(problem, snap_every=0, nthreads=0, nt=None):
+    """Coupled FDTD + density-matrix run.  Returns dict with 'probe' (nt+1),
+    'e_snap' (nsnap, nx), 'pop' (nsnap, N, n_med), 'diag'."""
+    med, g, src = problem.medium, problem.grid, problem.source
+    nt = g.nt if nt is None else nt
+    n, h0, mu, nj, jumps, rates, deph, relax, rho0 = _medium_args(med)
+    nsnap = nt // snap_every if snap_every > 0 else 0
+    probe = np.zeros(nt + 1)
+    e_snap = np.zeros((max(nsnap, 1), g.nx))
+    pop = np.zeros((max(nsnap, 1), n, max(g.n_med, 1)))
+    diag = np.zeros(4)
+    samples = np.ascontiguousarray(src.samples[: nt + 1], dtype=np.float64)
+    rc = lib().orc_run(n, _p(h0), _p(mu), nj, _p(jumps), _p(rates), deph, _p(relax), _p(rho0),
+                       float(med.density), g.nx, nt, g.dx, g.dt, g.med_begin, g.med_end,
+                       g.eps_r, g.mu_r, g.sigma, _p(samples), float(src.amplitude),
+                       snap_every, _p(e_snap), _p(pop), _p(probe), _p(diag), nthreads)
+    if rc:
+        raise RuntimeError(f"oracle run failed ({rc})")
+    return dict(probe=probe, e_snap=e_snap[:nsnap], pop=pop[:nsnap, :, : g.n_med],
+                diag=dict(trace=diag[0], herm=diag[1], min_eig=diag[2], purity=diag[3]))
+
+
+def bloch(med, efield, dt, nthreads=0):
+    """Prescribed-field mode: efield[t, c] drives cell c at step t.  Returns
+    'pop' (nt, N, ncell), 'dp' (nt, ncell), 'rho' (ncell, N, N), 'diag'."""
+    efield = np.ascontiguousarray(np.atleast_2d(np.asarray(efield, dtype=np.float64)))
+    nt, ncell = efield.shape
+    n, h0, mu, nj, jumps, rates, deph, relax, rho0 = _medium_args(med)
+    pop = np.zeros((nt, n, ncell))
+    dp = np.zeros((nt, ncell))
+    rho = np.zeros((ncell, n, n), dtype=np.complex128)
+    diag = np.zeros(4)
+    rc = lib().orc_bloch(n, _p(h0), _p(mu), nj, _p(jumps), _p(rates), deph, _p(relax), _p(rho0),
+                         float(med.density), ncell, nt, dt, _p(efield), _p(pop), _p(dp),
+                         _p(rho.view(np.float64)), _p(diag), nthreads)
+    if rc:
+        raise RuntimeError(f"oracle bloch failed ({rc})")
+    return dict(pop=pop, dp=dp, rho=rho,
+                diag=dict(trace=diag[0], herm=diag[1], min_eig=diag[2], purity=diag[3]))

@@ -1,0 +1,558 @@
+/*
+ * mln_oracle.c -- plain FP64 CPU reference for the Maxwell-Liouville-von
+ * Neumann (MLN) system of Riesch & Jirauschek, arXiv:1710.09799.
+ *
+ * TEST INFRASTRUCTURE.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark call this code.  It shares no source,
+ * header, table or helper with the GPU library; the only thing the two sides
+ * have in common is the seeded input description (medium, grid, source
+ * samples) produced in Python.
+ *
+ * What it computes (deliberately the slow, obvious way):
+ *   * the FULL complex N x N density matrix of every medium cell -- no
+ *     adjoint / Bloch-vector representation anywhere;
+ *   * the field-free generator L0 + G (Sec. 2, Eq. liouville) as an
+ *     N^2 x N^2 superoperator S acting on the row-major vectorisation of rho,
+ *     built by applying the map to every basis matrix |c><d|;
+ *   * the symmetric Strang splitting of Sec. 4.1 (Eqs. for d', d'', d^{n+1/2})
+ *     carried out on rho:  half step exp(S dt/2), full interaction step
+ *     rho -> W rho W^+ with W = exp(+i mu E^n dt / hbar) (the exact flow of
+ *     -i/hbar [-mu E, rho] for a field frozen at the midpoint value E^n),
+ *     half step exp(S dt/2);
+ *   * every matrix exponential by ONE generic scaling-and-squaring diagonal
+ *     Pade approximant [6/6] (Moler & Van Loan, "Nineteen dubious ways",
+ *     Sec. 3: with ||X||_1 <= 1/2 the [6/6] backward error is below 3.4e-16),
+ *     LU with partial pivoting, no structure exploited;
+ *   * the polarisation derivative from Eq. polarization2,
+ *     dP/dt = N_a Re Tr{ mu (L0(rho) + G(rho)) }, evaluated on rho^{n+1/2};
+ *   * the 1-D Yee FDTD update of Eq. maxwell on the staggered grid of Fig. 1.
+ *
+ * Readings of points the paper leaves open (same on the GPU side, but written
+ * independently there):
+ *   * hard source E(cell 0, step n) = amp * src[n];
+ *   * first-order Mur absorbing boundary at cell nx-1 with coefficient
+ *     (c dt - dx)/(c dt + dx), c = 1/sqrt(eps mu);
+ *   * conductivity handled semi-implicitly (average of E^n and E^{n+1});
+ *   * the medium occupies cells [med_begin, med_end), 1 <= begin <= end <= nx-1;
+ *   * snapshot s records E^{(s+1) k} and the populations of rho^{(s+1)k - 1/2}
+ *     for k = snap_every; the probe records E at cell nx-1 for steps 0..nt.
+ *
+ * Physical constants: CODATA 2018.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cx;
+
+#define ORC_HBAR 1.054571817e-34
+#define ORC_C0 299792458.0
+#define ORC_EPS0 8.8541878128e-12
+#define ORC_MU0 1.25663706212e-6
+
+#define PADE_Q 6
+
+void orc_constants(double *out)
+{
+    out[0] = ORC_HBAR;
+    out[1] = ORC_C0;
+    out[2] = ORC_EPS0;
+    out[3] = ORC_MU0;
+}
+
+/* ----------------------------------------------------------------------- */
+/* dense complex linear algebra, row-major n x n                            */
+
+static void mat_mul(int n, const cx *A, const cx *B, cx *C)
+{
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            cx s = 0;
+            for (int k = 0; k < n; ++k) s += A[i * n + k] * B[k * n + j];
+            C[i * n + j] = s;
+        }
+}
+
+/* Solve A X = B for X (n x n right-hand sides), Gaussian elimination with
+ * partial pivoting.  A and B are overwritten; X is returned in B. */
+static int lu_solve(int n, cx *A, cx *B)
+{
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        double best = cabs(A[k * n + k]);
+        for (int i = k + 1; i < n; ++i)
+            if (cabs(A[i * n + k]) > best) { best = cabs(A[i * n + k]); p = i; }
+        if (best == 0.0) return -1;
+        if (p != k)
+            for (int j = 0; j < n; ++j) {
+                cx t = A[k * n + j]; A[k * n + j] = A[p * n + j]; A[p * n + j] = t;
+                t = B[k * n + j]; B[k * n + j] = B[p * n + j]; B[p * n + j] = t;
+            }
+        for (int i = k + 1; i < n; ++i) {
+            cx f = A[i * n + k] / A[k * n + k];
+            if (f == 0) continue;
+            for (int j = k; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
+            for (int j = 0; j < n; ++j) B[i * n + j] -= f * B[k * n + j];
+        }
+    }
+    for (int k = n - 1; k >= 0; --k)
+        for (int j = 0; j < n; ++j) {
+            cx s = B[k * n + j];
+            for (int i = k + 1; i < n; ++i) s -= A[k * n + i] * B[i * n + j];
+            B[k * n + j] = s / A[k * n + k];
+        }
+    return 0;
+}
+
+static double fact(int k)
+{
+    double f = 1.0;
+    for (int i = 2; i <= k; ++i) f *= i;
+    return f;
+}
+
+/* Coefficient c_k of the diagonal [q/q] Pade numerator of exp:
+ * c_k = (2q-k)! q! / ((2q)! k! (q-k)!)   (Moler & Van Loan, Sec. 3). */
+double orc_pade_coef(int q, int k)
+{
+    return fact(2 * q - k) * fact(q) / (fact(2 * q) * fact(k) * fact(q - k));
+}
+
+/* F = exp(A) for a general complex n x n matrix.  work: 5 n^2 complex. */
+static int expm_work(int n, const cx *A, cx *F, cx *work)
+{
+    cx *X = work, *P = work + n * n, *T = work + 2 * n * n;
+    cx *Nm = work + 3 * n * n, *Dm = work + 4 * n * n;
+    double nrm = 0.0;
+    for (int j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += cabs(A[i * n + j]);
+        if (s > nrm) nrm = s;
+    }
+    int sq = 0;
+    double scale = 1.0;
+    while (nrm * scale > 0.5) { scale *= 0.5; ++sq; }
+    for (int i = 0; i < n * n; ++i) X[i] = A[i] * scale;
+    /* P = X^k, accumulated powers */
+    for (int i = 0; i < n * n; ++i) { P[i] = 0; Nm[i] = 0; Dm[i] = 0; }
+    for (int i = 0; i < n; ++i) { P[i * n + i] = 1; }
+    for (int k = 0; k <= PADE_Q; ++k) {
+        double c = orc_pade_coef(PADE_Q, k);
+        double sg = (k % 2) ? -1.0 : 1.0;
+        for (int i = 0; i < n * n; ++i) { Nm[i] += c * P[i]; Dm[i] += sg * c * P[i]; }
+        if (k < PADE_Q) {
+            mat_mul(n, P, X, T);
+            memcpy(P, T, sizeof(cx) * n * n);
+        }
+    }
+    if (lu_solve(n, Dm, Nm)) return -1;
+    for (int s = 0; s < sq; ++s) {
+        mat_mul(n, Nm, Nm, T);
+        memcpy(Nm, T, sizeof(cx) * n * n);
+    }
+    memcpy(F, Nm, sizeof(cx) * n * n);
+    return 0;
+}
+
+/* exported for the oracle's own pin tests: interleaved (re, im) arrays */
+int orc_expm(int n, const double *A, double *F)
+{
+    cx *w = (cx *)malloc(sizeof(cx) * (size_t)n * n * 7);
+    cx *a = w + 5 * n * n, *f = w + 6 * n * n;
+    for (int i = 0; i < n * n; ++i) a[i] = A[2 * i] + I * A[2 * i + 1];
+    int rc = expm_work(n, a, f, w);
+    for (int i = 0; i < n * n; ++i) { F[2 * i] = creal(f[i]); F[2 * i + 1] = cimag(f[i]); }
+    free(w);
+    return rc;
+}
+
+/* ----------------------------------------------------------------------- */
+/* the quantum medium                                                       */
+
+typedef struct {
+    int n;
+    cx *h0, *mu;              /* n x n */
+    int n_jump;
+    cx *jump;                 /* n_jump x n x n */
+    double *rate;
+    double dephasing;
+    cx *relax;                /* n^2 x n^2 or NULL */
+    cx *S;                    /* n^2 x n^2 superoperator of L0 + G */
+    cx *E0;                   /* exp(S dt/2) */
+} medium_t;
+
+static cx *load_cx(const double *p, int count)
+{
+    if (!p) return NULL;
+    cx *o = (cx *)malloc(sizeof(cx) * count);
+    for (int i = 0; i < count; ++i) o[i] = p[2 * i] + I * p[2 * i + 1];
+    return o;
+}
+
+/* out = -(i/hbar)[H0, X] + sum_k r_k (L X L^+ - 1/2 L^+L X - 1/2 X L^+L)
+ *       - dephasing * offdiag(X) + R vec(X)              (paper Eq. liouville) */
+static void field_free_map(const medium_t *m, const cx *X, cx *out, cx *t1, cx *t2)
+{
+    int n = m->n;
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+            cx s = 0;
+            for (int k = 0; k < n; ++k)
+                s += m->h0[a * n + k] * X[k * n + b] - X[a * n + k] * m->h0[k * n + b];
+            out[a * n + b] = -I / ORC_HBAR * s;
+        }
+    for (int j = 0; j < m->n_jump; ++j) {
+        const cx *L = m->jump + (size_t)j * n * n;
+        double r = m->rate[j];
+        /* t1 = L X, t2 = (L X) L^+ */
+        mat_mul(n, L, X, t1);
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b) {
+                cx s = 0;
+                for (int k = 0; k < n; ++k) s += t1[a * n + k] * conj(L[b * n + k]);
+                t2[a * n + b] = s;
+            }
+        for (int a = 0; a < n * n; ++a) out[a] += r * t2[a];
+        /* t1 = L^+ L */
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b) {
+                cx s = 0;
+                for (int k = 0; k < n; ++k) s += conj(L[k * n + a]) * L[k * n + b];
+                t1[a * n + b] = s;
+            }
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b) {
+                cx s = 0;
+                for (int k = 0; k < n; ++k)
+                    s += t1[a * n + k] * X[k * n + b] + X[a * n + k] * t1[k * n + b];
+                out[a * n + b] -= 0.5 * r * s;
+            }
+    }
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b)
+            if (a != b) out[a * n + b] -= m->dephasing * X[a * n + b];
+    if (m->relax) {
+        int n2 = n * n;
+        for (int p = 0; p < n2; ++p) {
+            cx s = 0;
+            for (int q = 0; q < n2; ++q) s += m->relax[p * n2 + q] * X[q];
+            out[p] += s;
+        }
+    }
+}
+
+static int medium_init(medium_t *m, int n, const double *h0, const double *mu, int n_jump,
+                       const double *jump, const double *rate, double deph,
+                       const double *relax, double dt)
+{
+    memset(m, 0, sizeof(*m));
+    m->n = n;
+    m->h0 = load_cx(h0, n * n);
+    m->mu = load_cx(mu, n * n);
+    m->n_jump = n_jump;
+    m->jump = n_jump ? load_cx(jump, n_jump * n * n) : NULL;
+    m->rate = (double *)malloc(sizeof(double) * (n_jump ? n_jump : 1));
+    for (int j = 0; j < n_jump; ++j) m->rate[j] = rate[j];
+    m->dephasing = deph;
+    m->relax = relax ? load_cx(relax, n * n * n * n) : NULL;
+    int n2 = n * n;
+    m->S = (cx *)calloc((size_t)n2 * n2, sizeof(cx));
+    m->E0 = (cx *)calloc((size_t)n2 * n2, sizeof(cx));
+    cx *X = (cx *)calloc(n2, sizeof(cx)), *Y = (cx *)calloc(n2, sizeof(cx));
+    cx *t1 = (cx *)calloc(n2, sizeof(cx)), *t2 = (cx *)calloc(n2, sizeof(cx));
+    for (int q = 0; q < n2; ++q) {
+        memset(X, 0, sizeof(cx) * n2);
+        X[q] = 1.0;
+        field_free_map(m, X, Y, t1, t2);
+        for (int p = 0; p < n2; ++p) m->S[p * n2 + q] = Y[p];
+    }
+    cx *A = (cx *)malloc(sizeof(cx) * n2 * n2), *w = (cx *)malloc(sizeof(cx) * 5 * n2 * n2);
+    for (int i = 0; i < n2 * n2; ++i) A[i] = m->S[i] * (0.5 * dt);
+    int rc = expm_work(n2, A, m->E0, w);
+    free(A); free(w); free(X); free(Y); free(t1); free(t2);
+    return rc;
+}
+
+static void medium_free(medium_t *m)
+{
+    free(m->h0); free(m->mu); free(m->jump); free(m->rate); free(m->relax);
+    free(m->S); free(m->E0);
+}
+
+/* exported for tests: S (n^2 x n^2, interleaved) and exp(S dt/2) */
+int orc_superop(int n, const double *h0, const double *mu, int n_jump, const double *jump,
+                const double *rate, double deph, const double *relax, double dt,
+                double *S_out, double *E0_out)
+{
+    medium_t m;
+    int rc = medium_init(&m, n, h0, mu, n_jump, jump, rate, deph, relax, dt);
+    int n4 = n * n * n * n;
+    for (int i = 0; i < n4; ++i) {
+        if (S_out) { S_out[2 * i] = creal(m.S[i]); S_out[2 * i + 1] = cimag(m.S[i]); }
+        if (E0_out) { E0_out[2 * i] = creal(m.E0[i]); E0_out[2 * i + 1] = cimag(m.E0[i]); }
+    }
+    medium_free(&m);
+    return rc;
+}
+
+/* per-thread scratch for one cell update */
+typedef struct {
+    cx *v, *w, *W, *Wa, *t, *ex;
+} cell_ws_t;
+
+static void ws_alloc(cell_ws_t *s, int n)
+{
+    int n2 = n * n;
+    s->v = (cx *)malloc(sizeof(cx) * n2);
+    s->w = (cx *)malloc(sizeof(cx) * n2);
+    s->W = (cx *)malloc(sizeof(cx) * n2);
+    s->Wa = (cx *)malloc(sizeof(cx) * n2);
+    s->t = (cx *)malloc(sizeof(cx) * n2);
+    s->ex = (cx *)malloc(sizeof(cx) * 5 * n2);
+}
+
+static void ws_free(cell_ws_t *s)
+{
+    free(s->v); free(s->w); free(s->W); free(s->Wa); free(s->t); free(s->ex);
+}
+
+/* y = M x for the n^2 x n^2 matrix M on vec(rho) */
+static void super_apply(int n2, const cx *M, const cx *x, cx *y)
+{
+    for (int p = 0; p < n2; ++p) {
+        cx s = 0;
+        for (int q = 0; q < n2; ++q) s += M[p * n2 + q] * x[q];
+        y[p] = s;
+    }
+}
+
+/* One Strang step of Sec. 4.1 on the density matrix rho (in place), field E
+ * frozen at the midpoint.  Returns dP/dt = N_a Re Tr{mu (L0+G)(rho^{n+1/2})}. */
+static double cell_step(const medium_t *m, cx *rho, double E, double dt, double Na, cell_ws_t *s)
+{
+    int n = m->n, n2 = n * n;
+    super_apply(n2, m->E0, rho, s->v);                       /* rho'  */
+    for (int i = 0; i < n2; ++i) s->Wa[i] = (I * dt * E / ORC_HBAR) * m->mu[i];
+    expm_work(n, s->Wa, s->W, s->ex);                         /* W = exp(i mu E dt/hbar) */
+    mat_mul(n, s->W, s->v, s->t);
+    for (int a = 0; a < n; ++a)                               /* rho'' = W rho' W^+ */
+        for (int b = 0; b < n; ++b) {
+            cx acc = 0;
+            for (int k = 0; k < n; ++k) acc += s->t[a * n + k] * conj(s->W[b * n + k]);
+            s->w[a * n + b] = acc;
+        }
+    super_apply(n2, m->E0, s->w, rho);                        /* rho^{n+1/2} */
+    super_apply(n2, m->S, rho, s->v);                         /* (L0 + G)(rho) */
+    cx tr = 0;
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) tr += m->mu[a * n + b] * s->v[b * n + a];
+    return Na * creal(tr);
+}
+
+/* min eigenvalue of a Hermitian matrix: cyclic Jacobi on the real symmetric
+ * embedding [[Re, -Im], [Im, Re]] (every eigenvalue of rho appears twice). */
+static double herm_min_eig(int n, const cx *A)
+{
+    int m = 2 * n;
+    double *B = (double *)malloc(sizeof(double) * m * m);
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+            double re = 0.5 * (creal(A[a * n + b]) + creal(A[b * n + a]));
+            double im = 0.5 * (cimag(A[a * n + b]) - cimag(A[b * n + a]));
+            B[a * m + b] = re;
+            B[(a + n) * m + (b + n)] = re;
+            B[a * m + (b + n)] = -im;
+            B[(a + n) * m + b] = im;
+        }
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < m; ++p)
+            for (int q = p + 1; q < m; ++q) off += B[p * m + q] * B[p * m + q];
+        if (off < 1e-40) break;
+        for (int p = 0; p < m; ++p)
+            for (int q = p + 1; q < m; ++q) {
+                double apq = B[p * m + q];
+                if (fabs(apq) < 1e-300) continue;
+                double tau = (B[q * m + q] - B[p * m + p]) / (2.0 * apq);
+                double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                double c = 1.0 / sqrt(1.0 + t * t), sn = t * c;
+                for (int k = 0; k < m; ++k) {   /* columns */
+                    double bkp = B[k * m + p], bkq = B[k * m + q];
+                    B[k * m + p] = c * bkp - sn * bkq;
+                    B[k * m + q] = sn * bkp + c * bkq;
+                }
+                for (int k = 0; k < m; ++k) {   /* rows */
+                    double bpk = B[p * m + k], bqk = B[q * m + k];
+                    B[p * m + k] = c * bpk - sn * bqk;
+                    B[q * m + k] = sn * bpk + c * bqk;
+                }
+            }
+    }
+    double mn = B[0];
+    for (int i = 1; i < m; ++i) if (B[i * m + i] < mn) mn = B[i * m + i];
+    free(B);
+    return mn;
+}
+
+double orc_min_eig(int n, const double *A)
+{
+    cx *a = load_cx(A, n * n);
+    double r = herm_min_eig(n, a);
+    free(a);
+    return r;
+}
+
+/* diagnostics: [0] max |Tr rho - 1|, [1] max |rho - rho^+|, [2] min eigenvalue,
+ * [3] max |Tr rho^2 - Tr rho0^2| */
+static void check_rho(int n, const cx *rho, double pur0, double *diag)
+{
+    cx tr = 0, pur = 0;
+    double herm = 0.0;
+    for (int a = 0; a < n; ++a) {
+        tr += rho[a * n + a];
+        for (int b = 0; b < n; ++b) {
+            double d = cabs(rho[a * n + b] - conj(rho[b * n + a]));
+            if (d > herm) herm = d;
+            pur += rho[a * n + b] * rho[b * n + a];
+        }
+    }
+    double e = cabs(tr - 1.0);
+    double ev = herm_min_eig(n, rho);
+    double pd = fabs(creal(pur) - pur0);
+#pragma omp critical(orc_diag)
+    {
+        if (e > diag[0]) diag[0] = e;
+        if (herm > diag[1]) diag[1] = herm;
+        if (ev < diag[2]) diag[2] = ev;
+        if (pd > diag[3]) diag[3] = pd;
+    }
+}
+
+static double purity_of(int n, const cx *r)
+{
+    cx p = 0;
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) p += r[a * n + b] * r[b * n + a];
+    return creal(p);
+}
+
+/* ----------------------------------------------------------------------- */
+/* coupled Maxwell + Liouville run                                          */
+
+int orc_run(int n, const double *h0, const double *mu, int n_jump, const double *jump,
+            const double *rate, double deph, const double *relax, const double *rho0,
+            double Na, int64_t nx, int64_t nt, double dx, double dt, int64_t mb, int64_t me,
+            double eps_r, double mu_r, double sigma, const double *src, double amp,
+            int64_t snap_every, double *e_snap, double *pop_snap, double *probe,
+            double *diag, int nthreads)
+{
+    if (n < 2 || nx < 3 || nt < 0 || mb < 1 || me < mb || me > nx - 1) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    medium_t m;
+    if (medium_init(&m, n, h0, mu, n_jump, jump, rate, deph, relax, dt)) return -2;
+    int n2 = n * n;
+    int64_t nmed = me - mb;
+    cx *rho = (cx *)malloc(sizeof(cx) * (size_t)(nmed ? nmed : 1) * n2);
+    cx *r0 = load_cx(rho0, n2);
+    for (int64_t c = 0; c < nmed; ++c) memcpy(rho + c * n2, r0, sizeof(cx) * n2);
+    double pur0 = purity_of(n, r0);
+    double *E = (double *)calloc(nx, sizeof(double));
+    double *H = (double *)calloc(nx, sizeof(double));
+    double *P = (double *)calloc(nmed ? nmed : 1, sizeof(double));
+    double eps = ORC_EPS0 * eps_r, muu = ORC_MU0 * mu_r;
+    double cl = 1.0 / sqrt(eps * muu);
+    double kmur = (cl * dt - dx) / (cl * dt + dx);
+    double sg = sigma * dt / (2.0 * eps);
+    double ca = (1.0 - sg) / (1.0 + sg), cb = (dt / eps) / (1.0 + sg);
+    double ch = dt / (muu * dx);
+    E[0] = amp * src[0];
+    if (probe) probe[0] = E[nx - 1];
+    if (diag) { diag[0] = 0; diag[1] = 0; diag[2] = 1e300; diag[3] = 0; }
+    for (int64_t t = 0; t < nt; ++t) {
+        for (int64_t i = 0; i + 1 < nx; ++i) H[i] += ch * (E[i + 1] - E[i]);
+#pragma omp parallel
+        {
+            cell_ws_t ws;
+            ws_alloc(&ws, n);
+#pragma omp for schedule(static)
+            for (int64_t c = 0; c < nmed; ++c)
+                P[c] = cell_step(&m, rho + c * n2, E[mb + c], dt, Na, &ws);
+            ws_free(&ws);
+        }
+        double e_nm2 = E[nx - 2], e_nm1 = E[nx - 1];
+        for (int64_t i = 1; i + 1 < nx; ++i) {
+            double dp = (i >= mb && i < me) ? P[i - mb] : 0.0;
+            E[i] = ca * E[i] + cb * (-dp + (H[i] - H[i - 1]) / dx);
+        }
+        E[0] = amp * src[t + 1];
+        E[nx - 1] = e_nm2 + kmur * (E[nx - 2] - e_nm1);
+        if (probe) probe[t + 1] = E[nx - 1];
+        if (snap_every > 0 && (t + 1) % snap_every == 0) {
+            int64_t s = (t + 1) / snap_every - 1;
+            if (e_snap) memcpy(e_snap + s * nx, E, sizeof(double) * nx);
+            for (int64_t c = 0; c < nmed; ++c) {
+                const cx *r = rho + c * n2;
+                if (pop_snap)
+                    for (int a = 0; a < n; ++a)
+                        pop_snap[(s * n + a) * nmed + c] = creal(r[a * n + a]);
+                if (diag) check_rho(n, r, pur0, diag);
+            }
+        }
+    }
+    free(rho); free(r0); free(E); free(H); free(P);
+    medium_free(&m);
+    return 0;
+}
+
+/* Prescribed-field mode (no FDTD): cell c sees E = efield[t * ncell + c] at
+ * step t.  Records the populations of rho^{t+1/2} and dP/dt per step, and the
+ * final density matrices. */
+int orc_bloch(int n, const double *h0, const double *mu, int n_jump, const double *jump,
+              const double *rate, double deph, const double *relax, const double *rho0,
+              double Na, int64_t ncell, int64_t nt, double dt, const double *efield,
+              double *pop, double *dp, double *rho_final, double *diag, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    medium_t m;
+    if (medium_init(&m, n, h0, mu, n_jump, jump, rate, deph, relax, dt)) return -2;
+    int n2 = n * n;
+    cx *r0 = load_cx(rho0, n2);
+    double pur0 = purity_of(n, r0);
+    if (diag) { diag[0] = 0; diag[1] = 0; diag[2] = 1e300; diag[3] = 0; }
+#pragma omp parallel
+    {
+        cell_ws_t ws;
+        ws_alloc(&ws, n);
+        cx *rho = (cx *)malloc(sizeof(cx) * n2);
+#pragma omp for schedule(static)
+        for (int64_t c = 0; c < ncell; ++c) {
+            memcpy(rho, r0, sizeof(cx) * n2);
+            for (int64_t t = 0; t < nt; ++t) {
+                double p = cell_step(&m, rho, efield[t * ncell + c], dt, Na, &ws);
+                if (dp) dp[t * ncell + c] = p;
+                if (pop)
+                    for (int a = 0; a < n; ++a) pop[(t * n + a) * ncell + c] = creal(rho[a * n + a]);
+            }
+            if (diag) check_rho(n, rho, pur0, diag);
+            if (rho_final)
+                for (int i = 0; i < n2; ++i) {
+                    rho_final[(c * n2 + i) * 2] = creal(rho[i]);
+                    rho_final[(c * n2 + i) * 2 + 1] = cimag(rho[i]);
+                }
+        }
+        free(rho);
+        ws_free(&ws);
+    }
+    free(r0);
+    medium_free(&m);
+    return 0;
+}

@@ -1,0 +1,294 @@
+"""Seeded synthetic inputs for the Maxwell-Liouville-von Neumann solver.
+
+This module only *describes* problems: the quantum medium (level energies,
+dipole operator, relaxation channels, initial density matrix, particle
+density), the 1-D grid and the sampled source pulse.  It contains none of the
+method's arithmetic (no generators, no Bloch vectors, no exponentials, no
+field updates), so that both the GPU path and the independent FP64 checker
+can consume exactly the same inputs.
+
+Physical set-up follows the two-level and three-level test systems of the
+paper (Sec. 5.1, Sec. 5.2: Hamiltonian H = H0 - mu E_z, relaxation
+superoperator G, ground-state initial condition, Courant number 0.5).  The
+concrete sizes are synthetic stand-ins for the paper's literature test cases,
+whose pulse parameters and reference curves are not part of the paper text.
+
+Units: SI throughout (J, C m, s, m, V/m, 1/m^3).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+# CODATA 2018 exact / recommended values (used here only to size pulses and
+# grids; each solver carries its own copy of the constants it computes with).
+HBAR = 1.054571817e-34
+C0 = 299792458.0
+E_CHARGE = 1.602176634e-19
+H_PLANCK = 6.62607015e-34
+
+
+@dataclasses.dataclass
+class Medium:
+    """An N-level quantum medium (paper Sec. 2, Eq. liouville).
+
+    h0        : (N, N) complex Hermitian, field-free Hamiltonian [J]
+    dipole    : (N, N) complex Hermitian dipole operator mu [C m]; the
+                interaction Hamiltonian is -mu E_z
+    jumps     : list of (N, N) complex Lindblad operators L_k (unit norm
+                convention: G(rho) += rate_k (L rho L^+ - {L^+ L, rho}/2))
+    jump_rates: rates of the Lindblad channels [1/s]
+    dephasing : pure-dephasing rate applied to every off-diagonal element
+    relax_superop: optional (N^2, N^2) complex matrix acting on the
+                row-major vectorisation of rho, added to G
+    rho0      : (N, N) complex initial density matrix
+    density   : particle density N_a [1/m^3]
+    """
+
+    h0: np.ndarray
+    dipole: np.ndarray
+    rho0: np.ndarray
+    density: float
+    jumps: List[np.ndarray] = dataclasses.field(default_factory=list)
+    jump_rates: List[float] = dataclasses.field(default_factory=list)
+    dephasing: float = 0.0
+    relax_superop: Optional[np.ndarray] = None
+
+    @property
+    def n_levels(self) -> int:
+        return int(self.h0.shape[0])
+
+
+@dataclasses.dataclass
+class Grid:
+    """1-D Yee grid (paper Sec. 4, Fig. 1).
+
+    E_z lives on cells 0..nx-1 (integer time steps), H_y on the nx-1 faces
+    between them (half-integer steps).  The medium occupies cells
+    [med_begin, med_end), strictly inside the domain.  Cell 0 carries the
+    hard source, cell nx-1 a first-order Mur absorbing boundary and the
+    probe.
+    """
+
+    nx: int
+    nt: int
+    dx: float
+    dt: float
+    med_begin: int
+    med_end: int
+    eps_r: float = 1.0
+    mu_r: float = 1.0
+    sigma: float = 0.0
+
+    @property
+    def n_med(self) -> int:
+        return self.med_end - self.med_begin
+
+
+@dataclasses.dataclass
+class Source:
+    """Hard source: E_z(cell 0, step n) = amplitude * samples[n], n = 0..nt."""
+
+    samples: np.ndarray
+    amplitude: float
+
+
+@dataclasses.dataclass
+class Problem:
+    name: str
+    medium: Medium
+    grid: Grid
+    source: Source
+
+
+# ---------------------------------------------------------------------------
+# building blocks
+
+
+def ladder_medium(energies, dipoles, density, decay=0.0, dephasing=0.0):
+    """Ladder system: diagonal H0, real nearest-neighbour dipoles, downward
+    Lindblad decay |a><a+1| at one shared rate, ground-state start."""
+    n = len(energies)
+    h0 = np.diag(np.asarray(energies, dtype=np.complex128))
+    mu = np.zeros((n, n), dtype=np.complex128)
+    for a, m in enumerate(dipoles):
+        mu[a, a + 1] = m
+        mu[a + 1, a] = m
+    jumps, rates = [], []
+    if decay > 0.0:
+        for a in range(n - 1):
+            L = np.zeros((n, n), dtype=np.complex128)
+            L[a, a + 1] = 1.0
+            jumps.append(L)
+            rates.append(decay)
+    rho0 = np.zeros((n, n), dtype=np.complex128)
+    rho0[0, 0] = 1.0
+    return Medium(h0=h0, dipole=mu, rho0=rho0, density=density, jumps=jumps,
+                  jump_rates=rates, dephasing=dephasing)
+
+
+def sech_pulse(nt, dt, omega, tau, t0):
+    t = np.arange(nt + 1, dtype=np.float64) * dt
+    return (1.0 / np.cosh((t - t0) / tau)) * np.sin(omega * (t - t0))
+
+
+def gauss_pulse(nt, dt, omega, sigma_t, t0):
+    t = np.arange(nt + 1, dtype=np.float64) * dt
+    return np.exp(-0.5 * ((t - t0) / sigma_t) ** 2) * np.sin(omega * (t - t0))
+
+
+def cw_wave(nt, dt, omega):
+    t = np.arange(nt + 1, dtype=np.float64) * dt
+    return np.sin(omega * t)
+
+
+# reference optical frequency of the synthetic two- and three-level cases
+OMEGA0 = 2.0 * math.pi * 2e14
+LAMBDA0 = 2.0 * math.pi * C0 / OMEGA0
+DX0 = LAMBDA0 / 40.0
+DT0 = 0.5 * DX0 / C0          # Courant number 0.5
+
+
+def two_level(nx=2000, nt=10000, name="two_level_2pi_sech"):
+    """N=2 self-induced-transparency set-up: ground state, no relaxation,
+    medium in the central half, 2-pi sech pulse (100 fs envelope FWHM)."""
+    mu12 = 1e-29
+    med = ladder_medium([-0.5 * HBAR * OMEGA0, 0.5 * HBAR * OMEGA0], [mu12],
+                        density=1e24)
+    tau = 100e-15 / (2.0 * math.acosh(2.0))
+    e0 = 2.0 * HBAR / (mu12 * tau)          # area (mu/hbar) E0 pi tau = 2 pi
+    grid = Grid(nx=nx, nt=nt, dx=DX0, dt=DT0, med_begin=nx // 4,
+                med_end=nx // 4 + nx // 2)
+    src = Source(samples=sech_pulse(nt, DT0, OMEGA0, tau, 6.0 * tau), amplitude=e0)
+    return Problem(name, med, grid, src)
+
+
+def three_level(nx=20000, nt=100000, name="three_level_ladder_pi_gauss"):
+    """N=3 ladder: energies hbar*omega0*{0, 1.0, 2.1}, mu01=1e-29,
+    mu12=0.8e-29, Lindblad decay 1e12/s, pure dephasing 5e12/s, medium fills
+    cells [1, nx-1), Gaussian pi pulse with 200 fs envelope FWHM at omega0."""
+    mu01 = 1e-29
+    med = ladder_medium([0.0, HBAR * OMEGA0, 2.1 * HBAR * OMEGA0], [mu01, 0.8e-29],
+                        density=1e24, decay=1e12, dephasing=5e12)
+    sig = 200e-15 / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+    e0 = math.pi * HBAR / (mu01 * sig * math.sqrt(2.0 * math.pi))
+    grid = Grid(nx=nx, nt=nt, dx=DX0, dt=DT0, med_begin=1, med_end=nx - 1)
+    src = Source(samples=gauss_pulse(nt, DT0, OMEGA0, sig, 600e-15), amplitude=e0)
+    return Problem(name, med, grid, src)
+
+
+def six_level(nx=50000, nt=200000, seed=1710, name="six_level_qcl_cw"):
+    """N=6 QCL-like region: energies U[0,60] meV (sorted), tridiagonal real
+    dipoles U[1,5] nm*e, one Lindblad channel |a><b| per pair a<b with
+    log-uniform rate in [1e11, 1e13]/s, CW drive at the level-1 -> level-2
+    transition (0-based) with 1e6 V/m."""
+    rng = np.random.default_rng(seed)
+    ev = np.sort(rng.uniform(0.0, 60e-3, size=6)) * E_CHARGE
+    dip = rng.uniform(1.0, 5.0, size=5) * 1e-9 * E_CHARGE
+    rates = 10.0 ** rng.uniform(11.0, 13.0, size=15)
+    med = ladder_medium(ev, dip, density=1e22)
+    k = 0
+    for a in range(6):
+        for b in range(a + 1, 6):
+            L = np.zeros((6, 6), dtype=np.complex128)
+            L[a, b] = 1.0
+            med.jumps.append(L)
+            med.jump_rates.append(float(rates[k]))
+            k += 1
+    lam = H_PLANCK * C0 / (60e-3 * E_CHARGE)
+    dx = lam / 40.0
+    dt = 0.5 * dx / C0
+    w21 = (ev[2] - ev[1]) / HBAR
+    grid = Grid(nx=nx, nt=nt, dx=dx, dt=dt, med_begin=1, med_end=nx - 1)
+    src = Source(samples=cw_wave(nt, dt, w21), amplitude=1e6)
+    return Problem(name, med, grid, src)
+
+
+def adjoint_case(nx=10000, nt=50000, name="three_level_adjoint"):
+    """Three-level ladder medium and pulse on a shorter grid, used for the
+    transmitted-energy gradient runs."""
+    p = three_level(nx=nx, nt=nt, name=name)
+    return p
+
+
+def batched_sweep(n_inst=64, nt=20000, seed=9799, nx_range=(1000, 30000)):
+    """Independent instances, half two-level and half three-level, with
+    per-instance grid length, detuning, density and dipole strength."""
+    rng = np.random.default_rng(seed)
+    kinds = np.array([2] * (n_inst // 2) + [3] * (n_inst - n_inst // 2))
+    rng.shuffle(kinds)
+    out = []
+    for i, kind in enumerate(kinds):
+        nx = int(rng.integers(nx_range[0], nx_range[1] + 1))
+        det = rng.uniform(-0.05, 0.05)
+        dens = 10.0 ** rng.uniform(23.0, 25.0)
+        mu01 = 10.0 ** rng.uniform(math.log10(0.5e-29), math.log10(2e-29))
+        if kind == 2:
+            p = two_level(nx=nx, nt=nt, name=f"inst{i}_n2")
+            e = np.diag(p.medium.h0).real * (1.0 + det)
+            p.medium = ladder_medium(e, [mu01], density=dens)
+        else:
+            p = three_level(nx=nx, nt=nt, name=f"inst{i}_n3")
+            e = np.diag(p.medium.h0).real * (1.0 + det)
+            p.medium = ladder_medium(e, [mu01, 0.8 * mu01], density=dens,
+                                     decay=1e12, dephasing=5e12)
+        out.append(p)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# small random problems for brute-force parity
+
+
+def random_hermitian(rng, n, scale):
+    a = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    return 0.5 * scale * (a + a.conj().T)
+
+
+def random_density(rng, n, pure=False):
+    if pure:
+        psi = rng.normal(size=n) + 1j * rng.normal(size=n)
+        psi /= np.linalg.norm(psi)
+        return np.outer(psi, psi.conj())
+    a = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    r = a @ a.conj().T
+    return r / np.trace(r).real
+
+
+def random_medium(n, seed, relax=True, density=1e24, dipole_scale=1e-29,
+                  complex_dipole=True):
+    """Random N-level medium of the same physical scale as the ladder cases:
+    level spacings around hbar*omega0, dipoles around 1e-29 C m, a few random
+    Lindblad channels and a dephasing rate near 1e12/s."""
+    rng = np.random.default_rng(seed)
+    ev = np.sort(rng.uniform(0.0, 2.0 * n, size=n)) * HBAR * OMEGA0 * 0.5
+    h0 = np.diag(ev).astype(np.complex128)
+    h0 = h0 + random_hermitian(rng, n, 0.05 * HBAR * OMEGA0)
+    mu = random_hermitian(rng, n, dipole_scale)
+    if not complex_dipole:
+        mu = mu.real.astype(np.complex128)
+    med = Medium(h0=h0, dipole=mu, rho0=random_density(rng, n), density=density)
+    if relax:
+        for _ in range(n):
+            L = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+            L /= np.linalg.norm(L)
+            med.jumps.append(L)
+            med.jump_rates.append(float(10.0 ** rng.uniform(11.0, 12.5)))
+        med.dephasing = float(10.0 ** rng.uniform(11.0, 12.5))
+    return med
+
+
+def random_problem(n, seed, nx=48, nt=300, relax=True, med=None):
+    """Short coupled run on a small grid with a strong resonant pulse, so that
+    every cell of the medium sees a field within a few hundred steps."""
+    rng = np.random.default_rng(seed + 7)
+    medium = random_medium(n, seed, relax=relax)
+    b, e = (1, nx - 1) if med is None else med
+    grid = Grid(nx=nx, nt=nt, dx=DX0, dt=DT0, med_begin=b, med_end=e)
+    sig = 20 * DT0 * float(rng.uniform(1.0, 2.0))
+    src = Source(samples=gauss_pulse(nt, DT0, OMEGA0, sig, 4.0 * sig),
+                 amplitude=float(rng.uniform(1e9, 3e9)))
+    return Problem(f"random_n{n}_s{seed}", medium, grid, src)
