@@ -1,0 +1,222 @@
+/*
+ * mln.h -- C ABI of the MI355X (gfx950) Maxwell-Liouville-von Neumann solver.
+ *
+ * Method: Riesch & Jirauschek, "Numerical Method for the Maxwell-Liouville-von
+ * Neumann Equations using Efficient Matrix Exponential Computations",
+ * arXiv:1710.09799.  The density matrix of every medium cell is carried as a
+ * real Bloch vector d in R^(N^2-1) in the SU(N) adjoint representation
+ * (Sec. 3, Eq. comp_rho), advanced by the symmetric Strang splitting of
+ * Sec. 4.1 (half step exp(M dt/2), full step exp(U E^n dt), half step
+ * exp(M dt/2)), and coupled to a 1-D Yee FDTD update of E_z / H_y
+ * (Sec. 2, Eq. maxwell; Fig. 1) through the polarisation derivative
+ * dP/dt = 1/2 N_a v^T (M d + d_eq) (Sec. 3, last equation).
+ *
+ * Conventions shared by every call:
+ *   * Every entry point returns int: 0 (MLN_OK) or a negative MLN_E* code.
+ *     No C++ exception crosses this boundary.  mln_last_error() returns a
+ *     human-readable message for the last failure on the calling thread.
+ *   * Complex N x N matrices are row-major arrays of 2*N*N doubles with real
+ *     and imaginary parts interleaved.
+ *   * SI units: J, C m, s, m, V/m, 1/m^3.
+ *   * Inputs are copied during the call; the caller may free them afterwards.
+ *   * Output buffers are owned by the caller.  They are device pointers when
+ *     mln_record.out_on_device = 1 (e.g. the data_ptr() of a torch tensor on
+ *     the GPU), host pointers otherwise.
+ *   * All device work is enqueued on the HIP stream given in mln_options
+ *     (NULL = the default stream).  A handle must not be used from two host
+ *     threads at once.
+ */
+#ifndef MLN_H
+#define MLN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define MLN_OK 0
+#define MLN_EINVAL (-1)              /* null pointer, size or range error          */
+#define MLN_ENOTHERMITIAN (-2)       /* H0 or mu not Hermitian (1e-12 relative)    */
+#define MLN_ENOTTRACEPRESERVING (-3) /* Tr G(X) != 0 for some X: the adjoint
+                                        representation needs trace preservation
+                                        (Sec. 3, Eq. comp_rho)                     */
+#define MLN_ECOURANT (-4)            /* c dt / dx > 1: explicit Yee update unstable */
+#define MLN_EBADRHO (-5)             /* rho0 not Hermitian, not trace 1 or not PSD  */
+#define MLN_ENOMEM (-6)              /* device or host allocation failed            */
+#define MLN_EHIP (-7)                /* a HIP runtime call failed                   */
+#define MLN_ENOTSUPPORTED (-8)       /* level count / precision / route not built   */
+#define MLN_ENONFINITE (-9)          /* NaN or Inf seen in the recorded output      */
+#define MLN_ESTATE (-10)             /* call not valid in the handle's state        */
+#define MLN_ENUMERIC (-11)           /* a one-time factorisation failed to converge */
+
+/* ---- enumerations ------------------------------------------------------ */
+typedef enum {
+  MLN_FP64 = 0,           /* state, factors and arithmetic in double precision          */
+  MLN_FP32 = 1,           /* plain single precision (fast, loses ~1e-4 over 1e4 steps)  */
+  MLN_FP32_COMP = 2,      /* single precision with a compensated (two-float) state and
+                             two-float factors                                          */
+  MLN_FP32_BF16SPLIT = 3  /* compensated FP32 state; the shared-factor transform runs on
+                             MFMA as three-way BF16-split products, FP32 accumulation   */
+} mln_precision;
+
+typedef enum {
+  MLN_ROUTE_ROTATION = 0, /* fused form of the generalised Rodrigues route: 2x2 rotations
+                             in the eigenbasis of U, the two half steps merged into one
+                             shared D x D factor                                         */
+  MLN_ROUTE_DIAG = 1,     /* Sec. 4.2 first route: A_I = R exp(Lambda E dt) R^+          */
+  MLN_ROUTE_RODRIGUES = 2 /* Sec. 4.2 second route: A_I = I + sum sin S_i + (1-cos) S_i^2 */
+} mln_route;
+
+/* ---- problem description ---------------------------------------------- */
+
+/* The quantum medium: Sec. 2 (Eq. liouville, H = H0 - mu E_z) and the test
+ * systems of Sec. 5.  The relaxation superoperator G is the sum of
+ *   * Lindblad channels: G(rho) += rate_k (L_k rho L_k^+ - 1/2 {L_k^+ L_k, rho}),
+ *   * pure dephasing:    G(rho)_ab -= dephasing * rho_ab for a != b,
+ *   * a general linear map given as an N^2 x N^2 complex matrix acting on the
+ *     row-major vectorisation of rho (NULL if unused).
+ * G must be trace preserving.  N = n_levels; the GPU kernels are built for
+ * N = 2, 3, 4 and 6 (mln_setup_factors accepts 2 <= N <= 6). */
+typedef struct {
+  int32_t n_levels;
+  const double *h0;            /* N*N complex, Hermitian [J]                       */
+  const double *dipole;        /* N*N complex, Hermitian [C m]                     */
+  int32_t n_jump;              /* number of Lindblad channels (>= 0)               */
+  const double *jump;          /* n_jump * N*N complex                             */
+  const double *jump_rate;     /* n_jump rates [1/s]                               */
+  double dephasing;            /* [1/s]                                            */
+  const double *relax_superop; /* N^2*N^2 complex, or NULL                         */
+  const double *rho0;          /* N*N complex initial density matrix               */
+  double density;              /* N_a [1/m^3]                                      */
+} mln_medium;
+
+/* 1-D Yee grid (Fig. 1): E_z on cells 0..nx-1 at integer steps, H_y on the
+ * nx-1 faces at half-integer steps, the medium on cells [med_begin, med_end)
+ * with 1 <= med_begin <= med_end <= nx-1.  Cell 0 is a hard source, cell nx-1
+ * a first-order Mur absorbing boundary and the probe. */
+typedef struct {
+  int64_t nx, nt;
+  double dx, dt;
+  int64_t med_begin, med_end;
+  double eps_r, mu_r, sigma;   /* relative permittivity / permeability, conductivity */
+} mln_grid;
+
+/* E_z(cell 0, step n) = amplitude * samples[n] for n = 0..nt (n_samples >= nt+1). */
+typedef struct {
+  const double *samples;
+  int64_t n_samples;
+  double amplitude;
+} mln_source;
+
+/* What the run records (all float64).  Snapshot s = 0 .. nt/snap_every - 1 is
+ * taken when step (s+1)*snap_every - 1 completes: E at every cell
+ * (e_out[s*nx + i]) and the populations rho_aa of d^{n+1/2} on every medium
+ * cell (pop_out[(s*N + a)*n_med + c]).  The probe holds E at cell nx-1 for
+ * steps 0..nt (probe_out[n]).  Any pointer may be NULL. */
+typedef struct {
+  int64_t snap_every;          /* 0: no snapshots                                  */
+  double *pop_out;
+  double *e_out;
+  double *probe_out;
+  int32_t out_on_device;       /* 1: the pointers above are device pointers        */
+} mln_record;
+
+typedef struct {
+  int32_t precision;           /* mln_precision                                    */
+  int32_t route;               /* mln_route                                        */
+  int32_t steps_per_launch;    /* time steps fused into one launch (0 = automatic) */
+  int32_t tile;                /* cells per workgroup tile (0 = automatic)         */
+  void *stream;                /* hipStream_t, NULL = default stream               */
+} mln_options;
+
+typedef struct mln_handle mln_handle;
+
+/* ---- lifecycle and forward propagation -------------------------------- */
+
+/* Validate the problem, build the one-time FP64 factors (Sec. 3 generators,
+ * M, U, v, d_eq; A0 = exp(M dt/2) and its inhomogeneous part from one
+ * augmented exponential; the factorisation of U for the chosen route,
+ * Sec. 4.2), upload them and set the initial state (d from rho0, E = H = 0,
+ * E at cell 0 = amplitude*samples[0]).  Allocates all device memory the handle
+ * needs.  Errors: MLN_EINVAL, MLN_ENOTHERMITIAN, MLN_ENOTTRACEPRESERVING,
+ * MLN_ECOURANT, MLN_EBADRHO, MLN_ENOTSUPPORTED, MLN_ENOMEM, MLN_EHIP,
+ * MLN_ENUMERIC.  On error *out is set to NULL. */
+int mln_init(const mln_medium *medium, const mln_grid *grid, const mln_source *source,
+             const mln_record *record, const mln_options *options, mln_handle **out);
+
+/* Advance n_steps time steps (clamped to the steps left), enqueued on the
+ * handle's stream; returns without waiting.  Allocates nothing. */
+int mln_step(mln_handle *h, int64_t n_steps);
+
+/* Advance to step nt, wait for the stream, copy host-side records and check
+ * the recorded output for NaN/Inf (MLN_ENONFINITE). */
+int mln_run(mln_handle *h);
+
+/* Return to the initial state (step 0) without rebuilding factors. */
+int mln_reset(mln_handle *h);
+
+/* Current step index (number of completed time steps). */
+int mln_current_step(const mln_handle *h, int64_t *step);
+
+/* Copy the current fields to host arrays E[nx] (step n) and H[nx-1]
+ * (step n-1/2).  Synchronises the stream. */
+int mln_get_fields(mln_handle *h, double *E, double *H);
+
+/* Opaque full-state checkpoint (fields, Bloch state, step counter).
+ * mln_state_bytes gives the size; save/load copy to/from a host buffer and
+ * synchronise.  A loaded state continues bit-identically. */
+int mln_state_bytes(const mln_handle *h, int64_t *bytes);
+int mln_save_state(mln_handle *h, void *host_buf);
+int mln_load_state(mln_handle *h, const void *host_buf);
+
+/* Prescribed-field mode (no FDTD, used by the tests): medium cell c sees
+ * E = efield[t*n_med + c] at step t for t = 0..n_steps-1, starting from
+ * rho0.  Records the populations of d^{t+1/2} (pop_out[(t*N + a)*n_med + c])
+ * and dP/dt (dp_out[t*n_med + c]); either may be NULL.  efield, pop_out and
+ * dp_out are device pointers if out_on_device was set at init, else host
+ * pointers.  Synchronises.  Does not touch the coupled-run state. */
+int mln_bloch_only(mln_handle *h, const double *efield, int64_t n_steps, double *pop_out,
+                   double *dp_out);
+
+void mln_free(mln_handle *h);
+
+const char *mln_strerror(int code);
+const char *mln_last_error(void);
+
+/* ---- one-time factors (host only, no GPU needed) ---------------------- */
+
+/* The FP64 quantities built once per medium and time step.  D = N^2-1,
+ * q = N(N-1)/2.  Any pointer may be NULL.
+ *   gen    D*N*N complex  SU(N) generators s_j: all u_jk, then all v_jk
+ *                         (pairs j<k in lexicographic order), then
+ *                         w_1..w_{N-1} (Sec. 3)
+ *   M, U   D*D            Eq. elems2 (row-major, m_jk, u_jk)
+ *   deq, v, d0  D         d_eq (Sec. 3), dipole vector (Eq. comp_mu), d(rho0)
+ *   A0, b0 D*D, D         d -> A0 d + b0 is the exact half step of L1
+ *                         (Sec. 4.1); b0 = (A0 - I) M^-1 d_eq when M is
+ *                         invertible, and is defined for singular M as well
+ *   T      D*D            orthogonal; T^T U T is block diagonal with q blocks
+ *                         theta_i [[0,1],[-1,0]] followed by zeros
+ *   theta  q              rotation rates of U's eigenvalue pairs +-i theta_i
+ *   R      D*D complex    route-D eigenvectors (U = R Lambda R^+)
+ *   lam    D complex      route-D eigenvalues (purely imaginary)
+ *   S      q*D*D          route-R matrices S_i with U = sum theta_i S_i
+ *   K, c   D*D, D         fused factor T^T A0^2 T and T^T (A0 + I) b0
+ *   w, p0  D, 1           dP/dt = w . z'' + p0 in T-coordinates
+ */
+typedef struct {
+  double *gen, *M, *U, *deq, *v, *d0, *A0, *b0, *T, *theta, *R, *lam, *S, *K, *c, *w, *p0;
+} mln_factors;
+
+int mln_setup_factors(const mln_medium *medium, double dt, mln_factors *out);
+
+/* Library version (major*10000 + minor*100 + patch). */
+int mln_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLN_H */

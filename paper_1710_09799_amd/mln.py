@@ -1,0 +1,265 @@
+"""Thin Python binding of the C ABI in ``include/mln.h`` (argument marshalling
+only: every step of the time integration runs in the HIP kernels of
+``libmln.so``).  PyTorch provides the device memory for the recorded outputs
+and the HIP stream the library enqueues on.
+
+The binding never falls back to another implementation: if ``libmln.so`` is
+missing or a call fails, it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmln.so")
+
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp32c": 2, "bf16x": 3}
+ROUTES = {"rotation": 0, "diag": 1, "rodrigues": 2}
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class MLNError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mln error {code}: {msg}")
+        self.code = code
+
+
+class _Medium(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int32), ("h0", _dp), ("dipole", _dp),
+                ("n_jump", ctypes.c_int32), ("jump", _dp), ("jump_rate", _dp),
+                ("dephasing", ctypes.c_double), ("relax_superop", _dp), ("rho0", _dp),
+                ("density", ctypes.c_double)]
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("nt", ctypes.c_int64), ("dx", ctypes.c_double),
+                ("dt", ctypes.c_double), ("med_begin", ctypes.c_int64), ("med_end", ctypes.c_int64),
+                ("eps_r", ctypes.c_double), ("mu_r", ctypes.c_double), ("sigma", ctypes.c_double)]
+
+
+class _Source(ctypes.Structure):
+    _fields_ = [("samples", _dp), ("n_samples", ctypes.c_int64), ("amplitude", ctypes.c_double)]
+
+
+class _Record(ctypes.Structure):
+    _fields_ = [("snap_every", ctypes.c_int64), ("pop_out", _dp), ("e_out", _dp),
+                ("probe_out", _dp), ("out_on_device", ctypes.c_int32)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("route", ctypes.c_int32),
+                ("steps_per_launch", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+class _Factors(ctypes.Structure):
+    _fields_ = [(n, _dp) for n in ("gen", "M", "U", "deq", "v", "d0", "A0", "b0", "T", "theta",
+                                   "R", "lam", "S", "K", "c", "w", "p0")]
+
+
+# every symbol include/mln.h declares
+EXPORTS = ["mln_init", "mln_step", "mln_run", "mln_reset", "mln_current_step", "mln_get_fields",
+           "mln_state_bytes", "mln_save_state", "mln_load_state", "mln_bloch_only", "mln_free",
+           "mln_strerror", "mln_last_error", "mln_setup_factors", "mln_version"]
+
+_lib = None
+
+
+def load():
+    """Load libmln.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} not found: build it with `python -m paper_1710_09799_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    sig = {
+        "mln_init": ([ctypes.POINTER(_Medium), ctypes.POINTER(_Grid), ctypes.POINTER(_Source),
+                      ctypes.POINTER(_Record), ctypes.POINTER(_Options), ctypes.POINTER(P)], ctypes.c_int),
+        "mln_step": ([P, ctypes.c_int64], ctypes.c_int),
+        "mln_run": ([P], ctypes.c_int),
+        "mln_reset": ([P], ctypes.c_int),
+        "mln_current_step": ([P, i64p], ctypes.c_int),
+        "mln_get_fields": ([P, _dp, _dp], ctypes.c_int),
+        "mln_state_bytes": ([P, i64p], ctypes.c_int),
+        "mln_save_state": ([P, P], ctypes.c_int),
+        "mln_load_state": ([P, P], ctypes.c_int),
+        "mln_bloch_only": ([P, _dp, ctypes.c_int64, _dp, _dp], ctypes.c_int),
+        "mln_free": ([P], None),
+        "mln_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "mln_last_error": ([], ctypes.c_char_p),
+        "mln_setup_factors": ([ctypes.POINTER(_Medium), ctypes.c_double, ctypes.POINTER(_Factors)],
+                              ctypes.c_int),
+        "mln_version": ([], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        L = load()
+        raise MLNError(rc, L.mln_last_error().decode())
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_dp) if a is not None else None
+
+
+def _cx(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.complex128)).view(np.float64)
+
+
+class _MediumArgs:
+    """Keeps the numpy arrays alive while the C struct points at them."""
+
+    def __init__(self, med):
+        n = med.n_levels
+        self.h0 = _cx(med.h0)
+        self.mu = _cx(med.dipole)
+        self.rho0 = _cx(med.rho0)
+        nj = len(med.jumps)
+        self.jump = _cx(np.array(med.jumps).reshape(nj, n, n)) if nj else None
+        self.rate = np.ascontiguousarray(np.array(med.jump_rates, dtype=np.float64)) if nj else None
+        self.relax = _cx(med.relax_superop) if med.relax_superop is not None else None
+        self.s = _Medium(n, _ptr(self.h0), _ptr(self.mu), nj, _ptr(self.jump), _ptr(self.rate),
+                         float(med.dephasing), _ptr(self.relax), _ptr(self.rho0), float(med.density))
+
+
+def setup_factors(medium, dt):
+    """Host-only FP64 factors (no GPU needed).  Returns a dict of numpy arrays."""
+    L = load()
+    n = medium.n_levels
+    D, q = n * n - 1, n * (n - 1) // 2
+    out = dict(gen=np.zeros((D, n, n), complex), M=np.zeros((D, D)), U=np.zeros((D, D)),
+               deq=np.zeros(D), v=np.zeros(D), d0=np.zeros(D), A0=np.zeros((D, D)), b0=np.zeros(D),
+               T=np.zeros((D, D)), theta=np.zeros(q), R=np.zeros((D, D), complex),
+               lam=np.zeros(D, complex), S=np.zeros((q, D, D)), K=np.zeros((D, D)), c=np.zeros(D),
+               w=np.zeros(D), p0=np.zeros(1))
+    ptrs = {k: (v.view(np.float64) if np.iscomplexobj(v) else v).ctypes.data_as(_dp) for k, v in out.items()}
+    fs = _Factors(**ptrs)
+    ma = _MediumArgs(medium)
+    _check(L.mln_setup_factors(ctypes.byref(ma.s), float(dt), ctypes.byref(fs)))
+    out["p0"] = float(out["p0"][0])
+    return out
+
+
+class Solver:
+    """One coupled simulation on the GPU.
+
+    Outputs (torch float64 tensors on the device) after run():
+      probe (nt+1,), e_snap (nsnap, nx), pop (nsnap, N, n_med).
+    """
+
+    def __init__(self, problem, precision="fp64", route="rotation", snap_every=0,
+                 steps_per_launch=0, tile=0, record_probe=True, record_pop=True, record_e=True):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("Solver needs a HIP device")
+        L = load()
+        self.problem = problem
+        med, g, src = problem.medium, problem.grid, problem.source
+        n = med.n_levels
+        self.nsnap = g.nt // snap_every if snap_every > 0 else 0
+        dev = torch.device("cuda")
+        self.probe = torch.zeros(g.nt + 1, dtype=torch.float64, device=dev) if record_probe else None
+        self.e_snap = (torch.zeros((self.nsnap, g.nx), dtype=torch.float64, device=dev)
+                       if (record_e and self.nsnap) else None)
+        self.pop = (torch.zeros((self.nsnap, n, g.n_med), dtype=torch.float64, device=dev)
+                    if (record_pop and self.nsnap) else None)
+        self._ma = _MediumArgs(med)
+        self._samples = np.ascontiguousarray(src.samples, dtype=np.float64)
+        gs = _Grid(g.nx, g.nt, g.dx, g.dt, g.med_begin, g.med_end, g.eps_r, g.mu_r, g.sigma)
+        ss = _Source(_ptr(self._samples), len(self._samples), float(src.amplitude))
+
+        def dptr(t):
+            return ctypes.cast(ctypes.c_void_p(t.data_ptr()), _dp) if t is not None else None
+
+        rs = _Record(snap_every, dptr(self.pop), dptr(self.e_snap), dptr(self.probe), 1)
+        self.stream = torch.cuda.current_stream()
+        os_ = _Options(PRECISIONS[precision], ROUTES[route], steps_per_launch, tile,
+                       ctypes.c_void_p(self.stream.cuda_stream))
+        h = ctypes.c_void_p()
+        _check(L.mln_init(ctypes.byref(self._ma.s), ctypes.byref(gs), ctypes.byref(ss),
+                          ctypes.byref(rs), ctypes.byref(os_), ctypes.byref(h)))
+        self._h = h
+        self._L = L
+
+    def step(self, n):
+        _check(self._L.mln_step(self._h, int(n)))
+
+    def run(self):
+        _check(self._L.mln_run(self._h))
+        return self.outputs()
+
+    def reset(self):
+        _check(self._L.mln_reset(self._h))
+
+    def current_step(self):
+        v = ctypes.c_int64()
+        _check(self._L.mln_current_step(self._h, ctypes.byref(v)))
+        return v.value
+
+    def outputs(self):
+        return dict(probe=self.probe, e_snap=self.e_snap, pop=self.pop)
+
+    def fields(self):
+        nx = self.problem.grid.nx
+        E = np.zeros(nx)
+        H = np.zeros(nx - 1)
+        _check(self._L.mln_get_fields(self._h, _ptr(E), _ptr(H)))
+        return E, H
+
+    def save_state(self):
+        nb = ctypes.c_int64()
+        _check(self._L.mln_state_bytes(self._h, ctypes.byref(nb)))
+        buf = np.zeros(nb.value, dtype=np.uint8)
+        _check(self._L.mln_save_state(self._h, buf.ctypes.data_as(ctypes.c_void_p)))
+        return buf
+
+    def load_state(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        _check(self._L.mln_load_state(self._h, buf.ctypes.data_as(ctypes.c_void_p)))
+
+    def bloch_only(self, efield):
+        """Prescribed field efield (nt, n_med) as a torch float64 device tensor."""
+        import torch
+        efield = efield.contiguous()
+        nt, nc = efield.shape
+        n = self.problem.medium.n_levels
+        pop = torch.zeros((nt, n, nc), dtype=torch.float64, device=efield.device)
+        dp = torch.zeros((nt, nc), dtype=torch.float64, device=efield.device)
+        cast = lambda t: ctypes.cast(ctypes.c_void_p(t.data_ptr()), _dp)
+        _check(self._L.mln_bloch_only(self._h, cast(efield), nt, cast(pop), cast(dp)))
+        return dict(pop=pop, dp=dp)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.mln_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run(problem, **kw):
+    """Convenience: build, run to the end, return outputs as numpy arrays."""
+    s = Solver(problem, **kw)
+    out = s.run()
+    res = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+    s.close()
+    return res

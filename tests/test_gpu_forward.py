@@ -1,0 +1,223 @@
+"""GPU parity of the forward path against the FP64 oracle, through the C ABI.
+
+Error measures (same on every test):
+  err_E   = max |E - E_oracle| / max |E_oracle| over all recorded E (snapshots
+            and the boundary probe);
+  err_pop = max |rho_aa - rho_aa_oracle| over recorded populations.
+FP64 tolerance 1e-10 (both quantities).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1710_09799_amd import mln
+from paper_1710_09799_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+
+def _errs(got, ref):
+    e = np.concatenate([got["e_snap"].ravel(), got["probe"].ravel()])
+    er = np.concatenate([ref["e_snap"].ravel(), ref["probe"].ravel()])
+    err_e = np.max(np.abs(e - er)) / np.max(np.abs(er))
+    err_p = np.max(np.abs(got["pop"] - ref["pop"])) if ref["pop"].size else 0.0
+    return err_e, err_p
+
+
+def _print_case(name, **kw):
+    print(f"[case] {name} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+@pytest.fixture(scope="module")
+def ref_cache(orc):
+    cache = {}
+
+    def get(key, problem, snap):
+        if key not in cache:
+            cache[key] = orc.run(problem, snap_every=snap)
+        return cache[key]
+    return get
+
+
+SMALL = [(2, 1), (3, 2), (4, 3), (6, 4)]
+
+
+@pytest.mark.parametrize("n,seed", SMALL)
+@pytest.mark.parametrize("route", ["rotation", "diag", "rodrigues"])
+@pytest.mark.parametrize("tile,k", [(64, 8), (256, 32), (128, 50)])
+def test_coupled_fp64_small(ref_cache, n, seed, route, tile, k):
+    """Random medium with Lindblad relaxation on a grid spanning several tiles
+    with a ragged last tile; every recorded E and population."""
+    p = W.random_problem(n, seed, nx=203, nt=360)
+    _print_case("coupled_small", n=n, seed=seed, route=route, tile=tile, k=k)
+    ref = ref_cache((n, seed), p, 40)
+    got = mln.run(p, precision="fp64", route=route, snap_every=40, tile=tile, steps_per_launch=k)
+    ee, ep = _errs(got, ref)
+    assert ee < TOL64 and ep < TOL64, (ee, ep)
+
+
+def test_two_level_full_fp64(orc):
+    """Two-level self-induced transparency set-up at full size: 2000 cells,
+    10000 steps, 2 pi sech pulse through a medium filling the central half."""
+    p = W.two_level()
+    _print_case("two_level_full")
+    ref = orc.run(p, snap_every=1000)
+    got = mln.run(p, precision="fp64", snap_every=1000)
+    ee, ep = _errs(got, ref)
+    print("two_level_full err_E", ee, "err_pop", ep)
+    assert ee < TOL64 and ep < TOL64
+    # the pulse went through the medium and came out
+    assert np.max(np.abs(ref["probe"])) > 0.3 * p.source.amplitude
+
+
+def test_three_level_reduced_fp64(orc):
+    """Three-level ladder at 2000 cells x 10000 steps (pi Gaussian pulse,
+    Lindblad decay and dephasing)."""
+    p = W.three_level(nx=2000, nt=10000)
+    _print_case("three_level_reduced")
+    ref = orc.run(p, snap_every=500)
+    got = mln.run(p, precision="fp64", snap_every=500)
+    ee, ep = _errs(got, ref)
+    print("three_level_reduced err_E", ee, "err_pop", ep)
+    assert ee < TOL64 and ep < TOL64
+    assert np.max(ref["pop"][:, 1]) > 1e-2  # the pulse moved population
+
+
+def test_three_level_full_grid_first_steps(orc):
+    """Full 20000-cell grid in the benchmark's launch configuration; the
+    oracle follows the first 1000 steps, compared element by element."""
+    p = W.three_level()
+    p.grid.nt = 1000
+    _print_case("three_level_full_grid")
+    ref = orc.run(p, snap_every=250)
+    got = mln.run(p, precision="fp64", snap_every=250)
+    ee, ep = _errs(got, ref)
+    assert ee < TOL64 and ep < TOL64
+
+
+@pytest.mark.parametrize("n,seed", SMALL)
+@pytest.mark.parametrize("route", ["rotation", "diag", "rodrigues"])
+def test_bloch_only_fp64(orc, n, seed, route):
+    import torch
+    med = W.random_medium(n, seed + 50)
+    rng = np.random.default_rng(seed)
+    nt, nc = 500, 37
+    f = rng.uniform(-3e9, 3e9, size=(nt, nc))
+    grid = W.Grid(nx=nc + 2, nt=1, dx=W.DX0, dt=W.DT0, med_begin=1, med_end=nc + 1)
+    prob = W.Problem("b", med, grid, W.Source(np.zeros(2), 0.0))
+    ref = orc.bloch(med, f, W.DT0)
+    s = mln.Solver(prob, precision="fp64", route=route)
+    out = s.bloch_only(torch.tensor(f, device="cuda"))
+    pop = out["pop"].cpu().numpy()
+    dp = out["dp"].cpu().numpy()
+    assert np.max(np.abs(pop - ref["pop"])) < TOL64
+    assert np.max(np.abs(dp - ref["dp"])) < TOL64 * np.max(np.abs(ref["dp"]))
+
+
+def test_vacuum_magic_time_step_exact(orc):
+    """Empty medium at Courant number 1: the signal moves one cell per step."""
+    c = orc.constants()
+    nx, nt, dx = 300, 700, 1e-7
+    dt = dx * math.sqrt(c["eps0"] * c["mu0"])
+    rng = np.random.default_rng(2)
+    s = rng.normal(size=nt + 1)
+    med = W.ladder_medium([0.0, 1e-19], [1e-29], density=0.0)
+    prob = W.Problem("vac", med, W.Grid(nx=nx, nt=nt, dx=dx, dt=dt, med_begin=1, med_end=1),
+                     W.Source(s, 1.5))
+    got = mln.run(prob, precision="fp64", snap_every=7)
+    for si in range(nt // 7):
+        n = 7 * (si + 1)
+        i = np.arange(nx - 1)
+        want = np.where(i <= n, 1.5 * s[np.clip(n - i, 0, None)], 0.0)
+        assert np.max(np.abs(got["e_snap"][si, : nx - 1] - want)) < 1e-12 * 1.5 * np.abs(s).max()
+    k = np.arange(nt + 1) - (nx - 1)
+    want = np.where(k >= 0, 1.5 * s[np.clip(k, 0, None)], 0.0)
+    assert np.max(np.abs(got["probe"] - want)) < 1e-12 * 1.5 * np.abs(s).max()
+
+
+@pytest.mark.parametrize("mb,me", [(1, 2), (5, 5), (1, 199), (150, 199)])
+def test_medium_edge_cases(orc, mb, me):
+    """One-cell medium, empty medium, medium touching both boundaries'
+    neighbours."""
+    p = W.random_problem(3, 77, nx=200, nt=300, med=(mb, me))
+    _print_case("medium_edges", mb=mb, me=me)
+    ref = orc.run(p, snap_every=30)
+    got = mln.run(p, precision="fp64", snap_every=30, tile=64, steps_per_launch=16)
+    ee, ep = _errs(got, ref)
+    assert ee < TOL64 and ep < TOL64
+
+
+def test_minimal_grid_and_zero_steps(orc):
+    p = W.random_problem(2, 5, nx=3, nt=50, med=(1, 2))
+    ref = orc.run(p, snap_every=5)
+    got = mln.run(p, precision="fp64", snap_every=5)
+    ee, ep = _errs(got, ref)
+    assert ee < TOL64 and ep < TOL64
+    p0 = W.random_problem(2, 5, nx=30, nt=0)
+    got = mln.run(p0, precision="fp64")
+    assert got["probe"].shape == (1,) and got["probe"][0] == 0.0
+
+
+def test_chunked_stepping_and_determinism():
+    """Stepping in uneven chunks equals one call, bit for bit; two runs are
+    bitwise identical (no races between workgroups)."""
+    p = W.random_problem(3, 8, nx=500, nt=777)
+    a = mln.run(p, precision="fp64", snap_every=37)
+    b = mln.run(p, precision="fp64", snap_every=37)
+    s = mln.Solver(p, precision="fp64", snap_every=37)
+    for k in (1, 6, 30, 100, 3):
+        s.step(k)
+    s.run()
+    c = {k: v.cpu().numpy() for k, v in s.outputs().items()}
+    for key in ("probe", "e_snap", "pop"):
+        assert np.array_equal(a[key], b[key])
+        assert np.array_equal(a[key], c[key])
+
+
+def test_checkpoint_resume_bitwise():
+    p = W.random_problem(3, 9, nx=300, nt=600)
+    s = mln.Solver(p, precision="fp64", snap_every=50)
+    s.step(250)
+    ck = s.save_state()
+    s.run()
+    ref = {k: v.cpu().numpy().copy() for k, v in s.outputs().items()}
+    E_end, H_end = s.fields()
+    s.reset()
+    s.step(10)
+    s.load_state(ck)
+    assert s.current_step() == 250
+    s.run()
+    got = {k: v.cpu().numpy() for k, v in s.outputs().items()}
+    assert np.array_equal(ref["probe"][251:], got["probe"][251:])
+    assert np.array_equal(ref["e_snap"][5:], got["e_snap"][5:])
+    E2, H2 = s.fields()
+    assert np.array_equal(E_end, E2) and np.array_equal(H_end, H2)
+
+
+def test_reset_reproduces_run():
+    p = W.random_problem(2, 10, nx=400, nt=500)
+    s = mln.Solver(p, precision="fp64", snap_every=100)
+    s.run()
+    a = {k: v.cpu().numpy().copy() for k, v in s.outputs().items()}
+    s.reset()
+    s.run()
+    b = {k: v.cpu().numpy() for k, v in s.outputs().items()}
+    for k in a:
+        assert np.array_equal(a[k], b[k])
+
+
+def test_three_level_full_run_invariants():
+    """Full three-level run (20000 cells, 100000 steps) in the benchmark
+    configuration: finite output, populations in [0, 1] summing to one, and
+    no field ahead of the light cone at the first snapshot."""
+    p = W.three_level()
+    got = mln.run(p, precision="fp64", snap_every=10000)
+    pop = got["pop"]
+    assert np.all(np.isfinite(pop)) and np.all(np.isfinite(got["e_snap"]))
+    assert pop.min() > -1e-12 and pop.max() < 1 + 1e-12
+    assert np.max(np.abs(pop.sum(axis=1) - 1.0)) < 1e-12
+    # at step 10000 light has moved 5000 cells (Courant 0.5)
+    assert np.all(got["e_snap"][0, 5002:] == 0.0)
