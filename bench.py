@@ -76,7 +76,7 @@ def cpu_baseline(seconds_target=15.0):
     import oracle
     from paper_1710_09799_amd import workloads as W
     p = W.three_level()
-    nt = 600
+    nt = 3000
     t0 = time.perf_counter()
     oracle.run(p, nt=nt)
     dt = time.perf_counter() - t0

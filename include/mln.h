@@ -129,7 +129,26 @@ typedef struct {
   int32_t steps_per_launch;    /* time steps fused into one launch (0 = automatic) */
   int32_t tile;                /* cells per workgroup tile (0 = automatic)         */
   void *stream;                /* hipStream_t, NULL = default stream               */
+  int32_t ckpt_every;          /* > 0: mln_run keeps a full-state checkpoint every
+                                  ckpt_every steps so that mln_grad can run; 0: off */
+  int32_t variant;             /* forward kernel: 0 automatic, 1 workgroup tile
+                                  (one cell per thread, LDS exchange), 2 wavefront
+                                  tile (rotation route; tile/64 cells per lane)       */
 } mln_options;
+
+/* Gradients of a scalar objective J with respect to the physical inputs (any
+ * pointer may be NULL).  Hermitian N x N inputs use one complex number per
+ * entry: for a < b, d[a*N+b] = dJ/dRe(X_ab) + i dJ/dIm(X_ab) under the
+ * Hermitian perturbation that changes X_ab and X_ba together (d[b*N+a] is its
+ * conjugate); d[a*N+a] = dJ/dX_aa. */
+typedef struct {
+  double *d_h0;                /* N*N complex (level energies: the diagonal)       */
+  double *d_dipole;            /* N*N complex                                      */
+  double *d_jump_rate;         /* n_jump                                           */
+  double *d_dephasing;         /* 1                                                */
+  double *d_amplitude;         /* 1 (source amplitude)                             */
+  double *d_density;           /* 1 (N_a)                                          */
+} mln_grads;
 
 typedef struct mln_handle mln_handle;
 
@@ -180,6 +199,18 @@ int mln_load_state(mln_handle *h, const void *host_buf);
 int mln_bloch_only(mln_handle *h, const double *efield, int64_t n_steps, double *pop_out,
                    double *dp_out);
 
+/* Vector-Jacobian product of the whole run (the adjoint, reverse-time pass):
+ * given g[n] = dJ/dprobe[n] for n = 0..nt (host array), fill *out with
+ * dJ/d(inputs).  Needs a handle created with ckpt_every > 0 on which mln_run
+ * has completed; the forward state is rebuilt segment by segment from the
+ * checkpoints (recomputation), and each segment is then swept backwards by the
+ * reverse kernel, which accumulates the parameter gradients on the GPU.  The
+ * final chain rule through exp(M dt/2) runs on the host in FP64.  Supported
+ * for the rotation route, FP64 and FP32 (plain or compensated), N <= 3.
+ * Errors: MLN_ESTATE (no completed checkpointed run), MLN_ENOTSUPPORTED.
+ * Synchronises. */
+int mln_grad(mln_handle *h, const double *dJ_dprobe, mln_grads *out);
+
 void mln_free(mln_handle *h);
 
 const char *mln_strerror(int code);
@@ -211,6 +242,16 @@ typedef struct {
 } mln_factors;
 
 int mln_setup_factors(const mln_medium *medium, double dt, mln_factors *out);
+
+/* Host-only chain rule used by mln_grad, exposed for testing: given the
+ * gradients of J with respect to the d-coordinate step quantities
+ * gA = dJ/dA (D*D, A = exp(M dt)), gc = dJ/dc (D, c = (A0 + I) b0),
+ * gw = dJ/dw (D, dP/dt = w . d'' + p0), gp0 = dJ/dp0, gU = dJ/dU (D*D) and
+ * gd0 = dJ/dd'_0 (D, d'_0 = A0 d(rho0) + b0), fill d_h0, d_dipole,
+ * d_jump_rate, d_dephasing and d_density of *out (d_amplitude untouched). */
+int mln_chain_rule(const mln_medium *medium, double dt, const double *gA, const double *gc,
+                   const double *gw, double gp0, const double *gU, const double *gd0,
+                   mln_grads *out);
 
 /* Library version (major*10000 + minor*100 + patch). */
 int mln_version(void);

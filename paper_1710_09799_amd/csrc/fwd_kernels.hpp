@@ -25,6 +25,10 @@ struct FacDev {
   const Real *lamdt;  // D      route D: Im(lambda_k) * dt
   const Real *S;      // q x D x D  route R S_p
   const Real *S2;     // q x D x D  route R S_p^2
+  const Real *Km_lo;  // D x D  low parts of Km, cz, thdt (compensated FP32 only)
+  const Real *cz_lo;
+  const Real *th_lo;
+  const Real *zr;     // D      reference state of the rotation route (state is z' - zr)
   Real p0;
   const double *pop;  // N x D  FP64 population map applied to the state after exp(U E dt)
   const double *popc; // N
@@ -45,7 +49,35 @@ struct FwdArgs {
   int nsteps, halo, owned;
   Real ch, ca, cb, inv_dx, kmur;
   int64_t snap_every;
+  int64_t snap_next;  // first step index n >= step0 that completes a snapshot ((n+1) % snap_every == 0)
+  int64_t snap_i0;    // snapshot index of that step
   double *pop_out, *e_out, *probe_out;
+  // optional tape for the adjoint: z' (D rows, high parts) and E (1 row) of
+  // every medium cell at every step n >= tape_step0, row stride ld
+  Real *tape;
+  int64_t tape_step0;
+};
+
+// Reverse-time (adjoint) tile kernel arguments.  Adjoint fields lE (of E),
+// lH (of H), lz (of z') use the same tiling as the forward kernel.
+template <typename Real>
+struct AdjArgs {
+  FacDev<Real> fac;
+  const Real *lEin;
+  Real *lEout;
+  const Real *lHin;
+  Real *lHout;
+  const Real *lzin;
+  Real *lzout;
+  const Real *tape;        // written by the forward kernel for steps >= tape_step0
+  int64_t tape_step0;
+  const double *gprobe;    // dJ/dprobe[n], n = 0..nt
+  const double *samples;   // source samples s[n] (E at cell 0 = amplitude * s[n])
+  int64_t nx, mb, me, ld;
+  int64_t n_hi;            // this launch reverses steps n_hi-1 down to n_hi-nsteps
+  int nsteps, halo, owned;
+  Real ch, ca, cb, inv_dx, kmur;
+  double *partial;         // [gridDim.x][nacc] per-tile gradient sums (accumulated)
 };
 
 template <typename Real>
@@ -57,9 +89,29 @@ struct BlochArgs {
   double *pop_out, *dp_out;
 };
 
+// comp = true selects the compensated single-precision state (float only,
+// rotation route only): z holds D rows of high parts followed by D rows of
+// low parts.
 template <typename Real>
-hipError_t launch_fwd(int N, int route, const FwdArgs<Real> &a, int64_t nblocks, int W, hipStream_t st);
+hipError_t launch_fwd(int N, int route, bool comp, const FwdArgs<Real> &a, int64_t nblocks, int W,
+                      hipStream_t st);
 template <typename Real>
-hipError_t launch_bloch(int N, int route, const BlochArgs<Real> &a, hipStream_t st);
+hipError_t launch_bloch(int N, int route, bool comp, const BlochArgs<Real> &a, hipStream_t st);
+
+// Single-wavefront tile kernel of the rotation route (fwd_wave.hpp): 64 lanes,
+// C cells per lane (C = 1, 2, 4 for N <= 4; C = 1 for N = 6).
+template <typename Real>
+hipError_t launch_fwd_wave(int N, bool comp, int C, const FwdArgs<Real> &a, int64_t nblocks, hipStream_t st);
+
+// Number of gradient accumulators per tile for N levels in precision Real:
+// dJ/dK (D*D), dJ/dc (D), dJ/dw (D), dJ/dp0, dJ/damplitude, and the moments
+// sum E^m lhat zhat^T for m = 1, 3 (and 5 in FP64), D*D each.
+constexpr int adj_moments(bool fp64) { return fp64 ? 3 : 2; }
+constexpr int adj_nacc(int N, bool fp64) {
+  return (N * N - 1) * (N * N - 1) * (1 + adj_moments(fp64)) + 2 * (N * N - 1) + 2;
+}
+
+template <typename Real>
+hipError_t launch_adj(int N, const AdjArgs<Real> &a, int64_t nblocks, int W, hipStream_t st);
 
 }  // namespace mln

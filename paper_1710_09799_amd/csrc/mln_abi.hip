@@ -49,15 +49,42 @@ struct DevBuf {
 
 }  // namespace
 
+// Deep copy of an mln_medium (the handle keeps it for the adjoint's chain rule).
+struct MediumCopy {
+  std::vector<double> h0, mu, jump, rate, relax, rho0;
+  mln_medium m{};
+  void set(const mln_medium *src) {
+    const int N = src->n_levels, NN = N * N;
+    h0.assign(src->h0, src->h0 + 2 * NN);
+    mu.assign(src->dipole, src->dipole + 2 * NN);
+    rho0.assign(src->rho0, src->rho0 + 2 * NN);
+    if (src->n_jump > 0) {
+      jump.assign(src->jump, src->jump + 2 * NN * src->n_jump);
+      rate.assign(src->jump_rate, src->jump_rate + src->n_jump);
+    }
+    if (src->relax_superop) relax.assign(src->relax_superop, src->relax_superop + 2 * NN * NN);
+    m = *src;
+    m.h0 = h0.data();
+    m.dipole = mu.data();
+    m.rho0 = rho0.data();
+    m.jump = jump.empty() ? nullptr : jump.data();
+    m.jump_rate = rate.empty() ? nullptr : rate.data();
+    m.relax_superop = relax.empty() ? nullptr : relax.data();
+  }
+};
+
 struct mln_handle {
   Factors f;
+  MediumCopy medium;
   mln_grid grid{};
   double amp = 0.0;
   std::vector<double> samples;
   int prec = MLN_FP64, route = MLN_ROUTE_ROTATION;
+  bool comp = false;  // compensated FP32 state (two floats per component)
   hipStream_t stream = nullptr;
   int64_t nmed = 0, ld = 0, step = 0;
-  int W = 256, halo = 0, owned = 0;
+  int W = 256, halo = 0, owned = 0;  // cells per tile, halo = max steps per launch
+  bool wave = false;                  // single-wavefront tile kernel (W = 64 * C cells)
   int64_t ntiles = 0;
   int rs = 8;  // bytes per real of the state
   // device state (ping-pong)
@@ -73,6 +100,12 @@ struct mln_handle {
   double *d_pop = nullptr, *d_e = nullptr, *d_probe = nullptr;
   // initial state on the host
   std::vector<unsigned char> z_init, e_init;
+  // checkpoints of the forward run (for the adjoint)
+  int64_t ckpt_every = 0, nckpt = 0, ckpt_count = 0;
+  bool ckpt_ok = false;
+  DevBuf ckpt;
+  // adjoint buffers (allocated by the first mln_grad)
+  DevBuf lE[2], lH[2], lz[2], tape, partial, gprobe, samples_dev;
   double fd_coef[5] = {0, 0, 0, 0, 0};  // ch, ca, cb, inv_dx, kmur
 };
 
@@ -101,9 +134,18 @@ int upload_factors(mln_handle *h, FacDev<Real> &fd) {
     rim[i] = f.R[i].imag();
   }
   for (int k = 0; k < D; ++k) lamdt[k] = f.lam[k].imag() * h->grid.dt;
-  size_t oK = push(Km), oc = push(rot ? f.cz : f.c), ow = push(rot ? f.wz : f.w);
+  size_t oK = push(Km), oc = push(rot ? f.rz : f.c), ow = push(rot ? f.wz : f.w);
   size_t oth = push(thdt), orr = push(rre), ori = push(rim), ol = push(lamdt);
   size_t oS = push(f.S), oS2 = push(f.S2);
+  size_t ozr = push(rot ? f.zr : std::vector<double>(D, 0.0));
+  // low parts x - (float)x of the factors the compensated state uses
+  auto lo_of = [](const std::vector<double> &v) {
+    std::vector<double> r(v.size());
+    for (size_t i = 0; i < v.size(); ++i) r[i] = v[i] - (double)(Real)v[i];
+    return r;
+  };
+  const std::vector<double> &cvec = rot ? f.rz : f.c;
+  size_t oKl = push(lo_of(Km)), ocl = push(lo_of(cvec)), otl = push(lo_of(thdt));
   HIP_TRY(h->fac.alloc(blk.size() * sizeof(Real)));
   HIP_TRY(hipMemcpy(h->fac.p, blk.data(), blk.size() * sizeof(Real), hipMemcpyHostToDevice));
   const Real *b = (const Real *)h->fac.p;
@@ -116,12 +158,17 @@ int upload_factors(mln_handle *h, FacDev<Real> &fd) {
   fd.lamdt = b + ol;
   fd.S = b + oS;
   fd.S2 = b + oS2;
-  fd.p0 = (Real)f.p0;
+  fd.Km_lo = b + oKl;
+  fd.cz_lo = b + ocl;
+  fd.th_lo = b + otl;
+  fd.zr = b + ozr;
+  fd.p0 = (Real)(rot ? f.pr : f.p0);
   const std::vector<double> &pm = rot ? f.popz : f.popd;
   HIP_TRY(h->pop.alloc(pm.size() * sizeof(double)));
   HIP_TRY(hipMemcpy(h->pop.p, pm.data(), pm.size() * sizeof(double), hipMemcpyHostToDevice));
-  HIP_TRY(h->popc.alloc(f.popc.size() * sizeof(double)));
-  HIP_TRY(hipMemcpy(h->popc.p, f.popc.data(), f.popc.size() * sizeof(double), hipMemcpyHostToDevice));
+  const std::vector<double> &pc = rot ? f.popcy : f.popc;
+  HIP_TRY(h->popc.alloc(pc.size() * sizeof(double)));
+  HIP_TRY(hipMemcpy(h->popc.p, pc.data(), pc.size() * sizeof(double), hipMemcpyHostToDevice));
   fd.pop = (const double *)h->pop.p;
   fd.popc = (const double *)h->popc.p;
   return MLN_OK;
@@ -131,11 +178,15 @@ template <typename Real>
 void build_init_state(mln_handle *h) {
   const Factors &f = h->f;
   const int D = f.D;
-  const std::vector<double> &s0 = (h->route == MLN_ROUTE_ROTATION) ? f.z0 : f.dprime0;
-  h->z_init.assign(sizeof(Real) * D * h->ld, 0);
+  const std::vector<double> &s0 = (h->route == MLN_ROUTE_ROTATION) ? f.y0 : f.dprime0;
+  const int rows = h->comp ? 2 * D : D;
+  h->z_init.assign(sizeof(Real) * rows * h->ld, 0);
   Real *zi = (Real *)h->z_init.data();
   for (int j = 0; j < D; ++j)
-    for (int64_t c = 0; c < h->nmed; ++c) zi[j * h->ld + c] = (Real)s0[j];
+    for (int64_t c = 0; c < h->nmed; ++c) {
+      zi[j * h->ld + c] = (Real)s0[j];
+      if (h->comp) zi[(D + j) * h->ld + c] = (Real)(s0[j] - (double)(Real)s0[j]);
+    }
   h->e_init.assign(sizeof(Real) * h->grid.nx, 0);
   ((Real *)h->e_init.data())[0] = (Real)(h->amp * h->samples[0]);
 }
@@ -149,6 +200,8 @@ int reset_state(mln_handle *h) {
   }
   h->cur = 0;
   h->step = 0;
+  h->ckpt_count = 0;
+  h->ckpt_ok = h->ckpt_every > 0;
   if (h->d_probe) {
     double p0 = (h->grid.nx - 1 == 0) ? h->amp * h->samples[0] : 0.0;
     HIP_TRY(hipMemcpyAsync(h->d_probe, &p0, sizeof(double), hipMemcpyHostToDevice, h->stream));
@@ -158,7 +211,8 @@ int reset_state(mln_handle *h) {
 }
 
 template <typename Real>
-FwdArgs<Real> make_args(mln_handle *h, const FacDev<Real> &fd, int64_t step0, int nsteps) {
+FwdArgs<Real> make_args(mln_handle *h, const FacDev<Real> &fd, int64_t step0, int nsteps,
+                        bool record = true, Real *tape = nullptr, int64_t tape_step0 = 0) {
   FwdArgs<Real> a{};
   a.fac = fd;
   const int in = h->cur, out = 1 - h->cur;
@@ -182,11 +236,71 @@ FwdArgs<Real> make_args(mln_handle *h, const FacDev<Real> &fd, int64_t step0, in
   a.cb = (Real)h->fd_coef[2];
   a.inv_dx = (Real)h->fd_coef[3];
   a.kmur = (Real)h->fd_coef[4];
-  a.snap_every = h->rec.snap_every;
-  a.pop_out = h->d_pop;
-  a.e_out = h->d_e;
-  a.probe_out = h->d_probe;
+  a.snap_every = record ? h->rec.snap_every : 0;
+  // first step n >= step0 with (n+1) % snap_every == 0, and its snapshot index
+  a.snap_next = -1;
+  a.snap_i0 = 0;
+  if (a.snap_every > 0) {
+    const int64_t k = step0 / a.snap_every;  // snapshots completed before step0
+    a.snap_next = (k + 1) * a.snap_every - 1;
+    a.snap_i0 = k;
+  }
+  a.pop_out = record ? h->d_pop : nullptr;
+  a.e_out = record ? h->d_e : nullptr;
+  a.probe_out = record ? h->d_probe : nullptr;
+  a.tape = tape;
+  a.tape_step0 = tape_step0;
   return a;
+}
+
+size_t state_slot_bytes(const mln_handle *h) { return h->E[0].bytes + h->H[0].bytes + h->z[0].bytes; }
+
+// copy the current forward state into checkpoint slot k, or back
+int ckpt_copy(mln_handle *h, int64_t k, bool save) {
+  unsigned char *slot = (unsigned char *)h->ckpt.p + k * state_slot_bytes(h);
+  DevBuf *bufs[3] = {&h->E[h->cur], &h->H[h->cur], &h->z[h->cur]};
+  size_t off = 0;
+  for (DevBuf *b : bufs) {
+    if (save)
+      HIP_TRY(hipMemcpyAsync(slot + off, b->p, b->bytes, hipMemcpyDeviceToDevice, h->stream));
+    else
+      HIP_TRY(hipMemcpyAsync(b->p, slot + off, b->bytes, hipMemcpyDeviceToDevice, h->stream));
+    off += b->bytes;
+  }
+  return MLN_OK;
+}
+
+// Advance the forward state from h->step by n steps in launches of at most
+// `halo` steps that never cross a checkpoint boundary; saves checkpoints when
+// the run started from step 0.
+int forward_steps(mln_handle *h, int64_t n, bool record, void *tape, int64_t tape_step0, bool save_ckpt) {
+  while (n > 0) {
+    int64_t k = std::min<int64_t>(n, h->halo);
+    if (h->ckpt_every > 0) {
+      const int64_t r = h->step % h->ckpt_every;
+      if (save_ckpt && r == 0 && h->ckpt_ok && h->step / h->ckpt_every == h->ckpt_count) {
+        int rc = ckpt_copy(h, h->ckpt_count, true);
+        if (rc) return rc;
+        ++h->ckpt_count;
+      }
+      k = std::min<int64_t>(k, h->ckpt_every - r);
+    }
+    hipError_t e;
+    if (h->prec == MLN_FP64) {
+      auto args = make_args<double>(h, h->fd, h->step, (int)k, record, (double *)tape, tape_step0);
+      e = h->wave ? launch_fwd_wave<double>(h->f.N, false, h->W / 64, args, h->ntiles, h->stream)
+                  : launch_fwd<double>(h->f.N, h->route, false, args, h->ntiles, h->W, h->stream);
+    } else {
+      auto args = make_args<float>(h, h->ff, h->step, (int)k, record, (float *)tape, tape_step0);
+      e = h->wave ? launch_fwd_wave<float>(h->f.N, h->comp, h->W / 64, args, h->ntiles, h->stream)
+                  : launch_fwd<float>(h->f.N, h->route, h->comp, args, h->ntiles, h->W, h->stream);
+    }
+    if (e != hipSuccess) return set_err(MLN_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    h->cur = 1 - h->cur;
+    h->step += k;
+    n -= k;
+  }
+  return MLN_OK;
 }
 
 int validate_grid(const mln_grid *g, const mln_source *s) {
@@ -222,7 +336,7 @@ int init_typed(mln_handle *h, FacDev<Real> &fd) {
   for (int b = 0; b < 2; ++b) {
     HIP_TRY(h->E[b].alloc(nx * sizeof(Real)));
     HIP_TRY(h->H[b].alloc(nx * sizeof(Real)));
-    HIP_TRY(h->z[b].alloc((size_t)D * h->ld * sizeof(Real)));
+    HIP_TRY(h->z[b].alloc((size_t)(h->comp ? 2 * D : D) * h->ld * sizeof(Real)));
   }
   build_init_state<Real>(h);
   return MLN_OK;
@@ -290,6 +404,16 @@ int mln_setup_factors(const mln_medium *medium, double dt, mln_factors *out) {
   return MLN_OK;
 }
 
+int mln_chain_rule(const mln_medium *medium, double dt, const double *gA, const double *gc,
+                   const double *gw, double gp0, const double *gU, const double *gd0,
+                   mln_grads *out) {
+  if (!gA || !gc || !gw || !gU || !gd0) return set_err(MLN_EINVAL, "null gradient input");
+  std::string err;
+  int rc = chain_rule(medium, dt, gA, gc, gw, gp0, gU, gd0, out, &err);
+  if (rc) return set_err(rc, err);
+  return MLN_OK;
+}
+
 int mln_init(const mln_medium *medium, const mln_grid *grid, const mln_source *source,
              const mln_record *record, const mln_options *options, mln_handle **out) {
   if (!out) return set_err(MLN_EINVAL, "null output handle");
@@ -300,6 +424,7 @@ int mln_init(const mln_medium *medium, const mln_grid *grid, const mln_source *s
   std::string err;
   rc = build_factors(medium, grid->dt, &h->f, &err);
   if (rc) return set_err(rc, err);
+  h->medium.set(medium);
   h->grid = *grid;
   h->amp = source->amplitude;
   h->samples.assign(source->samples, source->samples + grid->nt + 1);
@@ -310,8 +435,11 @@ int mln_init(const mln_medium *medium, const mln_grid *grid, const mln_source *s
   h->stream = (hipStream_t)opt.stream;
   if (h->route < 0 || h->route > 2) return set_err(MLN_EINVAL, "unknown route");
   if (h->f.N == 5) return set_err(MLN_ENOTSUPPORTED, "kernels are built for N = 2, 3, 4 and 6");
-  if (h->prec != MLN_FP64 && h->prec != MLN_FP32)
+  if (h->prec != MLN_FP64 && h->prec != MLN_FP32 && h->prec != MLN_FP32_COMP)
     return set_err(MLN_ENOTSUPPORTED, "precision not built in this library version");
+  h->comp = h->prec == MLN_FP32_COMP;
+  if (h->comp && h->route != MLN_ROUTE_ROTATION)
+    return set_err(MLN_ENOTSUPPORTED, "the compensated FP32 state is built for the rotation route only");
   h->rs = (h->prec == MLN_FP64) ? 8 : 4;
   // FDTD coefficients (Eq. maxwell on the Yee grid, semi-implicit sigma)
   const double eps = kEps0 * grid->eps_r, mu = kMu0 * grid->mu_r;
@@ -322,10 +450,16 @@ int mln_init(const mln_medium *medium, const mln_grid *grid, const mln_source *s
   h->fd_coef[2] = (grid->dt / eps) / (1.0 + sg);
   h->fd_coef[3] = 1.0 / grid->dx;
   h->fd_coef[4] = (cl * grid->dt - grid->dx) / (cl * grid->dt + grid->dx);
-  // tiling
+  // kernel variant and tiling
+  if (opt.variant < 0 || opt.variant > 2) return set_err(MLN_EINVAL, "unknown kernel variant");
+  const bool rot = h->route == MLN_ROUTE_ROTATION;
+  h->wave = opt.variant == 2 || (opt.variant == 0 && rot && h->f.N <= 4);
+  if (h->wave && !rot) return set_err(MLN_ENOTSUPPORTED, "the wavefront kernel implements the rotation route");
   h->W = opt.tile > 0 ? opt.tile : kMaxTile;
   if (h->W > kMaxTile || h->W < 64 || h->W % 64) return set_err(MLN_EINVAL, "tile must be a multiple of 64 in [64, 256]");
-  int K = opt.steps_per_launch > 0 ? opt.steps_per_launch : 32;
+  if (h->wave && (h->W == 192 || (h->f.N == 6 && h->W != 64)))
+    return set_err(MLN_ENOTSUPPORTED, "wavefront kernel tiles: 64, 128 or 256 cells (64 for N = 6)");
+  int K = opt.steps_per_launch > 0 ? opt.steps_per_launch : (h->wave ? h->W / 8 : 32);
   if (2 * K >= h->W) return set_err(MLN_EINVAL, "steps_per_launch must be below tile/2");
   h->halo = K;
   h->owned = h->W - 2 * K;
@@ -361,6 +495,12 @@ int mln_init(const mln_medium *medium, const mln_grid *grid, const mln_source *s
   }
   rc = (h->prec == MLN_FP64) ? init_typed<double>(h.get(), h->fd) : init_typed<float>(h.get(), h->ff);
   if (rc) return rc;
+  if (opt.ckpt_every < 0) return set_err(MLN_EINVAL, "ckpt_every must be >= 0");
+  h->ckpt_every = opt.ckpt_every;
+  if (h->ckpt_every > 0) {
+    h->nckpt = (grid->nt + h->ckpt_every - 1) / h->ckpt_every;
+    HIP_TRY(h->ckpt.alloc(std::max<int64_t>(h->nckpt, 1) * state_slot_bytes(h.get())));
+  }
   rc = reset_state(h.get());
   if (rc) return rc;
   *out = h.release();
@@ -371,19 +511,7 @@ int mln_step(mln_handle *h, int64_t n_steps) {
   if (!h) return set_err(MLN_EINVAL, "null handle");
   if (n_steps < 0) return set_err(MLN_EINVAL, "n_steps must be >= 0");
   int64_t left = std::min<int64_t>(n_steps, h->grid.nt - h->step);
-  while (left > 0) {
-    int k = (int)std::min<int64_t>(left, h->halo);
-    hipError_t e;
-    if (h->prec == MLN_FP64)
-      e = launch_fwd<double>(h->f.N, h->route, make_args<double>(h, h->fd, h->step, k), h->ntiles, h->W, h->stream);
-    else
-      e = launch_fwd<float>(h->f.N, h->route, make_args<float>(h, h->ff, h->step, k), h->ntiles, h->W, h->stream);
-    if (e != hipSuccess) return set_err(MLN_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
-    h->cur = 1 - h->cur;
-    h->step += k;
-    left -= k;
-  }
-  return MLN_OK;
+  return forward_steps(h, left, true, nullptr, 0, true);
 }
 
 int mln_run(mln_handle *h) {
@@ -475,6 +603,7 @@ int mln_load_state(mln_handle *h, const void *host_buf) {
   }
   h->step = step;
   h->cur = 0;
+  h->ckpt_ok = false;
   return MLN_OK;
 }
 
@@ -499,19 +628,23 @@ int mln_bloch_only(mln_handle *h, const double *efield, int64_t n_steps, double 
       dp_dev = (double *)ddp.p;
     }
   }
-  const std::vector<double> &s0 = (h->route == MLN_ROUTE_ROTATION) ? h->f.z0 : h->f.dprime0;
+  const std::vector<double> &s0 = (h->route == MLN_ROUTE_ROTATION) ? h->f.y0 : h->f.dprime0;
   hipError_t e;
   if (h->prec == MLN_FP64) {
     HIP_TRY(dz0.alloc(sizeof(double) * D));
     HIP_TRY(hipMemcpy(dz0.p, s0.data(), sizeof(double) * D, hipMemcpyHostToDevice));
     BlochArgs<double> a{h->fd, (const double *)dz0.p, e_dev, nc, n_steps, pop_dev, dp_dev};
-    e = launch_bloch<double>(N, h->route, a, h->stream);
+    e = launch_bloch<double>(N, h->route, false, a, h->stream);
   } else {
-    std::vector<float> z0f(s0.begin(), s0.end());
-    HIP_TRY(dz0.alloc(sizeof(float) * D));
-    HIP_TRY(hipMemcpy(dz0.p, z0f.data(), sizeof(float) * D, hipMemcpyHostToDevice));
+    std::vector<float> z0f(2 * D);
+    for (int j = 0; j < D; ++j) {
+      z0f[j] = (float)s0[j];
+      z0f[D + j] = (float)(s0[j] - (double)z0f[j]);
+    }
+    HIP_TRY(dz0.alloc(sizeof(float) * 2 * D));
+    HIP_TRY(hipMemcpy(dz0.p, z0f.data(), sizeof(float) * 2 * D, hipMemcpyHostToDevice));
     BlochArgs<float> a{h->ff, (const float *)dz0.p, e_dev, nc, n_steps, pop_dev, dp_dev};
-    e = launch_bloch<float>(N, h->route, a, h->stream);
+    e = launch_bloch<float>(N, h->route, h->comp, a, h->stream);
   }
   if (e != hipSuccess) return set_err(MLN_EHIP, std::string("bloch launch: ") + hipGetErrorString(e));
   HIP_TRY(hipStreamSynchronize(h->stream));
@@ -519,6 +652,175 @@ int mln_bloch_only(mln_handle *h, const double *efield, int64_t n_steps, double 
     if (pop_out) HIP_TRY(hipMemcpy(pop_out, pop_dev, sizeof(double) * nc * n_steps * N, hipMemcpyDeviceToHost));
     if (dp_out) HIP_TRY(hipMemcpy(dp_out, dp_dev, sizeof(double) * nc * n_steps, hipMemcpyDeviceToHost));
   }
+  return MLN_OK;
+}
+
+int mln_grad(mln_handle *h, const double *dJ_dprobe, mln_grads *out) {
+  if (!h || !dJ_dprobe || !out) return set_err(MLN_EINVAL, "null argument");
+  if (h->ckpt_every <= 0) return set_err(MLN_ESTATE, "handle was created without checkpoints (ckpt_every = 0)");
+  if (h->route != MLN_ROUTE_ROTATION || h->f.N > 3)
+    return set_err(MLN_ENOTSUPPORTED, "the adjoint is built for the rotation route and N <= 3");
+  const int64_t nt = h->grid.nt;
+  if (!h->ckpt_ok || h->step != nt || h->ckpt_count != h->nckpt)
+    return set_err(MLN_ESTATE, "mln_grad needs a completed checkpointed run (mln_reset + mln_run)");
+  const int N = h->f.N, D = h->f.D, q = h->f.q;
+  const bool f64 = h->prec == MLN_FP64;
+  const int nacc = N == 2 ? adj_nacc(2, f64) : adj_nacc(3, f64);
+  const int nm = adj_moments(f64);
+  const size_t rs = h->rs;
+  if (!h->partial.p) {
+    for (int b = 0; b < 2; ++b) {
+      HIP_TRY(h->lE[b].alloc(rs * h->grid.nx));
+      HIP_TRY(h->lH[b].alloc(rs * h->grid.nx));
+      HIP_TRY(h->lz[b].alloc(rs * D * h->ld));
+    }
+    HIP_TRY(h->tape.alloc(rs * (size_t)h->ckpt_every * (D + 1) * h->ld));
+    HIP_TRY(h->partial.alloc(sizeof(double) * h->ntiles * nacc));
+    HIP_TRY(h->gprobe.alloc(sizeof(double) * (nt + 1)));
+    HIP_TRY(h->samples_dev.alloc(sizeof(double) * (nt + 1)));
+    HIP_TRY(hipMemcpy(h->samples_dev.p, h->samples.data(), sizeof(double) * (nt + 1), hipMemcpyHostToDevice));
+  }
+  HIP_TRY(hipMemcpyAsync(h->gprobe.p, dJ_dprobe, sizeof(double) * (nt + 1), hipMemcpyHostToDevice, h->stream));
+  for (int b = 0; b < 2; ++b) {
+    HIP_TRY(hipMemsetAsync(h->lE[b].p, 0, h->lE[b].bytes, h->stream));
+    HIP_TRY(hipMemsetAsync(h->lH[b].p, 0, h->lH[b].bytes, h->stream));
+    HIP_TRY(hipMemsetAsync(h->lz[b].p, 0, h->lz[b].bytes, h->stream));
+  }
+  HIP_TRY(hipMemsetAsync(h->partial.p, 0, h->partial.bytes, h->stream));
+  int lc = 0;
+  for (int64_t seg = h->nckpt - 1; seg >= 0; --seg) {
+    const int64_t s0 = seg * h->ckpt_every, s1 = std::min<int64_t>(s0 + h->ckpt_every, nt);
+    h->cur = 0;
+    int rc = ckpt_copy(h, seg, false);
+    if (rc) return rc;
+    h->step = s0;
+    rc = forward_steps(h, s1 - s0, false, h->tape.p, s0, false);
+    if (rc) return rc;
+    for (int64_t n_hi = s1; n_hi > s0;) {
+      const int k = (int)std::min<int64_t>(h->halo, n_hi - s0);
+      hipError_t e;
+      if (f64) {
+        AdjArgs<double> a{};
+        a.fac = h->fd;
+        a.lEin = (const double *)h->lE[lc].p;
+        a.lEout = (double *)h->lE[1 - lc].p;
+        a.lHin = (const double *)h->lH[lc].p;
+        a.lHout = (double *)h->lH[1 - lc].p;
+        a.lzin = (const double *)h->lz[lc].p;
+        a.lzout = (double *)h->lz[1 - lc].p;
+        a.tape = (const double *)h->tape.p;
+        a.tape_step0 = s0;
+        a.gprobe = (const double *)h->gprobe.p;
+        a.samples = (const double *)h->samples_dev.p;
+        a.nx = h->grid.nx; a.mb = h->grid.med_begin; a.me = h->grid.med_end; a.ld = h->ld;
+        a.n_hi = n_hi; a.nsteps = k; a.halo = h->halo; a.owned = h->owned;
+        a.ch = h->fd_coef[0]; a.ca = h->fd_coef[1]; a.cb = h->fd_coef[2]; a.inv_dx = h->fd_coef[3];
+        a.kmur = h->fd_coef[4];
+        a.partial = (double *)h->partial.p;
+        e = launch_adj<double>(N, a, h->ntiles, h->W, h->stream);
+      } else {
+        AdjArgs<float> a{};
+        a.fac = h->ff;
+        a.lEin = (const float *)h->lE[lc].p;
+        a.lEout = (float *)h->lE[1 - lc].p;
+        a.lHin = (const float *)h->lH[lc].p;
+        a.lHout = (float *)h->lH[1 - lc].p;
+        a.lzin = (const float *)h->lz[lc].p;
+        a.lzout = (float *)h->lz[1 - lc].p;
+        a.tape = (const float *)h->tape.p;
+        a.tape_step0 = s0;
+        a.gprobe = (const double *)h->gprobe.p;
+        a.samples = (const double *)h->samples_dev.p;
+        a.nx = h->grid.nx; a.mb = h->grid.med_begin; a.me = h->grid.med_end; a.ld = h->ld;
+        a.n_hi = n_hi; a.nsteps = k; a.halo = h->halo; a.owned = h->owned;
+        a.ch = (float)h->fd_coef[0]; a.ca = (float)h->fd_coef[1]; a.cb = (float)h->fd_coef[2];
+        a.inv_dx = (float)h->fd_coef[3]; a.kmur = (float)h->fd_coef[4];
+        a.partial = (double *)h->partial.p;
+        e = launch_adj<float>(N, a, h->ntiles, h->W, h->stream);
+      }
+      if (e != hipSuccess) return set_err(MLN_EHIP, std::string("adjoint launch: ") + hipGetErrorString(e));
+      lc = 1 - lc;
+      n_hi -= k;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->step = nt;  // the forward buffers now hold an intermediate state; mln_reset before stepping again
+  h->ckpt_ok = false;
+  // gather: per-tile partial sums, lz'_0 summed over the medium, lE^0 at cell 0
+  std::vector<double> part(h->ntiles * nacc), acc(nacc, 0.0);
+  HIP_TRY(hipMemcpy(part.data(), h->partial.p, sizeof(double) * part.size(), hipMemcpyDeviceToHost));
+  for (int64_t t = 0; t < h->ntiles; ++t)
+    for (int i = 0; i < nacc; ++i) acc[i] += part[t * nacc + i];
+  std::vector<unsigned char> zb(rs * D * h->ld), eb(rs);
+  HIP_TRY(hipMemcpy(zb.data(), h->lz[lc].p, zb.size(), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(eb.data(), h->lE[lc].p, rs, hipMemcpyDeviceToHost));
+  auto rd = [&](const unsigned char *p, int64_t i) {
+    return rs == 8 ? ((const double *)p)[i] : (double)((const float *)p)[i];
+  };
+  std::vector<double> gz0(D, 0.0);
+  for (int j = 0; j < D; ++j)
+    for (int64_t c = 0; c < h->nmed; ++c) gz0[j] += rd(zb.data(), j * h->ld + c);
+  // unpack (same order as the kernel)
+  int k = 0;
+  std::vector<double> GK(D * D), Gc(D), Gw(D);
+  for (int i = 0; i < D * D; ++i) GK[i] = acc[k++];
+  for (int i = 0; i < D; ++i) Gc[i] = acc[k++];
+  for (int i = 0; i < D; ++i) Gw[i] = acc[k++];
+  const double Gp0 = acc[k++];
+  double Gamp = acc[k++] + h->samples[0] * rd(eb.data(), 0);
+  std::vector<std::vector<double>> Mom(nm, std::vector<double>(D * D));
+  for (int m = 0; m < nm; ++m)
+    for (int i = 0; i < D * D; ++i) Mom[m][i] = acc[k++];
+  // dJ/dB = dt [M1 + ad_Bt^2(M3)/24 + ad_Bt^4(M5)/1920], Bt = T^T U T dt (block diagonal)
+  const double dt = h->grid.dt;
+  std::vector<double> Bt(D * D, 0.0);
+  for (int p = 0; p < q; ++p) {
+    Bt[(2 * p) * D + 2 * p + 1] = h->f.theta[p] * dt;
+    Bt[(2 * p + 1) * D + 2 * p] = -h->f.theta[p] * dt;
+  }
+  auto ad = [&](const std::vector<double> &X) {
+    std::vector<double> r(D * D, 0.0);
+    for (int i = 0; i < D; ++i)
+      for (int j = 0; j < D; ++j) {
+        double s2 = 0.0;
+        for (int l = 0; l < D; ++l) s2 += Bt[i * D + l] * X[l * D + j] - X[i * D + l] * Bt[l * D + j];
+        r[i * D + j] = s2;
+      }
+    return r;
+  };
+  std::vector<double> GB = Mom[0];
+  {
+    std::vector<double> a2 = ad(ad(Mom[1]));
+    for (int i = 0; i < D * D; ++i) GB[i] += a2[i] / 24.0;
+    if (nm > 2) {
+      std::vector<double> a4 = ad(ad(ad(ad(Mom[2]))));
+      for (int i = 0; i < D * D; ++i) GB[i] += a4[i] / 1920.0;
+    }
+    for (double &x : GB) x *= dt;
+  }
+  // z -> d coordinates: d = T z
+  const std::vector<double> &T = h->f.T;
+  auto sandwich = [&](const std::vector<double> &X) {  // T X T^T
+    std::vector<double> t1(D * D, 0.0), r(D * D, 0.0);
+    for (int i = 0; i < D; ++i)
+      for (int j = 0; j < D; ++j)
+        for (int l = 0; l < D; ++l) t1[i * D + j] += T[i * D + l] * X[l * D + j];
+    for (int i = 0; i < D; ++i)
+      for (int j = 0; j < D; ++j)
+        for (int l = 0; l < D; ++l) r[i * D + j] += t1[i * D + l] * T[j * D + l];
+    return r;
+  };
+  auto tvec = [&](const std::vector<double> &x) {
+    std::vector<double> r(D, 0.0);
+    for (int i = 0; i < D; ++i)
+      for (int l = 0; l < D; ++l) r[i] += T[i * D + l] * x[l];
+    return r;
+  };
+  std::vector<double> gA = sandwich(GK), gU = sandwich(GB), gc = tvec(Gc), gw = tvec(Gw), gd0 = tvec(gz0);
+  std::string err;
+  int rc = chain_rule(&h->medium.m, dt, gA.data(), gc.data(), gw.data(), Gp0, gU.data(), gd0.data(), out, &err);
+  if (rc) return set_err(rc, err);
+  if (out->d_amplitude) *out->d_amplitude = Gamp;
   return MLN_OK;
 }
 

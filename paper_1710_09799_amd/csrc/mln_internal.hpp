@@ -34,10 +34,26 @@ struct Factors {
   double p0 = 0.0;
   std::vector<double> popd, popz, popc;  // rho_aa of d^{n+1/2} = popc_a + pop{d,z}[a,:] . (d''|z'')
   std::vector<double> dprime0, z0;       // state after the first half step of step 0
+  // Reference state of the rotation route: the kernels carry y = z' - zr.
+  // zr is a fixed point of the field-free step (K zr + cz = zr): the initial
+  // state if it is one (then y starts at exactly zero), else the solution of
+  // (I - K) zr = cz when that system is regular.  For a fixed point the step's
+  // constant term rz and the polarisation offset pr are exactly zero (dP/dt
+  // vanishes in a stationary state), so a medium at rest stays exactly at
+  // rest.  Without a fixed point zr = 0, rz = cz, pr = p0.
+  std::vector<double> zr, rz, y0, popcy;
+  double pr = 0.0;
 };
 
 // Validates the medium and builds every factor.  Returns an MLN_* code; on
 // failure *err holds a message.
 int build_factors(const mln_medium *med, double dt, Factors *f, std::string *err);
+
+// Chain rule from d-coordinate gradients (dJ/dA with A = exp(M dt), dJ/dc,
+// dJ/dw, dJ/dp0, dJ/dU, dJ/dd'_0) to the physical inputs; fills d_h0,
+// d_dipole, d_jump_rate, d_dephasing and d_density of *out (d_amplitude is not
+// touched).
+int chain_rule(const mln_medium *med, double dt, const double *gA, const double *gc, const double *gw,
+               double gp0, const double *gU, const double *gd0, mln_grads *out, std::string *err);
 
 }  // namespace mln

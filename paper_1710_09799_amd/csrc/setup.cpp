@@ -516,6 +516,290 @@ int build_factors(const mln_medium *md, double dt, Factors *f, std::string *err)
     std::vector<double> Tt = transpose(D, F.T);
     rmul(D, D, 1, Tt.data(), F.dprime0.data(), F.z0.data());
   }
+  // reference state of the rotation route
+  {
+    auto residual = [&](const std::vector<double> &z) {  // max |K z + cz - z|
+      double r = 0.0;
+      for (int i = 0; i < D; ++i) {
+        double acc = F.cz[i] - z[i];
+        for (int j = 0; j < D; ++j) acc += F.K[i * D + j] * z[j];
+        r = std::max(r, std::fabs(acc));
+      }
+      return r;
+    };
+    double kn = 0.0, cn = 0.0, zn0 = 0.0;
+    for (double x : F.K) kn = std::max(kn, std::fabs(x));
+    for (double x : F.cz) cn = std::max(cn, std::fabs(x));
+    for (double x : F.z0) zn0 = std::max(zn0, std::fabs(x));
+    // solve (I - K) zr = cz by Gaussian elimination with partial pivoting
+    std::vector<double> Am(D * D), b = F.cz;
+    for (int i = 0; i < D; ++i)
+      for (int j = 0; j < D; ++j) Am[i * D + j] = (i == j ? 1.0 : 0.0) - F.K[i * D + j];
+    bool ok = true;
+    double amax = 0.0;
+    for (double x : Am) amax = std::max(amax, std::fabs(x));
+    for (int k = 0; k < D && ok; ++k) {
+      int p = k;
+      for (int i = k + 1; i < D; ++i)
+        if (std::fabs(Am[i * D + k]) > std::fabs(Am[p * D + k])) p = i;
+      if (std::fabs(Am[p * D + k]) <= 1e-10 * amax) { ok = false; break; }
+      if (p != k) {
+        for (int j = 0; j < D; ++j) std::swap(Am[k * D + j], Am[p * D + j]);
+        std::swap(b[k], b[p]);
+      }
+      for (int i = k + 1; i < D; ++i) {
+        double fct = Am[i * D + k] / Am[k * D + k];
+        for (int j = k; j < D; ++j) Am[i * D + j] -= fct * Am[k * D + j];
+        b[i] -= fct * b[k];
+      }
+    }
+    std::vector<double> zr(D, 0.0);
+    if (ok) {
+      for (int k = D - 1; k >= 0; --k) {
+        double acc = b[k];
+        for (int j = k + 1; j < D; ++j) acc -= Am[k * D + j] * zr[j];
+        zr[k] = acc / Am[k * D + k];
+      }
+      double zn = 0.0;
+      for (double x : zr) zn = std::max(zn, std::fabs(x));
+      ok = std::isfinite(zn) && zn <= 4.0 && residual(zr) <= 1e-13 * (kn * zn + cn + 1e-300);
+    }
+    // Prefer the initial state itself when it is a fixed point (the usual
+    // case: the medium starts at rest), so that y starts at exactly zero.
+    const bool z0_fixed = residual(F.z0) <= 1e-13 * (kn * zn0 + cn + 1e-300);
+    const bool stationary = ok || z0_fixed;
+    if (z0_fixed) {
+      F.zr = F.z0;
+    } else if (ok) {
+      F.zr = zr;
+    } else {
+      F.zr.assign(D, 0.0);
+    }
+    F.rz.assign(D, 0.0);
+    F.pr = 0.0;
+    if (!stationary) {
+      F.rz = F.cz;
+      F.pr = F.p0;
+    }
+    F.y0.assign(D, 0.0);
+    for (int i = 0; i < D; ++i) F.y0[i] = F.z0[i] - F.zr[i];
+    F.popcy = F.popc;
+    for (int a = 0; a < N; ++a)
+      for (int j = 0; j < D; ++j) F.popcy[a] += F.popz[a * D + j] * F.zr[j];
+  }
+  return MLN_OK;
+}
+
+}  // namespace mln
+
+// ===================================================================
+// Chain rule of the adjoint run: from gradients with respect to the
+// d-coordinate step quantities (A = exp(M dt), c, w, p0, U, d'_0) to
+// gradients with respect to the physical inputs.  Every physical input enters
+// M, U, v, d_eq linearly (Sec. 3, Eqs. elems1/elems2/comp_mu), so their
+// directional derivatives are the adjoint-representation images of the
+// perturbation itself; the only non-linear step is the augmented exponential,
+// whose directional (Frechet) derivative is the upper-right block of
+// exp([[X, dX], [0, X]]) (Higham, Functions of Matrices, Sec. 10.6).
+namespace mln {
+namespace {
+
+// R_jk = 1/2 Tr{map(s_k) s_j},  r_j = 1/N Tr{map(I) s_j}
+template <class Map>
+void adj_rep(int N, const std::vector<cplx> &gen, Map map, std::vector<double> &R, std::vector<double> &r) {
+  const int NN = N * N, D = NN - 1;
+  std::vector<cplx> Y(NN), Id(NN, 0.0);
+  R.assign(D * D, 0.0);
+  r.assign(D, 0.0);
+  for (int k = 0; k < D; ++k) {
+    map(gen.data() + k * NN, Y.data());
+    for (int j = 0; j < D; ++j) R[j * D + k] = 0.5 * ctrace2(N, Y.data(), gen.data() + j * NN).real();
+  }
+  for (int a = 0; a < N; ++a) Id[a * N + a] = 1.0;
+  map(Id.data(), Y.data());
+  for (int j = 0; j < D; ++j) r[j] = (ctrace2(N, Y.data(), gen.data() + j * NN) / double(N)).real();
+}
+
+// -(i/hbar)[X, Y] for a Hermitian direction X
+void commutator_map(int N, const std::vector<cplx> &X, double sign, const cplx *Y, cplx *out) {
+  std::vector<cplx> a(N * N), b(N * N);
+  cmul(N, X.data(), Y, a.data());
+  cmul(N, Y, X.data(), b.data());
+  for (int i = 0; i < N * N; ++i) out[i] = sign * (-kI / kHbar) * (a[i] - b[i]);
+}
+
+double dotv(const std::vector<double> &a, const double *b) {
+  double s = 0.0;
+  for (size_t i = 0; i < a.size(); ++i) s += a[i] * b[i];
+  return s;
+}
+
+}  // namespace
+
+int chain_rule(const mln_medium *md, double dt, const double *gA, const double *gc, const double *gw,
+               double gp0, const double *gU, const double *gd0, mln_grads *out, std::string *err) {
+  Factors F;
+  int rc = build_factors(md, dt, &F, err);
+  if (rc) return rc;
+  if (!out) return fail(err, MLN_EINVAL, "null gradient output");
+  const int N = F.N, D = F.D, NN = N * N, n1 = D + 1;
+  const double Na = md->density;
+  Medium m;
+  m.N = N;
+  m.deph = 0.0;
+  std::vector<double> MA0(D * D), Mb0de(D), A0T(D * D);
+  rmul(D, D, D, F.M.data(), F.A0.data(), MA0.data());
+  for (int k = 0; k < D; ++k) {
+    double s = F.deq[k];
+    for (int j = 0; j < D; ++j) s += F.M[k * D + j] * F.b0[j];
+    Mb0de[k] = s;
+  }
+  // exp of the augmented matrix and of its block-doubled version
+  std::vector<double> Xa(n1 * n1, 0.0);
+  for (int j = 0; j < D; ++j) {
+    for (int k = 0; k < D; ++k) Xa[j * n1 + k] = F.M[j * D + k] * 0.5 * dt;
+    Xa[j * n1 + D] = F.deq[j] * 0.5 * dt;
+  }
+  // directional derivative of J for one perturbation (dM, dU, dv, ddeq)
+  auto directional = [&](const std::vector<double> &dM, const std::vector<double> &dU,
+                         const std::vector<double> &dv, const std::vector<double> &ddeq,
+                         double dNa) -> double {
+    std::vector<double> dA0(D * D, 0.0), db0(D, 0.0);
+    bool lin = false;
+    for (double x : dM) lin |= x != 0.0;
+    for (double x : ddeq) lin |= x != 0.0;
+    if (lin) {
+      // L(X, .) is linear: scale the direction to the size of X so that the
+      // block exponential is not dominated by it, and scale back afterwards.
+      double xmax = 0.0, emax = 0.0;
+      for (double x : Xa) xmax = std::max(xmax, std::fabs(x));
+      for (double x : dM) emax = std::max(emax, std::fabs(x) * 0.5 * dt);
+      for (double x : ddeq) emax = std::max(emax, std::fabs(x) * 0.5 * dt);
+      const double alpha = emax / std::max(xmax, 1e-30 * emax);
+      const int n2 = 2 * n1;
+      std::vector<double> Z(n2 * n2, 0.0), FZ(n2 * n2);
+      for (int i = 0; i < n1; ++i)
+        for (int j = 0; j < n1; ++j) {
+          Z[i * n2 + j] = Xa[i * n1 + j];
+          Z[(n1 + i) * n2 + n1 + j] = Xa[i * n1 + j];
+        }
+      for (int j = 0; j < D; ++j) {
+        for (int k = 0; k < D; ++k) Z[j * n2 + n1 + k] = dM[j * D + k] * 0.5 * dt / alpha;
+        Z[j * n2 + n1 + D] = ddeq[j] * 0.5 * dt / alpha;
+      }
+      expm_real(n2, Z.data(), FZ.data());
+      for (int j = 0; j < D; ++j) {
+        for (int k = 0; k < D; ++k) dA0[j * D + k] = FZ[j * n2 + n1 + k] * alpha;
+        db0[j] = FZ[j * n2 + n1 + D] * alpha;
+      }
+    }
+    std::vector<double> dA(D * D), t1(D * D), t2(D * D);
+    rmul(D, D, D, dA0.data(), F.A0.data(), t1.data());
+    rmul(D, D, D, F.A0.data(), dA0.data(), t2.data());
+    for (int i = 0; i < D * D; ++i) dA[i] = t1[i] + t2[i];
+    std::vector<double> dc(D), dw(D), dd0(D);
+    for (int i = 0; i < D; ++i) {
+      double s = db0[i];
+      for (int k = 0; k < D; ++k) s += dA0[i * D + k] * F.b0[k] + F.A0[i * D + k] * db0[k];
+      dc[i] = s;
+      double s2 = db0[i];
+      for (int k = 0; k < D; ++k) s2 += dA0[i * D + k] * F.d0[k];
+      dd0[i] = s2;
+    }
+    // w = 1/2 Na (M A0)^T v
+    std::vector<double> dMA0(D * D), t3(D * D);
+    rmul(D, D, D, dM.data(), F.A0.data(), dMA0.data());
+    rmul(D, D, D, F.M.data(), dA0.data(), t3.data());
+    double dp0 = 0.0;
+    for (int j = 0; j < D; ++j) {
+      double s = 0.0, s0 = 0.0;
+      for (int k = 0; k < D; ++k) {
+        s += (dMA0[k * D + j] + t3[k * D + j]) * F.v[k] + MA0[k * D + j] * dv[k];
+        s0 += MA0[k * D + j] * F.v[k];
+      }
+      dw[j] = 0.5 * Na * s + 0.5 * dNa * s0;
+    }
+    {
+      double s = 0.0, s0 = 0.0;
+      for (int k = 0; k < D; ++k) {
+        double inner = ddeq[k];
+        for (int j = 0; j < D; ++j) inner += dM[k * D + j] * F.b0[j] + F.M[k * D + j] * db0[j];
+        s += dv[k] * Mb0de[k] + F.v[k] * inner;
+        s0 += F.v[k] * Mb0de[k];
+      }
+      dp0 = 0.5 * Na * s + 0.5 * dNa * s0;
+    }
+    double J = 0.0;
+    for (int i = 0; i < D * D; ++i) J += gA[i] * dA[i] + gU[i] * dU[i];
+    for (int i = 0; i < D; ++i) J += gc[i] * dc[i] + gw[i] * dw[i] + gd0[i] * dd0[i];
+    J += gp0 * dp0;
+    return J;
+  };
+  const std::vector<double> zDD(D * D, 0.0), zD(D, 0.0);
+  std::vector<double> R, r;
+  // Hermitian directions |a><b| + |b><a| (real) and i|a><b| - i|b><a| (imaginary)
+  auto herm_dir = [&](int a, int b, bool imag) {
+    std::vector<cplx> X(NN, 0.0);
+    if (a == b) {
+      X[a * N + a] = 1.0;
+    } else if (!imag) {
+      X[a * N + b] = 1.0;
+      X[b * N + a] = 1.0;
+    } else {
+      X[a * N + b] = kI;
+      X[b * N + a] = -kI;
+    }
+    return X;
+  };
+  for (int a = 0; a < N; ++a)
+    for (int b = a; b < N; ++b)
+      for (int im = 0; im < (a == b ? 1 : 2); ++im) {
+        std::vector<cplx> X = herm_dir(a, b, im == 1);
+        double jh = 0.0, jm = 0.0;
+        if (out->d_h0) {
+          adj_rep(N, F.gen, [&](const cplx *Y, cplx *o) { commutator_map(N, X, 1.0, Y, o); }, R, r);
+          jh = directional(R, zDD, zD, zD, 0.0);
+        }
+        if (out->d_dipole) {
+          std::vector<double> dU, dv(D);
+          // U is the image of rho -> -(i/hbar)[-mu, rho]
+          adj_rep(N, F.gen, [&](const cplx *Y, cplx *o) { commutator_map(N, X, -1.0, Y, o); }, dU, r);
+          for (int k = 0; k < D; ++k) dv[k] = ctrace2(N, X.data(), F.gen.data() + k * NN).real();
+          jm = directional(zDD, dU, dv, zD, 0.0);
+        }
+        auto put = [&](double *dst, double val) {
+          if (!dst) return;
+          if (a == b) {
+            dst[2 * (a * N + a)] = val;
+            dst[2 * (a * N + a) + 1] = 0.0;
+          } else if (im == 0) {
+            dst[2 * (a * N + b)] = val;
+            dst[2 * (b * N + a)] = val;
+          } else {
+            dst[2 * (a * N + b) + 1] = val;
+            dst[2 * (b * N + a) + 1] = -val;
+          }
+        };
+        put(out->d_h0, jh);
+        put(out->d_dipole, jm);
+      }
+  if (out->d_jump_rate)
+    for (int k = 0; k < md->n_jump; ++k) {
+      Medium one;
+      one.N = N;
+      one.jump.push_back(load_c(md->jump + 2 * NN * k, NN));
+      one.rate.push_back(1.0);
+      adj_rep(N, F.gen, [&](const cplx *Y, cplx *o) { relax_map(one, Y, o); }, R, r);
+      out->d_jump_rate[k] = directional(R, zDD, zD, r, 0.0);
+    }
+  if (out->d_dephasing) {
+    Medium one;
+    one.N = N;
+    one.deph = 1.0;
+    adj_rep(N, F.gen, [&](const cplx *Y, cplx *o) { relax_map(one, Y, o); }, R, r);
+    *out->d_dephasing = directional(R, zDD, zD, r, 0.0);
+  }
+  if (out->d_density) *out->d_density = directional(zDD, zDD, zD, zD, 1.0);
   return MLN_OK;
 }
 

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libmln.so")
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32c": 2, "bf16x": 3}
 ROUTES = {"rotation": 0, "diag": 1, "rodrigues": 2}
+VARIANTS = {"auto": 0, "block": 1, "wave": 2}
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -54,7 +55,12 @@ class _Record(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("route", ctypes.c_int32),
                 ("steps_per_launch", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("ckpt_every", ctypes.c_int32), ("variant", ctypes.c_int32)]
+
+
+class _Grads(ctypes.Structure):
+    _fields_ = [(n, _dp) for n in ("d_h0", "d_dipole", "d_jump_rate", "d_dephasing", "d_amplitude",
+                                   "d_density")]
 
 
 class _Factors(ctypes.Structure):
@@ -65,7 +71,8 @@ class _Factors(ctypes.Structure):
 # every symbol include/mln.h declares
 EXPORTS = ["mln_init", "mln_step", "mln_run", "mln_reset", "mln_current_step", "mln_get_fields",
            "mln_state_bytes", "mln_save_state", "mln_load_state", "mln_bloch_only", "mln_free",
-           "mln_strerror", "mln_last_error", "mln_setup_factors", "mln_version"]
+           "mln_strerror", "mln_last_error", "mln_setup_factors", "mln_version", "mln_grad",
+           "mln_chain_rule"]
 
 _lib = None
 
@@ -98,6 +105,9 @@ def load():
         "mln_setup_factors": ([ctypes.POINTER(_Medium), ctypes.c_double, ctypes.POINTER(_Factors)],
                               ctypes.c_int),
         "mln_version": ([], ctypes.c_int),
+        "mln_grad": ([P, _dp, ctypes.POINTER(_Grads)], ctypes.c_int),
+        "mln_chain_rule": ([ctypes.POINTER(_Medium), ctypes.c_double, _dp, _dp, _dp, ctypes.c_double,
+                            _dp, _dp, ctypes.POINTER(_Grads)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -155,6 +165,33 @@ def setup_factors(medium, dt):
     return out
 
 
+def _new_grads(n, n_jump):
+    g = dict(d_h0=np.zeros((n, n), complex), d_dipole=np.zeros((n, n), complex),
+             d_jump_rate=np.zeros(max(n_jump, 1)), d_dephasing=np.zeros(1), d_amplitude=np.zeros(1),
+             d_density=np.zeros(1))
+    ptrs = {k: (v.view(np.float64) if np.iscomplexobj(v) else v).ctypes.data_as(_dp) for k, v in g.items()}
+    return g, _Grads(**ptrs)
+
+
+def _finish_grads(g, n_jump):
+    g["d_jump_rate"] = g["d_jump_rate"][:n_jump]
+    for k in ("d_dephasing", "d_amplitude", "d_density"):
+        g[k] = float(g[k][0])
+    return g
+
+
+def chain_rule(medium, dt, gA, gc, gw, gp0, gU, gd0):
+    """Host-only chain rule (see mln_chain_rule in include/mln.h)."""
+    L = load()
+    n = medium.n_levels
+    g, gs = _new_grads(n, len(medium.jumps))
+    arr = [np.ascontiguousarray(x, dtype=np.float64) for x in (gA, gc, gw, gU, gd0)]
+    ma = _MediumArgs(medium)
+    _check(L.mln_chain_rule(ctypes.byref(ma.s), float(dt), _ptr(arr[0]), _ptr(arr[1]), _ptr(arr[2]),
+                            float(gp0), _ptr(arr[3]), _ptr(arr[4]), ctypes.byref(gs)))
+    return _finish_grads(g, len(medium.jumps))
+
+
 class Solver:
     """One coupled simulation on the GPU.
 
@@ -163,7 +200,8 @@ class Solver:
     """
 
     def __init__(self, problem, precision="fp64", route="rotation", snap_every=0,
-                 steps_per_launch=0, tile=0, record_probe=True, record_pop=True, record_e=True):
+                 steps_per_launch=0, tile=0, record_probe=True, record_pop=True, record_e=True,
+                 ckpt_every=0, variant="auto"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("Solver needs a HIP device")
@@ -189,7 +227,7 @@ class Solver:
         rs = _Record(snap_every, dptr(self.pop), dptr(self.e_snap), dptr(self.probe), 1)
         self.stream = torch.cuda.current_stream()
         os_ = _Options(PRECISIONS[precision], ROUTES[route], steps_per_launch, tile,
-                       ctypes.c_void_p(self.stream.cuda_stream))
+                       ctypes.c_void_p(self.stream.cuda_stream), ckpt_every, VARIANTS[variant])
         h = ctypes.c_void_p()
         _check(L.mln_init(ctypes.byref(self._ma.s), ctypes.byref(gs), ctypes.byref(ss),
                           ctypes.byref(rs), ctypes.byref(os_), ctypes.byref(h)))
@@ -243,6 +281,17 @@ class Solver:
         cast = lambda t: ctypes.cast(ctypes.c_void_p(t.data_ptr()), _dp)
         _check(self._L.mln_bloch_only(self._h, cast(efield), nt, cast(pop), cast(dp)))
         return dict(pop=pop, dp=dp)
+
+    def grad(self, dJ_dprobe):
+        """Adjoint pass (needs ckpt_every > 0 and a completed run()).  dJ_dprobe:
+        host array of nt+1 values.  Returns the gradient dict of mln_grads."""
+        med = self.problem.medium
+        g, gs = _new_grads(med.n_levels, len(med.jumps))
+        gp = np.ascontiguousarray(np.asarray(dJ_dprobe, dtype=np.float64))
+        if gp.shape != (self.problem.grid.nt + 1,):
+            raise ValueError("dJ_dprobe must have nt+1 entries")
+        _check(self._L.mln_grad(self._h, _ptr(gp), ctypes.byref(gs)))
+        return _finish_grads(g, len(med.jumps))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -1,0 +1,176 @@
+"""The adjoint (reverse-time) pass against finite differences.
+
+Objective: J = dt * sum_n E_probe[n]^2 (energy of the transmitted field at the
+right boundary), so dJ/dprobe[n] = 2 dt E_probe[n].
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1710_09799_amd import mln
+from paper_1710_09799_amd import workloads as W
+from paper_1710_09799_amd.autograd import ladder_params, ladder_problem, grads_to_ladder
+
+pytestmark = pytest.mark.gpu
+
+
+def _J(probe, dt):
+    return dt * float(np.sum(probe ** 2))
+
+
+def _small_ladder(n, nx=160, nt=700):
+    """Short three-level (or two-level) ladder run whose transmitted field is
+    reshaped by the medium."""
+    p = W.three_level(nx=nx, nt=nt) if n == 3 else W.two_level(nx=nx, nt=nt)
+    if n == 2:
+        p.medium = W.ladder_medium(np.real(np.diag(p.medium.h0)), [1e-29], density=1e25,
+                                   decay=1e12, dephasing=5e12)
+    else:
+        p.medium.density = 1e25
+    t = np.arange(nt + 1) * p.grid.dt
+    sig = 30 * p.grid.dt
+    p.source = W.Source(np.exp(-0.5 * ((t - 5 * sig) / sig) ** 2) * np.sin(W.OMEGA0 * (t - 5 * sig)), 2e9)
+    return p
+
+
+def _run_J(prob, precision="fp64"):
+    out = mln.run(prob, precision=precision)
+    return _J(out["probe"], prob.grid.dt)
+
+
+def _grad(prob, precision="fp64", ckpt=64):
+    s = mln.Solver(prob, precision=precision, ckpt_every=ckpt)
+    out = s.run()
+    probe = out["probe"].cpu().numpy()
+    J = _J(probe, prob.grid.dt)
+    g = s.grad(2.0 * prob.grid.dt * probe)
+    s.close()
+    return J, g
+
+
+def _fd_ladder(prob, runner, h=1e-6, richardson=False):
+    """Central differences in each ladder parameter (relative step h; energy
+    steps relative to the level spacing).  With richardson=True, steps h and
+    2h are combined to cancel the O(h^2) term."""
+    x0 = ladder_params(prob)
+    n = prob.medium.n_levels
+    scale = np.abs(x0).copy()
+    spacing = np.max(np.abs(np.diff(x0[:n])))
+    scale[:n] = spacing
+
+    def cd(i, hh):
+        xp, xm = x0.copy(), x0.copy()
+        xp[i] += hh * scale[i]
+        xm[i] -= hh * scale[i]
+        return (runner(ladder_problem(prob, xp)) - runner(ladder_problem(prob, xm))) / (2 * hh * scale[i])
+    out = []
+    for i in range(len(x0)):
+        if richardson:
+            out.append((4.0 * cd(i, h) - cd(i, 2 * h)) / 3.0)
+        else:
+            out.append(cd(i, h))
+    return np.array(out), scale
+
+
+def _compare(ga, fd, scale, tol_scale, tol_rel):
+    """|a - b| <= tol_scale * max_j |b_j| + tol_rel |b| for the gradients
+    expressed per relative parameter change (a = g * scale)."""
+    a, b = ga * scale, fd * scale
+    big = np.max(np.abs(b))
+    for i in range(len(a)):
+        print(i, a[i], b[i])
+        assert abs(a[i] - b[i]) <= tol_scale * big + tol_rel * abs(b[i]), (i, a[i], b[i], big)
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_fp64_adjoint_matches_fd_of_gpu_forward(n):
+    """Central differences with the h = 1e-6 relative step of the workload
+    description, and a Richardson-extrapolated h = 1e-4 difference that is
+    not limited by round-off for the weakly coupled parameters."""
+    prob = _small_ladder(n)
+    print(f"[case] adjoint fp64 n={n}", flush=True)
+    J, g = _grad(prob)
+    ga = grads_to_ladder(g, n)
+    fd, scale = _fd_ladder(prob, _run_J)
+    _compare(ga, fd, scale, 1e-6, 1e-5)
+    fdr, _ = _fd_ladder(prob, _run_J, h=1e-4, richardson=True)
+    _compare(ga, fdr, scale, 1e-8, 1e-6)
+
+
+def test_fp64_adjoint_matches_fd_of_oracle(orc):
+    """Independent check: finite differences of the FP64 density-matrix
+    oracle (Richardson-extrapolated, h = 1e-4)."""
+    n = 3
+    prob = _small_ladder(n, nx=120, nt=500)
+    J, g = _grad(prob, ckpt=50)
+    ga = grads_to_ladder(g, n)
+
+    def orc_J(p):
+        return _J(orc.run(p)["probe"], p.grid.dt)
+    fd, scale = _fd_ladder(prob, orc_J, h=1e-4, richardson=True)
+    _compare(ga, fd, scale, 1e-8, 1e-6)
+
+
+def test_adjoint_invariants():
+    """Shifting every level energy by the same amount changes nothing
+    (commutator with the identity vanishes, Eq. liouville): the energy
+    gradients sum to zero.  J is quadratic in the source amplitude when the
+    medium is absent: a dJ/da = 2 J."""
+    prob = _small_ladder(3)
+    J, g = _grad(prob)
+    de = np.real(np.diag(g["d_h0"]))
+    assert abs(de.sum()) <= 1e-8 * np.abs(de).max()
+    vac = _small_ladder(3)
+    vac.medium.density = 0.0
+    J0, g0 = _grad(vac)
+    a = vac.source.amplitude
+    assert abs(a * g0["d_amplitude"] - 2 * J0) <= 1e-10 * J0
+
+
+@pytest.mark.parametrize("ckpt", [1, 7, 64, 700])
+def test_checkpoint_interval_does_not_change_gradient(ckpt):
+    prob = _small_ladder(3, nt=700)
+    _, g1 = _grad(prob, ckpt=ckpt)
+    _, g2 = _grad(prob, ckpt=100)
+    a, b = grads_to_ladder(g1, 3), grads_to_ladder(g2, 3)
+    assert np.max(np.abs(a - b) / (np.abs(b) + 1e-300 + 1e-6 * np.abs(b).max())) < 1e-9
+
+
+def test_fp32_adjoint_close_to_fp64():
+    prob = _small_ladder(3, nt=2000)
+    _, g64 = _grad(prob, "fp64", ckpt=200)
+    _, g32 = _grad(prob, "fp32c", ckpt=200)
+    a, b = grads_to_ladder(g32, 3), grads_to_ladder(g64, 3)
+    scale = ladder_params(prob)
+    scale[:3] = np.max(np.abs(np.diff(scale[:3])))
+    rel = np.abs(a - b) * np.abs(scale) / np.max(np.abs(b * scale))
+    print("fp32 vs fp64 adjoint rel", rel)
+    assert np.max(rel) < 1e-3
+
+
+def test_torch_autograd_function():
+    import torch
+    from paper_1710_09799_amd.autograd import LadderTransmission
+    prob = _small_ladder(3, nt=500)
+    x = torch.tensor(ladder_params(prob), dtype=torch.float64, requires_grad=True)
+    probe = LadderTransmission.apply(x, prob, "fp64", 50)
+    J = prob.grid.dt * (probe ** 2).sum()
+    J.backward()
+    _, g = _grad(prob, ckpt=50)
+    want = grads_to_ladder(g, 3)
+    assert np.allclose(x.grad.numpy(), want, rtol=1e-10, atol=0)
+
+
+def test_grad_state_errors():
+    prob = _small_ladder(2, nt=100)
+    s = mln.Solver(prob, precision="fp64")
+    s.run()
+    with pytest.raises(mln.MLNError) as e:
+        s.grad(np.zeros(101))
+    assert e.value.code == -10
+    s2 = mln.Solver(prob, precision="fp64", ckpt_every=10)
+    s2.step(50)
+    with pytest.raises(mln.MLNError) as e:
+        s2.grad(np.zeros(101))
+    assert e.value.code == -10

@@ -59,6 +59,23 @@ def test_coupled_fp64_small(ref_cache, n, seed, route, tile, k):
     assert ee < TOL64 and ep < TOL64, (ee, ep)
 
 
+@pytest.mark.parametrize("n,seed", SMALL)
+@pytest.mark.parametrize("variant,tile,k", [("block", 256, 32), ("wave", 64, 8), ("wave", 128, 24),
+                                            ("wave", 256, 50), ("wave", 256, 127)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32c", 1e-5)])
+def test_coupled_rotation_variants(ref_cache, n, seed, variant, tile, k, precision, tol):
+    """Rotation route: workgroup-tile and wavefront-tile kernels with every
+    cells-per-lane count, against the oracle."""
+    if n == 6 and variant == "wave" and tile != 64:
+        pytest.skip("wavefront tiles for N = 6 hold one cell per lane")
+    p = W.random_problem(n, seed, nx=203, nt=360)
+    _print_case("variants", n=n, variant=variant, tile=tile, k=k, precision=precision)
+    ref = ref_cache((n, seed), p, 40)
+    got = mln.run(p, precision=precision, snap_every=40, tile=tile, steps_per_launch=k, variant=variant)
+    ee, ep = _errs(got, ref)
+    assert ee < tol and ep < tol, (ee, ep)
+
+
 def test_two_level_full_fp64(orc):
     """Two-level self-induced transparency set-up at full size: 2000 cells,
     10000 steps, 2 pi sech pulse through a medium filling the central half."""
@@ -86,16 +103,21 @@ def test_three_level_reduced_fp64(orc):
     assert np.max(ref["pop"][:, 1]) > 1e-2  # the pulse moved population
 
 
-def test_three_level_full_grid_first_steps(orc):
-    """Full 20000-cell grid in the benchmark's launch configuration; the
-    oracle follows the first 1000 steps, compared element by element."""
+@pytest.mark.slow
+def test_three_level_full_grid_through_pulse(orc):
+    """Full 20000-cell grid in the benchmark's launch configuration, followed
+    by the oracle for 12000 steps: the pi pulse (peak at step 9600) has
+    entered the medium, so the comparison is not dominated by the ~1e-9 V/m
+    fields ahead of it, where both solvers sit at their round-off floor."""
     p = W.three_level()
-    p.grid.nt = 1000
+    p.grid.nt = 12000
     _print_case("three_level_full_grid")
-    ref = orc.run(p, snap_every=250)
-    got = mln.run(p, precision="fp64", snap_every=250)
+    ref = orc.run(p, snap_every=3000)
+    got = mln.run(p, precision="fp64", snap_every=3000)
     ee, ep = _errs(got, ref)
+    print("three_level_full_grid err_E", ee, "err_pop", ep)
     assert ee < TOL64 and ep < TOL64
+    assert np.max(np.abs(ref["e_snap"])) > 1e-2 * p.source.amplitude
 
 
 @pytest.mark.parametrize("n,seed", SMALL)
@@ -217,7 +239,10 @@ def test_three_level_full_run_invariants():
     got = mln.run(p, precision="fp64", snap_every=10000)
     pop = got["pop"]
     assert np.all(np.isfinite(pop)) and np.all(np.isfinite(got["e_snap"]))
-    assert pop.min() > -1e-12 and pop.max() < 1 + 1e-12
+    # round-off floor after 1e5 FP64 steps is ~1e-12
+    assert pop.min() > -1e-10 and pop.max() < 1 + 1e-10
     assert np.max(np.abs(pop.sum(axis=1) - 1.0)) < 1e-12
-    # at step 10000 light has moved 5000 cells (Courant 0.5)
-    assert np.all(got["e_snap"][0, 5002:] == 0.0)
+    # the Yee stencil's dependency cone grows one cell per step, so at step
+    # 10000 every cell beyond 10001 is still exactly zero
+    assert np.all(got["e_snap"][0, 10002:] == 0.0)
+    assert np.max(np.abs(got["e_snap"][0, :5000])) > 1e-3 * p.source.amplitude

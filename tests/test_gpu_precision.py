@@ -1,0 +1,84 @@
+"""Reduced-precision paths against the FP64 oracle.
+
+Tolerances: compensated single precision ("fp32c") must meet 1e-5 on err_E
+and err_pop (the FP32 target); plain single precision ("fp32") is reported
+and held to a looser bound that documents its known drift (factor rounding
+accumulates linearly over the near-identity steps).
+"""
+import numpy as np
+import pytest
+
+from paper_1710_09799_amd import mln
+from paper_1710_09799_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _errs(got, ref):
+    e = np.concatenate([got["e_snap"].ravel(), got["probe"].ravel()])
+    er = np.concatenate([ref["e_snap"].ravel(), ref["probe"].ravel()])
+    return (np.max(np.abs(e - er)) / np.max(np.abs(er)),
+            np.max(np.abs(got["pop"] - ref["pop"])) if ref["pop"].size else 0.0)
+
+
+@pytest.fixture(scope="module")
+def three_level_ref(orc):
+    p = W.three_level(nx=2000, nt=10000)
+    return p, orc.run(p, snap_every=500)
+
+
+@pytest.fixture(scope="module")
+def two_level_ref(orc):
+    p = W.two_level()
+    return p, orc.run(p, snap_every=1000)
+
+
+def test_fp32c_three_level(three_level_ref):
+    p, ref = three_level_ref
+    got = mln.run(p, precision="fp32c", snap_every=500)
+    ee, ep = _errs(got, ref)
+    print(f"fp32c three_level err_E={ee:.3e} err_pop={ep:.3e}")
+    assert ee < 1e-5 and ep < 1e-5
+
+
+def test_fp32c_two_level(two_level_ref):
+    p, ref = two_level_ref
+    got = mln.run(p, precision="fp32c", snap_every=1000)
+    ee, ep = _errs(got, ref)
+    print(f"fp32c two_level err_E={ee:.3e} err_pop={ep:.3e}")
+    assert ee < 1e-5 and ep < 1e-5
+
+
+@pytest.mark.parametrize("route", ["rotation", "diag", "rodrigues"])
+def test_fp32_plain_three_level(three_level_ref, route):
+    p, ref = three_level_ref
+    got = mln.run(p, precision="fp32", route=route, snap_every=500)
+    ee, ep = _errs(got, ref)
+    print(f"fp32 {route} three_level err_E={ee:.3e} err_pop={ep:.3e}")
+    assert ee < 1e-3 and ep < 1e-3
+
+
+def test_fp32c_small_random(orc):
+    for n, seed in ((2, 1), (3, 2), (4, 3), (6, 4)):
+        p = W.random_problem(n, seed, nx=203, nt=360)
+        ref = orc.run(p, snap_every=40)
+        got = mln.run(p, precision="fp32c", snap_every=40, tile=64, steps_per_launch=8)
+        ee, ep = _errs(got, ref)
+        print(f"fp32c random n={n} err_E={ee:.3e} err_pop={ep:.3e}")
+        assert ee < 1e-5 and ep < 1e-5
+
+
+def test_fp32c_bloch_only(orc):
+    import torch
+    med = W.random_medium(3, 60)
+    rng = np.random.default_rng(1)
+    nt, nc = 4000, 16
+    f = rng.uniform(-3e9, 3e9, size=(nt, nc))
+    grid = W.Grid(nx=nc + 2, nt=1, dx=W.DX0, dt=W.DT0, med_begin=1, med_end=nc + 1)
+    prob = W.Problem("b", med, grid, W.Source(np.zeros(2), 0.0))
+    ref = orc.bloch(med, f, W.DT0)
+    s = mln.Solver(prob, precision="fp32c")
+    out = s.bloch_only(torch.tensor(f, device="cuda"))
+    err = np.max(np.abs(out["pop"].cpu().numpy() - ref["pop"]))
+    print(f"fp32c bloch err_pop={err:.3e}")
+    assert err < 1e-5
