@@ -57,8 +57,11 @@ typedef enum {
   MLN_FP32 = 1,           /* plain single precision (fast, loses ~1e-4 over 1e4 steps)  */
   MLN_FP32_COMP = 2,      /* single precision with a compensated (two-float) state and
                              two-float factors                                          */
-  MLN_FP32_BF16SPLIT = 3  /* compensated FP32 state; the shared-factor transform runs on
-                             MFMA as three-way BF16-split products, FP32 accumulation   */
+  MLN_FP32_BF16SPLIT = 3, /* compensated FP32 state; the shared-factor transform runs on
+                             MFMA with three-part BF16 splits of both operands and six
+                             products (~2^-24 relative), FP32 accumulation; N = 4, 6   */
+  MLN_FP32_BF16X3 = 4     /* as MLN_FP32_BF16SPLIT with two-part splits and three
+                             products (~2^-16 relative)                                */
 } mln_precision;
 
 typedef enum {
@@ -133,7 +136,9 @@ typedef struct {
                                   ckpt_every steps so that mln_grad can run; 0: off */
   int32_t variant;             /* forward kernel: 0 automatic, 1 workgroup tile
                                   (one cell per thread, LDS exchange), 2 wavefront
-                                  tile (rotation route; tile/64 cells per lane)       */
+                                  tile (rotation route; tile/64 cells per lane),
+                                  3 quad tile (rotation route, N <= 3; four lanes
+                                  per cell, tile = cells per workgroup)             */
 } mln_options;
 
 /* Gradients of a scalar objective J with respect to the physical inputs (any

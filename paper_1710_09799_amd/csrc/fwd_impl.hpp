@@ -132,19 +132,48 @@ struct RotLds {
   }
 };
 
+// Factor access of the rotation route: from LDS (small D, where the
+// compiler keeps them in registers) or through scalar loads (large D, where a
+// per-FMA LDS read would make the step LDS-bound).
+template <int N, typename Real, bool COMP>
+struct LdsAcc {
+  using L = RotLds<N, Real, COMP>;
+  const Real *sF;
+  __device__ Real K(int i) const { return sF[L::oK + i]; }
+  __device__ Real Kl(int i) const { return sF[L::oKl + i]; }
+  __device__ Real c(int i) const { return sF[L::oc + i]; }
+  __device__ Real cl(int i) const { return sF[L::ocl + i]; }
+  __device__ Real w(int i) const { return sF[L::ow + i]; }
+  __device__ Real th(int i) const { return sF[L::oth + i]; }
+  __device__ Real thl(int i) const { return sF[L::otl + i]; }
+  __device__ Real zr(int i) const { return sF[L::ozr + i]; }
+};
+template <typename Real>
+struct SmemAcc {
+  const FacDev<Real> *f;
+  int64_t o;  // loop-variant zero offset
+  __device__ Real K(int i) const { return cld(f->Km + o, i); }
+  __device__ Real Kl(int i) const { return cld(f->Km_lo + o, i); }
+  __device__ Real c(int i) const { return cld(f->cz + o, i); }
+  __device__ Real cl(int i) const { return cld(f->cz_lo + o, i); }
+  __device__ Real w(int i) const { return cld(f->wz + o, i); }
+  __device__ Real th(int i) const { return cld(f->thdt + o, i); }
+  __device__ Real thl(int i) const { return cld(f->th_lo + o, i); }
+  __device__ Real zr(int i) const { return cld(f->zr + o, i); }
+};
+
 // Rotation route, one cell: y'' = Rot(y) + (Rot - I) zr (the state is
 // y = z' - zr), dP/dt = w.y'' + p, y_next = y'' + (K - I) y'' + r.
-template <int N, typename Real>
-__device__ __forceinline__ Real rot_cell(const Real *sF, Real p0, Real E, Real (&z)[N * N - 1],
+template <int N, typename Real, class Acc>
+__device__ __forceinline__ Real rot_cell(const Acc &F, Real p0, Real E, Real (&z)[N * N - 1],
                                          const double *sP, double *pout, int64_t stride) {
-  using L = RotLds<N, Real, false>;
-  constexpr int D = L::D, Q = L::Q;
+  constexpr int D = N * N - 1, Q = N * (N - 1) / 2;
 #pragma unroll
   for (int p = 0; p < Q; ++p) {
     Real s, cm1;
-    sincm1(sF[L::oth + p] * E, s, cm1);
+    sincm1(F.th(p) * E, s, cm1);
     const Real a = z[2 * p], b = z[2 * p + 1];
-    const Real ar = sF[L::ozr + 2 * p], br = sF[L::ozr + 2 * p + 1];
+    const Real ar = F.zr(2 * p), br = F.zr(2 * p + 1);
     z[2 * p] = a + ((cm1 * a + s * b) + (cm1 * ar + s * br));
     z[2 * p + 1] = b + ((cm1 * b - s * a) + (cm1 * br - s * ar));
   }
@@ -159,13 +188,13 @@ __device__ __forceinline__ Real rot_cell(const Real *sF, Real p0, Real E, Real (
   }
   Real P = p0;
 #pragma unroll
-  for (int j = 0; j < D; ++j) P += sF[L::ow + j] * z[j];
+  for (int j = 0; j < D; ++j) P += F.w(j) * z[j];
   Real nz[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) {
-    Real acc = sF[L::oc + i];
+    Real acc = F.c(i);
 #pragma unroll
-    for (int j = 0; j < D; ++j) acc += sF[L::oK + i * D + j] * z[j];
+    for (int j = 0; j < D; ++j) acc += F.K(i * D + j) * z[j];
     nz[i] = z[i] + acc;
   }
 #pragma unroll
@@ -179,18 +208,17 @@ __device__ __forceinline__ Real rot_cell(const Real *sF, Real p0, Real E, Real (
 // added to hi + lo exactly; K - I, the constant term and theta*dt are float
 // pairs, and two accumulators keep the low-part products from being absorbed
 // by the high-part sum.
-template <int N>
-__device__ __forceinline__ float rot_cell_comp(const float *sF, float p0, float E, float (&z)[N * N - 1],
+template <int N, class Acc>
+__device__ __forceinline__ float rot_cell_comp(const Acc &F, float p0, float E, float (&z)[N * N - 1],
                                                float (&zl)[N * N - 1], const double *sP, double *pout,
                                                int64_t stride) {
-  using L = RotLds<N, float, true>;
-  constexpr int D = L::D, Q = L::Q;
+  constexpr int D = N * N - 1, Q = N * (N - 1) / 2;
 #pragma unroll
   for (int p = 0; p < Q; ++p) {
     float s, cm1;
-    sincm1(fmaf(sF[L::oth + p], E, sF[L::otl + p] * E), s, cm1);
+    sincm1(fmaf(F.th(p), E, F.thl(p) * E), s, cm1);
     const float a = z[2 * p], b = z[2 * p + 1];
-    const float ar = sF[L::ozr + 2 * p], br = sF[L::ozr + 2 * p + 1];
+    const float ar = F.zr(2 * p), br = F.zr(2 * p + 1);
     add_comp(z[2 * p], zl[2 * p], (cm1 * a + s * b) + (cm1 * ar + s * br));
     add_comp(z[2 * p + 1], zl[2 * p + 1], (cm1 * b - s * a) + (cm1 * br - s * ar));
   }
@@ -205,15 +233,15 @@ __device__ __forceinline__ float rot_cell_comp(const float *sF, float p0, float 
   }
   float P = p0;
 #pragma unroll
-  for (int j = 0; j < D; ++j) P += sF[L::ow + j] * z[j];
+  for (int j = 0; j < D; ++j) P += F.w(j) * z[j];
   float dl[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) {
-    float ah = sF[L::oc + i], al = sF[L::ocl + i];
+    float ah = F.c(i), al = F.cl(i);
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      ah = fmaf(sF[L::oK + i * D + j], z[j], ah);
-      al = fmaf(sF[L::oKl + i * D + j], z[j], al);
+      ah = fmaf(F.K(i * D + j), z[j], ah);
+      al = fmaf(F.Kl(i * D + j), z[j], al);
     }
     dl[i] = ah + al;
   }
@@ -329,15 +357,29 @@ __device__ __forceinline__ void record_pop(const FacDev<Real> &f, const Real (&z
 }
 
 // one Liouville cell step: exp(U E dt), optional population record, merged L1
+// factors of the rotation route through scalar loads when D > 8
+template <int N>
+constexpr bool rot_smem() { return N * N - 1 > 8; }
+
 template <int N, typename Real, int ROUTE, bool COMP>
 __device__ __forceinline__ Real cell_step(const FacDev<Real> &f, const Real *sF, const double *sP, Real E,
                                           Real (&z)[N * N - 1],
                                           Real (&zl)[COMP ? N * N - 1 : 1], double *pop,
-                                          int64_t stride) {
-  if constexpr (COMP) {
-    return rot_cell_comp<N>(sF, f.p0, E, z, zl, sP, pop, stride);
-  } else if constexpr (ROUTE == ROUTE_ROT) {
-    return rot_cell<N, Real>(sF, f.p0, E, z, sP, pop, stride);
+                                          int64_t stride, int64_t zoff) {
+  if constexpr (COMP || ROUTE == ROUTE_ROT) {
+    if constexpr (rot_smem<N>()) {
+      SmemAcc<Real> F{&f, zoff};
+      if constexpr (COMP)
+        return rot_cell_comp<N>(F, f.p0, E, z, zl, sP, pop, stride);
+      else
+        return rot_cell<N, Real>(F, f.p0, E, z, sP, pop, stride);
+    } else {
+      LdsAcc<N, Real, COMP> F{sF};
+      if constexpr (COMP)
+        return rot_cell_comp<N>(F, f.p0, E, z, zl, sP, pop, stride);
+      else
+        return rot_cell<N, Real>(F, f.p0, E, z, sP, pop, stride);
+    }
   } else {
     interaction<N, Real, ROUTE>(f, E, z);
     if (pop) record_pop<N, Real, COMP>(f, z, zl, pop, stride);
@@ -351,6 +393,7 @@ __global__ void __launch_bounds__(kMaxTile) fwd_tile_kernel(FwdArgs<Real> a) {
   constexpr int DL = COMP ? D : 1;
   __shared__ Real sE[kMaxTile];
   __shared__ Real sH[kMaxTile];
+  __shared__ Real sSrc[kMaxStepsPerLaunch];
   __shared__ Real sMur;
   __shared__ Real sF[ROUTE == ROUTE_ROT ? RotLds<N, Real, COMP>::size : 1];
   __shared__ double sP[ROUTE == ROUTE_ROT ? N * (N * N - 1) + N : 1];
@@ -380,6 +423,9 @@ __global__ void __launch_bounds__(kMaxTile) fwd_tile_kernel(FwdArgs<Real> a) {
 #pragma unroll
   for (int j = 0; j < DL; ++j) zl[j] = (COMP && is_med) ? a.zin[(D + j) * a.ld + c] : Real(0);
 
+  // source samples of this launch (read by the tile holding cell 0)
+  for (int i = threadIdx.x; i < a.nsteps; i += blockDim.x) sSrc[i] = a.src[a.step0 + 1 + i];
+  __syncthreads();
   int64_t snap_next = a.snap_next, si = a.snap_i0;
   for (int s = 0; s < a.nsteps; ++s) {
     const int64_t n = a.step0 + s;
@@ -398,7 +444,7 @@ __global__ void __launch_bounds__(kMaxTile) fwd_tile_kernel(FwdArgs<Real> a) {
     }
     if (tile_med && is_med) {
       double *pp = (snap && owned && a.pop_out) ? a.pop_out + si * N * (a.me - a.mb) + c : nullptr;
-      P = cell_step<N, Real, ROUTE, COMP>(a.fac, sF, sP, E, z, zl, pp, a.me - a.mb);
+      P = cell_step<N, Real, ROUTE, COMP>(a.fac, sF, sP, E, z, zl, pp, a.me - a.mb, a.opaque0 * s);
     }
     sH[lid] = H;
     __syncthreads();
@@ -407,7 +453,7 @@ __global__ void __launch_bounds__(kMaxTile) fwd_tile_kernel(FwdArgs<Real> a) {
     if (g >= 1 && g < a.nx - 1)
       E = a.ca * E + a.cb * (-P + (H - Hl) * a.inv_dx);
     else if (g == 0)
-      E = a.src[n + 1];
+      E = sSrc[s];
     if (has_right) {  // first-order Mur boundary at cell nx-1
       if (g == a.nx - 2) sMur = E;
       __syncthreads();
@@ -458,7 +504,7 @@ __global__ void __launch_bounds__(256) bloch_kernel(BlochArgs<Real> a) {
   for (int64_t t = 0; t < a.nsteps; ++t) {
     const Real E = (Real)a.efield[t * a.ncell + c];
     double *pp = a.pop_out ? a.pop_out + t * N * a.ncell + c : nullptr;
-    const Real P = cell_step<N, Real, ROUTE, COMP>(a.fac, sF, sP, E, z, zl, pp, a.ncell);
+    const Real P = cell_step<N, Real, ROUTE, COMP>(a.fac, sF, sP, E, z, zl, pp, a.ncell, a.opaque0 * t);
     if (a.dp_out) a.dp_out[t * a.ncell + c] = (double)P;
   }
 }
@@ -512,9 +558,16 @@ __global__ void __launch_bounds__(kMaxTile) adj_tile_kernel(AdjArgs<Real> a) {
   }
 #pragma unroll
   for (int i = 0; i < D; ++i) { ac[i] = 0; aw[i] = 0; }
+  // objective weights and source samples of this launch, staged in LDS
+  __shared__ double sG[kMaxStepsPerLaunch], sS[kMaxStepsPerLaunch];
+  for (int i = threadIdx.x; i < a.nsteps; i += blockDim.x) {
+    sG[i] = a.gprobe[a.n_hi - i];
+    sS[i] = a.samples[a.n_hi - i];
+  }
+  __syncthreads();
   for (int s = 0; s < a.nsteps; ++s) {
     const int64_t n = a.n_hi - 1 - s;
-    if (g == a.nx - 1) lE += (Real)a.gprobe[n + 1];
+    if (g == a.nx - 1) lE += (Real)sG[s];
     sE[lid] = lE;
     __syncthreads();
     const Real lEr = (lid + 1 < W) ? sE[lid + 1] : Real(0);
@@ -534,7 +587,7 @@ __global__ void __launch_bounds__(kMaxTile) adj_tile_kernel(AdjArgs<Real> a) {
       if (interior) lH += cbdx * lEe;
       if (rinterior) lH -= cbdx * lEre;
     }
-    if (g == 0 && owned) aamp += (Real)a.samples[n + 1] * lE;
+    if (g == 0 && owned) aamp += (Real)sS[s] * lE;
     if (g == a.nx - 1) newE = -a.kmur * lE;
     if (g == a.nx - 2) newE += lEr;
     if (is_med) {

@@ -9,7 +9,9 @@ namespace mln {
 
 enum { ROUTE_ROT = 0, ROUTE_DIAG = 1, ROUTE_RODR = 2 };
 
-constexpr int kMaxTile = 256;  // threads (= cells) per tile workgroup
+constexpr int kMaxTile = 256;      // threads (= cells) per tile workgroup
+constexpr int kMaxQuadTile = 256;  // cells per tile of the four-lanes-per-cell kernel
+constexpr int kMaxStepsPerLaunch = 128;  // time steps fused into one launch (halo <= tile/2 < 128)
 
 // Device copies of the per-medium factors, in the precision of the state.
 // Indices are uniform across a wavefront, so the compiler reads them with
@@ -56,6 +58,10 @@ struct FwdArgs {
   // every medium cell at every step n >= tape_step0, row stride ld
   Real *tape;
   int64_t tape_step0;
+  // always 0; the kernels index the shared factor with (opaque0 * step) so that
+  // its scalar loads stay inside the step loop for large D instead of being
+  // hoisted into more SGPRs than exist
+  int64_t opaque0;
 };
 
 // Reverse-time (adjoint) tile kernel arguments.  Adjoint fields lE (of E),
@@ -83,6 +89,7 @@ struct AdjArgs {
 template <typename Real>
 struct BlochArgs {
   FacDev<Real> fac;
+  int64_t opaque0;  // always 0 (see FwdArgs)
   const Real *z0;
   const double *efield;  // nsteps x ncell
   int64_t ncell, nsteps;
@@ -102,6 +109,16 @@ hipError_t launch_bloch(int N, int route, bool comp, const BlochArgs<Real> &a, h
 // C cells per lane (C = 1, 2, 4 for N <= 4; C = 1 for N = 6).
 template <typename Real>
 hipError_t launch_fwd_wave(int N, bool comp, int C, const FwdArgs<Real> &a, int64_t nblocks, hipStream_t st);
+
+// Workgroup tile kernel of the rotation route with the shared-factor GEMM on
+// the matrix cores, split-BF16 with NPROD = 6 or 3 products (fwd_mfma.hpp);
+// compensated FP32 state; N = 4 or 6; W = 64, 128 or 256 cells.
+hipError_t launch_fwd_mfma(int N, int nprod, const FwdArgs<float> &a, int64_t nblocks, int W, hipStream_t st);
+
+// Four-lanes-per-cell tile kernel of the rotation route (fwd_quad.hpp), N <= 3;
+// W cells per tile (W in 64..256, multiple of 16), 4 W threads.
+template <typename Real>
+hipError_t launch_fwd_quad(int N, bool comp, int W, const FwdArgs<Real> &a, int64_t nblocks, hipStream_t st);
 
 // Number of gradient accumulators per tile for N levels in precision Real:
 // dJ/dK (D*D), dJ/dc (D), dJ/dw (D), dJ/dp0, dJ/damplitude, and the moments

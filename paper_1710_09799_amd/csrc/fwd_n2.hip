@@ -1,6 +1,7 @@
 // fwd_n2.hip -- instantiations of the forward kernels for N = 2 levels.
 #include <type_traits>
 
+#include "fwd_quad.hpp"
 #include "fwd_wave.hpp"
 
 namespace mln {
@@ -64,6 +65,19 @@ hipError_t launch_fwd_wave_n2(bool comp, int C, const FwdArgs<Real> &a, int64_t 
 }
 
 template <typename Real>
+hipError_t launch_fwd_quad_n2(bool comp, int W, const FwdArgs<Real> &a, int64_t nblocks, hipStream_t st) {
+  if (comp) {
+    if constexpr (std::is_same<Real, float>::value)
+      hipLaunchKernelGGL((fwd_quad_kernel<2, float, true>), dim3((unsigned)nblocks), dim3(4 * W), 0, st, a);
+    else
+      return hipErrorInvalidValue;
+  } else {
+    hipLaunchKernelGGL((fwd_quad_kernel<2, Real, false>), dim3((unsigned)nblocks), dim3(4 * W), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+template <typename Real>
 hipError_t launch_bloch_n2(int route, bool comp, const BlochArgs<Real> &a, hipStream_t st) {
   const unsigned nb = (unsigned)((a.ncell + 255) / 256);
   if (comp) {
@@ -95,6 +109,8 @@ template hipError_t launch_fwd_n2<double>(int, bool, const FwdArgs<double> &, in
 template hipError_t launch_fwd_n2<float>(int, bool, const FwdArgs<float> &, int64_t, int, hipStream_t);
 template hipError_t launch_fwd_wave_n2<double>(bool, int, const FwdArgs<double> &, int64_t, hipStream_t);
 template hipError_t launch_fwd_wave_n2<float>(bool, int, const FwdArgs<float> &, int64_t, hipStream_t);
+template hipError_t launch_fwd_quad_n2<double>(bool, int, const FwdArgs<double> &, int64_t, hipStream_t);
+template hipError_t launch_fwd_quad_n2<float>(bool, int, const FwdArgs<float> &, int64_t, hipStream_t);
 template hipError_t launch_bloch_n2<double>(int, bool, const BlochArgs<double> &, hipStream_t);
 template hipError_t launch_bloch_n2<float>(int, bool, const BlochArgs<float> &, hipStream_t);
 

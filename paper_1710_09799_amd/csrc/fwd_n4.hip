@@ -1,6 +1,7 @@
 // fwd_n4.hip -- instantiations of the forward kernels for N = 4 levels.
 #include <type_traits>
 
+#include "fwd_mfma.hpp"
 #include "fwd_wave.hpp"
 
 namespace mln {
@@ -59,6 +60,26 @@ hipError_t launch_fwd_wave_n4(bool comp, int C, const FwdArgs<Real> &a, int64_t 
       break;
     default:
       return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd_mfma_n4(int nprod, const FwdArgs<float> &a, int64_t nblocks, int W, hipStream_t st) {
+  constexpr int D = 4 * 4 - 1;
+  if (nprod == 6) {
+    const size_t lds = mfma_lds_bytes<D, 6>(W);
+    hipError_t e = hipFuncSetAttribute((const void *)fwd_mfma_kernel<4, 6>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((fwd_mfma_kernel<4, 6>), dim3((unsigned)nblocks), dim3(W), lds, st, a);
+  } else if (nprod == 3) {
+    const size_t lds = mfma_lds_bytes<D, 3>(W);
+    hipError_t e = hipFuncSetAttribute((const void *)fwd_mfma_kernel<4, 3>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((fwd_mfma_kernel<4, 3>), dim3((unsigned)nblocks), dim3(W), lds, st, a);
+  } else {
+    return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

@@ -1,0 +1,250 @@
+// fwd_quad.hpp -- rotation-route tile kernel with four lanes per cell.
+//
+// For small level counts the per-step work of one cell (q rotations, the
+// D x D shared-factor product, dP/dt, the Yee updates) is a long dependency
+// chain, and a few hundred tiles give about one wavefront per SIMD, so a step
+// costs the latency of that chain.  Here one cell is spread over a quad of
+// lanes (N <= 3, D <= 8):
+//   * in T-coordinates every lane owns one 2-component slice of the state:
+//     lanes 0..q-1 a rotation pair (u_ab, v_ab), the next lane the population
+//     components; the exp(U E dt) rotation is lane-local;
+//   * the quad gathers the rotated state with DPP quad_perm broadcasts, each
+//     lane forms two rows of (K - I) y'' from its rows of K held in registers
+//     for the whole launch, and dP/dt is a two-step quad reduction whose
+//     addition order gives bit-identical sums on all four lanes;
+//   * E, H and the Yee updates are replicated in the four lanes (identical
+//     operands, identical results), the H face left of each cell is kept as a
+//     private copy (it is updated exactly as the neighbour updates it), so a
+//     step needs one LDS exchange of E and one workgroup barrier
+//     (double-buffered exchange array);
+//   * a workgroup holds up to 256 cells (1024 lanes, 4 wavefronts per SIMD).
+// Temporal blocking as in the other tile kernels: a launch advances
+// nsteps <= halo steps and writes back the owned central cells.
+#pragma once
+
+#include "fwd_impl.hpp"
+
+namespace mln {
+
+// DPP quad_perm: every lane of a quad receives lane J's value
+template <int J>
+__device__ __forceinline__ float quad_bcast(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), J | (J << 2) | (J << 4) | (J << 6), 0xf,
+                                                 0xf, false));
+}
+template <int J>
+__device__ __forceinline__ double quad_bcast(double x) {
+  constexpr int c = J | (J << 2) | (J << 4) | (J << 6);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), c, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), c, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+// lane i of a quad receives lane perm(i) for quad_perm [1,0,3,2] and [2,3,0,1]
+template <int CTRL>
+__device__ __forceinline__ float quad_perm(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double quad_perm(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+constexpr int kQuadSwap1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);  // [1,0,3,2]
+constexpr int kQuadSwap2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);  // [2,3,0,1]
+
+// (x0 + x1) + (x2 + x3) on every lane, in an order that makes the four
+// results bitwise equal
+template <typename Real>
+__device__ __forceinline__ Real quad_sum(Real x) {
+  const Real a = x + quad_perm<kQuadSwap1>(x);
+  return a + quad_perm<kQuadSwap2>(a);
+}
+
+template <int N, typename Real, bool COMP>
+__global__ void __launch_bounds__(1024) fwd_quad_kernel(FwdArgs<Real> a) {
+  constexpr int D = N * N - 1, Q = N * (N - 1) / 2;
+  static_assert(D <= 8, "four lanes of two components each");
+  __shared__ Real sE[2][kMaxQuadTile];
+  __shared__ Real sSrc[kMaxStepsPerLaunch];
+  __shared__ Real sMur;
+  const int t = threadIdx.x;
+  const int r = t & 3;      // lane within the quad: state components 2r, 2r+1
+  const int cl = t >> 2;    // cell within the tile
+  const int W = blockDim.x >> 2;
+  const int64_t base = (int64_t)blockIdx.x * a.owned - a.halo;
+  const int64_t g = base + cl;
+  const bool in_dom = g >= 0 && g < a.nx;
+  const bool is_med = g >= a.mb && g < a.me;
+  const bool tile_med = (base < a.me) && (base + W > a.mb);
+  const bool has_right = (base <= a.nx - 1) && (base + W > a.nx - 1);
+  const bool owned = in_dom && cl >= a.halo && cl < a.halo + a.owned;
+  const int64_t c = g - a.mb;
+  const int64_t nmed = a.me - a.mb;
+  const int i0 = 2 * r, i1 = 2 * r + 1;
+  const bool v0 = i0 < D, v1 = i1 < D;
+
+  // this lane's rows of the factors, in registers for the whole launch
+  Real K0[8], K1[8], K0l[8], K1l[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    K0[j] = (v0 && j < D) ? cld(a.fac.Km, i0 * D + j) : Real(0);
+    K1[j] = (v1 && j < D) ? cld(a.fac.Km, i1 * D + j) : Real(0);
+    K0l[j] = (COMP && v0 && j < D) ? cld(a.fac.Km_lo, i0 * D + j) : Real(0);
+    K1l[j] = (COMP && v1 && j < D) ? cld(a.fac.Km_lo, i1 * D + j) : Real(0);
+  }
+  const Real c0 = v0 ? cld(a.fac.cz, i0) : Real(0), c1 = v1 ? cld(a.fac.cz, i1) : Real(0);
+  const Real c0l = (COMP && v0) ? cld(a.fac.cz_lo, i0) : Real(0);
+  const Real c1l = (COMP && v1) ? cld(a.fac.cz_lo, i1) : Real(0);
+  const Real w0 = v0 ? cld(a.fac.wz, i0) : Real(0), w1 = v1 ? cld(a.fac.wz, i1) : Real(0);
+  const Real zr0 = v0 ? cld(a.fac.zr, i0) : Real(0), zr1 = v1 ? cld(a.fac.zr, i1) : Real(0);
+  const bool rot = r < Q;
+  const Real th = rot ? cld(a.fac.thdt, r) : Real(0);
+  const Real thl = (COMP && rot) ? cld(a.fac.th_lo, r) : Real(0);
+
+  Real E = 0, H = 0, Hl = 0;
+  Real y0 = 0, y1 = 0, l0 = 0, l1 = 0;
+  if (in_dom) {
+    E = a.Ein[g];
+    if (g <= a.nx - 2) H = a.Hin[g];
+    if (g >= 1) Hl = a.Hin[g - 1];
+  }
+  if (is_med) {
+    if (v0) y0 = a.zin[i0 * a.ld + c];
+    if (v1) y1 = a.zin[i1 * a.ld + c];
+    if constexpr (COMP) {
+      if (v0) l0 = a.zin[(D + i0) * a.ld + c];
+      if (v1) l1 = a.zin[(D + i1) * a.ld + c];
+    }
+  }
+
+  // source samples of this launch (read by the tile holding cell 0)
+  for (int i = threadIdx.x; i < a.nsteps; i += blockDim.x) sSrc[i] = a.src[a.step0 + 1 + i];
+  __syncthreads();
+  int64_t snap_next = a.snap_next, si = a.snap_i0;
+  for (int s = 0; s < a.nsteps; ++s) {
+    const int64_t n = a.step0 + s;
+    const bool snap = n == snap_next;
+    const int b = s & 1;
+    if (r == 0) sE[b][cl] = E;
+    __syncthreads();
+    const Real El = (cl > 0) ? sE[b][cl - 1] : Real(0);
+    const Real Er = (cl + 1 < W) ? sE[b][cl + 1] : Real(0);
+    if (in_dom) {
+      if (g >= 1) Hl += a.ch * (E - El);
+      if (g <= a.nx - 2) H += a.ch * (Er - E);
+    }
+    Real P = 0;
+    if (tile_med && is_med) {
+      if (a.tape && owned && n >= a.tape_step0) {
+        Real *tp = a.tape + (n - a.tape_step0) * (D + 1) * a.ld + c;
+        if (v0) tp[i0 * a.ld] = y0;
+        if (v1) tp[i1 * a.ld] = y1;
+        if (r == 0) tp[D * a.ld] = E;
+      }
+      // y'' = Rot(y) + (Rot - I) zr on this lane's pair
+      if (rot) {
+        Real sn, cm;
+        if constexpr (COMP)
+          sincm1(fmaf(th, E, thl * E), sn, cm);
+        else
+          sincm1(th * E, sn, cm);
+        const Real d0 = (cm * y0 + sn * y1) + (cm * zr0 + sn * zr1);
+        const Real d1 = (cm * y1 - sn * y0) + (cm * zr1 - sn * zr0);
+        if constexpr (COMP) {
+          add_comp(y0, l0, d0);
+          add_comp(y1, l1, d1);
+        } else {
+          y0 += d0;
+          y1 += d1;
+        }
+      }
+      // gather y'' of the quad
+      Real zz[8];
+      zz[0] = quad_bcast<0>(y0);
+      zz[1] = quad_bcast<0>(y1);
+      zz[2] = quad_bcast<1>(y0);
+      zz[3] = quad_bcast<1>(y1);
+      zz[4] = quad_bcast<2>(y0);
+      zz[5] = quad_bcast<2>(y1);
+      zz[6] = quad_bcast<3>(y0);
+      zz[7] = quad_bcast<3>(y1);
+      if (snap && owned && a.pop_out) {
+        // all four lanes take part in the broadcasts; lanes 0..N-1 each
+        // form the population of one level
+        double ll[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) ll[j] = 0.0;
+        if constexpr (COMP) {
+          ll[0] = (double)quad_bcast<0>(l0);
+          ll[1] = (double)quad_bcast<0>(l1);
+          ll[2] = (double)quad_bcast<1>(l0);
+          ll[3] = (double)quad_bcast<1>(l1);
+          ll[4] = (double)quad_bcast<2>(l0);
+          ll[5] = (double)quad_bcast<2>(l1);
+          ll[6] = (double)quad_bcast<3>(l0);
+          ll[7] = (double)quad_bcast<3>(l1);
+        }
+        if (r < N) {
+          double acc = cld(a.fac.popc, r);
+#pragma unroll
+          for (int j = 0; j < D; ++j) acc += cld(a.fac.pop, r * D + j) * ((double)zz[j] + ll[j]);
+          a.pop_out[si * N * nmed + (int64_t)r * nmed + c] = acc;
+        }
+      }
+      P = a.fac.p0 + quad_sum(w0 * y0 + w1 * y1);
+      // y_next = y'' + (K - I) y'' + constant, rows 2r and 2r+1
+      Real a0 = c0, a1 = c1, b0 = c0l, b1 = c1l;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        a0 += K0[j] * zz[j];
+        a1 += K1[j] * zz[j];
+        if constexpr (COMP) {
+          b0 += K0l[j] * zz[j];
+          b1 += K1l[j] * zz[j];
+        }
+      }
+      if constexpr (COMP) {
+        add_comp(y0, l0, a0 + b0);
+        add_comp(y1, l1, a1 + b1);
+      } else {
+        y0 += a0;
+        y1 += a1;
+      }
+    }
+    const Real Eold = E;
+    if (g >= 1 && g <= a.nx - 2)
+      E = a.ca * E + a.cb * (-P + (H - Hl) * a.inv_dx);
+    else if (g == 0)
+      E = sSrc[s];
+    if (has_right) {  // first-order Mur boundary at cell nx-1
+      if (g == a.nx - 2 && r == 0) sMur = E;
+      __syncthreads();
+      if (g == a.nx - 1) {
+        E = El + a.kmur * (sMur - Eold);
+        if (a.probe_out && owned && r == 0) a.probe_out[n + 1] = (double)E;
+      }
+    }
+    if (snap) {
+      if (owned && r == 0 && a.e_out) a.e_out[si * a.nx + g] = (double)E;
+      snap_next += a.snap_every;
+      ++si;
+    }
+  }
+  if (owned) {
+    if (r == 0) {
+      a.Eout[g] = E;
+      if (g <= a.nx - 2) a.Hout[g] = H;
+    }
+    if (is_med) {
+      if (v0) a.zout[i0 * a.ld + c] = y0;
+      if (v1) a.zout[i1 * a.ld + c] = y1;
+      if constexpr (COMP) {
+        if (v0) a.zout[(D + i0) * a.ld + c] = l0;
+        if (v1) a.zout[(D + i1) * a.ld + c] = l1;
+      }
+    }
+  }
+}
+
+}  // namespace mln

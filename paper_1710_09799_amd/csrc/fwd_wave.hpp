@@ -44,6 +44,7 @@ __global__ void __launch_bounds__(64) fwd_wave_kernel(FwdArgs<Real> a) {
   constexpr int DL = COMP ? D : 1;
   using L = RotLds<N, Real, COMP>;
   __shared__ Real sF[L::size];
+  __shared__ Real sSrc[kMaxStepsPerLaunch];
   __shared__ double sP[N * D + N];
   L::stage(a.fac, sF);
   L::stage_pop(a.fac, sP);
@@ -75,6 +76,9 @@ __global__ void __launch_bounds__(64) fwd_wave_kernel(FwdArgs<Real> a) {
     return t >= a.halo && t < a.halo + a.owned && g >= 0 && g < a.nx;
   };
 
+  // source samples of this launch (read by the tile holding cell 0)
+  for (int i = threadIdx.x; i < a.nsteps; i += blockDim.x) sSrc[i] = a.src[a.step0 + 1 + i];
+  __syncthreads();
   int64_t snap_next = a.snap_next, si = a.snap_i0;
   for (int s = 0; s < a.nsteps; ++s) {
     const int64_t n = a.step0 + s;
@@ -105,10 +109,7 @@ __global__ void __launch_bounds__(64) fwd_wave_kernel(FwdArgs<Real> a) {
           tp[D * a.ld] = E[j];
         }
         double *pp = (snap && own && a.pop_out) ? a.pop_out + si * N * nmed + c : nullptr;
-        if constexpr (COMP)
-          P[j] = rot_cell_comp<N>(sF, a.fac.p0, E[j], z[j], zl[j], sP, pp, nmed);
-        else
-          P[j] = rot_cell<N, Real>(sF, a.fac.p0, E[j], z[j], sP, pp, nmed);
+        P[j] = cell_step<N, Real, ROUTE_ROT, COMP>(a.fac, sF, sP, E[j], z[j], zl[j], pp, nmed, a.opaque0 * s);
       }
     }
     // E^{n+1}
@@ -121,7 +122,7 @@ __global__ void __launch_bounds__(64) fwd_wave_kernel(FwdArgs<Real> a) {
       if (g >= 1 && g <= a.nx - 2)
         E[j] = a.ca * E[j] + a.cb * (-P[j] + (H[j] - Hleft) * a.inv_dx);
       else if (g == 0)
-        E[j] = a.src[n + 1];
+        E[j] = sSrc[s];
     }
     // first-order Mur boundary at cell nx-1 (needs E^n and E^{n+1} of nx-2)
     const Real Eln = wave_shift<kDppWaveShr1>(E[C - 1]);

@@ -81,10 +81,12 @@ struct mln_handle {
   std::vector<double> samples;
   int prec = MLN_FP64, route = MLN_ROUTE_ROTATION;
   bool comp = false;  // compensated FP32 state (two floats per component)
+  int mfma = 0;       // split-BF16 products of the MFMA shared-factor kernel (6, 3) or 0
   hipStream_t stream = nullptr;
   int64_t nmed = 0, ld = 0, step = 0;
   int W = 256, halo = 0, owned = 0;  // cells per tile, halo = max steps per launch
   bool wave = false;                  // single-wavefront tile kernel (W = 64 * C cells)
+  bool quad = false;                  // four-lanes-per-cell tile kernel (W cells, 4 W threads)
   int64_t ntiles = 0;
   int rs = 8;  // bytes per real of the state
   // device state (ping-pong)
@@ -250,6 +252,7 @@ FwdArgs<Real> make_args(mln_handle *h, const FacDev<Real> &fd, int64_t step0, in
   a.probe_out = record ? h->d_probe : nullptr;
   a.tape = tape;
   a.tape_step0 = tape_step0;
+  a.opaque0 = 0;
   return a;
 }
 
@@ -288,12 +291,15 @@ int forward_steps(mln_handle *h, int64_t n, bool record, void *tape, int64_t tap
     hipError_t e;
     if (h->prec == MLN_FP64) {
       auto args = make_args<double>(h, h->fd, h->step, (int)k, record, (double *)tape, tape_step0);
-      e = h->wave ? launch_fwd_wave<double>(h->f.N, false, h->W / 64, args, h->ntiles, h->stream)
-                  : launch_fwd<double>(h->f.N, h->route, false, args, h->ntiles, h->W, h->stream);
+      e = h->quad   ? launch_fwd_quad<double>(h->f.N, false, h->W, args, h->ntiles, h->stream)
+          : h->wave ? launch_fwd_wave<double>(h->f.N, false, h->W / 64, args, h->ntiles, h->stream)
+                    : launch_fwd<double>(h->f.N, h->route, false, args, h->ntiles, h->W, h->stream);
     } else {
       auto args = make_args<float>(h, h->ff, h->step, (int)k, record, (float *)tape, tape_step0);
-      e = h->wave ? launch_fwd_wave<float>(h->f.N, h->comp, h->W / 64, args, h->ntiles, h->stream)
-                  : launch_fwd<float>(h->f.N, h->route, h->comp, args, h->ntiles, h->W, h->stream);
+      e = h->mfma   ? launch_fwd_mfma(h->f.N, h->mfma, args, h->ntiles, h->W, h->stream)
+          : h->quad ? launch_fwd_quad<float>(h->f.N, h->comp, h->W, args, h->ntiles, h->stream)
+          : h->wave ? launch_fwd_wave<float>(h->f.N, h->comp, h->W / 64, args, h->ntiles, h->stream)
+                    : launch_fwd<float>(h->f.N, h->route, h->comp, args, h->ntiles, h->W, h->stream);
     }
     if (e != hipSuccess) return set_err(MLN_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
     h->cur = 1 - h->cur;
@@ -435,11 +441,14 @@ int mln_init(const mln_medium *medium, const mln_grid *grid, const mln_source *s
   h->stream = (hipStream_t)opt.stream;
   if (h->route < 0 || h->route > 2) return set_err(MLN_EINVAL, "unknown route");
   if (h->f.N == 5) return set_err(MLN_ENOTSUPPORTED, "kernels are built for N = 2, 3, 4 and 6");
-  if (h->prec != MLN_FP64 && h->prec != MLN_FP32 && h->prec != MLN_FP32_COMP)
-    return set_err(MLN_ENOTSUPPORTED, "precision not built in this library version");
-  h->comp = h->prec == MLN_FP32_COMP;
+  if (h->prec < MLN_FP64 || h->prec > MLN_FP32_BF16X3)
+    return set_err(MLN_ENOTSUPPORTED, "unknown precision");
+  h->comp = h->prec >= MLN_FP32_COMP;
+  h->mfma = h->prec == MLN_FP32_BF16SPLIT ? 6 : (h->prec == MLN_FP32_BF16X3 ? 3 : 0);
   if (h->comp && h->route != MLN_ROUTE_ROTATION)
     return set_err(MLN_ENOTSUPPORTED, "the compensated FP32 state is built for the rotation route only");
+  if (h->mfma && h->f.N != 4 && h->f.N != 6)
+    return set_err(MLN_ENOTSUPPORTED, "the split-BF16 MFMA kernel is built for N = 4 and 6");
   h->rs = (h->prec == MLN_FP64) ? 8 : 4;
   // FDTD coefficients (Eq. maxwell on the Yee grid, semi-implicit sigma)
   const double eps = kEps0 * grid->eps_r, mu = kMu0 * grid->mu_r;
@@ -451,16 +460,32 @@ int mln_init(const mln_medium *medium, const mln_grid *grid, const mln_source *s
   h->fd_coef[3] = 1.0 / grid->dx;
   h->fd_coef[4] = (cl * grid->dt - grid->dx) / (cl * grid->dt + grid->dx);
   // kernel variant and tiling
-  if (opt.variant < 0 || opt.variant > 2) return set_err(MLN_EINVAL, "unknown kernel variant");
+  if (opt.variant < 0 || opt.variant > 3) return set_err(MLN_EINVAL, "unknown kernel variant");
   const bool rot = h->route == MLN_ROUTE_ROTATION;
-  h->wave = opt.variant == 2 || (opt.variant == 0 && rot && h->f.N <= 4);
-  if (h->wave && !rot) return set_err(MLN_ENOTSUPPORTED, "the wavefront kernel implements the rotation route");
-  h->W = opt.tile > 0 ? opt.tile : kMaxTile;
-  if (h->W > kMaxTile || h->W < 64 || h->W % 64) return set_err(MLN_EINVAL, "tile must be a multiple of 64 in [64, 256]");
+  int variant = opt.variant;
+  if (variant == 0) variant = !rot ? 1 : (h->f.N <= 3 ? 3 : (h->f.N == 4 ? 2 : 1));
+  if (h->mfma) {
+    if (variant != 1 && opt.variant != 0)
+      return set_err(MLN_ENOTSUPPORTED, "the split-BF16 MFMA kernel is a workgroup-tile kernel");
+    variant = 1;
+  }
+  h->wave = variant == 2;
+  h->quad = variant == 3;
+  if ((h->wave || h->quad) && !rot)
+    return set_err(MLN_ENOTSUPPORTED, "the wavefront and quad kernels implement the rotation route");
+  if (h->quad && h->f.N > 3) return set_err(MLN_ENOTSUPPORTED, "the quad kernel is built for N <= 3");
+  h->W = opt.tile > 0 ? opt.tile : (h->quad ? 128 : kMaxTile);
+  if (h->quad) {
+    if (h->W > kMaxQuadTile || h->W < 32 || h->W % 16)
+      return set_err(MLN_EINVAL, "quad kernel tile must be a multiple of 16 in [32, 256]");
+  } else if (h->W > kMaxTile || h->W < 64 || h->W % 64) {
+    return set_err(MLN_EINVAL, "tile must be a multiple of 64 in [64, 256]");
+  }
   if (h->wave && (h->W == 192 || (h->f.N == 6 && h->W != 64)))
     return set_err(MLN_ENOTSUPPORTED, "wavefront kernel tiles: 64, 128 or 256 cells (64 for N = 6)");
-  int K = opt.steps_per_launch > 0 ? opt.steps_per_launch : (h->wave ? h->W / 8 : 32);
-  if (2 * K >= h->W) return set_err(MLN_EINVAL, "steps_per_launch must be below tile/2");
+  int K = opt.steps_per_launch > 0 ? opt.steps_per_launch : (h->wave ? h->W / 8 : (h->quad ? h->W / 4 : 32));
+  if (2 * K >= h->W || K > kMaxStepsPerLaunch)
+    return set_err(MLN_EINVAL, "steps_per_launch must be below tile/2 (and at most 128)");
   h->halo = K;
   h->owned = h->W - 2 * K;
   h->ntiles = (grid->nx + h->owned - 1) / h->owned;
@@ -633,7 +658,7 @@ int mln_bloch_only(mln_handle *h, const double *efield, int64_t n_steps, double 
   if (h->prec == MLN_FP64) {
     HIP_TRY(dz0.alloc(sizeof(double) * D));
     HIP_TRY(hipMemcpy(dz0.p, s0.data(), sizeof(double) * D, hipMemcpyHostToDevice));
-    BlochArgs<double> a{h->fd, (const double *)dz0.p, e_dev, nc, n_steps, pop_dev, dp_dev};
+    BlochArgs<double> a{h->fd, 0, (const double *)dz0.p, e_dev, nc, n_steps, pop_dev, dp_dev};
     e = launch_bloch<double>(N, h->route, false, a, h->stream);
   } else {
     std::vector<float> z0f(2 * D);
@@ -643,7 +668,7 @@ int mln_bloch_only(mln_handle *h, const double *efield, int64_t n_steps, double 
     }
     HIP_TRY(dz0.alloc(sizeof(float) * 2 * D));
     HIP_TRY(hipMemcpy(dz0.p, z0f.data(), sizeof(float) * 2 * D, hipMemcpyHostToDevice));
-    BlochArgs<float> a{h->ff, (const float *)dz0.p, e_dev, nc, n_steps, pop_dev, dp_dev};
+    BlochArgs<float> a{h->ff, 0, (const float *)dz0.p, e_dev, nc, n_steps, pop_dev, dp_dev};
     e = launch_bloch<float>(N, h->route, h->comp, a, h->stream);
   }
   if (e != hipSuccess) return set_err(MLN_EHIP, std::string("bloch launch: ") + hipGetErrorString(e));

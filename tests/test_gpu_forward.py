@@ -61,13 +61,16 @@ def test_coupled_fp64_small(ref_cache, n, seed, route, tile, k):
 
 @pytest.mark.parametrize("n,seed", SMALL)
 @pytest.mark.parametrize("variant,tile,k", [("block", 256, 32), ("wave", 64, 8), ("wave", 128, 24),
-                                            ("wave", 256, 50), ("wave", 256, 127)])
+                                            ("wave", 256, 50), ("wave", 256, 127), ("quad", 32, 8),
+                                            ("quad", 128, 32), ("quad", 256, 63), ("quad", 80, 20)])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32c", 1e-5)])
 def test_coupled_rotation_variants(ref_cache, n, seed, variant, tile, k, precision, tol):
     """Rotation route: workgroup-tile and wavefront-tile kernels with every
     cells-per-lane count, against the oracle."""
     if n == 6 and variant == "wave" and tile != 64:
         pytest.skip("wavefront tiles for N = 6 hold one cell per lane")
+    if n > 3 and variant == "quad":
+        pytest.skip("the quad kernel covers N <= 3")
     p = W.random_problem(n, seed, nx=203, nt=360)
     _print_case("variants", n=n, variant=variant, tile=tile, k=k, precision=precision)
     ref = ref_cache((n, seed), p, 40)
