@@ -221,6 +221,61 @@ void mln_free(mln_handle *h);
 const char *mln_strerror(int code);
 const char *mln_last_error(void);
 
+/* ---- many independent problems in one launch sequence ----------------- */
+
+/* A batch advances n_inst independent problems in lockstep: parameter
+ * sweeps over media, densities, dipoles and grid lengths, each problem
+ * being the single-medium problem of Sec. 2 with its own Bloch-vector
+ * propagation (Sec. 3, 4.1).  Every launch covers one chunk of time steps for
+ * all problems: workgroup g is tile t of problem i according to a table on
+ * the device, two- and three-level problems share the launch, and the tiles
+ * are the four-lanes-per-cell tiles of the rotation route.
+ *   media, grids, sources  arrays of n_inst descriptors (as for mln_init);
+ *                          every grid has the same dt and nt; N = 2 or 3
+ *   records                array of n_inst recordings, or NULL (none)
+ *   options                precision MLN_FP64, MLN_FP32 or MLN_FP32_COMP;
+ *                          route MLN_ROUTE_ROTATION; variant 0 or 3;
+ *                          ckpt_every 0; tile / steps_per_launch as for
+ *                          mln_init (0: 128 cells, 16 steps); stream shared
+ *                          by all problems
+ * Each problem gets its own handle (device state, factors, recording), owned
+ * by the batch; mln_batch_instance lends it out (do not mln_free it).
+ * Errors: those of mln_init (prefixed with the problem index in
+ * mln_last_error), MLN_EINVAL (unequal dt or nt), MLN_ENOTSUPPORTED. */
+typedef struct mln_batch mln_batch;
+int mln_init_batch(int32_t n_inst, const mln_medium *media, const mln_grid *grids,
+                   const mln_source *sources, const mln_record *records,
+                   const mln_options *options, mln_batch **out);
+
+/* Autotuner: time every candidate tile shape (cells per tile, steps per
+ * launch) on the batch itself over about trial_steps steps (HIP events on
+ * the batch's stream), keep the fastest per time step, and reset the batch
+ * to step 0.  The chosen shape is returned in *tile and *steps_per_launch
+ * (either may be NULL).  Synchronises. */
+int mln_batch_tune(mln_batch *b, int32_t trial_steps, int32_t *tile, int32_t *steps_per_launch);
+
+/* Set the tile shape explicitly (batch at step 0) / read it back together
+ * with the number of workgroups of one launch. */
+int mln_batch_configure(mln_batch *b, int32_t tile, int32_t steps_per_launch);
+int mln_batch_get_config(const mln_batch *b, int32_t *tile, int32_t *steps_per_launch,
+                         int64_t *workgroups);
+
+/* on = 1 (default): mln_batch_run from step 0 replays one HIP graph holding
+ * every launch of the run (captured on first use, rebuilt after a change of
+ * tile shape); on = 0: launches are enqueued one by one. */
+int mln_batch_use_graph(mln_batch *b, int32_t on);
+
+/* Advance every problem by n_steps (clipped at nt); asynchronous. */
+int mln_batch_step(mln_batch *b, int64_t n_steps);
+/* Run every problem to nt and deliver the recordings; synchronises.
+ * MLN_ESTATE if a problem was stepped on its own since the last reset. */
+int mln_batch_run(mln_batch *b);
+/* Back to step 0 for every problem; synchronises. */
+int mln_batch_reset(mln_batch *b);
+/* Borrow the handle of problem i (for mln_get_fields, mln_save_state, ...). */
+int mln_batch_instance(mln_batch *b, int32_t i, mln_handle **h);
+void mln_batch_free(mln_batch *b);
+
 /* ---- one-time factors (host only, no GPU needed) ---------------------- */
 
 /* The FP64 quantities built once per medium and time step.  D = N^2-1,

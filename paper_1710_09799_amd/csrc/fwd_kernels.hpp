@@ -120,6 +120,27 @@ hipError_t launch_fwd_mfma(int N, int nprod, const FwdArgs<float> &a, int64_t nb
 template <typename Real>
 hipError_t launch_fwd_quad(int N, bool comp, int W, const FwdArgs<Real> &a, int64_t nblocks, hipStream_t st);
 
+// Batched launch (fwd_batch.hpp): per-problem arguments for reading from
+// ping-pong slot 0 and from slot 1 (step0, nsteps and the snapshot schedule
+// are filled in per launch), and the workgroup -> (problem, tile) table.
+template <typename Real>
+struct BatchInst {
+  FwdArgs<Real> a[2];
+  int32_t n_levels;  // 2 or 3
+  int32_t pad_;
+};
+struct BatchTile {
+  int32_t inst;
+  int32_t tile;
+};
+
+// Four-lanes-per-cell tiles of many problems (N = 2 and 3) in one launch of
+// nblocks workgroups of 4 W lanes.  Real = double (plain) or float (plain or
+// compensated).
+template <typename Real>
+hipError_t launch_fwd_quad_batch(bool comp, int W, const BatchInst<Real> *inst, const BatchTile *tiles,
+                                 int64_t nblocks, int64_t step0, int nsteps, int slot, hipStream_t st);
+
 // Number of gradient accumulators per tile for N levels in precision Real:
 // dJ/dK (D*D), dJ/dc (D), dJ/dw (D), dJ/dp0, dJ/damplitude, and the moments
 // sum E^m lhat zhat^T for m = 1, 3 (and 5 in FP64), D*D each.

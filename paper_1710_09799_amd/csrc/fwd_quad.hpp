@@ -61,8 +61,10 @@ __device__ __forceinline__ Real quad_sum(Real x) {
   return a + quad_perm<kQuadSwap2>(a);
 }
 
+// One tile (index `tile` of the problem described by `a`) on one workgroup of
+// 4 W lanes.
 template <int N, typename Real, bool COMP>
-__global__ void __launch_bounds__(1024) fwd_quad_kernel(FwdArgs<Real> a) {
+__device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) {
   constexpr int D = N * N - 1, Q = N * (N - 1) / 2;
   static_assert(D <= 8, "four lanes of two components each");
   __shared__ Real sE[2][kMaxQuadTile];
@@ -72,7 +74,7 @@ __global__ void __launch_bounds__(1024) fwd_quad_kernel(FwdArgs<Real> a) {
   const int r = t & 3;      // lane within the quad: state components 2r, 2r+1
   const int cl = t >> 2;    // cell within the tile
   const int W = blockDim.x >> 2;
-  const int64_t base = (int64_t)blockIdx.x * a.owned - a.halo;
+  const int64_t base = tile * a.owned - a.halo;
   const int64_t g = base + cl;
   const bool in_dom = g >= 0 && g < a.nx;
   const bool is_med = g >= a.mb && g < a.me;
@@ -245,6 +247,11 @@ __global__ void __launch_bounds__(1024) fwd_quad_kernel(FwdArgs<Real> a) {
       }
     }
   }
+}
+
+template <int N, typename Real, bool COMP>
+__global__ void __launch_bounds__(1024) fwd_quad_kernel(FwdArgs<Real> a) {
+  quad_tile<N, Real, COMP>(a, blockIdx.x);
 }
 
 }  // namespace mln

@@ -11,105 +11,19 @@
 #include <string>
 #include <vector>
 
-#include "../../include/mln.h"
-#include "fwd_kernels.hpp"
-#include "mln_internal.hpp"
+#include "handle.hpp"
 
 using namespace mln;
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
-int set_err(int code, const std::string &msg) {
+int mln::set_err(int code, const std::string &msg) {
   g_last_error = msg;
   return code;
 }
 
-#define HIP_TRY(expr)                                                                   \
-  do {                                                                                  \
-    hipError_t e_ = (expr);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      return set_err(e_ == hipErrorOutOfMemory ? MLN_ENOMEM : MLN_EHIP,                 \
-                     std::string(#expr) + ": " + hipGetErrorString(e_));                \
-  } while (0)
-
-// A device allocation owned by the handle.
-struct DevBuf {
-  void *p = nullptr;
-  size_t bytes = 0;
-  ~DevBuf() {
-    if (p) (void)hipFree(p);
-  }
-  hipError_t alloc(size_t n) {
-    bytes = n;
-    return hipMalloc(&p, n ? n : 1);
-  }
-};
-
-}  // namespace
-
-// Deep copy of an mln_medium (the handle keeps it for the adjoint's chain rule).
-struct MediumCopy {
-  std::vector<double> h0, mu, jump, rate, relax, rho0;
-  mln_medium m{};
-  void set(const mln_medium *src) {
-    const int N = src->n_levels, NN = N * N;
-    h0.assign(src->h0, src->h0 + 2 * NN);
-    mu.assign(src->dipole, src->dipole + 2 * NN);
-    rho0.assign(src->rho0, src->rho0 + 2 * NN);
-    if (src->n_jump > 0) {
-      jump.assign(src->jump, src->jump + 2 * NN * src->n_jump);
-      rate.assign(src->jump_rate, src->jump_rate + src->n_jump);
-    }
-    if (src->relax_superop) relax.assign(src->relax_superop, src->relax_superop + 2 * NN * NN);
-    m = *src;
-    m.h0 = h0.data();
-    m.dipole = mu.data();
-    m.rho0 = rho0.data();
-    m.jump = jump.empty() ? nullptr : jump.data();
-    m.jump_rate = rate.empty() ? nullptr : rate.data();
-    m.relax_superop = relax.empty() ? nullptr : relax.data();
-  }
-};
-
-struct mln_handle {
-  Factors f;
-  MediumCopy medium;
-  mln_grid grid{};
-  double amp = 0.0;
-  std::vector<double> samples;
-  int prec = MLN_FP64, route = MLN_ROUTE_ROTATION;
-  bool comp = false;  // compensated FP32 state (two floats per component)
-  int mfma = 0;       // split-BF16 products of the MFMA shared-factor kernel (6, 3) or 0
-  hipStream_t stream = nullptr;
-  int64_t nmed = 0, ld = 0, step = 0;
-  int W = 256, halo = 0, owned = 0;  // cells per tile, halo = max steps per launch
-  bool wave = false;                  // single-wavefront tile kernel (W = 64 * C cells)
-  bool quad = false;                  // four-lanes-per-cell tile kernel (W cells, 4 W threads)
-  int64_t ntiles = 0;
-  int rs = 8;  // bytes per real of the state
-  // device state (ping-pong)
-  DevBuf E[2], H[2], z[2];
-  int cur = 0;
-  DevBuf src, fac, pop, popc;
-  FacDev<double> fd{};
-  FacDev<float> ff{};
-  // recording
-  mln_record rec{};
-  int64_t nsnap = 0;
-  DevBuf st_pop, st_e, st_probe;  // device staging for host outputs
-  double *d_pop = nullptr, *d_e = nullptr, *d_probe = nullptr;
-  // initial state on the host
-  std::vector<unsigned char> z_init, e_init;
-  // checkpoints of the forward run (for the adjoint)
-  int64_t ckpt_every = 0, nckpt = 0, ckpt_count = 0;
-  bool ckpt_ok = false;
-  DevBuf ckpt;
-  // adjoint buffers (allocated by the first mln_grad)
-  DevBuf lE[2], lH[2], lz[2], tape, partial, gprobe, samples_dev;
-  double fd_coef[5] = {0, 0, 0, 0, 0};  // ch, ca, cb, inv_dx, kmur
-};
 
 namespace {
 
@@ -191,69 +105,6 @@ void build_init_state(mln_handle *h) {
     }
   h->e_init.assign(sizeof(Real) * h->grid.nx, 0);
   ((Real *)h->e_init.data())[0] = (Real)(h->amp * h->samples[0]);
-}
-
-int reset_state(mln_handle *h) {
-  const size_t rs = h->rs;
-  for (int b = 0; b < 2; ++b) {
-    HIP_TRY(hipMemsetAsync(h->H[b].p, 0, h->H[b].bytes, h->stream));
-    HIP_TRY(hipMemcpyAsync(h->E[b].p, h->e_init.data(), rs * h->grid.nx, hipMemcpyHostToDevice, h->stream));
-    HIP_TRY(hipMemcpyAsync(h->z[b].p, h->z_init.data(), h->z_init.size(), hipMemcpyHostToDevice, h->stream));
-  }
-  h->cur = 0;
-  h->step = 0;
-  h->ckpt_count = 0;
-  h->ckpt_ok = h->ckpt_every > 0;
-  if (h->d_probe) {
-    double p0 = (h->grid.nx - 1 == 0) ? h->amp * h->samples[0] : 0.0;
-    HIP_TRY(hipMemcpyAsync(h->d_probe, &p0, sizeof(double), hipMemcpyHostToDevice, h->stream));
-  }
-  HIP_TRY(hipStreamSynchronize(h->stream));
-  return MLN_OK;
-}
-
-template <typename Real>
-FwdArgs<Real> make_args(mln_handle *h, const FacDev<Real> &fd, int64_t step0, int nsteps,
-                        bool record = true, Real *tape = nullptr, int64_t tape_step0 = 0) {
-  FwdArgs<Real> a{};
-  a.fac = fd;
-  const int in = h->cur, out = 1 - h->cur;
-  a.Ein = (const Real *)h->E[in].p;
-  a.Eout = (Real *)h->E[out].p;
-  a.Hin = (const Real *)h->H[in].p;
-  a.Hout = (Real *)h->H[out].p;
-  a.zin = (const Real *)h->z[in].p;
-  a.zout = (Real *)h->z[out].p;
-  a.src = (const Real *)h->src.p;
-  a.nx = h->grid.nx;
-  a.mb = h->grid.med_begin;
-  a.me = h->grid.med_end;
-  a.ld = h->ld;
-  a.step0 = step0;
-  a.nsteps = nsteps;
-  a.halo = h->halo;
-  a.owned = h->owned;
-  a.ch = (Real)h->fd_coef[0];
-  a.ca = (Real)h->fd_coef[1];
-  a.cb = (Real)h->fd_coef[2];
-  a.inv_dx = (Real)h->fd_coef[3];
-  a.kmur = (Real)h->fd_coef[4];
-  a.snap_every = record ? h->rec.snap_every : 0;
-  // first step n >= step0 with (n+1) % snap_every == 0, and its snapshot index
-  a.snap_next = -1;
-  a.snap_i0 = 0;
-  if (a.snap_every > 0) {
-    const int64_t k = step0 / a.snap_every;  // snapshots completed before step0
-    a.snap_next = (k + 1) * a.snap_every - 1;
-    a.snap_i0 = k;
-  }
-  a.pop_out = record ? h->d_pop : nullptr;
-  a.e_out = record ? h->d_e : nullptr;
-  a.probe_out = record ? h->d_probe : nullptr;
-  a.tape = tape;
-  a.tape_step0 = tape_step0;
-  a.opaque0 = 0;
-  return a;
 }
 
 size_t state_slot_bytes(const mln_handle *h) { return h->E[0].bytes + h->H[0].bytes + h->z[0].bytes; }
@@ -349,6 +200,42 @@ int init_typed(mln_handle *h, FacDev<Real> &fd) {
 }
 
 }  // namespace
+
+int mln::reset_state(mln_handle *h) {
+  const size_t rs = h->rs;
+  for (int b = 0; b < 2; ++b) {
+    HIP_TRY(hipMemsetAsync(h->H[b].p, 0, h->H[b].bytes, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->E[b].p, h->e_init.data(), rs * h->grid.nx, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->z[b].p, h->z_init.data(), h->z_init.size(), hipMemcpyHostToDevice, h->stream));
+  }
+  h->cur = 0;
+  h->step = 0;
+  h->ckpt_count = 0;
+  h->ckpt_ok = h->ckpt_every > 0;
+  if (h->d_probe) {
+    double p0 = (h->grid.nx - 1 == 0) ? h->amp * h->samples[0] : 0.0;
+    HIP_TRY(hipMemcpyAsync(h->d_probe, &p0, sizeof(double), hipMemcpyHostToDevice, h->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return MLN_OK;
+}
+
+int mln::finish_run(mln_handle *h) {
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (!h->rec.out_on_device) {
+    const int N = h->f.N;
+    if (h->st_pop.p)
+      HIP_TRY(hipMemcpy(h->rec.pop_out, h->st_pop.p, sizeof(double) * h->nsnap * N * h->nmed, hipMemcpyDeviceToHost));
+    if (h->st_e.p)
+      HIP_TRY(hipMemcpy(h->rec.e_out, h->st_e.p, sizeof(double) * h->nsnap * h->grid.nx, hipMemcpyDeviceToHost));
+    if (h->st_probe.p)
+      HIP_TRY(hipMemcpy(h->rec.probe_out, h->st_probe.p, sizeof(double) * (h->grid.nt + 1), hipMemcpyDeviceToHost));
+    if (h->rec.probe_out)
+      for (int64_t i = 0; i <= h->grid.nt; ++i)
+        if (!std::isfinite(h->rec.probe_out[i])) return set_err(MLN_ENONFINITE, "non-finite probe value");
+  }
+  return MLN_OK;
+}
 
 extern "C" {
 
@@ -543,20 +430,7 @@ int mln_run(mln_handle *h) {
   if (!h) return set_err(MLN_EINVAL, "null handle");
   int rc = mln_step(h, h->grid.nt - h->step);
   if (rc) return rc;
-  HIP_TRY(hipStreamSynchronize(h->stream));
-  if (!h->rec.out_on_device) {
-    const int N = h->f.N;
-    if (h->st_pop.p)
-      HIP_TRY(hipMemcpy(h->rec.pop_out, h->st_pop.p, sizeof(double) * h->nsnap * N * h->nmed, hipMemcpyDeviceToHost));
-    if (h->st_e.p)
-      HIP_TRY(hipMemcpy(h->rec.e_out, h->st_e.p, sizeof(double) * h->nsnap * h->grid.nx, hipMemcpyDeviceToHost));
-    if (h->st_probe.p)
-      HIP_TRY(hipMemcpy(h->rec.probe_out, h->st_probe.p, sizeof(double) * (h->grid.nt + 1), hipMemcpyDeviceToHost));
-    if (h->rec.probe_out)
-      for (int64_t i = 0; i <= h->grid.nt; ++i)
-        if (!std::isfinite(h->rec.probe_out[i])) return set_err(MLN_ENONFINITE, "non-finite probe value");
-  }
-  return MLN_OK;
+  return finish_run(h);
 }
 
 int mln_reset(mln_handle *h) {

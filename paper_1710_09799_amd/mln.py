@@ -72,7 +72,9 @@ class _Factors(ctypes.Structure):
 EXPORTS = ["mln_init", "mln_step", "mln_run", "mln_reset", "mln_current_step", "mln_get_fields",
            "mln_state_bytes", "mln_save_state", "mln_load_state", "mln_bloch_only", "mln_free",
            "mln_strerror", "mln_last_error", "mln_setup_factors", "mln_version", "mln_grad",
-           "mln_chain_rule"]
+           "mln_chain_rule", "mln_init_batch", "mln_batch_tune", "mln_batch_configure",
+           "mln_batch_get_config", "mln_batch_use_graph", "mln_batch_step", "mln_batch_run",
+           "mln_batch_reset", "mln_batch_instance", "mln_batch_free"]
 
 _lib = None
 
@@ -87,6 +89,7 @@ def load():
     L = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     i64p = ctypes.POINTER(ctypes.c_int64)
+    i32p = ctypes.POINTER(ctypes.c_int32)
     sig = {
         "mln_init": ([ctypes.POINTER(_Medium), ctypes.POINTER(_Grid), ctypes.POINTER(_Source),
                       ctypes.POINTER(_Record), ctypes.POINTER(_Options), ctypes.POINTER(P)], ctypes.c_int),
@@ -108,6 +111,18 @@ def load():
         "mln_grad": ([P, _dp, ctypes.POINTER(_Grads)], ctypes.c_int),
         "mln_chain_rule": ([ctypes.POINTER(_Medium), ctypes.c_double, _dp, _dp, _dp, ctypes.c_double,
                             _dp, _dp, ctypes.POINTER(_Grads)], ctypes.c_int),
+        "mln_init_batch": ([ctypes.c_int32, ctypes.POINTER(_Medium), ctypes.POINTER(_Grid),
+                            ctypes.POINTER(_Source), ctypes.POINTER(_Record), ctypes.POINTER(_Options),
+                            ctypes.POINTER(P)], ctypes.c_int),
+        "mln_batch_tune": ([P, ctypes.c_int32, i32p, i32p], ctypes.c_int),
+        "mln_batch_configure": ([P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+        "mln_batch_get_config": ([P, i32p, i32p, i64p], ctypes.c_int),
+        "mln_batch_use_graph": ([P, ctypes.c_int32], ctypes.c_int),
+        "mln_batch_step": ([P, ctypes.c_int64], ctypes.c_int),
+        "mln_batch_run": ([P], ctypes.c_int),
+        "mln_batch_reset": ([P], ctypes.c_int),
+        "mln_batch_instance": ([P, ctypes.c_int32, ctypes.POINTER(P)], ctypes.c_int),
+        "mln_batch_free": ([P], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -296,6 +311,99 @@ class Solver:
     def close(self):
         if getattr(self, "_h", None):
             self._L.mln_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _dptr(t):
+    return ctypes.cast(ctypes.c_void_p(t.data_ptr()), _dp) if t is not None else None
+
+
+class Batch:
+    """Many independent problems (N = 2 or 3, equal dt and nt) advanced in
+    lockstep by one launch per chunk of time steps (mln_init_batch).
+
+    outputs(i) gives problem i's recordings (torch float64 device tensors), as
+    Solver.outputs() does.
+    """
+
+    def __init__(self, problems, precision="fp32c", snap_every=0, steps_per_launch=0, tile=0,
+                 record_probe=True, record_pop=True, record_e=True, graph=True):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("Batch needs a HIP device")
+        L = load()
+        self._L = L
+        self.problems = list(problems)
+        n = len(self.problems)
+        dev = torch.device("cuda")
+        self._keep = []
+        meds = (_Medium * n)()
+        grids = (_Grid * n)()
+        srcs = (_Source * n)()
+        recs = (_Record * n)()
+        self._out = []
+        for i, p in enumerate(self.problems):
+            g = p.grid
+            nsnap = g.nt // snap_every if snap_every > 0 else 0
+            o = dict(probe=torch.zeros(g.nt + 1, dtype=torch.float64, device=dev) if record_probe else None,
+                     e_snap=(torch.zeros((nsnap, g.nx), dtype=torch.float64, device=dev)
+                             if (record_e and nsnap) else None),
+                     pop=(torch.zeros((nsnap, p.medium.n_levels, g.n_med), dtype=torch.float64, device=dev)
+                          if (record_pop and nsnap) else None))
+            self._out.append(o)
+            ma = _MediumArgs(p.medium)
+            smp = np.ascontiguousarray(p.source.samples, dtype=np.float64)
+            self._keep += [ma, smp]
+            meds[i] = ma.s
+            grids[i] = _Grid(g.nx, g.nt, g.dx, g.dt, g.med_begin, g.med_end, g.eps_r, g.mu_r, g.sigma)
+            srcs[i] = _Source(_ptr(smp), len(smp), float(p.source.amplitude))
+            recs[i] = _Record(snap_every, _dptr(o["pop"]), _dptr(o["e_snap"]), _dptr(o["probe"]), 1)
+        self.stream = torch.cuda.current_stream()
+        opt = _Options(PRECISIONS[precision], ROUTES["rotation"], steps_per_launch, tile,
+                       ctypes.c_void_p(self.stream.cuda_stream), 0, VARIANTS["quad"])
+        h = ctypes.c_void_p()
+        _check(L.mln_init_batch(n, meds, grids, srcs, recs, ctypes.byref(opt), ctypes.byref(h)))
+        self._h = h
+        self.use_graph(graph)
+
+    def tune(self, trial_steps=256):
+        w, k = ctypes.c_int32(), ctypes.c_int32()
+        _check(self._L.mln_batch_tune(self._h, int(trial_steps), ctypes.byref(w), ctypes.byref(k)))
+        return w.value, k.value
+
+    def configure(self, tile, steps_per_launch):
+        _check(self._L.mln_batch_configure(self._h, int(tile), int(steps_per_launch)))
+
+    def config(self):
+        w, k, nb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(self._L.mln_batch_get_config(self._h, ctypes.byref(w), ctypes.byref(k), ctypes.byref(nb)))
+        return dict(tile=w.value, steps_per_launch=k.value, workgroups=nb.value)
+
+    def use_graph(self, on):
+        _check(self._L.mln_batch_use_graph(self._h, 1 if on else 0))
+
+    def step(self, n):
+        _check(self._L.mln_batch_step(self._h, int(n)))
+
+    def run(self):
+        _check(self._L.mln_batch_run(self._h))
+        return self._out
+
+    def reset(self):
+        _check(self._L.mln_batch_reset(self._h))
+
+    def outputs(self, i):
+        return self._out[i]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.mln_batch_free(self._h)
             self._h = None
 
     def __del__(self):

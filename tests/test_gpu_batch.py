@@ -1,0 +1,161 @@
+"""Batched lockstep launch (mln_init_batch): many two- and three-level
+problems of different lengths in one launch per chunk of steps, its HIP graph
+and its tile autotuner.
+
+The batched launch runs the same per-tile arithmetic as the single-problem
+four-lanes-per-cell kernel, so with equal tile shapes the recordings of each
+problem agree with a single-problem run to the last bit; every problem is
+also checked against the FP64 oracle.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_1710_09799_amd import mln
+from paper_1710_09799_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _np(out):
+    return {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+
+
+def _errs(got, ref):
+    e = np.concatenate([got["e_snap"].ravel(), got["probe"].ravel()])
+    er = np.concatenate([ref["e_snap"].ravel(), ref["probe"].ravel()])
+    return (np.max(np.abs(e - er)) / np.max(np.abs(er)),
+            np.max(np.abs(got["pop"] - ref["pop"])) if ref["pop"].size else 0.0)
+
+
+def _small_sweep(n=6, nt=600, seed=5):
+    # lengths from 150 to 700 cells: several tiles per problem, ragged last tiles
+    return W.batched_sweep(n_inst=n, nt=nt, seed=seed, nx_range=(150, 700))
+
+
+@pytest.fixture(scope="module")
+def sweep_ref(orc):
+    probs = _small_sweep()
+    return probs, [orc.run(p, snap_every=100) for p in probs]
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32c", 1e-5), ("fp32", 1e-3)])
+@pytest.mark.parametrize("tile,k", [(128, 16), (64, 8)])
+def test_batch_equals_single_runs_and_oracle(sweep_ref, precision, tol, tile, k):
+    probs, refs = sweep_ref
+    print(f"[case] batch {precision} tile={tile} k={k}", flush=True)
+    b = mln.Batch(probs, precision=precision, snap_every=100, tile=tile, steps_per_launch=k)
+    outs = [_np(o) for o in b.run()]
+    b.close()
+    for i, p in enumerate(probs):
+        single = mln.run(p, precision=precision, variant="quad", tile=tile, steps_per_launch=k, snap_every=100)
+        for key in ("probe", "e_snap", "pop"):
+            assert np.array_equal(outs[i][key], single[key]), (i, key)
+        ee, ep = _errs(outs[i], refs[i])
+        print(f"  inst {i} N={p.medium.n_levels} nx={p.grid.nx} err_E={ee:.3e} err_pop={ep:.3e}")
+        assert ee < tol and ep < tol
+
+
+def test_graph_replays_match_eager(sweep_ref):
+    """The captured whole-run graph, replayed several times with other work
+    on the stream in between, gives the eager launch sequence's results."""
+    import torch
+    probs, _ = sweep_ref
+    b = mln.Batch(probs, precision="fp32c", snap_every=100, graph=False)
+    eager = [_np(o) for o in b.run()]
+    b.reset()
+    b.use_graph(True)
+    for rep in range(3):
+        x = torch.randn(1 << 16, device="cuda")
+        torch.cuda.synchronize()
+        got = [_np(o) for o in b.run()]
+        for i in range(len(probs)):
+            for key in ("probe", "e_snap", "pop"):
+                assert np.array_equal(got[i][key], eager[i][key]), (rep, i, key)
+        _ = (x * 2).sum().item()
+        b.reset()
+    b.close()
+
+
+def test_stepping_in_chunks_equals_run(sweep_ref):
+    probs, _ = sweep_ref
+    b = mln.Batch(probs, precision="fp64", snap_every=100, graph=False)
+    full = [_np(o) for o in b.run()]
+    b.reset()
+    for n in (1, 7, 33, 100, 59):
+        b.step(n)
+    out = [_np(o) for o in b.run()]
+    for i in range(len(probs)):
+        for key in ("probe", "e_snap", "pop"):
+            assert np.array_equal(out[i][key], full[i][key]), (i, key)
+    b.close()
+
+
+def test_autotuner_picks_a_valid_shape(sweep_ref):
+    probs, refs = sweep_ref
+    b = mln.Batch(probs, precision="fp32c", snap_every=100)
+    w, k = b.tune(trial_steps=64)
+    cfg = b.config()
+    print("tuned", w, k, cfg)
+    assert cfg["tile"] == w and cfg["steps_per_launch"] == k
+    assert 32 <= w <= 256 and w % 16 == 0 and 2 * k < w
+    assert cfg["workgroups"] == sum(-(-p.grid.nx // (w - 2 * k)) for p in probs)
+    outs = [_np(o) for o in b.run()]
+    b.close()
+    for i in range(len(probs)):
+        ee, ep = _errs(outs[i], refs[i])
+        assert ee < 1e-5 and ep < 1e-5
+
+
+def test_batch_errors():
+    probs = _small_sweep(n=2, nt=100)
+    bad = _small_sweep(n=2, nt=100)
+    bad[1].grid.nt = 90
+    bad[1].source.samples = bad[1].source.samples[:91]
+    with pytest.raises(mln.MLNError) as e:
+        mln.Batch(bad)
+    assert e.value.code == -1
+    with pytest.raises(mln.MLNError) as e:
+        mln.Batch([W.random_problem(4, 1, nx=100, nt=100)])
+    assert e.value.code == -8
+    with pytest.raises(mln.MLNError) as e:
+        mln.Batch(probs, precision="bf16x6")
+    assert e.value.code == -8
+    with pytest.raises(mln.MLNError) as e:
+        mln.Batch(probs, tile=100)
+    assert e.value.code == -1
+    # a problem stepped on its own leaves the lockstep
+    b = mln.Batch(probs, precision="fp64")
+    L = mln.load()
+    h = ctypes.c_void_p()
+    assert L.mln_batch_instance(b._h, 1, ctypes.byref(h)) == 0
+    assert L.mln_step(h, 3) == 0
+    with pytest.raises(mln.MLNError) as e:
+        b.run()
+    assert e.value.code == -10
+    b.reset()
+    b.run()
+    b.close()
+
+
+def test_full_sweep_64_instances(orc):
+    """The 64-problem sweep at full size (lengths 1000..30000 cells, 20000
+    steps, compensated FP32) after autotuning, through the graph.  The two
+    shortest problems (one of each level count) are checked against the
+    oracle over the whole run; all probes are finite."""
+    probs = W.batched_sweep()
+    nt = probs[0].grid.nt
+    b = mln.Batch(probs, precision="fp32c", snap_every=nt)
+    w, k = b.tune(trial_steps=256)
+    print("tuned", w, k, b.config(), flush=True)
+    outs = [_np(o) for o in b.run()]
+    b.close()
+    for o in outs:
+        assert np.all(np.isfinite(o["probe"]))
+    for n in (2, 3):
+        i = min((j for j, p in enumerate(probs) if p.medium.n_levels == n), key=lambda j: probs[j].grid.nx)
+        ref = orc.run(probs[i], snap_every=nt)
+        ee, ep = _errs(outs[i], ref)
+        print(f"inst {i} N={n} nx={probs[i].grid.nx} err_E={ee:.3e} err_pop={ep:.3e}")
+        assert ee < 1e-5 and ep < 1e-5
