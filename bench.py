@@ -2,22 +2,30 @@
 Neumann solver on one MI355X.
 
 One benchmark step = one complete simulation of the three-level ladder
-workload (20000 cells, medium on cells [1, 19999), 100000 time steps, pi
-Gaussian pulse, Lindblad decay and dephasing): state reset, every time step
-(H update, Strang Liouville step, dP/dt, E update, source and boundary) and
-the recording (probe every step, E and populations every 10000 steps).
-Factor set-up happens once before timing (as in the paper's protocol, which
-excludes construction and includes result storage).
+(N = 3: 20000 cells, medium on cells [1, 19999), 100000 time steps, pi
+Gaussian pulse, Lindblad decay and dephasing) in compensated single
+precision: state reset, every time step (H update, Strang Liouville step,
+dP/dt, E update, source and boundary) and the recording (probe every step,
+E and populations every 10000 steps, written to device memory).  The factors
+are built once before timing; the paper's protocol likewise excludes set-up
+and includes result storage.
 
-Prints ONE JSON line.  Extra keys:
-  roofline      dominant kernel (the fused tile kernel): algorithmic FLOP per
-                launch / average launch time from HIP events on the launch
-                stream, against the FP64 (or FP32) vector peak;
-  cpu_baseline  the FP64 oracle on the host cores, bounded sample;
-  paper_P       the paper's grid-point metric N_x N_t / t;
-  variants      other precisions / routes / sizes timed the same way.
+Prints ONE JSON line.  Keys beyond the common ones:
+  roofline      the dominant kernel (four-lanes-per-cell tile kernel, N = 3,
+                compensated FP32): algorithmic FLOP per launch (medium cells x
+                steps per launch x FLOP per cell-update) / average launch
+                duration (HIP events on the launch stream over the timed
+                region, divided by the number of launches), against the FP32
+                vector peak; traffic = HBM bytes per launch from rocprofv3
+                counters when they were taken on the current kernel sources
+  cpu_baseline  the FP64 oracle on the host cores, bounded sample
+  paper_P       the paper's grid-point metric N_x N_t / t
+  variants      the other precisions, routes and workloads, each timed the
+                same way (one warm-up, one timed run); reduced-precision runs
+                report their full-length deviation from the GPU FP64 run
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,6 +35,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12}
+CSRC = os.path.join(ROOT, "paper_1710_09799_amd", "csrc")
+# sources of the dominant kernel; the committed counter summary records their hash
+QUAD_SOURCES = ["fwd_quad.hpp", "fwd_impl.hpp", "fwd_kernels.hpp", "fwd_n3.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwd_quad_n3_fp32c_three_level_traffic.txt")
 
 
 def flops_per_update(n):
@@ -37,54 +49,172 @@ def flops_per_update(n):
     return 2 * D * D + 3 * D + 6 * q + 8
 
 
-def time_solver(problem, precision, route, steps, warmup, snap, spl=0, tile=0, per_launch=True):
+def source_hash(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, or None when it is missing or was taken on
+    other kernel sources."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if ":" in line:
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_source_sha256") != source_hash(QUAD_SOURCES):
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def time_solver(problem, steps, warmup, snap, keep=False, **kw):
+    """Time `steps` complete runs (reset + all time steps).  Returns wall time
+    per run, GPU time per run (HIP events on the launch stream), launches per
+    run and, with keep=True, the recorded outputs of the last run."""
     import torch
     from paper_1710_09799_amd import mln
-    s = mln.Solver(problem, precision=precision, route=route, snap_every=snap,
-                   steps_per_launch=spl, tile=tile)
+    s = mln.Solver(problem, snap_every=snap, **kw)
     for _ in range(warmup):
         s.reset()
         s.run()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    e0, e1 = _events()
+    wall = 0.0
+    gpu = 0.0
     for _ in range(steps):
         s.reset()
-        s.run()
-    torch.cuda.synchronize()
-    t = (time.perf_counter() - t0) / steps
-    launch_ms = None
-    halo = None
-    if per_launch:
-        # per-launch kernel time with HIP events on the launch stream
-        s.reset()
-        from paper_1710_09799_amd.mln import load
-        import ctypes
-        halo = spl if spl > 0 else 32
-        nl = min(200, problem.grid.nt // halo)
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nl)]
-        for a, b in evs:
-            a.record()
-            s.step(halo)
-            b.record()
         torch.cuda.synchronize()
-        launch_ms = sum(a.elapsed_time(b) for a, b in evs) / nl
+        t0 = time.perf_counter()
+        e0.record()
+        s.step(problem.grid.nt)
+        e1.record()
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        gpu += e0.elapsed_time(e1) * 1e-3
+    k = kw.get("steps_per_launch") or 32
+    out = None
+    if keep:
+        out = {key: (v.cpu().numpy() if v is not None else None) for key, v in s.outputs().items()}
     s.close()
-    return t, launch_ms, halo
+    launches = -(-problem.grid.nt // k)
+    return wall / steps, gpu / steps, launches, out
 
 
-def cpu_baseline(seconds_target=15.0):
+def rel_err(a, b):
+    import numpy as np
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def cpu_baseline(p, nt):
     import oracle
-    from paper_1710_09799_amd import workloads as W
-    p = W.three_level()
-    nt = 3000
+    threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or (os.cpu_count() or 1)
     t0 = time.perf_counter()
-    oracle.run(p, nt=nt)
+    oracle.run(p, nt=nt, nthreads=threads)
     dt = time.perf_counter() - t0
-    ups = p.grid.n_med * nt / dt
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": ups, "unit": "Liouville cell-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"three-level workload, full 20000-cell grid, first {nt} of 100000 steps, "
-                      f"FP64 density-matrix oracle with OpenMP over cells ({dt:.1f} s)"}
+    return {"value": p.grid.n_med * nt / dt, "unit": "Liouville cell-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"three-level ladder on the full 20000-cell grid, first {nt} of "
+                      f"{p.grid.nt} steps, FP64 density-matrix oracle, OpenMP over cells "
+                      f"({dt:.1f} s)"}
+
+
+def variants(p3, fp64_probe):
+    """The other configurations of the metric, one warm-up and one timed run
+    each."""
+    import numpy as np
+    from paper_1710_09799_amd import mln
+    from paper_1710_09799_amd import workloads as W
+    var = {}
+    n3 = p3.grid.n_med * p3.grid.nt
+    # N = 3: precisions on the four-lanes-per-cell kernel, and the paper's
+    # two routes (and the rotation form) on the one-cell-per-thread kernel
+    for name, kw in (("n3_fp32_quad", dict(precision="fp32", variant="quad", tile=128, steps_per_launch=16)),
+                     ("n3_fp64_block_rotation", dict(precision="fp64", variant="block", route="rotation",
+                                                     tile=256, steps_per_launch=32)),
+                     ("n3_fp64_block_diag", dict(precision="fp64", variant="block", route="diag",
+                                                 tile=256, steps_per_launch=32)),
+                     ("n3_fp64_block_rodrigues", dict(precision="fp64", variant="block", route="rodrigues",
+                                                      tile=256, steps_per_launch=32))):
+        t, g, nl, out = time_solver(p3, 1, 1, 10000, keep=True, **kw)
+        var[name] = {"value": n3 / t, "ms": t * 1e3, "launch_ms": g * 1e3 / nl,
+                     "err_E_vs_fp64": rel_err(out["probe"], fp64_probe), **kw}
+    # N = 6: six-level region, 50000 cells x 200000 steps
+    p6 = W.six_level()
+    n6 = p6.grid.n_med * p6.grid.nt
+    ref6 = None
+    for name, kw in (("n6_fp64", dict(precision="fp64", variant="block", tile=256, steps_per_launch=16)),
+                     ("n6_fp32", dict(precision="fp32", variant="block", tile=256, steps_per_launch=16)),
+                     ("n6_fp32c", dict(precision="fp32c", variant="block", tile=256, steps_per_launch=16)),
+                     ("n6_bf16x6_mfma", dict(precision="bf16x6", tile=256, steps_per_launch=16)),
+                     ("n6_bf16x3_mfma", dict(precision="bf16x3", tile=256, steps_per_launch=16))):
+        t, g, nl, out = time_solver(p6, 1, 1, 0, keep=True, record_pop=False, record_e=False, **kw)
+        rec = {"value": n6 / t, "ms": t * 1e3, "launch_ms": g * 1e3 / nl,
+               "tflops": n6 * flops_per_update(6) / g / 1e12, **kw}
+        if ref6 is None:
+            ref6 = out["probe"]
+        else:
+            rec["err_E_vs_fp64"] = rel_err(out["probe"], ref6)
+        var[name] = rec
+    var["n6_speedup_vs_fp64"] = {k: var[k]["value"] / var["n6_fp64"]["value"]
+                                 for k in ("n6_fp32", "n6_fp32c", "n6_bf16x6_mfma", "n6_bf16x3_mfma")}
+    # N = 2: the two-level 2-pi sech workload (2000 cells x 10000 steps, FP64)
+    p2 = W.two_level()
+    t, g, nl, _ = time_solver(p2, 1, 1, 1000, precision="fp64", variant="quad", tile=128, steps_per_launch=16)
+    var["n2_fp64_two_level"] = {"value": p2.grid.n_med * p2.grid.nt / t, "ms": t * 1e3,
+                                "launch_ms": g * 1e3 / nl}
+    # batched: 64 independent problems (N = 2 and 3 mixed, 1000..30000 cells,
+    # 20000 steps), autotuned tiles, whole run replayed from one HIP graph
+    import torch
+    probs = W.batched_sweep()
+    b = mln.Batch(probs, precision="fp32c", snap_every=0, record_pop=False, record_e=False)
+    tile, k = b.tune(trial_steps=256)
+    b.run()
+    b.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run()
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    cfg = b.config()
+    b.close()
+    nb = sum(p.grid.n_med for p in probs) * probs[0].grid.nt
+    var["batched_64_fp32c"] = {"value": nb / tb, "ms": tb * 1e3, "tile": tile, "steps_per_launch": k,
+                               "workgroups": cfg["workgroups"], "graph": True}
+    # adjoint: three-level ladder, 10000 cells x 50000 steps, checkpoints every 500
+    pa = W.adjoint_case()
+    s = mln.Solver(pa, precision="fp32c", ckpt_every=500, variant="quad", tile=128, steps_per_launch=16)
+    s.run()
+    s.grad(2 * pa.grid.dt * s.probe.cpu().numpy())  # warm-up (allocates the adjoint buffers)
+    s.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = s.run()
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    s.grad(2 * pa.grid.dt * out["probe"].cpu().numpy())
+    tg = time.perf_counter() - t0
+    s.close()
+    t_plain, _, _, _ = time_solver(pa, 1, 1, 0, precision="fp32c", variant="quad", tile=128, steps_per_launch=16,
+                                   record_pop=False, record_e=False)
+    var["adjoint_fp32c"] = {"forward_ms": t_plain * 1e3, "forward_with_checkpoints_ms": tf * 1e3,
+                            "grad_ms": tg * 1e3, "grad_over_forward": tg / t_plain,
+                            "total_over_forward": (tf + tg) / t_plain,
+                            "workload": "three-level ladder, 10000 cells, 50000 steps, checkpoint every 500"}
+    return var
 
 
 def main():
@@ -92,32 +222,38 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp64")
-    ap.add_argument("--route", default="rotation")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=10000,
+                    help="time steps of the oracle sample (full grid)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver has no multi-GPU path "
-              "(a 1-D domain decomposition is described in DESIGN.md); run with --gpus 1",
-              file=sys.stderr)
+              "(the 1-D domain decomposition it would use is described in the design notes); "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1710_09799_amd import workloads as W
     torch.cuda.init()
     p = W.three_level()
     n_upd = p.grid.n_med * p.grid.nt
-    t, launch_ms, halo = time_solver(p, args.precision, args.route, args.steps, args.warmup, snap=10000)
+    K = 16
+    kw = dict(precision="fp32c", variant="quad", tile=128, steps_per_launch=K)
+    t, gpu_t, launches, out = time_solver(p, args.steps, args.warmup, 10000, keep=True, **kw)
     value = n_upd / t
     fl = flops_per_update(p.medium.n_levels)
-    # units one launch processes: medium cells x steps per launch
-    per_launch_flop = p.grid.n_med * halo * fl
-    achieved = per_launch_flop / (launch_ms * 1e-3)
-    peak = PEAK["fp64" if args.precision == "fp64" else "fp32"]
-    out = {
-        "metric": "Liouville cell-updates/s (three-level ladder, N=3)",
+    launch_s = gpu_t / launches
+    # units one launch processes: every medium cell advanced by K steps
+    per_launch_flop = p.grid.n_med * K * fl
+    achieved = per_launch_flop / launch_s
+    peak = PEAK["fp32"]
+    traffic = measured_traffic()
+    res = {
+        "metric": "Liouville cell-updates/s at N=3,6 (FP32/split vs FP64); adjoint/forward cost",
         "value": value,
-        "unit": "cell-updates/s",
+        "unit": "Liouville cell-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -125,28 +261,40 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32"}.get(args.precision, args.precision),
+        "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "three-level ladder N=3, 20000 cells, 100000 steps, pi Gaussian pulse",
+        "config": {"workload": "three-level ladder N=3, 20000 cells (medium 19998), 100000 steps, "
+                               "pi Gaussian pulse 200 fs FWHM, Lindblad decay + dephasing",
                    "nx": p.grid.nx, "nt": p.grid.nt, "n_med": p.grid.n_med,
-                   "precision": args.precision, "route": args.route, "steps_per_launch": halo},
+                   "precision": "fp32c (FP32 with compensated float-float state)",
+                   "kernel": "four lanes per cell", "tile": 128, "steps_per_launch": K},
         "paper_P": p.grid.nx * p.grid.nt / t,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
-                     "kernel": "fwd_tile_kernel", "launch_ms": launch_ms,
-                     "flop_per_update": fl},
+                     "frac": achieved / peak, "traffic": traffic,
+                     "kernel": "fwd_quad_kernel<3,float,compensated>", "launch_us": launch_s * 1e6,
+                     "flop_per_update": fl, "updates_per_launch": p.grid.n_med * K},
     }
     if not args.no_variants:
-        var = {}
-        for prec in ("fp64", "fp32"):
-            if prec == args.precision:
-                continue
-            tv, lm, _ = time_solver(p, prec, args.route, 1, 1, snap=10000)
-            var[f"n3_{prec}"] = {"value": n_upd / tv, "ms": tv * 1e3, "launch_ms": lm}
-        out["variants"] = var
+        t64, g64, nl64, out64 = time_solver(p, 1, 1, 10000, keep=True, precision="fp64", variant="quad",
+                                            tile=128, steps_per_launch=K)
+        import numpy as np
+        e32 = np.concatenate([out["probe"], out["e_snap"].ravel()])
+        e64 = np.concatenate([out64["probe"], out64["e_snap"].ravel()])
+        res["err_vs_fp64"] = {"err_E": rel_err(e32, e64),
+                              "err_pop": float(np.max(np.abs(out["pop"] - out64["pop"])))}
+        var = {"n3_fp64_quad": {"value": n_upd / t64, "ms": t64 * 1e3, "launch_ms": g64 * 1e3 / nl64}}
+        var["n3_speedup_fp32c_vs_fp64"] = value / var["n3_fp64_quad"]["value"]
+        var.update(variants(p, out64["probe"]))
+        res["variants"] = var
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline()
-    print(json.dumps(out))
+        res["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
+    if args.calib_copy:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        res["calib_copy_bytes"] = x.numel() * 4
+    print(json.dumps(res))
 
 
 if __name__ == "__main__":

@@ -151,5 +151,10 @@ constexpr int adj_nacc(int N, bool fp64) {
 
 template <typename Real>
 hipError_t launch_adj(int N, const AdjArgs<Real> &a, int64_t nblocks, int W, hipStream_t st);
+// Four-lanes-per-cell adjoint kernel (adj_quad.hpp), N = 2 or 3, W <= 128
+// cells per tile (4 W lanes), the tiling of the forward four-lanes-per-cell
+// kernel.
+template <typename Real>
+hipError_t launch_adj_quad(int N, const AdjArgs<Real> &a, int64_t nblocks, int W, hipStream_t st);
 
 }  // namespace mln

@@ -616,7 +616,8 @@ int mln_grad(mln_handle *h, const double *dJ_dprobe, mln_grads *out) {
         a.ch = h->fd_coef[0]; a.ca = h->fd_coef[1]; a.cb = h->fd_coef[2]; a.inv_dx = h->fd_coef[3];
         a.kmur = h->fd_coef[4];
         a.partial = (double *)h->partial.p;
-        e = launch_adj<double>(N, a, h->ntiles, h->W, h->stream);
+        e = (h->quad && h->W <= 128) ? launch_adj_quad<double>(N, a, h->ntiles, h->W, h->stream)
+                    : launch_adj<double>(N, a, h->ntiles, h->W, h->stream);
       } else {
         AdjArgs<float> a{};
         a.fac = h->ff;
@@ -635,7 +636,8 @@ int mln_grad(mln_handle *h, const double *dJ_dprobe, mln_grads *out) {
         a.ch = (float)h->fd_coef[0]; a.ca = (float)h->fd_coef[1]; a.cb = (float)h->fd_coef[2];
         a.inv_dx = (float)h->fd_coef[3]; a.kmur = (float)h->fd_coef[4];
         a.partial = (double *)h->partial.p;
-        e = launch_adj<float>(N, a, h->ntiles, h->W, h->stream);
+        e = (h->quad && h->W <= 128) ? launch_adj_quad<float>(N, a, h->ntiles, h->W, h->stream)
+                    : launch_adj<float>(N, a, h->ntiles, h->W, h->stream);
       }
       if (e != hipSuccess) return set_err(MLN_EHIP, std::string("adjoint launch: ") + hipGetErrorString(e));
       lc = 1 - lc;
