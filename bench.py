@@ -158,6 +158,7 @@ def variants(p3, fp64_probe):
     for name, kw in (("n6_fp64", dict(precision="fp64", variant="block", tile=256, steps_per_launch=16)),
                      ("n6_fp32", dict(precision="fp32", variant="block", tile=256, steps_per_launch=16)),
                      ("n6_fp32c", dict(precision="fp32c", variant="block", tile=256, steps_per_launch=16)),
+                     ("n6_fp32cf", dict(precision="fp32cf", variant="block", tile=256, steps_per_launch=16)),
                      ("n6_bf16x6_mfma", dict(precision="bf16x6", tile=256, steps_per_launch=16)),
                      ("n6_bf16x3_mfma", dict(precision="bf16x3", tile=256, steps_per_launch=16))):
         t, g, nl, out = time_solver(p6, 1, 1, 0, keep=True, record_pop=False, record_e=False, **kw)
@@ -169,7 +170,7 @@ def variants(p3, fp64_probe):
             rec["err_E_vs_fp64"] = rel_err(out["probe"], ref6)
         var[name] = rec
     var["n6_speedup_vs_fp64"] = {k: var[k]["value"] / var["n6_fp64"]["value"]
-                                 for k in ("n6_fp32", "n6_fp32c", "n6_bf16x6_mfma", "n6_bf16x3_mfma")}
+                                 for k in ("n6_fp32", "n6_fp32c", "n6_fp32cf", "n6_bf16x6_mfma", "n6_bf16x3_mfma")}
     # N = 2: the two-level 2-pi sech workload (2000 cells x 10000 steps, FP64)
     p2 = W.two_level()
     t, g, nl, _ = time_solver(p2, 1, 1, 1000, precision="fp64", variant="quad", tile=128, steps_per_launch=16)
@@ -195,7 +196,8 @@ def variants(p3, fp64_probe):
                                "workgroups": cfg["workgroups"], "graph": True}
     # adjoint: three-level ladder, 10000 cells x 50000 steps, checkpoints every 500
     pa = W.adjoint_case()
-    s = mln.Solver(pa, precision="fp32c", ckpt_every=500, variant="quad", tile=128, steps_per_launch=16)
+    akw = dict(precision="fp32c", variant="quad", tile=64, steps_per_launch=16)
+    s = mln.Solver(pa, ckpt_every=500, **akw)
     s.run()
     s.grad(2 * pa.grid.dt * s.probe.cpu().numpy())  # warm-up (allocates the adjoint buffers)
     s.reset()
@@ -208,12 +210,12 @@ def variants(p3, fp64_probe):
     s.grad(2 * pa.grid.dt * out["probe"].cpu().numpy())
     tg = time.perf_counter() - t0
     s.close()
-    t_plain, _, _, _ = time_solver(pa, 1, 1, 0, precision="fp32c", variant="quad", tile=128, steps_per_launch=16,
-                                   record_pop=False, record_e=False)
+    t_plain, _, _, _ = time_solver(pa, 1, 1, 0, record_pop=False, record_e=False, **akw)
     var["adjoint_fp32c"] = {"forward_ms": t_plain * 1e3, "forward_with_checkpoints_ms": tf * 1e3,
                             "grad_ms": tg * 1e3, "grad_over_forward": tg / t_plain,
                             "total_over_forward": (tf + tg) / t_plain,
-                            "workload": "three-level ladder, 10000 cells, 50000 steps, checkpoint every 500"}
+                            "workload": "three-level ladder, 10000 cells, 50000 steps, checkpoint every 500",
+                            **akw}
     return var
 
 

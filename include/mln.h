@@ -55,13 +55,18 @@ extern "C" {
 typedef enum {
   MLN_FP64 = 0,           /* state, factors and arithmetic in double precision          */
   MLN_FP32 = 1,           /* plain single precision (fast, loses ~1e-4 over 1e4 steps)  */
-  MLN_FP32_COMP = 2,      /* single precision with a compensated (two-float) state and
-                             two-float factors                                          */
-  MLN_FP32_BF16SPLIT = 3, /* compensated FP32 state; the shared-factor transform runs on
-                             MFMA with three-part BF16 splits of both operands and six
-                             products (~2^-24 relative), FP32 accumulation; N = 4, 6   */
-  MLN_FP32_BF16X3 = 4     /* as MLN_FP32_BF16SPLIT with two-part splits and three
+  MLN_FP32_COMP = 2,      /* single precision with a compensated (two-float) Bloch-vector
+                             state and two-float factors; E and H in plain FP32        */
+  MLN_FP32_BF16SPLIT = 3, /* compensated FP32 state and fields; the shared-factor
+                             transform runs on MFMA with three-part BF16 splits of both
+                             operands and six products (~2^-24 relative), FP32
+                             accumulation; N = 4, 6                                     */
+  MLN_FP32_BF16X3 = 4,    /* as MLN_FP32_BF16SPLIT with two-part splits and three
                              products (~2^-16 relative)                                */
+  MLN_FP32_COMP_FIELDS = 5 /* as MLN_FP32_COMP, and E, H and the source samples are
+                             two-float pairs as well (for runs of 1e5 steps and more,
+                             where FP32 rounding of the fields accumulates); workgroup
+                             and four-lanes-per-cell kernels                            */
 } mln_precision;
 
 typedef enum {
@@ -233,7 +238,8 @@ const char *mln_last_error(void);
  *   media, grids, sources  arrays of n_inst descriptors (as for mln_init);
  *                          every grid has the same dt and nt; N = 2 or 3
  *   records                array of n_inst recordings, or NULL (none)
- *   options                precision MLN_FP64, MLN_FP32 or MLN_FP32_COMP;
+ *   options                precision MLN_FP64, MLN_FP32, MLN_FP32_COMP or
+ *                          MLN_FP32_COMP_FIELDS;
  *                          route MLN_ROUTE_ROTATION; variant 0 or 3;
  *                          ckpt_every 0; tile / steps_per_launch as for
  *                          mln_init (0: 128 cells, 16 steps); stream shared

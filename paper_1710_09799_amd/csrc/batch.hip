@@ -17,17 +17,23 @@ using namespace mln;
 namespace mln {
 
 template <typename Real>
-hipError_t launch_fwd_quad_batch(bool comp, int W, const BatchInst<Real> *inst, const BatchTile *tiles,
+hipError_t launch_fwd_quad_batch(bool comp, bool cf, int W, const BatchInst<Real> *inst, const BatchTile *tiles,
                                  int64_t nblocks, int64_t step0, int nsteps, int slot, hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
+  if (cf && !comp) return hipErrorInvalidValue;
   if (comp) {
-    if constexpr (std::is_same<Real, float>::value)
-      hipLaunchKernelGGL((fwd_quad_batch_kernel<float, true>), dim3((unsigned)nblocks), dim3(4 * W), 0, st, inst,
-                         tiles, step0, nsteps, slot);
-    else
+    if constexpr (std::is_same<Real, float>::value) {
+      if (cf)
+        hipLaunchKernelGGL((fwd_quad_batch_kernel<float, true, true>), dim3((unsigned)nblocks), dim3(4 * W), 0, st,
+                           inst, tiles, step0, nsteps, slot);
+      else
+        hipLaunchKernelGGL((fwd_quad_batch_kernel<float, true, false>), dim3((unsigned)nblocks), dim3(4 * W), 0, st,
+                           inst, tiles, step0, nsteps, slot);
+    } else {
       return hipErrorInvalidValue;
+    }
   } else {
-    hipLaunchKernelGGL((fwd_quad_batch_kernel<Real, false>), dim3((unsigned)nblocks), dim3(4 * W), 0, st, inst,
+    hipLaunchKernelGGL((fwd_quad_batch_kernel<Real, false, false>), dim3((unsigned)nblocks), dim3(4 * W), 0, st, inst,
                        tiles, step0, nsteps, slot);
   }
   return hipGetLastError();
@@ -38,7 +44,7 @@ hipError_t launch_fwd_quad_batch(bool comp, int W, const BatchInst<Real> *inst, 
 struct mln_batch {
   std::vector<mln_handle *> inst;  // owned
   int prec = MLN_FP32;
-  bool comp = false;
+  bool comp = false, cf = false;     // compensated state / fields
   hipStream_t stream = nullptr;       // the caller's stream
   hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
   int W = 0, halo = 0;
@@ -118,10 +124,10 @@ int configure(mln_batch *b, int W, int K) {
 int enqueue(mln_batch *b, int64_t step0, int k, int slot, hipStream_t st) {
   hipError_t e;
   if (b->prec == MLN_FP64)
-    e = launch_fwd_quad_batch<double>(false, b->W, (const BatchInst<double> *)b->dinst.p,
+    e = launch_fwd_quad_batch<double>(false, false, b->W, (const BatchInst<double> *)b->dinst.p,
                                       (const BatchTile *)b->dtiles.p, b->nblocks, step0, k, slot, st);
   else
-    e = launch_fwd_quad_batch<float>(b->comp, b->W, (const BatchInst<float> *)b->dinst.p,
+    e = launch_fwd_quad_batch<float>(b->comp, b->cf, b->W, (const BatchInst<float> *)b->dinst.p,
                                      (const BatchTile *)b->dtiles.p, b->nblocks, step0, k, slot, st);
   if (e != hipSuccess) return set_err(MLN_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
   return MLN_OK;
@@ -194,7 +200,8 @@ int mln_init_batch(int32_t n_inst, const mln_medium *media, const mln_grid *grid
   if (n_inst < 1 || !media || !grids || !sources) return set_err(MLN_EINVAL, "need n_inst >= 1 problems");
   mln_options opt{};
   if (options) opt = *options;
-  if (opt.precision != MLN_FP64 && opt.precision != MLN_FP32 && opt.precision != MLN_FP32_COMP)
+  if (opt.precision != MLN_FP64 && opt.precision != MLN_FP32 && opt.precision != MLN_FP32_COMP &&
+      opt.precision != MLN_FP32_COMP_FIELDS)
     return set_err(MLN_ENOTSUPPORTED, "batched launch: FP64, FP32 or compensated FP32");
   if (opt.route != MLN_ROUTE_ROTATION) return set_err(MLN_ENOTSUPPORTED, "batched launch: rotation route only");
   if (opt.variant != 0 && opt.variant != 3)
@@ -211,7 +218,8 @@ int mln_init_batch(int32_t n_inst, const mln_medium *media, const mln_grid *grid
   }
   std::unique_ptr<mln_batch> b(new mln_batch());
   b->prec = opt.precision;
-  b->comp = opt.precision == MLN_FP32_COMP;
+  b->comp = opt.precision == MLN_FP32_COMP || opt.precision == MLN_FP32_COMP_FIELDS;
+  b->cf = opt.precision == MLN_FP32_COMP_FIELDS;
   b->stream = (hipStream_t)opt.stream;
   b->nt = grids[0].nt;
   mln_options o = opt;

@@ -14,7 +14,7 @@
 
 namespace mln {
 
-template <typename Real, bool COMP>
+template <typename Real, bool COMP, bool CF>
 __global__ void __launch_bounds__(1024)
     fwd_quad_batch_kernel(const BatchInst<Real> *__restrict__ inst, const BatchTile *__restrict__ tiles,
                           int64_t step0, int nsteps, int slot) {
@@ -31,9 +31,9 @@ __global__ void __launch_bounds__(1024)
     a.snap_i0 = k;
   }
   if (bi.n_levels == 2)
-    quad_tile<2, Real, COMP>(a, bt.tile);
+    quad_tile<2, Real, COMP, CF>(a, bt.tile);
   else
-    quad_tile<3, Real, COMP>(a, bt.tile);
+    quad_tile<3, Real, COMP, CF>(a, bt.tile);
 }
 
 }  // namespace mln

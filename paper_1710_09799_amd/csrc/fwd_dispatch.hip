@@ -5,15 +5,15 @@ namespace mln {
 
 #define MLN_DECL(NN)                                                                              \
   template <typename Real>                                                                        \
-  hipError_t launch_fwd_n##NN(int route, bool comp, const FwdArgs<Real> &a, int64_t nblocks, int W, hipStream_t st); \
+  hipError_t launch_fwd_n##NN(int route, bool comp, bool cf, const FwdArgs<Real> &a, int64_t nblocks, int W, hipStream_t st); \
   template <typename Real>                                                                        \
   hipError_t launch_fwd_wave_n##NN(bool comp, int C, const FwdArgs<Real> &a, int64_t nblocks, hipStream_t st); \
   template <typename Real>                                                                        \
   hipError_t launch_bloch_n##NN(int route, bool comp, const BlochArgs<Real> &a, hipStream_t st);
 template <typename Real>
-hipError_t launch_fwd_quad_n2(bool comp, int W, const FwdArgs<Real> &a, int64_t nblocks, hipStream_t st);
+hipError_t launch_fwd_quad_n2(bool comp, bool cf, int W, const FwdArgs<Real> &a, int64_t nblocks, hipStream_t st);
 template <typename Real>
-hipError_t launch_fwd_quad_n3(bool comp, int W, const FwdArgs<Real> &a, int64_t nblocks, hipStream_t st);
+hipError_t launch_fwd_quad_n3(bool comp, bool cf, int W, const FwdArgs<Real> &a, int64_t nblocks, hipStream_t st);
 hipError_t launch_fwd_mfma_n4(int nprod, const FwdArgs<float> &a, int64_t nblocks, int W, hipStream_t st);
 hipError_t launch_fwd_mfma_n6(int nprod, const FwdArgs<float> &a, int64_t nblocks, int W, hipStream_t st);
 
@@ -37,12 +37,12 @@ MLN_DECL(6)
 #undef MLN_DECL
 
 template <typename Real>
-hipError_t launch_fwd(int N, int route, bool comp, const FwdArgs<Real> &a, int64_t nblocks, int W, hipStream_t st) {
+hipError_t launch_fwd(int N, int route, bool comp, bool cf, const FwdArgs<Real> &a, int64_t nblocks, int W, hipStream_t st) {
   switch (N) {
-    case 2: return launch_fwd_n2<Real>(route, comp, a, nblocks, W, st);
-    case 3: return launch_fwd_n3<Real>(route, comp, a, nblocks, W, st);
-    case 4: return launch_fwd_n4<Real>(route, comp, a, nblocks, W, st);
-    case 6: return launch_fwd_n6<Real>(route, comp, a, nblocks, W, st);
+    case 2: return launch_fwd_n2<Real>(route, comp, cf, a, nblocks, W, st);
+    case 3: return launch_fwd_n3<Real>(route, comp, cf, a, nblocks, W, st);
+    case 4: return launch_fwd_n4<Real>(route, comp, cf, a, nblocks, W, st);
+    case 6: return launch_fwd_n6<Real>(route, comp, cf, a, nblocks, W, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -73,16 +73,16 @@ template hipError_t launch_fwd_wave<double>(int, bool, int, const FwdArgs<double
 template hipError_t launch_fwd_wave<float>(int, bool, int, const FwdArgs<float> &, int64_t, hipStream_t);
 
 template <typename Real>
-hipError_t launch_fwd_quad(int N, bool comp, int W, const FwdArgs<Real> &a, int64_t nblocks, hipStream_t st) {
+hipError_t launch_fwd_quad(int N, bool comp, bool cf, int W, const FwdArgs<Real> &a, int64_t nblocks, hipStream_t st) {
   switch (N) {
-    case 2: return launch_fwd_quad_n2<Real>(comp, W, a, nblocks, st);
-    case 3: return launch_fwd_quad_n3<Real>(comp, W, a, nblocks, st);
+    case 2: return launch_fwd_quad_n2<Real>(comp, cf, W, a, nblocks, st);
+    case 3: return launch_fwd_quad_n3<Real>(comp, cf, W, a, nblocks, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template hipError_t launch_fwd_quad<double>(int, bool, int, const FwdArgs<double> &, int64_t, hipStream_t);
-template hipError_t launch_fwd_quad<float>(int, bool, int, const FwdArgs<float> &, int64_t, hipStream_t);
+template hipError_t launch_fwd_quad<double>(int, bool, bool, int, const FwdArgs<double> &, int64_t, hipStream_t);
+template hipError_t launch_fwd_quad<float>(int, bool, bool, int, const FwdArgs<float> &, int64_t, hipStream_t);
 
 template <typename Real>
 hipError_t launch_adj(int N, const AdjArgs<Real> &a, int64_t nblocks, int W, hipStream_t st) {
@@ -95,8 +95,8 @@ hipError_t launch_adj(int N, const AdjArgs<Real> &a, int64_t nblocks, int W, hip
 
 template hipError_t launch_adj<double>(int, const AdjArgs<double> &, int64_t, int, hipStream_t);
 template hipError_t launch_adj<float>(int, const AdjArgs<float> &, int64_t, int, hipStream_t);
-template hipError_t launch_fwd<double>(int, int, bool, const FwdArgs<double> &, int64_t, int, hipStream_t);
-template hipError_t launch_fwd<float>(int, int, bool, const FwdArgs<float> &, int64_t, int, hipStream_t);
+template hipError_t launch_fwd<double>(int, int, bool, bool, const FwdArgs<double> &, int64_t, int, hipStream_t);
+template hipError_t launch_fwd<float>(int, int, bool, bool, const FwdArgs<float> &, int64_t, int, hipStream_t);
 template hipError_t launch_bloch<double>(int, int, bool, const BlochArgs<double> &, hipStream_t);
 template hipError_t launch_bloch<float>(int, int, bool, const BlochArgs<float> &, hipStream_t);
 

@@ -387,14 +387,17 @@ __device__ __forceinline__ Real cell_step(const FacDev<Real> &f, const Real *sF,
   }
 }
 
-template <int N, typename Real, int ROUTE, bool COMP>
+// COMP: compensated (float-float) state; CF: E and H as float-float pairs too.
+template <int N, typename Real, int ROUTE, bool COMP, bool CF = false>
 __global__ void __launch_bounds__(kMaxTile) fwd_tile_kernel(FwdArgs<Real> a) {
+  static_assert(COMP || !CF, "compensated fields come with the compensated state");
   constexpr int D = N * N - 1;
   constexpr int DL = COMP ? D : 1;
-  __shared__ Real sE[kMaxTile];
-  __shared__ Real sH[kMaxTile];
-  __shared__ Real sSrc[kMaxStepsPerLaunch];
-  __shared__ Real sMur;
+  constexpr int FL = CF ? kMaxTile : 1;  // low parts of the exchanged fields
+  __shared__ Real sE[kMaxTile], sEl[FL];
+  __shared__ Real sH[kMaxTile], sHl[FL];
+  __shared__ Real sSrc[kMaxStepsPerLaunch], sSrcl[CF ? kMaxStepsPerLaunch : 1];
+  __shared__ Real sMur, sMurl;
   __shared__ Real sF[ROUTE == ROUTE_ROT ? RotLds<N, Real, COMP>::size : 1];
   __shared__ double sP[ROUTE == ROUTE_ROT ? N * (N * N - 1) + N : 1];
   if constexpr (ROUTE == ROUTE_ROT) {
@@ -412,11 +415,15 @@ __global__ void __launch_bounds__(kMaxTile) fwd_tile_kernel(FwdArgs<Real> a) {
   const bool owned = in_dom && lid >= a.halo && lid < a.halo + a.owned;
   const int64_t c = g - a.mb;
 
-  Real E = 0, H = 0;
+  Real E = 0, H = 0, Elo = 0, Hlo = 0;
   Real z[D], zl[DL];
   if (in_dom) {
     E = a.Ein[g];
     if (g < a.nx - 1) H = a.Hin[g];
+    if constexpr (CF) {
+      Elo = a.Ein[a.nx + g];
+      if (g < a.nx - 1) Hlo = a.Hin[a.nx + g];
+    }
   }
 #pragma unroll
   for (int j = 0; j < D; ++j) z[j] = is_med ? a.zin[j * a.ld + c] : Real(0);
@@ -424,17 +431,31 @@ __global__ void __launch_bounds__(kMaxTile) fwd_tile_kernel(FwdArgs<Real> a) {
   for (int j = 0; j < DL; ++j) zl[j] = (COMP && is_med) ? a.zin[(D + j) * a.ld + c] : Real(0);
 
   // source samples of this launch (read by the tile holding cell 0)
-  for (int i = threadIdx.x; i < a.nsteps; i += blockDim.x) sSrc[i] = a.src[a.step0 + 1 + i];
+  for (int i = threadIdx.x; i < a.nsteps; i += blockDim.x) {
+    sSrc[i] = a.src[a.step0 + 1 + i];
+    if constexpr (CF) sSrcl[i] = a.src[a.nt + 1 + a.step0 + 1 + i];
+  }
   __syncthreads();
   int64_t snap_next = a.snap_next, si = a.snap_i0;
   for (int s = 0; s < a.nsteps; ++s) {
     const int64_t n = a.step0 + s;
     const bool snap = n == snap_next;
     sE[lid] = E;
+    if constexpr (CF) sEl[lid] = Elo;
     __syncthreads();
     const Real Er = (lid + 1 < W) ? sE[lid + 1] : Real(0);
     const Real El = (lid > 0) ? sE[lid - 1] : Real(0);
-    if (in_dom && g < a.nx - 1) H += a.ch * (Er - E);
+    Real Erl = 0, Ell = 0;
+    if constexpr (CF) {
+      Erl = (lid + 1 < W) ? sEl[lid + 1] : Real(0);
+      Ell = (lid > 0) ? sEl[lid - 1] : Real(0);
+    }
+    if (in_dom && g < a.nx - 1) {
+      if constexpr (CF)
+        add_comp(H, Hlo, a.ch * ((Er - E) + (Erl - Elo)));
+      else
+        H += a.ch * (Er - E);
+    }
     Real P = 0;
     if (a.tape && owned && is_med && n >= a.tape_step0) {
       Real *tp = a.tape + (n - a.tape_step0) * (D + 1) * a.ld + c;
@@ -447,23 +468,40 @@ __global__ void __launch_bounds__(kMaxTile) fwd_tile_kernel(FwdArgs<Real> a) {
       P = cell_step<N, Real, ROUTE, COMP>(a.fac, sF, sP, E, z, zl, pp, a.me - a.mb, a.opaque0 * s);
     }
     sH[lid] = H;
+    if constexpr (CF) sHl[lid] = Hlo;
     __syncthreads();
     const Real Hl = (lid > 0) ? sH[lid - 1] : Real(0);
-    const Real Eold = E;
-    if (g >= 1 && g < a.nx - 1)
-      E = a.ca * E + a.cb * (-P + (H - Hl) * a.inv_dx);
-    else if (g == 0)
+    const Real Eold = E, Eoldl = Elo;
+    if (g >= 1 && g < a.nx - 1) {
+      if constexpr (CF) {
+        const Real Hll = (lid > 0) ? sHl[lid - 1] : Real(0);
+        add_comp(E, Elo, a.cam1 * E + a.cb * (-P + ((H - Hl) + (Hlo - Hll)) * a.inv_dx));
+      } else {
+        E = a.ca * E + a.cb * (-P + (H - Hl) * a.inv_dx);
+      }
+    } else if (g == 0) {
       E = sSrc[s];
+      if constexpr (CF) Elo = sSrcl[s];
+    }
     if (has_right) {  // first-order Mur boundary at cell nx-1
-      if (g == a.nx - 2) sMur = E;
+      if (g == a.nx - 2) {
+        sMur = E;
+        sMurl = Elo;
+      }
       __syncthreads();
       if (g == a.nx - 1) {
-        E = El + a.kmur * (sMur - Eold);
-        if (a.probe_out) a.probe_out[n + 1] = (double)E;
+        if constexpr (CF) {
+          E = El;
+          Elo = Ell;
+          add_comp(E, Elo, a.kmur * ((sMur - Eold) + (sMurl - Eoldl)));
+        } else {
+          E = El + a.kmur * (sMur - Eold);
+        }
+        if (a.probe_out) a.probe_out[n + 1] = (double)E + (double)Elo;
       }
     }
     if (snap) {
-      if (owned && a.e_out) a.e_out[si * a.nx + g] = (double)E;
+      if (owned && a.e_out) a.e_out[si * a.nx + g] = (double)E + (double)Elo;
       snap_next += a.snap_every;
       ++si;
     }
@@ -471,6 +509,10 @@ __global__ void __launch_bounds__(kMaxTile) fwd_tile_kernel(FwdArgs<Real> a) {
   if (owned) {
     a.Eout[g] = E;
     if (g < a.nx - 1) a.Hout[g] = H;
+    if constexpr (CF) {
+      a.Eout[a.nx + g] = Elo;
+      if (g < a.nx - 1) a.Hout[a.nx + g] = Hlo;
+    }
     if (is_med) {
 #pragma unroll
       for (int j = 0; j < D; ++j) a.zout[j * a.ld + c] = z[j];

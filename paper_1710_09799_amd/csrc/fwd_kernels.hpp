@@ -45,11 +45,16 @@ struct FwdArgs {
   Real *Hout;
   const Real *zin;
   Real *zout;
-  const Real *src;    // amplitude * samples[n], n = 0..nt
+  // Fields: E and H are nx values each; with compensated fields (CF) they
+  // are float-float pairs, nx high parts followed by nx low parts, and so is
+  // src.
+  const Real *src;    // amplitude * samples[n], n = 0..nt (then the low parts with CF)
   int64_t nx, mb, me, ld;
   int64_t step0;
   int nsteps, halo, owned;
   Real ch, ca, cb, inv_dx, kmur;
+  Real cam1;          // ca - 1 (rounded from the FP64 value)
+  int64_t nt;         // source samples src[0..nt]
   int64_t snap_every;
   int64_t snap_next;  // first step index n >= step0 that completes a snapshot ((n+1) % snap_every == 0)
   int64_t snap_i0;    // snapshot index of that step
@@ -98,9 +103,10 @@ struct BlochArgs {
 
 // comp = true selects the compensated single-precision state (float only,
 // rotation route only): z holds D rows of high parts followed by D rows of
-// low parts.
+// low parts.  cf = true (with comp) also carries E, H and the source samples
+// as float-float pairs.
 template <typename Real>
-hipError_t launch_fwd(int N, int route, bool comp, const FwdArgs<Real> &a, int64_t nblocks, int W,
+hipError_t launch_fwd(int N, int route, bool comp, bool cf, const FwdArgs<Real> &a, int64_t nblocks, int W,
                       hipStream_t st);
 template <typename Real>
 hipError_t launch_bloch(int N, int route, bool comp, const BlochArgs<Real> &a, hipStream_t st);
@@ -118,7 +124,8 @@ hipError_t launch_fwd_mfma(int N, int nprod, const FwdArgs<float> &a, int64_t nb
 // Four-lanes-per-cell tile kernel of the rotation route (fwd_quad.hpp), N <= 3;
 // W cells per tile (W in 64..256, multiple of 16), 4 W threads.
 template <typename Real>
-hipError_t launch_fwd_quad(int N, bool comp, int W, const FwdArgs<Real> &a, int64_t nblocks, hipStream_t st);
+hipError_t launch_fwd_quad(int N, bool comp, bool cf, int W, const FwdArgs<Real> &a, int64_t nblocks,
+                           hipStream_t st);
 
 // Batched launch (fwd_batch.hpp): per-problem arguments for reading from
 // ping-pong slot 0 and from slot 1 (step0, nsteps and the snapshot schedule
@@ -138,7 +145,7 @@ struct BatchTile {
 // nblocks workgroups of 4 W lanes.  Real = double (plain) or float (plain or
 // compensated).
 template <typename Real>
-hipError_t launch_fwd_quad_batch(bool comp, int W, const BatchInst<Real> *inst, const BatchTile *tiles,
+hipError_t launch_fwd_quad_batch(bool comp, bool cf, int W, const BatchInst<Real> *inst, const BatchTile *tiles,
                                  int64_t nblocks, int64_t step0, int nsteps, int slot, hipStream_t st);
 
 // Number of gradient accumulators per tile for N levels in precision Real:

@@ -65,15 +65,18 @@ __global__ void __launch_bounds__(256) fwd_mfma_kernel(FwdArgs<float> a) {
   static_assert(2 * MP <= REC, "result row fits in the record");
   extern __shared__ __align__(16) unsigned char smem[];
   unsigned short *sY = (unsigned short *)smem;  // record of cell c at sY + c * REC
-  __shared__ float sE[2][kMaxTile];
-  __shared__ float sMur;
-  __shared__ float sSrc[kMaxStepsPerLaunch];
+  __shared__ float sE[2][kMaxTile], sEl[2][kMaxTile];  // exchanged fields, high and low parts
+  __shared__ float sMur, sMurl;
+  __shared__ float sSrc[kMaxStepsPerLaunch], sSrcl[kMaxStepsPerLaunch];
   __shared__ double sP[N * D + N];
   using L = RotLds<N, float, true>;
   __shared__ float sF[L::size];
   L::stage(a.fac, sF);
   L::stage_pop(a.fac, sP);
-  for (int i = threadIdx.x; i < a.nsteps; i += blockDim.x) sSrc[i] = a.src[a.step0 + 1 + i];
+  for (int i = threadIdx.x; i < a.nsteps; i += blockDim.x) {
+    sSrc[i] = a.src[a.step0 + 1 + i];
+    sSrcl[i] = a.src[a.nt + 1 + a.step0 + 1 + i];
+  }
 
   const int lid = threadIdx.x;
   const int W = blockDim.x;
@@ -113,11 +116,16 @@ __global__ void __launch_bounds__(256) fwd_mfma_kernel(FwdArgs<float> a) {
       }
   __syncthreads();
 
-  float E = 0, H = 0;
+  // fields as float-float pairs (E, Elo), (H, Hlo)
+  float E = 0, H = 0, Elo = 0, Hlo = 0;
   float z[D], zl[D];
   if (in_dom) {
     E = a.Ein[g];
-    if (g < a.nx - 1) H = a.Hin[g];
+    Elo = a.Ein[a.nx + g];
+    if (g < a.nx - 1) {
+      H = a.Hin[g];
+      Hlo = a.Hin[a.nx + g];
+    }
   }
 #pragma unroll
   for (int j = 0; j < D; ++j) {
@@ -131,10 +139,13 @@ __global__ void __launch_bounds__(256) fwd_mfma_kernel(FwdArgs<float> a) {
     const bool snap = n == snap_next;
     const int b = s & 1;
     sE[b][lid] = E;
+    sEl[b][lid] = Elo;
     __syncthreads();
     const float Er = (lid + 1 < W) ? sE[b][lid + 1] : 0.0f;
     const float El = (lid > 0) ? sE[b][lid - 1] : 0.0f;
-    if (in_dom && g < a.nx - 1) H += a.ch * (Er - E);
+    const float Erl = (lid + 1 < W) ? sEl[b][lid + 1] : 0.0f;
+    const float Ell = (lid > 0) ? sEl[b][lid - 1] : 0.0f;
+    if (in_dom && g < a.nx - 1) add_comp(H, Hlo, a.ch * ((Er - E) + (Erl - Elo)));
     float P = 0.0f;
     if (tile_med && is_med) {
       if (a.tape && owned && n >= a.tape_step0) {
@@ -229,32 +240,45 @@ __global__ void __launch_bounds__(256) fwd_mfma_kernel(FwdArgs<float> a) {
 #pragma unroll
       for (int i = 0; i < D; ++i) add_comp(z[i], zl[i], res[i] + (sF[L::oc + i] + sF[L::ocl + i]));
     }
-    const float Eold = E;
+    const float Eold = E, Eoldl = Elo;
     // H of the face left of this cell comes from the neighbour (LDS)
     sE[b][lid] = H;
+    sEl[b][lid] = Hlo;
     __syncthreads();
     const float Hleft = (lid > 0) ? sE[b][lid - 1] : 0.0f;
-    if (g >= 1 && g < a.nx - 1)
-      E = a.ca * E + a.cb * (-P + (H - Hleft) * a.inv_dx);
-    else if (g == 0)
+    const float Hleftl = (lid > 0) ? sEl[b][lid - 1] : 0.0f;
+    if (g >= 1 && g < a.nx - 1) {
+      add_comp(E, Elo, a.cam1 * E + a.cb * (-P + ((H - Hleft) + (Hlo - Hleftl)) * a.inv_dx));
+    } else if (g == 0) {
       E = sSrc[s];
+      Elo = sSrcl[s];
+    }
     if (has_right) {
-      if (g == a.nx - 2) sMur = E;
+      if (g == a.nx - 2) {
+        sMur = E;
+        sMurl = Elo;
+      }
       __syncthreads();
       if (g == a.nx - 1) {
-        E = El + a.kmur * (sMur - Eold);
-        if (a.probe_out && owned) a.probe_out[n + 1] = (double)E;
+        E = El;
+        Elo = Ell;
+        add_comp(E, Elo, a.kmur * ((sMur - Eold) + (sMurl - Eoldl)));
+        if (a.probe_out && owned) a.probe_out[n + 1] = (double)E + (double)Elo;
       }
     }
     if (snap) {
-      if (owned && a.e_out) a.e_out[si * a.nx + g] = (double)E;
+      if (owned && a.e_out) a.e_out[si * a.nx + g] = (double)E + (double)Elo;
       snap_next += a.snap_every;
       ++si;
     }
   }
   if (owned) {
     a.Eout[g] = E;
-    if (g < a.nx - 1) a.Hout[g] = H;
+    a.Eout[a.nx + g] = Elo;
+    if (g < a.nx - 1) {
+      a.Hout[g] = H;
+      a.Hout[a.nx + g] = Hlo;
+    }
     if (is_med) {
 #pragma unroll
       for (int j = 0; j < D; ++j) {

@@ -7,11 +7,15 @@
 namespace mln {
 
 template <typename Real>
-hipError_t launch_fwd_n3(int route, bool comp, const FwdArgs<Real> &a, int64_t nblocks, int W, hipStream_t st) {
+hipError_t launch_fwd_n3(int route, bool comp, bool cf, const FwdArgs<Real> &a, int64_t nblocks, int W, hipStream_t st) {
+  if (cf && !comp) return hipErrorInvalidValue;
   if (comp) {
     if constexpr (std::is_same<Real, float>::value) {
       if (route != ROUTE_ROT) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((fwd_tile_kernel<3, float, ROUTE_ROT, true>), dim3((unsigned)nblocks), dim3(W), 0, st, a);
+      if (cf)
+        hipLaunchKernelGGL((fwd_tile_kernel<3, float, ROUTE_ROT, true, true>), dim3((unsigned)nblocks), dim3(W), 0, st, a);
+      else
+        hipLaunchKernelGGL((fwd_tile_kernel<3, float, ROUTE_ROT, true>), dim3((unsigned)nblocks), dim3(W), 0, st, a);
       return hipGetLastError();
     }
     return hipErrorInvalidValue;
@@ -65,12 +69,17 @@ hipError_t launch_fwd_wave_n3(bool comp, int C, const FwdArgs<Real> &a, int64_t 
 }
 
 template <typename Real>
-hipError_t launch_fwd_quad_n3(bool comp, int W, const FwdArgs<Real> &a, int64_t nblocks, hipStream_t st) {
+hipError_t launch_fwd_quad_n3(bool comp, bool cf, int W, const FwdArgs<Real> &a, int64_t nblocks, hipStream_t st) {
+  if (cf && !comp) return hipErrorInvalidValue;
   if (comp) {
-    if constexpr (std::is_same<Real, float>::value)
-      hipLaunchKernelGGL((fwd_quad_kernel<3, float, true>), dim3((unsigned)nblocks), dim3(4 * W), 0, st, a);
-    else
+    if constexpr (std::is_same<Real, float>::value) {
+      if (cf)
+        hipLaunchKernelGGL((fwd_quad_kernel<3, float, true, true>), dim3((unsigned)nblocks), dim3(4 * W), 0, st, a);
+      else
+        hipLaunchKernelGGL((fwd_quad_kernel<3, float, true>), dim3((unsigned)nblocks), dim3(4 * W), 0, st, a);
+    } else {
       return hipErrorInvalidValue;
+    }
   } else {
     hipLaunchKernelGGL((fwd_quad_kernel<3, Real, false>), dim3((unsigned)nblocks), dim3(4 * W), 0, st, a);
   }
@@ -105,12 +114,12 @@ hipError_t launch_adj_n3(const AdjArgs<Real> &a, int64_t nblocks, int W, hipStre
 
 template hipError_t launch_adj_n3<double>(const AdjArgs<double> &, int64_t, int, hipStream_t);
 template hipError_t launch_adj_n3<float>(const AdjArgs<float> &, int64_t, int, hipStream_t);
-template hipError_t launch_fwd_n3<double>(int, bool, const FwdArgs<double> &, int64_t, int, hipStream_t);
-template hipError_t launch_fwd_n3<float>(int, bool, const FwdArgs<float> &, int64_t, int, hipStream_t);
+template hipError_t launch_fwd_n3<double>(int, bool, bool, const FwdArgs<double> &, int64_t, int, hipStream_t);
+template hipError_t launch_fwd_n3<float>(int, bool, bool, const FwdArgs<float> &, int64_t, int, hipStream_t);
 template hipError_t launch_fwd_wave_n3<double>(bool, int, const FwdArgs<double> &, int64_t, hipStream_t);
 template hipError_t launch_fwd_wave_n3<float>(bool, int, const FwdArgs<float> &, int64_t, hipStream_t);
-template hipError_t launch_fwd_quad_n3<double>(bool, int, const FwdArgs<double> &, int64_t, hipStream_t);
-template hipError_t launch_fwd_quad_n3<float>(bool, int, const FwdArgs<float> &, int64_t, hipStream_t);
+template hipError_t launch_fwd_quad_n3<double>(bool, bool, int, const FwdArgs<double> &, int64_t, hipStream_t);
+template hipError_t launch_fwd_quad_n3<float>(bool, bool, int, const FwdArgs<float> &, int64_t, hipStream_t);
 template hipError_t launch_bloch_n3<double>(int, bool, const BlochArgs<double> &, hipStream_t);
 template hipError_t launch_bloch_n3<float>(int, bool, const BlochArgs<float> &, hipStream_t);
 

@@ -7,11 +7,15 @@
 namespace mln {
 
 template <typename Real>
-hipError_t launch_fwd_n4(int route, bool comp, const FwdArgs<Real> &a, int64_t nblocks, int W, hipStream_t st) {
+hipError_t launch_fwd_n4(int route, bool comp, bool cf, const FwdArgs<Real> &a, int64_t nblocks, int W, hipStream_t st) {
+  if (cf && !comp) return hipErrorInvalidValue;
   if (comp) {
     if constexpr (std::is_same<Real, float>::value) {
       if (route != ROUTE_ROT) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((fwd_tile_kernel<4, float, ROUTE_ROT, true>), dim3((unsigned)nblocks), dim3(W), 0, st, a);
+      if (cf)
+        hipLaunchKernelGGL((fwd_tile_kernel<4, float, ROUTE_ROT, true, true>), dim3((unsigned)nblocks), dim3(W), 0, st, a);
+      else
+        hipLaunchKernelGGL((fwd_tile_kernel<4, float, ROUTE_ROT, true>), dim3((unsigned)nblocks), dim3(W), 0, st, a);
       return hipGetLastError();
     }
     return hipErrorInvalidValue;
@@ -104,8 +108,8 @@ hipError_t launch_bloch_n4(int route, bool comp, const BlochArgs<Real> &a, hipSt
   return hipGetLastError();
 }
 
-template hipError_t launch_fwd_n4<double>(int, bool, const FwdArgs<double> &, int64_t, int, hipStream_t);
-template hipError_t launch_fwd_n4<float>(int, bool, const FwdArgs<float> &, int64_t, int, hipStream_t);
+template hipError_t launch_fwd_n4<double>(int, bool, bool, const FwdArgs<double> &, int64_t, int, hipStream_t);
+template hipError_t launch_fwd_n4<float>(int, bool, bool, const FwdArgs<float> &, int64_t, int, hipStream_t);
 template hipError_t launch_fwd_wave_n4<double>(bool, int, const FwdArgs<double> &, int64_t, hipStream_t);
 template hipError_t launch_fwd_wave_n4<float>(bool, int, const FwdArgs<float> &, int64_t, hipStream_t);
 template hipError_t launch_bloch_n4<double>(int, bool, const BlochArgs<double> &, hipStream_t);

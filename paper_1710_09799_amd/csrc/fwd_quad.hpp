@@ -63,13 +63,14 @@ __device__ __forceinline__ Real quad_sum(Real x) {
 
 // One tile (index `tile` of the problem described by `a`) on one workgroup of
 // 4 W lanes.
-template <int N, typename Real, bool COMP>
+template <int N, typename Real, bool COMP, bool CF>
 __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) {
+  static_assert(COMP || !CF, "compensated fields come with the compensated state");
   constexpr int D = N * N - 1, Q = N * (N - 1) / 2;
   static_assert(D <= 8, "four lanes of two components each");
-  __shared__ Real sE[2][kMaxQuadTile];
-  __shared__ Real sSrc[kMaxStepsPerLaunch];
-  __shared__ Real sMur;
+  __shared__ Real sE[2][kMaxQuadTile], sEl[2][CF ? kMaxQuadTile : 1];
+  __shared__ Real sSrc[kMaxStepsPerLaunch], sSrcl[CF ? kMaxStepsPerLaunch : 1];
+  __shared__ Real sMur, sMurl;
   const int t = threadIdx.x;
   const int r = t & 3;      // lane within the quad: state components 2r, 2r+1
   const int cl = t >> 2;    // cell within the tile
@@ -104,12 +105,19 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
   const Real th = rot ? cld(a.fac.thdt, r) : Real(0);
   const Real thl = (COMP && rot) ? cld(a.fac.th_lo, r) : Real(0);
 
-  Real E = 0, H = 0, Hl = 0;
+  // E, H and the private copy Hl of the face left of the cell; with CF each
+  // has a low part (Elo, Hlo, Hll)
+  Real E = 0, H = 0, Hl = 0, Elo = 0, Hlo = 0, Hll = 0;
   Real y0 = 0, y1 = 0, l0 = 0, l1 = 0;
   if (in_dom) {
     E = a.Ein[g];
     if (g <= a.nx - 2) H = a.Hin[g];
     if (g >= 1) Hl = a.Hin[g - 1];
+    if constexpr (CF) {
+      Elo = a.Ein[a.nx + g];
+      if (g <= a.nx - 2) Hlo = a.Hin[a.nx + g];
+      if (g >= 1) Hll = a.Hin[a.nx + g - 1];
+    }
   }
   if (is_med) {
     if (v0) y0 = a.zin[i0 * a.ld + c];
@@ -121,20 +129,38 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
   }
 
   // source samples of this launch (read by the tile holding cell 0)
-  for (int i = threadIdx.x; i < a.nsteps; i += blockDim.x) sSrc[i] = a.src[a.step0 + 1 + i];
+  for (int i = threadIdx.x; i < a.nsteps; i += blockDim.x) {
+    sSrc[i] = a.src[a.step0 + 1 + i];
+    if constexpr (CF) sSrcl[i] = a.src[a.nt + 1 + a.step0 + 1 + i];
+  }
   __syncthreads();
   int64_t snap_next = a.snap_next, si = a.snap_i0;
   for (int s = 0; s < a.nsteps; ++s) {
     const int64_t n = a.step0 + s;
     const bool snap = n == snap_next;
     const int b = s & 1;
-    if (r == 0) sE[b][cl] = E;
+    if (r == 0) {
+      sE[b][cl] = E;
+      if constexpr (CF) sEl[b][cl] = Elo;
+    }
     __syncthreads();
     const Real El = (cl > 0) ? sE[b][cl - 1] : Real(0);
     const Real Er = (cl + 1 < W) ? sE[b][cl + 1] : Real(0);
+    Real Ell = 0, Erl = 0;
+    if constexpr (CF) {
+      Ell = (cl > 0) ? sEl[b][cl - 1] : Real(0);
+      Erl = (cl + 1 < W) ? sEl[b][cl + 1] : Real(0);
+    }
     if (in_dom) {
-      if (g >= 1) Hl += a.ch * (E - El);
-      if (g <= a.nx - 2) H += a.ch * (Er - E);
+      // the private copy is updated with the operands and operations the
+      // left neighbour uses for its own face, so the two stay bitwise equal
+      if constexpr (CF) {
+        if (g >= 1) add_comp(Hl, Hll, a.ch * ((E - El) + (Elo - Ell)));
+        if (g <= a.nx - 2) add_comp(H, Hlo, a.ch * ((Er - E) + (Erl - Elo)));
+      } else {
+        if (g >= 1) Hl += a.ch * (E - El);
+        if (g <= a.nx - 2) H += a.ch * (Er - E);
+      }
     }
     Real P = 0;
     if (tile_med && is_med) {
@@ -214,21 +240,35 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
         y1 += a1;
       }
     }
-    const Real Eold = E;
-    if (g >= 1 && g <= a.nx - 2)
-      E = a.ca * E + a.cb * (-P + (H - Hl) * a.inv_dx);
-    else if (g == 0)
+    const Real Eold = E, Eoldl = Elo;
+    if (g >= 1 && g <= a.nx - 2) {
+      if constexpr (CF)
+        add_comp(E, Elo, a.cam1 * E + a.cb * (-P + ((H - Hl) + (Hlo - Hll)) * a.inv_dx));
+      else
+        E = a.ca * E + a.cb * (-P + (H - Hl) * a.inv_dx);
+    } else if (g == 0) {
       E = sSrc[s];
+      if constexpr (CF) Elo = sSrcl[s];
+    }
     if (has_right) {  // first-order Mur boundary at cell nx-1
-      if (g == a.nx - 2 && r == 0) sMur = E;
+      if (g == a.nx - 2 && r == 0) {
+        sMur = E;
+        sMurl = Elo;
+      }
       __syncthreads();
       if (g == a.nx - 1) {
-        E = El + a.kmur * (sMur - Eold);
-        if (a.probe_out && owned && r == 0) a.probe_out[n + 1] = (double)E;
+        if constexpr (CF) {
+          E = El;
+          Elo = Ell;
+          add_comp(E, Elo, a.kmur * ((sMur - Eold) + (sMurl - Eoldl)));
+        } else {
+          E = El + a.kmur * (sMur - Eold);
+        }
+        if (a.probe_out && owned && r == 0) a.probe_out[n + 1] = (double)E + (double)Elo;
       }
     }
     if (snap) {
-      if (owned && r == 0 && a.e_out) a.e_out[si * a.nx + g] = (double)E;
+      if (owned && r == 0 && a.e_out) a.e_out[si * a.nx + g] = (double)E + (double)Elo;
       snap_next += a.snap_every;
       ++si;
     }
@@ -237,6 +277,10 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
     if (r == 0) {
       a.Eout[g] = E;
       if (g <= a.nx - 2) a.Hout[g] = H;
+      if constexpr (CF) {
+        a.Eout[a.nx + g] = Elo;
+        if (g <= a.nx - 2) a.Hout[a.nx + g] = Hlo;
+      }
     }
     if (is_med) {
       if (v0) a.zout[i0 * a.ld + c] = y0;
@@ -249,9 +293,10 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
   }
 }
 
-template <int N, typename Real, bool COMP>
+// COMP: compensated (float-float) state; CF: E and H as float-float pairs too.
+template <int N, typename Real, bool COMP, bool CF = false>
 __global__ void __launch_bounds__(1024) fwd_quad_kernel(FwdArgs<Real> a) {
-  quad_tile<N, Real, COMP>(a, blockIdx.x);
+  quad_tile<N, Real, COMP, CF>(a, blockIdx.x);
 }
 
 }  // namespace mln

@@ -79,6 +79,7 @@ struct mln_handle {
   std::vector<double> samples;
   int prec = MLN_FP64, route = MLN_ROUTE_ROTATION;
   bool comp = false;  // compensated FP32 state (two floats per component)
+  bool cf = false;    // compensated FP32 fields and source samples (two floats each)
   int mfma = 0;       // split-BF16 products of the MFMA shared-factor kernel (6, 3) or 0
   hipStream_t stream = nullptr;
   int64_t nmed = 0, ld = 0, step = 0;
@@ -106,7 +107,7 @@ struct mln_handle {
   DevBuf ckpt;
   // adjoint buffers (allocated by the first mln_grad)
   DevBuf lE[2], lH[2], lz[2], tape, partial, gprobe, samples_dev;
-  double fd_coef[5] = {0, 0, 0, 0, 0};  // ch, ca, cb, inv_dx, kmur
+  double fd_coef[6] = {0, 0, 0, 0, 0, 0};  // ch, ca, cb, inv_dx, kmur, ca - 1
 };
 
 namespace mln {
@@ -143,6 +144,8 @@ inline FwdArgs<Real> make_args(mln_handle *h, const FacDev<Real> &fd, int64_t st
   a.cb = (Real)h->fd_coef[2];
   a.inv_dx = (Real)h->fd_coef[3];
   a.kmur = (Real)h->fd_coef[4];
+  a.cam1 = (Real)h->fd_coef[5];
+  a.nt = h->grid.nt;
   a.snap_every = record ? h->rec.snap_every : 0;
   // first step n >= step0 with (n+1) % snap_every == 0, and its snapshot index
   a.snap_next = -1;

@@ -103,8 +103,12 @@ void build_init_state(mln_handle *h) {
       zi[j * h->ld + c] = (Real)s0[j];
       if (h->comp) zi[(D + j) * h->ld + c] = (Real)(s0[j] - (double)(Real)s0[j]);
     }
-  h->e_init.assign(sizeof(Real) * h->grid.nx, 0);
-  ((Real *)h->e_init.data())[0] = (Real)(h->amp * h->samples[0]);
+  // E (and with the compensated state its low parts after nx high parts)
+  const int64_t nx = h->grid.nx;
+  h->e_init.assign(sizeof(Real) * (h->cf ? 2 : 1) * nx, 0);
+  const double e0 = h->amp * h->samples[0];
+  ((Real *)h->e_init.data())[0] = (Real)e0;
+  if (h->cf) ((Real *)h->e_init.data())[nx] = (Real)(e0 - (double)(Real)e0);
 }
 
 size_t state_slot_bytes(const mln_handle *h) { return h->E[0].bytes + h->H[0].bytes + h->z[0].bytes; }
@@ -142,15 +146,15 @@ int forward_steps(mln_handle *h, int64_t n, bool record, void *tape, int64_t tap
     hipError_t e;
     if (h->prec == MLN_FP64) {
       auto args = make_args<double>(h, h->fd, h->step, (int)k, record, (double *)tape, tape_step0);
-      e = h->quad   ? launch_fwd_quad<double>(h->f.N, false, h->W, args, h->ntiles, h->stream)
+      e = h->quad   ? launch_fwd_quad<double>(h->f.N, false, false, h->W, args, h->ntiles, h->stream)
           : h->wave ? launch_fwd_wave<double>(h->f.N, false, h->W / 64, args, h->ntiles, h->stream)
-                    : launch_fwd<double>(h->f.N, h->route, false, args, h->ntiles, h->W, h->stream);
+                    : launch_fwd<double>(h->f.N, h->route, false, false, args, h->ntiles, h->W, h->stream);
     } else {
       auto args = make_args<float>(h, h->ff, h->step, (int)k, record, (float *)tape, tape_step0);
       e = h->mfma   ? launch_fwd_mfma(h->f.N, h->mfma, args, h->ntiles, h->W, h->stream)
-          : h->quad ? launch_fwd_quad<float>(h->f.N, h->comp, h->W, args, h->ntiles, h->stream)
+          : h->quad ? launch_fwd_quad<float>(h->f.N, h->comp, h->cf, h->W, args, h->ntiles, h->stream)
           : h->wave ? launch_fwd_wave<float>(h->f.N, h->comp, h->W / 64, args, h->ntiles, h->stream)
-                    : launch_fwd<float>(h->f.N, h->route, h->comp, args, h->ntiles, h->W, h->stream);
+                    : launch_fwd<float>(h->f.N, h->route, h->comp, h->cf, args, h->ntiles, h->W, h->stream);
     }
     if (e != hipSuccess) return set_err(MLN_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
     h->cur = 1 - h->cur;
@@ -186,13 +190,19 @@ int init_typed(mln_handle *h, FacDev<Real> &fd) {
   if (rc) return rc;
   const int64_t nx = h->grid.nx;
   const int D = h->f.D;
-  std::vector<Real> src(h->grid.nt + 1);
-  for (int64_t i = 0; i <= h->grid.nt; ++i) src[i] = (Real)(h->amp * h->samples[i]);
+  // source samples (then their low parts with the compensated state)
+  const int64_t ns = h->grid.nt + 1;
+  std::vector<Real> src((h->cf ? 2 : 1) * ns);
+  for (int64_t i = 0; i < ns; ++i) {
+    const double v = h->amp * h->samples[i];
+    src[i] = (Real)v;
+    if (h->cf) src[ns + i] = (Real)(v - (double)(Real)v);
+  }
   HIP_TRY(h->src.alloc(src.size() * sizeof(Real)));
   HIP_TRY(hipMemcpy(h->src.p, src.data(), src.size() * sizeof(Real), hipMemcpyHostToDevice));
   for (int b = 0; b < 2; ++b) {
-    HIP_TRY(h->E[b].alloc(nx * sizeof(Real)));
-    HIP_TRY(h->H[b].alloc(nx * sizeof(Real)));
+    HIP_TRY(h->E[b].alloc((h->cf ? 2 : 1) * nx * sizeof(Real)));
+    HIP_TRY(h->H[b].alloc((h->cf ? 2 : 1) * nx * sizeof(Real)));
     HIP_TRY(h->z[b].alloc((size_t)(h->comp ? 2 * D : D) * h->ld * sizeof(Real)));
   }
   build_init_state<Real>(h);
@@ -202,10 +212,9 @@ int init_typed(mln_handle *h, FacDev<Real> &fd) {
 }  // namespace
 
 int mln::reset_state(mln_handle *h) {
-  const size_t rs = h->rs;
   for (int b = 0; b < 2; ++b) {
     HIP_TRY(hipMemsetAsync(h->H[b].p, 0, h->H[b].bytes, h->stream));
-    HIP_TRY(hipMemcpyAsync(h->E[b].p, h->e_init.data(), rs * h->grid.nx, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->E[b].p, h->e_init.data(), h->e_init.size(), hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipMemcpyAsync(h->z[b].p, h->z_init.data(), h->z_init.size(), hipMemcpyHostToDevice, h->stream));
   }
   h->cur = 0;
@@ -328,10 +337,11 @@ int mln_init(const mln_medium *medium, const mln_grid *grid, const mln_source *s
   h->stream = (hipStream_t)opt.stream;
   if (h->route < 0 || h->route > 2) return set_err(MLN_EINVAL, "unknown route");
   if (h->f.N == 5) return set_err(MLN_ENOTSUPPORTED, "kernels are built for N = 2, 3, 4 and 6");
-  if (h->prec < MLN_FP64 || h->prec > MLN_FP32_BF16X3)
+  if (h->prec < MLN_FP64 || h->prec > MLN_FP32_COMP_FIELDS)
     return set_err(MLN_ENOTSUPPORTED, "unknown precision");
   h->comp = h->prec >= MLN_FP32_COMP;
   h->mfma = h->prec == MLN_FP32_BF16SPLIT ? 6 : (h->prec == MLN_FP32_BF16X3 ? 3 : 0);
+  h->cf = h->prec == MLN_FP32_COMP_FIELDS || h->mfma;
   if (h->comp && h->route != MLN_ROUTE_ROTATION)
     return set_err(MLN_ENOTSUPPORTED, "the compensated FP32 state is built for the rotation route only");
   if (h->mfma && h->f.N != 4 && h->f.N != 6)
@@ -346,17 +356,20 @@ int mln_init(const mln_medium *medium, const mln_grid *grid, const mln_source *s
   h->fd_coef[2] = (grid->dt / eps) / (1.0 + sg);
   h->fd_coef[3] = 1.0 / grid->dx;
   h->fd_coef[4] = (cl * grid->dt - grid->dx) / (cl * grid->dt + grid->dx);
+  h->fd_coef[5] = -2.0 * sg / (1.0 + sg);
   // kernel variant and tiling
   if (opt.variant < 0 || opt.variant > 3) return set_err(MLN_EINVAL, "unknown kernel variant");
   const bool rot = h->route == MLN_ROUTE_ROTATION;
   int variant = opt.variant;
-  if (variant == 0) variant = !rot ? 1 : (h->f.N <= 3 ? 3 : (h->f.N == 4 ? 2 : 1));
+  if (variant == 0) variant = !rot ? 1 : (h->f.N <= 3 ? 3 : (h->f.N == 4 && !h->cf ? 2 : 1));
   if (h->mfma) {
     if (variant != 1 && opt.variant != 0)
       return set_err(MLN_ENOTSUPPORTED, "the split-BF16 MFMA kernel is a workgroup-tile kernel");
     variant = 1;
   }
   h->wave = variant == 2;
+  if (h->wave && h->cf)
+    return set_err(MLN_ENOTSUPPORTED, "the wavefront kernel keeps E and H in plain precision");
   h->quad = variant == 3;
   if ((h->wave || h->quad) && !rot)
     return set_err(MLN_ENOTSUPPORTED, "the wavefront and quad kernels implement the rotation route");
@@ -448,17 +461,24 @@ int mln_get_fields(mln_handle *h, double *E, double *H) {
   if (!h) return set_err(MLN_EINVAL, "null handle");
   HIP_TRY(hipStreamSynchronize(h->stream));
   const int64_t nx = h->grid.nx;
-  std::vector<unsigned char> buf(h->rs * nx);
+  const int parts = h->cf ? 2 : 1;  // high parts, then low parts
+  std::vector<unsigned char> buf(h->rs * nx * parts);
   auto conv = [&](double *dst, int64_t n) {
-    for (int64_t i = 0; i < n; ++i)
-      dst[i] = (h->rs == 8) ? ((double *)buf.data())[i] : (double)((float *)buf.data())[i];
+    for (int64_t i = 0; i < n; ++i) {
+      if (h->rs == 8) {
+        dst[i] = ((double *)buf.data())[i];
+      } else {
+        const float *f = (const float *)buf.data();
+        dst[i] = (double)f[i] + (parts == 2 ? (double)f[nx + i] : 0.0);
+      }
+    }
   };
   if (E) {
-    HIP_TRY(hipMemcpy(buf.data(), h->E[h->cur].p, h->rs * nx, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(buf.data(), h->E[h->cur].p, buf.size(), hipMemcpyDeviceToHost));
     conv(E, nx);
   }
   if (H) {
-    HIP_TRY(hipMemcpy(buf.data(), h->H[h->cur].p, h->rs * nx, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(buf.data(), h->H[h->cur].p, buf.size(), hipMemcpyDeviceToHost));
     conv(H, nx - 1);
   }
   return MLN_OK;

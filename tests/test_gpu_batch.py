@@ -40,7 +40,7 @@ def sweep_ref(orc):
     return probs, [orc.run(p, snap_every=100) for p in probs]
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32c", 1e-5), ("fp32", 1e-3)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32c", 1e-5), ("fp32cf", 1e-5), ("fp32", 1e-3)])
 @pytest.mark.parametrize("tile,k", [(128, 16), (64, 8)])
 def test_batch_equals_single_runs_and_oracle(sweep_ref, precision, tol, tile, k):
     probs, refs = sweep_ref
@@ -139,23 +139,33 @@ def test_batch_errors():
     b.close()
 
 
-def test_full_sweep_64_instances(orc):
-    """The 64-problem sweep at full size (lengths 1000..30000 cells, 20000
-    steps, compensated FP32) after autotuning, through the graph.  The two
-    shortest problems (one of each level count) are checked against the
-    oracle over the whole run; all probes are finite."""
+@pytest.fixture(scope="module")
+def full_sweep(orc):
+    """The 64-problem sweep at full size and the oracle runs of its two
+    shortest problems (one of each level count)."""
     probs = W.batched_sweep()
     nt = probs[0].grid.nt
-    b = mln.Batch(probs, precision="fp32c", snap_every=nt)
+    picks = [min((j for j, p in enumerate(probs) if p.medium.n_levels == n), key=lambda j: probs[j].grid.nx)
+             for n in (2, 3)]
+    return probs, {i: orc.run(probs[i], snap_every=nt) for i in picks}
+
+
+@pytest.mark.parametrize("precision", ["fp32c", "fp32cf"])
+def test_full_sweep_64_instances(full_sweep, precision):
+    """The 64-problem sweep at full size (lengths 1000..30000 cells, 20000
+    steps) after autotuning, through the graph.  The two shortest problems
+    are checked against the oracle over the whole run; all probes are
+    finite."""
+    probs, refs = full_sweep
+    nt = probs[0].grid.nt
+    b = mln.Batch(probs, precision=precision, snap_every=nt)
     w, k = b.tune(trial_steps=256)
     print("tuned", w, k, b.config(), flush=True)
     outs = [_np(o) for o in b.run()]
     b.close()
     for o in outs:
         assert np.all(np.isfinite(o["probe"]))
-    for n in (2, 3):
-        i = min((j for j, p in enumerate(probs) if p.medium.n_levels == n), key=lambda j: probs[j].grid.nx)
-        ref = orc.run(probs[i], snap_every=nt)
+    for i, ref in refs.items():
         ee, ep = _errs(outs[i], ref)
-        print(f"inst {i} N={n} nx={probs[i].grid.nx} err_E={ee:.3e} err_pop={ep:.3e}")
+        print(f"{precision} inst {i} N={probs[i].medium.n_levels} nx={probs[i].grid.nx} err_E={ee:.3e} err_pop={ep:.3e}")
         assert ee < 1e-5 and ep < 1e-5

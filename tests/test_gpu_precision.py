@@ -1,9 +1,11 @@
 """Reduced-precision paths against the FP64 oracle.
 
-Tolerances: compensated single precision ("fp32c") must meet 1e-5 on err_E
-and err_pop (the FP32 target); plain single precision ("fp32") is reported
-and held to a looser bound that documents its known drift (factor rounding
-accumulates linearly over the near-identity steps).
+Tolerances: compensated single precision ("fp32c": two-float Bloch vectors
+and factors; "fp32cf": E and H as two-float pairs as well) must meet 1e-5 on
+err_E and err_pop (the FP32 target); plain single precision ("fp32") is
+reported and held to a looser bound that documents its known drift (factor
+rounding accumulates linearly over the near-identity steps); split-BF16
+meets 1e-4.
 """
 import numpy as np
 import pytest
@@ -33,11 +35,12 @@ def two_level_ref(orc):
     return p, orc.run(p, snap_every=1000)
 
 
-def test_fp32c_three_level(three_level_ref):
+@pytest.mark.parametrize("precision,variant", [("fp32c", "auto"), ("fp32cf", "quad"), ("fp32cf", "block")])
+def test_fp32c_three_level(three_level_ref, precision, variant):
     p, ref = three_level_ref
-    got = mln.run(p, precision="fp32c", snap_every=500)
+    got = mln.run(p, precision=precision, variant=variant, snap_every=500)
     ee, ep = _errs(got, ref)
-    print(f"fp32c three_level err_E={ee:.3e} err_pop={ep:.3e}")
+    print(f"{precision} {variant} three_level err_E={ee:.3e} err_pop={ep:.3e}")
     assert ee < 1e-5 and ep < 1e-5
 
 
@@ -58,13 +61,14 @@ def test_fp32_plain_three_level(three_level_ref, route):
     assert ee < 1e-3 and ep < 1e-3
 
 
-def test_fp32c_small_random(orc):
+@pytest.mark.parametrize("precision", ["fp32c", "fp32cf"])
+def test_fp32c_small_random(orc, precision):
     for n, seed in ((2, 1), (3, 2), (4, 3), (6, 4)):
         p = W.random_problem(n, seed, nx=203, nt=360)
         ref = orc.run(p, snap_every=40)
-        got = mln.run(p, precision="fp32c", snap_every=40, tile=64, steps_per_launch=8)
+        got = mln.run(p, precision=precision, snap_every=40, tile=64, steps_per_launch=8)
         ee, ep = _errs(got, ref)
-        print(f"fp32c random n={n} err_E={ee:.3e} err_pop={ep:.3e}")
+        print(f"{precision} random n={n} err_E={ee:.3e} err_pop={ep:.3e}")
         assert ee < 1e-5 and ep < 1e-5
 
 
@@ -91,7 +95,8 @@ def six_level_ref(orc):
 
 
 @pytest.mark.parametrize("precision,variant,tol", [("fp64", "block", 1e-10), ("fp64", "wave", 1e-10),
-                                                   ("fp32c", "block", 1e-5), ("fp32", "block", 1e-5),
+                                                   ("fp32c", "block", 1e-5), ("fp32cf", "block", 1e-5),
+                                                   ("fp32", "block", 1e-5),
                                                    ("bf16x6", "block", 1e-4), ("bf16x3", "block", 1e-4)])
 def test_six_level_reduced(six_level_ref, precision, variant, tol):
     """Six-level (N = 6, D = 35) region at 1000 cells x 20000 steps: CW drive,
@@ -117,3 +122,27 @@ def test_split_bf16_mfma_small_random(orc, precision, n, seed, tile, k):
     ee, ep = _errs(got, ref)
     print(f"{precision} random n={n} tile={tile} err_E={ee:.3e} err_pop={ep:.3e}")
     assert ee < 1e-4 and ep < 1e-4
+
+
+def test_compensated_fields_long_run():
+    """Over 1e5 steps of continuous drive the FP32 rounding of E and H
+    accumulates; with two-float fields the deviation from the FP64 path (which
+    matches the oracle to 1e-10) stays below the FP32 tolerance and below the
+    plain-field deviation."""
+    p = W.six_level(nx=600, nt=100000)
+    ref = mln.run(p, precision="fp64", record_pop=False, record_e=False)["probe"]
+    errs = {}
+    for prec in ("fp32c", "fp32cf", "bf16x6"):
+        got = mln.run(p, precision=prec, record_pop=False, record_e=False)["probe"]
+        errs[prec] = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    print("long-run deviation from FP64:", errs)
+    assert errs["fp32cf"] < 1e-5
+    assert errs["fp32cf"] < errs["fp32c"]
+    assert errs["bf16x6"] < 1e-4
+
+
+def test_wave_kernel_rejects_compensated_fields():
+    p = W.random_problem(4, 3, nx=100, nt=50)
+    with pytest.raises(mln.MLNError) as e:
+        mln.Solver(p, precision="fp32cf", variant="wave", tile=64, steps_per_launch=8)
+    assert e.value.code == -8
