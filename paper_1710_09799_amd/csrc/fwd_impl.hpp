@@ -37,16 +37,26 @@ __device__ __forceinline__ T cld(const T *p, int i) {
 }
 
 // sin(x) and cos(x) - 1.  For |x| <= 1/2 (every cell-step of any practical
-// field: the per-step rotation angles are ~1e-2) the Taylor series of sine
-// and of cos - 1 are summed to the last bit of the type, which also avoids the
-// cancellation 1 - cos(x) suffers; the polynomial is evaluated in Estrin form
-// to shorten the dependency chain.  If any lane of the wavefront has a larger
-// angle, the whole wavefront takes the device math library path instead (a
-// wave-uniform branch, so the common path has no divergence).
+// field: the per-step rotation angles are ~1e-3 .. 1e-2) the Taylor series of
+// sine and of cos - 1 are summed to the last bit of the type, which also avoids
+// the cancellation 1 - cos(x) suffers: a short series when every angle of the
+// wavefront is below 1/16, a longer one (Estrin form) up to 1/2.  Beyond that
+// the whole wavefront takes the device math library path instead (each test is
+// wave-uniform, so the common path has no divergence).
 __device__ __forceinline__ bool wave_any(bool p) { return __any(p); }
 
 __device__ __forceinline__ void sincm1(double x, double &s, double &cm1) {
-  if (!wave_any(fabs(x) > 0.5)) {
+  if (!wave_any(fabs(x) > 0.0625)) {
+    // |x| <= 1/16: terms through x^9 (sine) and x^10 (cos - 1) leave a
+    // truncation below 1e-19 relative
+    const double x2 = x * x, x4 = x2 * x2;
+    const double s0 = fma(x2, -1.0 / 6.0, 1.0);
+    const double s1 = fma(x4, 1.0 / 362880.0, fma(x2, -1.0 / 5040.0, 1.0 / 120.0));
+    s = x * fma(x4, s1, s0);
+    const double c0 = fma(x2, 1.0 / 24.0, -0.5);
+    const double c1 = fma(x4, -1.0 / 3628800.0, fma(x2, 1.0 / 40320.0, -1.0 / 720.0));
+    cm1 = x2 * fma(x4, c1, c0);
+  } else if (!wave_any(fabs(x) > 0.5)) {
     const double x2 = x * x, x4 = x2 * x2, x8 = x4 * x4;
     // sin x = x (1 - x^2/3! + x^4/5! - ... - x^14/15! + x^16/17!)
     const double s0 = fma(x2, -1.0 / 6.0, 1.0);
@@ -72,7 +82,13 @@ __device__ __forceinline__ void sincm1(double x, double &s, double &cm1) {
 }
 
 __device__ __forceinline__ void sincm1(float x, float &s, float &cm1) {
-  if (!wave_any(fabsf(x) > 0.5f)) {
+  if (!wave_any(fabsf(x) > 0.0625f)) {
+    // |x| <= 1/16: sin x = x + x^3 (-1/3! + x^2/5!), cos x - 1 =
+    // x^2 (-1/2 + x^2 (1/4! - x^2/6!)); truncation below 1e-11 relative
+    const float x2 = x * x;
+    s = fmaf(x * x2, fmaf(x2, 1.0f / 120.0f, -1.0f / 6.0f), x);
+    cm1 = x2 * fmaf(x2, fmaf(x2, -1.0f / 720.0f, 1.0f / 24.0f), -0.5f);
+  } else if (!wave_any(fabsf(x) > 0.5f)) {
     const float x2 = x * x, x4 = x2 * x2;
     // sin x = x (1 - x^2/3! + x^4/5! - x^6/7! + x^8/9!)
     const float sa = fmaf(x2, -1.0f / 6.0f, 1.0f), sb = fmaf(x2, -1.0f / 5040.0f, 1.0f / 120.0f);

@@ -170,48 +170,47 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
         if (v1) tp[i1 * a.ld] = y1;
         if (r == 0) tp[D * a.ld] = E;
       }
-      // y'' = Rot(y) + (Rot - I) zr on this lane's pair
-      if (rot) {
-        Real sn, cm;
-        if constexpr (COMP)
-          sincm1(fmaf(th, E, thl * E), sn, cm);
-        else
-          sincm1(th * E, sn, cm);
-        const Real d0 = (cm * y0 + sn * y1) + (cm * zr0 + sn * zr1);
-        const Real d1 = (cm * y1 - sn * y0) + (cm * zr1 - sn * zr0);
-        if constexpr (COMP) {
-          add_comp(y0, l0, d0);
-          add_comp(y1, l1, d1);
-        } else {
-          y0 += d0;
-          y1 += d1;
-        }
-      }
+      // y'' = Rot(y) + (Rot - I) zr on this lane's pair; a lane without a
+      // pair has th = 0, so its increment is exactly zero (no divergence)
+      Real sn, cm;
+      if constexpr (COMP)
+        sincm1(fmaf(th, E, thl * E), sn, cm);
+      else
+        sincm1(th * E, sn, cm);
+      const Real d0 = (cm * y0 + sn * y1) + (cm * zr0 + sn * zr1);
+      const Real d1 = (cm * y1 - sn * y0) + (cm * zr1 - sn * zr0);
+      // high parts of y''; the rotation increment joins the shared-factor
+      // increment below in one compensated addition
+      const Real u0 = y0 + d0, u1 = y1 + d1;
       // gather y'' of the quad
       Real zz[8];
-      zz[0] = quad_bcast<0>(y0);
-      zz[1] = quad_bcast<0>(y1);
-      zz[2] = quad_bcast<1>(y0);
-      zz[3] = quad_bcast<1>(y1);
-      zz[4] = quad_bcast<2>(y0);
-      zz[5] = quad_bcast<2>(y1);
-      zz[6] = quad_bcast<3>(y0);
-      zz[7] = quad_bcast<3>(y1);
+      zz[0] = quad_bcast<0>(u0);
+      zz[1] = quad_bcast<0>(u1);
+      zz[2] = quad_bcast<1>(u0);
+      zz[3] = quad_bcast<1>(u1);
+      zz[4] = quad_bcast<2>(u0);
+      zz[5] = quad_bcast<2>(u1);
+      zz[6] = quad_bcast<3>(u0);
+      zz[7] = quad_bcast<3>(u1);
       if (snap && owned && a.pop_out) {
         // all four lanes take part in the broadcasts; lanes 0..N-1 each
-        // form the population of one level
+        // form the population of one level.  With COMP the low parts of
+        // y'' are l + the rounding error of y + d (two-sum).
         double ll[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) ll[j] = 0.0;
         if constexpr (COMP) {
-          ll[0] = (double)quad_bcast<0>(l0);
-          ll[1] = (double)quad_bcast<0>(l1);
-          ll[2] = (double)quad_bcast<1>(l0);
-          ll[3] = (double)quad_bcast<1>(l1);
-          ll[4] = (double)quad_bcast<2>(l0);
-          ll[5] = (double)quad_bcast<2>(l1);
-          ll[6] = (double)quad_bcast<3>(l0);
-          ll[7] = (double)quad_bcast<3>(l1);
+          const Real bb0 = u0 - y0, bb1 = u1 - y1;
+          const Real e0 = l0 + ((y0 - (u0 - bb0)) + (d0 - bb0));
+          const Real e1 = l1 + ((y1 - (u1 - bb1)) + (d1 - bb1));
+          ll[0] = (double)quad_bcast<0>(e0);
+          ll[1] = (double)quad_bcast<0>(e1);
+          ll[2] = (double)quad_bcast<1>(e0);
+          ll[3] = (double)quad_bcast<1>(e1);
+          ll[4] = (double)quad_bcast<2>(e0);
+          ll[5] = (double)quad_bcast<2>(e1);
+          ll[6] = (double)quad_bcast<3>(e0);
+          ll[7] = (double)quad_bcast<3>(e1);
         }
         if (r < N) {
           double acc = cld(a.fac.popc, r);
@@ -220,7 +219,7 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
           a.pop_out[si * N * nmed + (int64_t)r * nmed + c] = acc;
         }
       }
-      P = a.fac.p0 + quad_sum(w0 * y0 + w1 * y1);
+      P = a.fac.p0 + quad_sum(w0 * u0 + w1 * u1);
       // y_next = y'' + (K - I) y'' + constant, rows 2r and 2r+1
       Real a0 = c0, a1 = c1, b0 = c0l, b1 = c1l;
 #pragma unroll
@@ -233,11 +232,11 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
         }
       }
       if constexpr (COMP) {
-        add_comp(y0, l0, a0 + b0);
-        add_comp(y1, l1, a1 + b1);
+        add_comp(y0, l0, d0 + (a0 + b0));
+        add_comp(y1, l1, d1 + (a1 + b1));
       } else {
-        y0 += a0;
-        y1 += a1;
+        y0 = u0 + a0;
+        y1 = u1 + a1;
       }
     }
     const Real Eold = E, Eoldl = Elo;
