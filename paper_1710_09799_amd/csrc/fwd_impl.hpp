@@ -103,6 +103,31 @@ __device__ __forceinline__ void sincm1(float x, float &s, float &cm1) {
   }
 }
 
+// The same with the device-library path (|x| > 1/2 somewhere in the
+// wavefront) kept out of line: kernels whose register budget is tight do not
+// carry that path's registers through their step loop.
+__device__ __noinline__ void sincm1_library(float x, float &s, float &cm1) {
+  const float h = sinf(0.5f * x);
+  s = sinf(x);
+  cm1 = -2.0f * h * h;
+}
+
+__device__ __forceinline__ void sincm1_lean(float x, float &s, float &cm1) {
+  if (!wave_any(fabsf(x) > 0.0625f)) {
+    const float x2 = x * x;
+    s = fmaf(x * x2, fmaf(x2, 1.0f / 120.0f, -1.0f / 6.0f), x);
+    cm1 = x2 * fmaf(x2, fmaf(x2, -1.0f / 720.0f, 1.0f / 24.0f), -0.5f);
+  } else if (!wave_any(fabsf(x) > 0.5f)) {
+    const float x2 = x * x, x4 = x2 * x2;
+    const float sa = fmaf(x2, -1.0f / 6.0f, 1.0f), sb = fmaf(x2, -1.0f / 5040.0f, 1.0f / 120.0f);
+    s = x * fmaf(x4, fmaf(x4, 1.0f / 362880.0f, sb), sa);
+    const float ca = fmaf(x2, 1.0f / 24.0f, -0.5f), cb = fmaf(x2, 1.0f / 40320.0f, -1.0f / 720.0f);
+    cm1 = x2 * fmaf(x4, fmaf(x4, -1.0f / 3628800.0f, cb), ca);
+  } else {
+    sincm1_library(x, s, cm1);
+  }
+}
+
 // Two-float arithmetic for the compensated state (Knuth's two-sum, Dekker's
 // fast two-sum): hi + lo carries about 48 significant bits.
 __device__ __forceinline__ void add_comp(float &hi, float &lo, float d) {

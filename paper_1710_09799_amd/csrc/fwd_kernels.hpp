@@ -120,6 +120,10 @@ hipError_t launch_fwd_wave(int N, bool comp, int C, const FwdArgs<Real> &a, int6
 // the matrix cores, split-BF16 with NPROD = 6 or 3 products (fwd_mfma.hpp);
 // compensated FP32 state; N = 4 or 6; W = 64, 128 or 256 cells.
 hipError_t launch_fwd_mfma(int N, int nprod, const FwdArgs<float> &a, int64_t nblocks, int W, hipStream_t st);
+// The same transform with four lanes per cell (fwd_mfmaq.hpp): N = 4 or 6,
+// W cells per tile (multiple of 16, at most 256), 4 W lanes; compensated
+// state and fields.
+hipError_t launch_fwd_mfmaq(int N, int nprod, const FwdArgs<float> &a, int64_t nblocks, int W, hipStream_t st);
 
 // Four-lanes-per-cell tile kernel of the rotation route (fwd_quad.hpp), N <= 3;
 // W cells per tile (W in 64..256, multiple of 16), 4 W threads.

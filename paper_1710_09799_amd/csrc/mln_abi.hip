@@ -151,7 +151,8 @@ int forward_steps(mln_handle *h, int64_t n, bool record, void *tape, int64_t tap
                     : launch_fwd<double>(h->f.N, h->route, false, false, args, h->ntiles, h->W, h->stream);
     } else {
       auto args = make_args<float>(h, h->ff, h->step, (int)k, record, (float *)tape, tape_step0);
-      e = h->mfma   ? launch_fwd_mfma(h->f.N, h->mfma, args, h->ntiles, h->W, h->stream)
+      e = (h->mfma && h->quad) ? launch_fwd_mfmaq(h->f.N, h->mfma, args, h->ntiles, h->W, h->stream)
+          : h->mfma ? launch_fwd_mfma(h->f.N, h->mfma, args, h->ntiles, h->W, h->stream)
           : h->quad ? launch_fwd_quad<float>(h->f.N, h->comp, h->cf, h->W, args, h->ntiles, h->stream)
           : h->wave ? launch_fwd_wave<float>(h->f.N, h->comp, h->W / 64, args, h->ntiles, h->stream)
                     : launch_fwd<float>(h->f.N, h->route, h->comp, h->cf, args, h->ntiles, h->W, h->stream);
@@ -363,9 +364,10 @@ int mln_init(const mln_medium *medium, const mln_grid *grid, const mln_source *s
   int variant = opt.variant;
   if (variant == 0) variant = !rot ? 1 : (h->f.N <= 3 ? 3 : (h->f.N == 4 && !h->cf ? 2 : 1));
   if (h->mfma) {
-    if (variant != 1 && opt.variant != 0)
-      return set_err(MLN_ENOTSUPPORTED, "the split-BF16 MFMA kernel is a workgroup-tile kernel");
-    variant = 1;
+    // one cell per thread (1) or four lanes per cell (3, the default)
+    if (opt.variant == 0) variant = 3;
+    if (variant != 1 && variant != 3)
+      return set_err(MLN_ENOTSUPPORTED, "the split-BF16 MFMA kernels are workgroup-tile or four-lanes-per-cell kernels");
   }
   h->wave = variant == 2;
   if (h->wave && h->cf)
@@ -373,8 +375,9 @@ int mln_init(const mln_medium *medium, const mln_grid *grid, const mln_source *s
   h->quad = variant == 3;
   if ((h->wave || h->quad) && !rot)
     return set_err(MLN_ENOTSUPPORTED, "the wavefront and quad kernels implement the rotation route");
-  if (h->quad && h->f.N > 3) return set_err(MLN_ENOTSUPPORTED, "the quad kernel is built for N <= 3");
-  h->W = opt.tile > 0 ? opt.tile : (h->quad ? 128 : kMaxTile);
+  if (h->quad && h->f.N > 3 && !h->mfma)
+    return set_err(MLN_ENOTSUPPORTED, "the quad kernel is built for N <= 3 (N = 4, 6: split-BF16 precisions)");
+  h->W = opt.tile > 0 ? opt.tile : (h->quad && !h->mfma ? 128 : kMaxTile);
   if (h->quad) {
     if (h->W > kMaxQuadTile || h->W < 32 || h->W % 16)
       return set_err(MLN_EINVAL, "quad kernel tile must be a multiple of 16 in [32, 256]");
@@ -383,7 +386,8 @@ int mln_init(const mln_medium *medium, const mln_grid *grid, const mln_source *s
   }
   if (h->wave && (h->W == 192 || (h->f.N == 6 && h->W != 64)))
     return set_err(MLN_ENOTSUPPORTED, "wavefront kernel tiles: 64, 128 or 256 cells (64 for N = 6)");
-  int K = opt.steps_per_launch > 0 ? opt.steps_per_launch : (h->wave ? h->W / 8 : (h->quad ? h->W / 4 : 32));
+  int K = opt.steps_per_launch > 0 ? opt.steps_per_launch
+                                   : (h->wave ? h->W / 8 : (h->mfma ? 16 : (h->quad ? h->W / 4 : 32)));
   if (2 * K >= h->W || K > kMaxStepsPerLaunch)
     return set_err(MLN_EINVAL, "steps_per_launch must be below tile/2 (and at most 128)");
   h->halo = K;

@@ -97,7 +97,8 @@ def six_level_ref(orc):
 @pytest.mark.parametrize("precision,variant,tol", [("fp64", "block", 1e-10), ("fp64", "wave", 1e-10),
                                                    ("fp32c", "block", 1e-5), ("fp32cf", "block", 1e-5),
                                                    ("fp32", "block", 1e-5),
-                                                   ("bf16x6", "block", 1e-4), ("bf16x3", "block", 1e-4)])
+                                                   ("bf16x6", "block", 1e-4), ("bf16x3", "block", 1e-4),
+                                                   ("bf16x6", "quad", 1e-4), ("bf16x3", "quad", 1e-4)])
 def test_six_level_reduced(six_level_ref, precision, variant, tol):
     """Six-level (N = 6, D = 35) region at 1000 cells x 20000 steps: CW drive,
     15 Lindblad channels, every recorded E and population."""
@@ -109,18 +110,19 @@ def test_six_level_reduced(six_level_ref, precision, variant, tol):
     assert ee < tol and ep < tol
 
 
+@pytest.mark.parametrize("variant", ["block", "quad"])
 @pytest.mark.parametrize("precision", ["bf16x6", "bf16x3"])
 @pytest.mark.parametrize("n,seed", [(4, 3), (6, 4)])
 @pytest.mark.parametrize("tile,k", [(64, 8), (128, 32), (256, 50)])
-def test_split_bf16_mfma_small_random(orc, precision, n, seed, tile, k):
+def test_split_bf16_mfma_small_random(orc, precision, n, seed, tile, k, variant):
     """Shared-factor transform on the matrix cores (split-BF16, FP32
-    accumulation) for random media, several tiles and a ragged last tile;
-    split-BF16 tolerance 1e-4."""
+    accumulation) for random media, several tiles and a ragged last tile,
+    one cell per thread and four lanes per cell; split-BF16 tolerance 1e-4."""
     p = W.random_problem(n, seed, nx=203, nt=360)
     ref = orc.run(p, snap_every=40)
-    got = mln.run(p, precision=precision, snap_every=40, tile=tile, steps_per_launch=k)
+    got = mln.run(p, precision=precision, variant=variant, snap_every=40, tile=tile, steps_per_launch=k)
     ee, ep = _errs(got, ref)
-    print(f"{precision} random n={n} tile={tile} err_E={ee:.3e} err_pop={ep:.3e}")
+    print(f"{precision} {variant} random n={n} tile={tile} err_E={ee:.3e} err_pop={ep:.3e}")
     assert ee < 1e-4 and ep < 1e-4
 
 
