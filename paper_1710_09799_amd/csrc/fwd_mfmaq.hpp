@@ -97,7 +97,8 @@ __global__ void __launch_bounds__(4 * kMaxMfmaqTile) fwd_mfmaq_kernel(FwdArgs<fl
   unsigned short *sY = (unsigned short *)smem;  // record of cell c at sY + c * REC
   // parking area: float2 (slots 2 h, 2 h + 1) of lane t at sPark[h * 4 W + t]
   constexpr int NH = (USED + 1) / 2;
-  __shared__ float2 sE[2][kMaxMfmaqTile];  // (E, low part of E)
+  // (E, low part of E) of cell c at index c + 1; indices 0 and W + 1 stay zero
+  __shared__ float2 sE[2][kMaxMfmaqTile + 2];
   __shared__ float sSrc[kMaxStepsPerLaunch], sSrcl[kMaxStepsPerLaunch];
   __shared__ float sMur, sMurl;
   // per-slot constants (slot order): (reference state, polarisation weight,
@@ -131,6 +132,7 @@ __global__ void __launch_bounds__(4 * kMaxMfmaqTile) fwd_mfmaq_kernel(FwdArgs<fl
     sSrcl[i] = a.src[a.nt + 1 + a.step0 + 1 + i];
   }
   for (int k = t; k < W * REC; k += blockDim.x) sY[k] = 0;
+  if (t < 4) sE[t & 1][(t >> 1) ? W + 1 : 0] = make_float2(0.0f, 0.0f);
 
   const int64_t base = (int64_t)blockIdx.x * a.owned - a.halo;
   const int64_t g = base + cl;
@@ -201,10 +203,9 @@ __global__ void __launch_bounds__(4 * kMaxMfmaqTile) fwd_mfmaq_kernel(FwdArgs<fl
     const int64_t n = a.step0 + s;
     const bool snap = n == snap_next;
     const int b = s & 1;
-    if (r == 0) sE[b][cl] = make_float2(E, Elo);
+    if (r == 0) sE[b][cl + 1] = make_float2(E, Elo);
     __syncthreads();
-    const float2 eL = (cl > 0) ? sE[b][cl - 1] : make_float2(0.0f, 0.0f);
-    const float2 eR = (cl + 1 < W) ? sE[b][cl + 1] : make_float2(0.0f, 0.0f);
+    const float2 eL = sE[b][cl], eR = sE[b][cl + 2];
     const float El = eL.x, Ell = eL.y, Er = eR.x, Erl = eR.y;
     if (in_dom) {
       if (g >= 1) add_comp(Hl, Hll, a.ch * ((E - El) + (Elo - Ell)));

@@ -68,7 +68,8 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
   static_assert(COMP || !CF, "compensated fields come with the compensated state");
   constexpr int D = N * N - 1, Q = N * (N - 1) / 2;
   static_assert(D <= 8, "four lanes of two components each");
-  __shared__ Real sE[2][kMaxQuadTile], sEl[2][CF ? kMaxQuadTile : 1];
+  // exchanged E of cell c at index c + 1; indices 0 and W + 1 stay zero
+  __shared__ Real sE[2][kMaxQuadTile + 2], sEl[2][CF ? kMaxQuadTile + 2 : 1];
   __shared__ Real sSrc[kMaxStepsPerLaunch], sSrcl[CF ? kMaxStepsPerLaunch : 1];
   __shared__ Real sMur, sMurl;
   const int t = threadIdx.x;
@@ -133,6 +134,11 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
     sSrc[i] = a.src[a.step0 + 1 + i];
     if constexpr (CF) sSrcl[i] = a.src[a.nt + 1 + a.step0 + 1 + i];
   }
+  if (threadIdx.x < 4) {  // the zero pads of both exchange buffers
+    const int b = threadIdx.x & 1, i = (threadIdx.x >> 1) ? W + 1 : 0;
+    sE[b][i] = Real(0);
+    if constexpr (CF) sEl[b][i] = Real(0);
+  }
   __syncthreads();
   int64_t snap_next = a.snap_next, si = a.snap_i0;
   for (int s = 0; s < a.nsteps; ++s) {
@@ -140,16 +146,15 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
     const bool snap = n == snap_next;
     const int b = s & 1;
     if (r == 0) {
-      sE[b][cl] = E;
-      if constexpr (CF) sEl[b][cl] = Elo;
+      sE[b][cl + 1] = E;
+      if constexpr (CF) sEl[b][cl + 1] = Elo;
     }
     __syncthreads();
-    const Real El = (cl > 0) ? sE[b][cl - 1] : Real(0);
-    const Real Er = (cl + 1 < W) ? sE[b][cl + 1] : Real(0);
+    const Real El = sE[b][cl], Er = sE[b][cl + 2];
     Real Ell = 0, Erl = 0;
     if constexpr (CF) {
-      Ell = (cl > 0) ? sEl[b][cl - 1] : Real(0);
-      Erl = (cl + 1 < W) ? sEl[b][cl + 1] : Real(0);
+      Ell = sEl[b][cl];
+      Erl = sEl[b][cl + 2];
     }
     if (in_dom) {
       // the private copy is updated with the operands and operations the
