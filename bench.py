@@ -131,7 +131,7 @@ def cpu_baseline(p, nt):
                       f"({dt:.1f} s)"}
 
 
-def variants(p3, ref64):
+def variants(p3, ref64, pop64):
     """The other configurations of the metric, one warm-up and one timed run
     each."""
     import numpy as np
@@ -151,7 +151,8 @@ def variants(p3, ref64):
         t, g, nl, out = time_solver(p3, 1, 1, 10000, keep=True, **kw)
         e = np.concatenate([out["probe"], out["e_snap"].ravel()])
         var[name] = {"value": n3 / t, "ms": t * 1e3, "launch_ms": g * 1e3 / nl,
-                     "err_E_vs_fp64": rel_err(e, ref64), **kw}
+                     "err_E_vs_fp64": rel_err(e, ref64),
+                     "err_pop_vs_fp64": float(np.max(np.abs(out["pop"] - pop64))), **kw}
     # N = 6: six-level region, 50000 cells x 200000 steps
     p6 = W.six_level()
     n6 = p6.grid.n_med * p6.grid.nt
@@ -287,7 +288,7 @@ def main():
                               "err_pop": float(np.max(np.abs(out["pop"] - out64["pop"])))}
         var = {"n3_fp64_quad": {"value": n_upd / t64, "ms": t64 * 1e3, "launch_ms": g64 * 1e3 / nl64}}
         var["n3_speedup_fp32c_vs_fp64"] = value / var["n3_fp64_quad"]["value"]
-        var.update(variants(p, e64))
+        var.update(variants(p, e64, out64["pop"]))
         res["variants"] = var
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
