@@ -38,7 +38,10 @@ PEAK = {"fp64": 78.6e12, "fp32": 157.3e12}
 CSRC = os.path.join(ROOT, "paper_1710_09799_amd", "csrc")
 # sources of the dominant kernel; the committed counter summary records their hash
 QUAD_SOURCES = ["fwd_quad.hpp", "fwd_impl.hpp", "fwd_kernels.hpp", "fwd_n3.hip"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwd_quad_n3_fp32c_three_level_traffic.txt")
+
+
+def traffic_file(precision):
+    return os.path.join(ROOT, "profiles", f"fwd_quad_n3_{precision}_three_level_traffic.txt")
 
 
 def flops_per_update(n):
@@ -57,13 +60,13 @@ def source_hash(files):
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(precision):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 counter summary, or None when it is missing or was taken on
     other kernel sources."""
     try:
         kv = {}
-        with open(TRAFFIC_FILE) as fh:
+        with open(traffic_file(precision)) as fh:
             for line in fh:
                 if ":" in line:
                     k, v = line.split(":", 1)
@@ -131,7 +134,7 @@ def cpu_baseline(p, nt):
                       f"({dt:.1f} s)"}
 
 
-def variants(p3, ref64, pop64):
+def variants(p3, ref64, pop64, headline):
     """The other configurations of the metric, one warm-up and one timed run
     each."""
     import numpy as np
@@ -141,7 +144,9 @@ def variants(p3, ref64, pop64):
     n3 = p3.grid.n_med * p3.grid.nt
     # N = 3: precisions on the four-lanes-per-cell kernel, and the paper's
     # two routes (and the rotation form) on the one-cell-per-thread kernel
-    for name, kw in (("n3_fp32_quad", dict(precision="fp32", variant="quad", tile=128, steps_per_launch=20)),
+    others = [pr for pr in ("fp32", "fp32c", "fp32cf") if pr != headline]
+    for name, kw in tuple((f"n3_{pr}_quad", dict(precision=pr, variant="quad", tile=128, steps_per_launch=20))
+                          for pr in others) + (
                      ("n3_fp64_block_rotation", dict(precision="fp64", variant="block", route="rotation",
                                                      tile=256, steps_per_launch=32)),
                      ("n3_fp64_block_diag", dict(precision="fp64", variant="block", route="diag",
@@ -198,7 +203,7 @@ def variants(p3, ref64, pop64):
                                "workgroups": cfg["workgroups"], "graph": True}
     # adjoint: three-level ladder, 10000 cells x 50000 steps, checkpoints every 500
     pa = W.adjoint_case()
-    akw = dict(precision="fp32c", variant="quad", tile=64, steps_per_launch=16)
+    akw = dict(precision="fp32c", variant="quad", tile=128, steps_per_launch=32)
     s = mln.Solver(pa, ckpt_every=500, **akw)
     s.run()
     s.grad(2 * pa.grid.dt * s.probe.cpu().numpy())  # warm-up (allocates the adjoint buffers)
@@ -230,6 +235,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=10000,
                     help="time steps of the oracle sample (full grid)")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32c", "fp32cf"],
+                    help="precision of the headline run (the others are reported as variants)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -244,7 +251,7 @@ def main():
     p = W.three_level()
     n_upd = p.grid.n_med * p.grid.nt
     K = 20
-    kw = dict(precision="fp32c", variant="quad", tile=128, steps_per_launch=K)
+    kw = dict(precision=args.precision, variant="quad", tile=128, steps_per_launch=K)
     t, gpu_t, launches, out = time_solver(p, args.steps, args.warmup, 10000, keep=True, **kw)
     value = n_upd / t
     fl = flops_per_update(p.medium.n_levels)
@@ -253,7 +260,7 @@ def main():
     per_launch_flop = p.grid.n_med * K * fl
     achieved = per_launch_flop / launch_s
     peak = PEAK["fp32"]
-    traffic = measured_traffic()
+    traffic = measured_traffic(args.precision)
     res = {
         "metric": "Liouville cell-updates/s at N=3,6 (FP32/split vs FP64); adjoint/forward cost",
         "value": value,
@@ -270,12 +277,14 @@ def main():
         "config": {"workload": "three-level ladder N=3, 20000 cells (medium 19998), 100000 steps, "
                                "pi Gaussian pulse 200 fs FWHM, Lindblad decay + dephasing",
                    "nx": p.grid.nx, "nt": p.grid.nt, "n_med": p.grid.n_med,
-                   "precision": "fp32c (FP32 with compensated float-float state)",
+                   "precision": {"fp32": "fp32 (single precision, deviation form)",
+                                 "fp32c": "fp32c (FP32 with compensated float-float state)",
+                                 "fp32cf": "fp32cf (compensated state and fields)"}[args.precision],
                    "kernel": "four lanes per cell", "tile": kw["tile"], "steps_per_launch": K},
         "paper_P": p.grid.nx * p.grid.nt / t,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
-                     "kernel": "fwd_quad_kernel<3,float,compensated>", "launch_us": launch_s * 1e6,
+                     "kernel": f"fwd_quad_kernel<3,float,{args.precision}>", "launch_us": launch_s * 1e6,
                      "flop_per_update": fl, "updates_per_launch": p.grid.n_med * K},
     }
     if not args.no_variants:
@@ -285,10 +294,12 @@ def main():
         e32 = np.concatenate([out["probe"], out["e_snap"].ravel()])
         e64 = np.concatenate([out64["probe"], out64["e_snap"].ravel()])
         res["err_vs_fp64"] = {"err_E": rel_err(e32, e64),
-                              "err_pop": float(np.max(np.abs(out["pop"] - out64["pop"])))}
+                              "err_pop": float(np.max(np.abs(out["pop"] - out64["pop"]))),
+                              "note": "full-length deviation from the FP64 GPU path, which matches the "
+                                      "oracle to 1e-10 on every parity shape"}
         var = {"n3_fp64_quad": {"value": n_upd / t64, "ms": t64 * 1e3, "launch_ms": g64 * 1e3 / nl64}}
-        var["n3_speedup_fp32c_vs_fp64"] = value / var["n3_fp64_quad"]["value"]
-        var.update(variants(p, e64, out64["pop"]))
+        var[f"n3_speedup_{args.precision}_vs_fp64"] = value / var["n3_fp64_quad"]["value"]
+        var.update(variants(p, e64, out64["pop"], args.precision))
         res["variants"] = var
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)

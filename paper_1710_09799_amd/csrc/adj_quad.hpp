@@ -16,7 +16,9 @@
 // every step come from the tape written by the forward kernel's recomputation
 // of the segment.  The quad gathers the full vectors it needs (lz', z'',
 // zhat) with DPP broadcasts.  The adjoint Yee updates are replicated in the
-// four lanes; the adjoint E and H are exchanged through LDS.
+// four lanes; the adjoint E is exchanged through LDS (one barrier per step,
+// double-buffered) and the adjoint H of the face left of each cell is a
+// private copy kept bitwise equal to the neighbour's.
 // The accumulator order is that of the one-cell-per-thread adjoint kernel
 // (dJ/dK, dJ/dc, dJ/dw, dJ/dp0, dJ/damplitude, Gamma_1, Gamma_3[, Gamma_5]);
 // each tile adds its sums to partial[tile][*].
@@ -36,8 +38,9 @@ __global__ void __launch_bounds__(4 * kMaxAdjQuadTile) adj_quad_kernel(AdjArgs<R
   constexpr int NM = adj_moments(F64);
   constexpr int NACC = adj_nacc(N, F64);
   constexpr int kMaxWaves = 4 * kMaxAdjQuadTile / 64;
-  __shared__ Real sE[kMaxAdjQuadTile];
-  __shared__ Real sH[kMaxAdjQuadTile];
+  // exchanged adjoint E of cell c at sE[b][c + 1] (double-buffered); indices
+  // 0, W + 1 and W + 2 stay zero
+  __shared__ Real sE[2][kMaxAdjQuadTile + 3];
   __shared__ double sG[kMaxStepsPerLaunch], sS[kMaxStepsPerLaunch];
   __shared__ double sRed[kMaxWaves][NACC];
 
@@ -67,10 +70,13 @@ __global__ void __launch_bounds__(4 * kMaxAdjQuadTile) adj_quad_kernel(AdjArgs<R
   const Real zr0 = v0 ? cld(a.fac.zr, i0) : Real(0), zr1 = v1 ? cld(a.fac.zr, i1) : Real(0);
   const Real th = rot ? cld(a.fac.thdt, r) : Real(0);
 
-  Real lE = 0, lH = 0, lz0 = 0, lz1 = 0;
+  // lHl: private copy of the adjoint H of the face left of the cell, updated
+  // with the operands and operations the left neighbour uses for its own
+  Real lE = 0, lH = 0, lHl = 0, lz0 = 0, lz1 = 0;
   if (in_dom) {
     lE = a.lEin[g];
     if (g < a.nx - 1) lH = a.lHin[g];
+    if (g >= 1) lHl = a.lHin[g - 1];
   }
   if (is_med) {
     if (v0) lz0 = a.lzin[i0 * a.ld + c];
@@ -93,14 +99,37 @@ __global__ void __launch_bounds__(4 * kMaxAdjQuadTile) adj_quad_kernel(AdjArgs<R
     sG[i] = a.gprobe[a.n_hi - i];
     sS[i] = a.samples[a.n_hi - i];
   }
+  if (t < 6) sE[t & 1][t < 2 ? 0 : (t < 4 ? W + 1 : W + 2)] = Real(0);
+  // tape values (y' of this lane's rows and E) of the step being reversed,
+  // loaded one step ahead so that their memory latency overlaps the work
+  Real ty0 = 0, ty1 = 0, tE = 0;
+  auto tape_load = [&](int64_t nn) {
+    if (is_med && a.nsteps > 0 && nn >= a.tape_step0) {
+      const Real *tp = a.tape + (nn - a.tape_step0) * (D + 1) * a.ld + c;
+      ty0 = v0 ? tp[i0 * a.ld] : Real(0);
+      ty1 = v1 ? tp[i1 * a.ld] : Real(0);
+      tE = tp[D * a.ld];
+    }
+  };
+  tape_load(a.n_hi - 1);
   __syncthreads();
   for (int s = 0; s < a.nsteps; ++s) {
     const int64_t n = a.n_hi - 1 - s;
     if (g == a.nx - 1) lE += (Real)sG[s];
-    if (r == 0) sE[cl] = lE;
-    __syncthreads();
-    const Real lEr = (cl + 1 < W) ? sE[cl + 1] : Real(0);
-    const Real lErr = (cl + 2 < W) ? sE[cl + 2] : Real(0);
+    const int b = s & 1;
+    if (r == 0) sE[b][cl + 1] = lE;
+    lds_barrier();
+    const Real lEl = sE[b][cl], lEr = sE[b][cl + 2], lErr = sE[b][cl + 3];
+    // the left neighbour's own H update (its lEe and lEre from lEl, lE, lEr)
+    {
+      Real lEeL = lEl, lEreL = lE;
+      if (g - 1 == a.nx - 2) lEeL += a.kmur * lE;
+      if (g - 1 == a.nx - 3) lEreL += a.kmur * lEr;
+      if (g >= 1 && g <= a.nx - 1) {
+        if (g >= 2) lHl += cbdx * lEeL;
+        if (g <= a.nx - 2) lHl -= cbdx * lEreL;
+      }
+    }
     // the Mur update also reads E^{n+1}_{nx-2}
     Real lEe = lE, lEre = lEr;
     if (g == a.nx - 2) lEe += a.kmur * lEr;
@@ -120,10 +149,10 @@ __global__ void __launch_bounds__(4 * kMaxAdjQuadTile) adj_quad_kernel(AdjArgs<R
     if (g == a.nx - 1) newE = -a.kmur * lE;
     if (g == a.nx - 2) newE += lEr;
     if (is_med) {
-      const Real *tp = a.tape + (n - a.tape_step0) * (D + 1) * a.ld + c;
-      const Real x0 = v0 ? tp[i0 * a.ld] + zr0 : Real(0);  // z' of this lane's rows
-      const Real x1 = v1 ? tp[i1 * a.ld] + zr1 : Real(0);
-      const Real E = tp[D * a.ld];
+      const Real x0 = v0 ? ty0 + zr0 : Real(0);  // z' of this lane's rows
+      const Real x1 = v1 ? ty1 + zr1 : Real(0);
+      const Real E = tE;
+      if (s + 1 < a.nsteps) tape_load(n - 1);
       Real sn = 0, cm = 0, z0 = x0, z1 = x1;  // z'' = Rot(x) z'
       if (rot) {
         sincm1(th * E, sn, cm);
@@ -210,9 +239,6 @@ __global__ void __launch_bounds__(4 * kMaxAdjQuadTile) adj_quad_kernel(AdjArgs<R
         lz1 = l21;
       }
     }
-    if (r == 0) sH[cl] = lH;
-    __syncthreads();
-    const Real lHl = (cl > 0) ? sH[cl - 1] : Real(0);
     if (in_dom) {
       if (g <= a.nx - 2) newE -= a.ch * lH;
       if (g >= 1) newE += a.ch * lHl;

@@ -36,6 +36,14 @@ __device__ __forceinline__ T cld(const T *p, int i) {
   return ((const __attribute__((address_space(4))) T *)p)[i];
 }
 
+// Workgroup barrier for kernels whose threads communicate only through LDS
+// within a launch: it waits for this wavefront's LDS operations (so its LDS
+// writes are visible after the barrier) but not for its global-memory loads
+// and stores, which stay in flight across the barrier (__syncthreads waits for
+// those as well).  The memory clobber keeps the compiler from moving memory
+// accesses across it.
+__device__ __forceinline__ void lds_barrier() { __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // sin(x) and cos(x) - 1.  For |x| <= 1/2 (every cell-step of any practical
 // field: the per-step rotation angles are ~1e-3 .. 1e-2) the Taylor series of
 // sine and of cos - 1 are summed to the last bit of the type, which also avoids

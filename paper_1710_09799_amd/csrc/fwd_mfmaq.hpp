@@ -204,7 +204,7 @@ __global__ void __launch_bounds__(4 * kMaxMfmaqTile) fwd_mfmaq_kernel(FwdArgs<fl
     const bool snap = n == snap_next;
     const int b = s & 1;
     if (r == 0) sE[b][cl + 1] = make_float2(E, Elo);
-    __syncthreads();
+    lds_barrier();
     const float2 eL = sE[b][cl], eR = sE[b][cl + 2];
     const float El = eL.x, Ell = eL.y, Er = eR.x, Erl = eR.y;
     if (in_dom) {
@@ -353,7 +353,7 @@ __global__ void __launch_bounds__(4 * kMaxMfmaqTile) fwd_mfmaq_kernel(FwdArgs<fl
         sMur = E;
         sMurl = Elo;
       }
-      __syncthreads();
+      lds_barrier();
       if (g == a.nx - 1) {
         E = El;
         Elo = Ell;

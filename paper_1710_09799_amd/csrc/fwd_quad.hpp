@@ -149,7 +149,7 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
       sE[b][cl + 1] = E;
       if constexpr (CF) sEl[b][cl + 1] = Elo;
     }
-    __syncthreads();
+    lds_barrier();
     const Real El = sE[b][cl], Er = sE[b][cl + 2];
     Real Ell = 0, Erl = 0;
     if constexpr (CF) {
@@ -259,7 +259,7 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
         sMur = E;
         sMurl = Elo;
       }
-      __syncthreads();
+      lds_barrier();
       if (g == a.nx - 1) {
         if constexpr (CF) {
           E = El;

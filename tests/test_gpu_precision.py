@@ -1,11 +1,12 @@
 """Reduced-precision paths against the FP64 oracle.
 
-Tolerances: compensated single precision ("fp32c": two-float Bloch vectors
-and factors; "fp32cf": E and H as two-float pairs as well) must meet 1e-5 on
-err_E and err_pop (the FP32 target); plain single precision ("fp32") is
-reported and held to a looser bound that documents its known drift (factor
-rounding accumulates linearly over the near-identity steps); split-BF16
-meets 1e-4.
+Tolerances: single precision ("fp32"; compensated "fp32c": two-float Bloch
+vectors and factors; "fp32cf": E and H as two-float pairs as well) must meet
+1e-5 on err_E and err_pop (the FP32 target); plain single precision on the
+diagonalisation and Rodrigues routes, which carry d rather than its deviation
+from the rest state, is held to a looser bound that documents its drift
+(factor rounding accumulates over the near-identity steps); split-BF16 meets
+1e-4.
 """
 import numpy as np
 import pytest
@@ -52,13 +53,26 @@ def test_fp32c_two_level(two_level_ref):
     assert ee < 1e-5 and ep < 1e-5
 
 
-@pytest.mark.parametrize("route", ["rotation", "diag", "rodrigues"])
-def test_fp32_plain_three_level(three_level_ref, route):
+@pytest.mark.parametrize("route,variant,tol", [("rotation", "quad", 1e-5), ("rotation", "block", 1e-5),
+                                               ("diag", "block", 1e-3), ("rodrigues", "block", 1e-3)])
+def test_fp32_plain_three_level(three_level_ref, route, variant, tol):
+    """Plain single precision.  The rotation route carries the deviation from
+    the (exact) rest state, so the rounding of the factors acts on the
+    excitation only and the FP32 tolerance holds; the diagonalisation and
+    Rodrigues routes carry d itself and are held to the documented 1e-3."""
     p, ref = three_level_ref
-    got = mln.run(p, precision="fp32", route=route, snap_every=500)
+    got = mln.run(p, precision="fp32", route=route, variant=variant, snap_every=500)
     ee, ep = _errs(got, ref)
-    print(f"fp32 {route} three_level err_E={ee:.3e} err_pop={ep:.3e}")
-    assert ee < 1e-3 and ep < 1e-3
+    print(f"fp32 {route} {variant} three_level err_E={ee:.3e} err_pop={ep:.3e}")
+    assert ee < tol and ep < tol
+
+
+def test_fp32_plain_two_level(two_level_ref):
+    p, ref = two_level_ref
+    got = mln.run(p, precision="fp32", snap_every=1000)
+    ee, ep = _errs(got, ref)
+    print(f"fp32 two_level err_E={ee:.3e} err_pop={ep:.3e}")
+    assert ee < 1e-5 and ep < 1e-5
 
 
 @pytest.mark.parametrize("precision", ["fp32c", "fp32cf"])
