@@ -235,7 +235,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=10000,
                     help="time steps of the oracle sample (full grid)")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32c", "fp32cf"],
+    ap.add_argument("--precision", default="fp32c", choices=["fp32", "fp32c", "fp32cf"],
                     help="precision of the headline run (the others are reported as variants)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM counters)")
