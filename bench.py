@@ -158,6 +158,23 @@ def variants(p3, ref64, pop64, headline):
         var[name] = {"value": n3 / t, "ms": t * 1e3, "launch_ms": g * 1e3 / nl,
                      "err_E_vs_fp64": rel_err(e, ref64),
                      "err_pop_vs_fp64": float(np.max(np.abs(out["pop"] - pop64))), **kw}
+    # the paper's comparison of the exponential routes (Sec. 5.3): the per-step
+    # Pade route against diagonalisation and Rodrigues, and the rotation form,
+    # all FP64 on the one-cell-per-thread kernel (tile 256, 32 steps per launch)
+    p2 = W.two_level()
+    comp = {}
+    for lbl, prob in (("n2_two_level", p2), ("n3_three_level", p3)):
+        nu = prob.grid.n_med * prob.grid.nt
+        rates = {}
+        for route in ("pade", "diag", "rodrigues", "rotation"):
+            t, _, _, _ = time_solver(prob, 1, 1, 0, precision="fp64", variant="block", route=route, tile=256,
+                                     steps_per_launch=32, record_pop=False, record_e=False)
+            rates[route] = nu / t
+        comp[lbl] = {"cell_updates_per_s": rates,
+                     "speedup_vs_pade": {r: rates[r] / rates["pade"] for r in ("diag", "rodrigues", "rotation")}}
+    comp["paper_speedup_vs_pade_single_cpu_thread"] = {"n2": {"diag": 1.26, "rodrigues": 3.48},
+                                                      "n3": {"diag": 1.55, "rodrigues": 7.35}}
+    var["route_comparison"] = comp
     # N = 6: six-level region, 50000 cells x 200000 steps
     p6 = W.six_level()
     n6 = p6.grid.n_med * p6.grid.nt

@@ -74,7 +74,11 @@ typedef enum {
                              in the eigenbasis of U, the two half steps merged into one
                              shared D x D factor                                         */
   MLN_ROUTE_DIAG = 1,     /* Sec. 4.2 first route: A_I = R exp(Lambda E dt) R^+          */
-  MLN_ROUTE_RODRIGUES = 2 /* Sec. 4.2 second route: A_I = I + sum sin S_i + (1-cos) S_i^2 */
+  MLN_ROUTE_RODRIGUES = 2, /* Sec. 4.2 second route: A_I = I + sum sin S_i + (1-cos) S_i^2 */
+  MLN_ROUTE_PADE = 3       /* the generic route the paper compares against (Sec. 4.2, Sec.
+                              5.3): exp(U E dt) by a scaled diagonal Pade approximant every
+                              step (degree 3, 5 or 7 from the 1-norm), applied to d by one
+                              linear solve; N <= 3, one-cell-per-thread kernel            */
 } mln_route;
 
 /* ---- problem description ---------------------------------------------- */

@@ -7,11 +7,12 @@
 
 namespace mln {
 
-enum { ROUTE_ROT = 0, ROUTE_DIAG = 1, ROUTE_RODR = 2 };
+enum { ROUTE_ROT = 0, ROUTE_DIAG = 1, ROUTE_RODR = 2, ROUTE_PADE = 3 };
 
 constexpr int kMaxTile = 256;      // threads (= cells) per tile workgroup
 constexpr int kMaxQuadTile = 256;  // cells per tile of the four-lanes-per-cell kernel
-constexpr int kMaxStepsPerLaunch = 128;  // time steps fused into one launch (halo <= tile/2 < 128)
+constexpr int kMaxStepsPerLaunch = 128;
+constexpr int kPadeMax = 7;  // highest Pade degree of the per-step Pade route  // time steps fused into one launch (halo <= tile/2 < 128)
 
 // Device copies of the per-medium factors, in the precision of the state.
 // Indices are uniform across a wavefront, so the compiler reads them with
@@ -31,6 +32,8 @@ struct FacDev {
   const Real *cz_lo;
   const Real *th_lo;
   const Real *zr;     // D      reference state of the rotation route (state is z' - zr)
+  const Real *Up;     // kPadeMax x D x D  per-step Pade route: (dt U)^k, k = 1..kPadeMax
+  Real unorm;         // ||dt U||_1
   Real p0;
   const double *pop;  // N x D  FP64 population map applied to the state after exp(U E dt)
   const double *popc; // N

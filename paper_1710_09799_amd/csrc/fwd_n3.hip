@@ -24,6 +24,7 @@ hipError_t launch_fwd_n3(int route, bool comp, bool cf, const FwdArgs<Real> &a, 
     case ROUTE_ROT: hipLaunchKernelGGL((fwd_tile_kernel<3, Real, ROUTE_ROT, false>), dim3((unsigned)nblocks), dim3(W), 0, st, a); break;
     case ROUTE_DIAG: hipLaunchKernelGGL((fwd_tile_kernel<3, Real, ROUTE_DIAG, false>), dim3((unsigned)nblocks), dim3(W), 0, st, a); break;
     case ROUTE_RODR: hipLaunchKernelGGL((fwd_tile_kernel<3, Real, ROUTE_RODR, false>), dim3((unsigned)nblocks), dim3(W), 0, st, a); break;
+    case ROUTE_PADE: hipLaunchKernelGGL((fwd_tile_kernel<3, Real, ROUTE_PADE, false>), dim3((unsigned)nblocks), dim3(W), 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -101,6 +102,7 @@ hipError_t launch_bloch_n3(int route, bool comp, const BlochArgs<Real> &a, hipSt
     case ROUTE_ROT: hipLaunchKernelGGL((bloch_kernel<3, Real, ROUTE_ROT, false>), dim3(nb), dim3(256), 0, st, a); break;
     case ROUTE_DIAG: hipLaunchKernelGGL((bloch_kernel<3, Real, ROUTE_DIAG, false>), dim3(nb), dim3(256), 0, st, a); break;
     case ROUTE_RODR: hipLaunchKernelGGL((bloch_kernel<3, Real, ROUTE_RODR, false>), dim3(nb), dim3(256), 0, st, a); break;
+    case ROUTE_PADE: hipLaunchKernelGGL((bloch_kernel<3, Real, ROUTE_PADE, false>), dim3(nb), dim3(256), 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

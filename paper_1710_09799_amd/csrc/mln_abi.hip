@@ -54,6 +54,28 @@ int upload_factors(mln_handle *h, FacDev<Real> &fd) {
   size_t oth = push(thdt), orr = push(rre), ori = push(rim), ol = push(lamdt);
   size_t oS = push(f.S), oS2 = push(f.S2);
   size_t ozr = push(rot ? f.zr : std::vector<double>(D, 0.0));
+  // per-step Pade route: powers (dt U)^k, k = 1..kPadeMax, and ||dt U||_1
+  std::vector<double> Up;
+  double unorm = 0.0;
+  if (h->route == MLN_ROUTE_PADE) {
+    Up.assign((size_t)kPadeMax * D * D, 0.0);
+    std::vector<double> P(D * D, 0.0);
+    for (int i = 0; i < D * D; ++i) P[i] = f.U[i] * h->grid.dt;
+    for (int k = 0; k < kPadeMax; ++k) {
+      std::copy(P.begin(), P.end(), Up.begin() + (size_t)k * D * D);
+      std::vector<double> nP(D * D, 0.0);
+      for (int i = 0; i < D; ++i)
+        for (int l = 0; l < D; ++l)
+          for (int j = 0; j < D; ++j) nP[i * D + j] += P[i * D + l] * f.U[l * D + j] * h->grid.dt;
+      P.swap(nP);
+    }
+    for (int j = 0; j < D; ++j) {
+      double cs = 0.0;
+      for (int i = 0; i < D; ++i) cs += std::fabs(f.U[i * D + j] * h->grid.dt);
+      unorm = std::max(unorm, cs);
+    }
+  }
+  size_t oUp = push(Up);
   // low parts x - (float)x of the factors the compensated state uses
   auto lo_of = [](const std::vector<double> &v) {
     std::vector<double> r(v.size());
@@ -78,6 +100,8 @@ int upload_factors(mln_handle *h, FacDev<Real> &fd) {
   fd.cz_lo = b + ocl;
   fd.th_lo = b + otl;
   fd.zr = b + ozr;
+  fd.Up = b + oUp;
+  fd.unorm = (Real)unorm;
   fd.p0 = (Real)(rot ? f.pr : f.p0);
   const std::vector<double> &pm = rot ? f.popz : f.popd;
   HIP_TRY(h->pop.alloc(pm.size() * sizeof(double)));
@@ -336,7 +360,9 @@ int mln_init(const mln_medium *medium, const mln_grid *grid, const mln_source *s
   h->prec = opt.precision;
   h->route = opt.route;
   h->stream = (hipStream_t)opt.stream;
-  if (h->route < 0 || h->route > 2) return set_err(MLN_EINVAL, "unknown route");
+  if (h->route < 0 || h->route > 3) return set_err(MLN_EINVAL, "unknown route");
+  if (h->route == MLN_ROUTE_PADE && h->f.N > 3)
+    return set_err(MLN_ENOTSUPPORTED, "the per-step Pade route is built for N <= 3");
   if (h->f.N == 5) return set_err(MLN_ENOTSUPPORTED, "kernels are built for N = 2, 3, 4 and 6");
   if (h->prec < MLN_FP64 || h->prec > MLN_FP32_COMP_FIELDS)
     return set_err(MLN_ENOTSUPPORTED, "unknown precision");

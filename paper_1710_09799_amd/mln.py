@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmln.so")
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32c": 2, "bf16x6": 3, "bf16x3": 4, "fp32cf": 5}
-ROUTES = {"rotation": 0, "diag": 1, "rodrigues": 2}
+ROUTES = {"rotation": 0, "diag": 1, "rodrigues": 2, "pade": 3}
 VARIANTS = {"auto": 0, "block": 1, "wave": 2, "quad": 3}
 
 _dp = ctypes.POINTER(ctypes.c_double)
