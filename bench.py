@@ -172,6 +172,21 @@ def variants(p3, ref64, pop64, headline):
             rates[route] = nu / t
         comp[lbl] = {"cell_updates_per_s": rates,
                      "speedup_vs_pade": {r: rates[r] / rates["pade"] for r in ("diag", "rodrigues", "rotation")}}
+    # N = 6 (the paper leaves many-level behaviour open): the six-level grid,
+    # a 512-step sample of its run; the Pade route on its one-wavefront-per-
+    # cell kernel (tile 128, 8 steps per launch), the others as above with 16
+    # steps per launch
+    p6s = W.six_level(nt=512)
+    nu = p6s.grid.n_med * p6s.grid.nt
+    rates = {}
+    for route in ("pade", "diag", "rodrigues", "rotation"):
+        tk = dict(tile=128, steps_per_launch=8) if route == "pade" else dict(tile=256, steps_per_launch=16)
+        t, _, _, _ = time_solver(p6s, 1, 1, 0, precision="fp64", variant="block", route=route,
+                                 record_pop=False, record_e=False, **tk)
+        rates[route] = nu / t
+    comp["n6_six_level_512_step_sample"] = {
+        "cell_updates_per_s": rates,
+        "speedup_vs_pade": {r: rates[r] / rates["pade"] for r in ("diag", "rodrigues", "rotation")}}
     comp["paper_speedup_vs_pade_single_cpu_thread"] = {"n2": {"diag": 1.26, "rodrigues": 3.48},
                                                       "n3": {"diag": 1.55, "rodrigues": 7.35}}
     var["route_comparison"] = comp

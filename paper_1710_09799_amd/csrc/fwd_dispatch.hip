@@ -38,6 +38,7 @@ MLN_DECL(6)
 
 template <typename Real>
 hipError_t launch_fwd(int N, int route, bool comp, bool cf, const FwdArgs<Real> &a, int64_t nblocks, int W, hipStream_t st) {
+  if (route == ROUTE_PADE && N >= 4) return comp ? hipErrorInvalidValue : launch_fwd_pade<Real>(N, a, nblocks, st);
   switch (N) {
     case 2: return launch_fwd_n2<Real>(route, comp, cf, a, nblocks, W, st);
     case 3: return launch_fwd_n3<Real>(route, comp, cf, a, nblocks, W, st);
@@ -49,6 +50,7 @@ hipError_t launch_fwd(int N, int route, bool comp, bool cf, const FwdArgs<Real> 
 
 template <typename Real>
 hipError_t launch_bloch(int N, int route, bool comp, const BlochArgs<Real> &a, hipStream_t st) {
+  if (route == ROUTE_PADE && N >= 4) return comp ? hipErrorInvalidValue : launch_bloch_pade<Real>(N, a, st);
   switch (N) {
     case 2: return launch_bloch_n2<Real>(route, comp, a, st);
     case 3: return launch_bloch_n3<Real>(route, comp, a, st);

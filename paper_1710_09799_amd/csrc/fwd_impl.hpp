@@ -343,13 +343,15 @@ __device__ __forceinline__ void interaction(const FacDev<Real> &f, Real E, Real 
     }
   } else if constexpr (ROUTE == ROUTE_PADE) {
     // The generic per-step route the paper measures the other two against:
-    // exp(X), X = E dt U, by the diagonal Pade approximant r_m(X) =
-    // q_m(X)^-1 p_m(X) with scaling (Higham 2005: the degree m in {3, 5, 7}
-    // and the scaling 2^s from ||X||_1), applied to the state: p_m(X) d from
-    // m products with dt U, q_m(X) = sum (-1)^k b_k X^k formed from the
-    // precomputed powers (dt U)^k, and q_m(X) f = p_m(X) d solved by Gaussian
-    // elimination (q_m(X) = b_0 I + O(||X||), no pivoting needed).
-    const Real xn = (E < 0 ? -E : E) * f.unorm;
+    // exp(X), X = E dt U = x V (x = E ||dt U||_1, ||V||_1 = 1), by the
+    // diagonal Pade approximant r_m(X) = q_m(X)^-1 p_m(X) with scaling
+    // (Higham 2005: the degree m in {3, 5, 7} and the scaling 2^s from
+    // ||X||_1 = |x|), applied to the state: p_m(X) d from m products with V,
+    // q_m(X) = sum (-1)^k b_k x^k V^k formed from the precomputed powers V^k,
+    // and q_m(X) f = p_m(X) d solved by Gaussian elimination (q_m(X) = b_0 I +
+    // O(||X||), no pivoting needed).
+    const Real xs = E * f.unorm;
+    const Real xn = xs < 0 ? -xs : xs;
     int m = 7;
     if (!wave_any(xn > Real(1.495585217958292e-2)))
       m = 3;
@@ -358,7 +360,7 @@ __device__ __forceinline__ void interaction(const FacDev<Real> &f, Real E, Real 
     int sc = 0;  // scaling exponent of this lane
     if (m == 7)
       while (sc < 60 && xn > Real(9.504178996162932e-1) * (Real)(1ull << sc)) ++sc;
-    const Real x = E / (Real)(1ull << sc);
+    const Real x = xs / (Real)(1ull << sc);
     double b[kPadeMax + 1];
     if (m == 3) {
       b[0] = 120; b[1] = 60; b[2] = 12; b[3] = 1;

@@ -11,8 +11,9 @@ enum { ROUTE_ROT = 0, ROUTE_DIAG = 1, ROUTE_RODR = 2, ROUTE_PADE = 3 };
 
 constexpr int kMaxTile = 256;      // threads (= cells) per tile workgroup
 constexpr int kMaxQuadTile = 256;  // cells per tile of the four-lanes-per-cell kernel
-constexpr int kMaxStepsPerLaunch = 128;
-constexpr int kPadeMax = 7;  // highest Pade degree of the per-step Pade route  // time steps fused into one launch (halo <= tile/2 < 128)
+constexpr int kMaxStepsPerLaunch = 128;  // time steps fused into one launch (halo <= tile/2 < 128)
+constexpr int kPadeMax = 7;              // highest Pade degree of the per-step Pade route
+constexpr size_t kPadeMaxLds = 160 * 1024;  // LDS of one compute unit
 
 // Device copies of the per-medium factors, in the precision of the state.
 // Indices are uniform across a wavefront, so the compiler reads them with
@@ -32,8 +33,8 @@ struct FacDev {
   const Real *cz_lo;
   const Real *th_lo;
   const Real *zr;     // D      reference state of the rotation route (state is z' - zr)
-  const Real *Up;     // kPadeMax x D x D  per-step Pade route: (dt U)^k, k = 1..kPadeMax
-  Real unorm;         // ||dt U||_1
+  const Real *Up;     // kPadeMax x D x D  per-step Pade route: V^k, k = 1..kPadeMax, V = dt U / unorm
+  Real unorm;         // ||dt U||_1 (X = E dt U = (E unorm) V)
   Real p0;
   const double *pop;  // N x D  FP64 population map applied to the state after exp(U E dt)
   const double *popc; // N
@@ -127,6 +128,16 @@ hipError_t launch_fwd_mfma(int N, int nprod, const FwdArgs<float> &a, int64_t nb
 // W cells per tile (multiple of 16, at most 256), 4 W lanes; compensated
 // state and fields.
 hipError_t launch_fwd_mfmaq(int N, int nprod, const FwdArgs<float> &a, int64_t nblocks, int W, hipStream_t st);
+
+// Per-step Pade route for N = 4 and 6 (fwd_pade.hpp): one wavefront per cell,
+// 512 threads per workgroup, tile of a.owned + 2 a.halo <= 512 cells whose
+// states sit in LDS (pade_lds_bytes(N, sizeof(Real), W) bytes, at most
+// kPadeMaxLds); FP64 or plain FP32.
+template <typename Real>
+hipError_t launch_fwd_pade(int N, const FwdArgs<Real> &a, int64_t nblocks, hipStream_t st);
+template <typename Real>
+hipError_t launch_bloch_pade(int N, const BlochArgs<Real> &a, hipStream_t st);
+size_t pade_lds_bytes(int N, int real_bytes, int W);
 
 // Four-lanes-per-cell tile kernel of the rotation route (fwd_quad.hpp), N <= 3;
 // W cells per tile (W in 64..256, multiple of 16), 4 W threads.

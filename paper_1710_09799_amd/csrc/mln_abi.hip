@@ -54,25 +54,28 @@ int upload_factors(mln_handle *h, FacDev<Real> &fd) {
   size_t oth = push(thdt), orr = push(rre), ori = push(rim), ol = push(lamdt);
   size_t oS = push(f.S), oS2 = push(f.S2);
   size_t ozr = push(rot ? f.zr : std::vector<double>(D, 0.0));
-  // per-step Pade route: powers (dt U)^k, k = 1..kPadeMax, and ||dt U||_1
+  // per-step Pade route: ||dt U||_1 and the powers V^k, k = 1..kPadeMax, of
+  // V = dt U / ||dt U||_1, so that X = E dt U = (E ||dt U||_1) V with both
+  // factors of order one (powers of E itself overflow single precision)
   std::vector<double> Up;
   double unorm = 0.0;
   if (h->route == MLN_ROUTE_PADE) {
+    for (int j = 0; j < D; ++j) {
+      double cs = 0.0;
+      for (int i = 0; i < D; ++i) cs += std::fabs(f.U[i * D + j] * h->grid.dt);
+      unorm = std::max(unorm, cs);
+    }
+    const double vs = unorm > 0.0 ? h->grid.dt / unorm : 0.0;
+    std::vector<double> V(D * D), P(D * D);
+    for (int i = 0; i < D * D; ++i) V[i] = P[i] = f.U[i] * vs;
     Up.assign((size_t)kPadeMax * D * D, 0.0);
-    std::vector<double> P(D * D, 0.0);
-    for (int i = 0; i < D * D; ++i) P[i] = f.U[i] * h->grid.dt;
     for (int k = 0; k < kPadeMax; ++k) {
       std::copy(P.begin(), P.end(), Up.begin() + (size_t)k * D * D);
       std::vector<double> nP(D * D, 0.0);
       for (int i = 0; i < D; ++i)
         for (int l = 0; l < D; ++l)
-          for (int j = 0; j < D; ++j) nP[i * D + j] += P[i * D + l] * f.U[l * D + j] * h->grid.dt;
+          for (int j = 0; j < D; ++j) nP[i * D + j] += P[i * D + l] * V[l * D + j];
       P.swap(nP);
-    }
-    for (int j = 0; j < D; ++j) {
-      double cs = 0.0;
-      for (int i = 0; i < D; ++i) cs += std::fabs(f.U[i * D + j] * h->grid.dt);
-      unorm = std::max(unorm, cs);
     }
   }
   size_t oUp = push(Up);
@@ -361,8 +364,6 @@ int mln_init(const mln_medium *medium, const mln_grid *grid, const mln_source *s
   h->route = opt.route;
   h->stream = (hipStream_t)opt.stream;
   if (h->route < 0 || h->route > 3) return set_err(MLN_EINVAL, "unknown route");
-  if (h->route == MLN_ROUTE_PADE && h->f.N > 3)
-    return set_err(MLN_ENOTSUPPORTED, "the per-step Pade route is built for N <= 3");
   if (h->f.N == 5) return set_err(MLN_ENOTSUPPORTED, "kernels are built for N = 2, 3, 4 and 6");
   if (h->prec < MLN_FP64 || h->prec > MLN_FP32_COMP_FIELDS)
     return set_err(MLN_ENOTSUPPORTED, "unknown precision");
@@ -403,7 +404,10 @@ int mln_init(const mln_medium *medium, const mln_grid *grid, const mln_source *s
     return set_err(MLN_ENOTSUPPORTED, "the wavefront and quad kernels implement the rotation route");
   if (h->quad && h->f.N > 3 && !h->mfma)
     return set_err(MLN_ENOTSUPPORTED, "the quad kernel is built for N <= 3 (N = 4, 6: split-BF16 precisions)");
-  h->W = opt.tile > 0 ? opt.tile : (h->quad && !h->mfma ? 128 : kMaxTile);
+  // the per-step Pade route for N >= 4 keeps the tile's states in LDS and is
+  // bound by arithmetic: smaller tiles, short halos
+  const bool pade_wave = h->route == MLN_ROUTE_PADE && h->f.N >= 4;
+  h->W = opt.tile > 0 ? opt.tile : ((h->quad && !h->mfma) || pade_wave ? 128 : kMaxTile);
   if (h->quad) {
     if (h->W > kMaxQuadTile || h->W < 32 || h->W % 16)
       return set_err(MLN_EINVAL, "quad kernel tile must be a multiple of 16 in [32, 256]");
@@ -412,10 +416,13 @@ int mln_init(const mln_medium *medium, const mln_grid *grid, const mln_source *s
   }
   if (h->wave && (h->W == 192 || (h->f.N == 6 && h->W != 64)))
     return set_err(MLN_ENOTSUPPORTED, "wavefront kernel tiles: 64, 128 or 256 cells (64 for N = 6)");
-  int K = opt.steps_per_launch > 0 ? opt.steps_per_launch
-                                   : (h->wave ? h->W / 8 : (h->mfma ? 16 : (h->quad ? h->W / 4 : 32)));
+  int K = opt.steps_per_launch > 0
+              ? opt.steps_per_launch
+              : (pade_wave ? 8 : (h->wave ? h->W / 8 : (h->mfma ? 16 : (h->quad ? h->W / 4 : 32))));
   if (2 * K >= h->W || K > kMaxStepsPerLaunch)
     return set_err(MLN_EINVAL, "steps_per_launch must be below tile/2 (and at most 128)");
+  if (pade_wave && pade_lds_bytes(h->f.N, h->rs, h->W) > kPadeMaxLds)
+    return set_err(MLN_EINVAL, "tile too large for the LDS of the per-step Pade kernel");
   h->halo = K;
   h->owned = h->W - 2 * K;
   h->ntiles = (grid->nx + h->owned - 1) / h->owned;

@@ -51,8 +51,6 @@ SMALL = [(2, 1), (3, 2), (4, 3), (6, 4)]
 def test_coupled_fp64_small(ref_cache, n, seed, route, tile, k):
     """Random medium with Lindblad relaxation on a grid spanning several tiles
     with a ragged last tile; every recorded E and population."""
-    if route == "pade" and n > 3:
-        pytest.skip("the per-step Pade route is built for N <= 3")
     p = W.random_problem(n, seed, nx=203, nt=360)
     _print_case("coupled_small", n=n, seed=seed, route=route, tile=tile, k=k)
     ref = ref_cache((n, seed), p, 40)
@@ -134,8 +132,6 @@ def test_bloch_only_fp64(orc, n, seed, route, fmax):
     diagonalisation routes take their library branch, the Pade route its
     degree-5 / degree-7 and scaled branches."""
     import torch
-    if route == "pade" and n > 3:
-        pytest.skip("the per-step Pade route is built for N <= 3")
     med = W.random_medium(n, seed + 50)
     rng = np.random.default_rng(seed)
     nt, nc = 500, 37
@@ -260,8 +256,49 @@ def test_three_level_full_run_invariants():
     assert np.max(np.abs(got["e_snap"][0, :5000])) > 1e-3 * p.source.amplitude
 
 
-def test_pade_route_rejects_large_n():
+@pytest.mark.parametrize("n,seed", SMALL)
+@pytest.mark.parametrize("fmax", [3e9, 3e11])
+def test_bloch_only_fp32_pade(orc, n, seed, fmax):
+    """Prescribed field, per-step Pade route in single precision, through the
+    degree-7 and scaled branches (fmax = 3e11 V/m): the powers of the field
+    never appear on their own (X = (E ||dt U||_1) V with ||V||_1 = 1), so
+    nothing overflows single precision."""
+    import torch
+    med = W.random_medium(n, seed + 50)
+    rng = np.random.default_rng(seed)
+    nt, nc = 500, 37
+    f = rng.uniform(-fmax, fmax, size=(nt, nc))
+    grid = W.Grid(nx=nc + 2, nt=1, dx=W.DX0, dt=W.DT0, med_begin=1, med_end=nc + 1)
+    prob = W.Problem("b", med, grid, W.Source(np.zeros(2), 0.0))
+    ref = orc.bloch(med, f, W.DT0)
+    s = mln.Solver(prob, precision="fp32", route="pade")
+    out = s.bloch_only(torch.tensor(f, device="cuda"))
+    pop = out["pop"].cpu().numpy()
+    dp = out["dp"].cpu().numpy()
+    print(f"bloch fp32 pade n={n} fmax={fmax:.0e} err_pop={np.max(np.abs(pop - ref['pop'])):.3e} "
+          f"err_dp={np.max(np.abs(dp - ref['dp'])) / np.max(np.abs(ref['dp'])):.3e}")
+    assert np.max(np.abs(pop - ref["pop"])) < 1e-3
+    assert np.max(np.abs(dp - ref["dp"])) < 1e-3 * np.max(np.abs(ref["dp"]))
+
+
+def test_pade_route_rejects_compensated_state():
     p = W.random_problem(4, 1, nx=100, nt=50)
-    with pytest.raises(mln.MLNError) as e:
-        mln.Solver(p, precision="fp64", route="pade")
-    assert e.value.code == -8
+    for prec in ("fp32c", "fp32cf"):
+        with pytest.raises(mln.MLNError) as e:
+            mln.Solver(p, precision=prec, route="pade")
+        assert e.value.code == -8
+
+
+@pytest.mark.parametrize("n,seed", [(4, 3), (6, 4)])
+@pytest.mark.parametrize("tile,k", [(64, 4), (128, 8), (256, 40)])
+def test_pade_wavefront_kernel_fp32(ref_cache, n, seed, tile, k):
+    """The per-step Pade route for N = 4 and 6 (one wavefront per cell) in
+    plain single precision: it carries d itself, like the diagonalisation
+    and Rodrigues routes, and is held to their 1e-3."""
+    p = W.random_problem(n, seed, nx=203, nt=360)
+    _print_case("pade_fp32", n=n, seed=seed, tile=tile, k=k)
+    ref = ref_cache((n, seed), p, 40)
+    got = mln.run(p, precision="fp32", route="pade", snap_every=40, tile=tile, steps_per_launch=k)
+    ee, ep = _errs(got, ref)
+    print(f"pade fp32 n={n} err_E={ee:.3e} err_pop={ep:.3e}")
+    assert ee < 1e-3 and ep < 1e-3

@@ -54,12 +54,14 @@ def test_fp32c_two_level(two_level_ref):
 
 
 @pytest.mark.parametrize("route,variant,tol", [("rotation", "quad", 1e-5), ("rotation", "block", 1e-5),
-                                               ("diag", "block", 1e-3), ("rodrigues", "block", 1e-3)])
+                                               ("diag", "block", 1e-3), ("rodrigues", "block", 1e-3),
+                                               ("pade", "block", 1e-3)])
 def test_fp32_plain_three_level(three_level_ref, route, variant, tol):
     """Plain single precision.  The rotation route carries the deviation from
     the (exact) rest state, so the rounding of the factors acts on the
-    excitation only and the FP32 tolerance holds; the diagonalisation and
-    Rodrigues routes carry d itself and are held to the documented 1e-3."""
+    excitation only and the FP32 tolerance holds; the diagonalisation,
+    Rodrigues and per-step Pade routes carry d itself and are held to the
+    documented 1e-3."""
     p, ref = three_level_ref
     got = mln.run(p, precision="fp32", route=route, variant=variant, snap_every=500)
     ee, ep = _errs(got, ref)
