@@ -78,7 +78,10 @@ typedef enum {
   MLN_ROUTE_PADE = 3       /* the generic route the paper compares against (Sec. 4.2, Sec.
                               5.3): exp(U E dt) by a scaled diagonal Pade approximant every
                               step (degree 3, 5 or 7 from the 1-norm), applied to d by one
-                              linear solve; N <= 3, one-cell-per-thread kernel            */
+                              linear solve; FP64 or plain FP32.  N <= 3: one cell per
+                              thread; N = 4, 6: one wavefront per cell, 512 threads per
+                              workgroup, default tile 128 and 8 steps per launch (a
+                              tile whose LDS need exceeds 160 KB gives MLN_EINVAL)       */
 } mln_route;
 
 /* ---- problem description ---------------------------------------------- */
