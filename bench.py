@@ -258,6 +258,42 @@ def variants(p3, ref64, pop64, headline):
     return var
 
 
+def calib_copy():
+    """A 1 GiB device-to-device copy: reads and writes 2^30 bytes, the
+    reference that maps the HBM counters to bytes."""
+    import torch
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    return x.numel() * 4
+
+
+# Single workloads for hardware-counter runs: (problem, solver options).  The
+# six-level cases run a 1600-step sample of the 200000-step run on the full
+# 50000-cell grid (every launch is alike).
+PROFILE_CASES = {
+    "n2_fp64": ("two_level", {}, dict(precision="fp64", variant="quad", tile=128, steps_per_launch=16)),
+    "n3_fp64": ("three_level", {}, dict(precision="fp64", variant="quad", tile=128, steps_per_launch=20)),
+    "n3_fp32c": ("three_level", {}, dict(precision="fp32c", variant="quad", tile=128, steps_per_launch=20)),
+    "n6_fp64": ("six_level", dict(nt=1600), dict(precision="fp64", variant="block", tile=256, steps_per_launch=16)),
+    "n6_bf16x6": ("six_level", dict(nt=1600), dict(precision="bf16x6", tile=256, steps_per_launch=16)),
+    "n6_bf16x3": ("six_level", dict(nt=1600), dict(precision="bf16x3", tile=256, steps_per_launch=16)),
+}
+
+
+def profile_case(name, steps, warmup, calib):
+    from paper_1710_09799_amd import workloads as W
+    wl, pkw, kw = PROFILE_CASES[name]
+    p = getattr(W, wl)(**pkw)
+    t, g, nl, _ = time_solver(p, steps, warmup, 0, record_pop=False, record_e=False, **kw)
+    if calib:
+        calib_copy()
+    print(json.dumps({"profile_case": name, "nx": p.grid.nx, "nt": p.grid.nt, "n_med": p.grid.n_med,
+                      "launches_per_run": nl, "ms_per_run": t * 1e3, "launch_us": g * 1e6 / nl,
+                      "cell_updates_per_s": p.grid.n_med * p.grid.nt / t, **kw}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,6 +307,8 @@ def main():
                     help="precision of the headline run (the others are reported as variants)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--profile-case", choices=sorted(PROFILE_CASES),
+                    help="run only this workload (for hardware counters) and print its timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver has no multi-GPU path "
@@ -280,6 +318,9 @@ def main():
     import torch
     from paper_1710_09799_amd import workloads as W
     torch.cuda.init()
+    if args.profile_case:
+        profile_case(args.profile_case, args.steps, args.warmup, args.calib_copy)
+        return
     p = W.three_level()
     n_upd = p.grid.n_med * p.grid.nt
     K = 20
@@ -336,11 +377,7 @@ def main():
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
     if args.calib_copy:
-        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-        y = torch.empty_like(x)
-        y.copy_(x)
-        torch.cuda.synchronize()
-        res["calib_copy_bytes"] = x.numel() * 4
+        res["calib_copy_bytes"] = calib_copy()
     print(json.dumps(res))
 
 
