@@ -108,6 +108,13 @@ struct mln_handle {
   // adjoint buffers (allocated by the first mln_grad)
   DevBuf lE[2], lH[2], lz[2], tape, partial, gprobe, samples_dev;
   double fd_coef[6] = {0, 0, 0, 0, 0, 0};  // ch, ca, cb, inv_dx, kmur, ca - 1
+  // the same coefficients for the single-precision kernels: ch and inv_dx
+  // chosen so that ch * cb * inv_dx (the squared Courant number that sets the
+  // phase velocity of the Yee scheme) matches the FP64 product far below FP32
+  // rounding; H is then carried in units scaled by ch32 / ch, undone by
+  // h_scale32 = ch / ch32 where H leaves the library
+  float fc32[6] = {0, 0, 0, 0, 0, 0};
+  double h_scale32 = 1.0;
 };
 
 namespace mln {
@@ -117,6 +124,21 @@ int reset_state(mln_handle *h);
 // After the last step: synchronise, copy host-side outputs back and check the
 // probe for non-finite values.
 int finish_run(mln_handle *h);
+
+// FDTD coefficients in the precision of the kernels.
+inline void fdtd_coefs(const mln_handle *h, double &ch, double &ca, double &cb, double &inv_dx, double &kmur,
+                       double &cam1) {
+  ch = h->fd_coef[0]; ca = h->fd_coef[1]; cb = h->fd_coef[2];
+  inv_dx = h->fd_coef[3]; kmur = h->fd_coef[4]; cam1 = h->fd_coef[5];
+}
+inline void fdtd_coefs(const mln_handle *h, float &ch, float &ca, float &cb, float &inv_dx, float &kmur,
+                       float &cam1) {
+  ch = h->fc32[0]; ca = h->fc32[1]; cb = h->fc32[2];
+  inv_dx = h->fc32[3]; kmur = h->fc32[4]; cam1 = h->fc32[5];
+}
+
+// Fill h->fc32 and h->h_scale32 from h->fd_coef.
+void tune_fp32_coefs(mln_handle *h);
 
 template <typename Real>
 inline FwdArgs<Real> make_args(mln_handle *h, const FacDev<Real> &fd, int64_t step0, int nsteps,
@@ -139,12 +161,7 @@ inline FwdArgs<Real> make_args(mln_handle *h, const FacDev<Real> &fd, int64_t st
   a.nsteps = nsteps;
   a.halo = h->halo;
   a.owned = h->owned;
-  a.ch = (Real)h->fd_coef[0];
-  a.ca = (Real)h->fd_coef[1];
-  a.cb = (Real)h->fd_coef[2];
-  a.inv_dx = (Real)h->fd_coef[3];
-  a.kmur = (Real)h->fd_coef[4];
-  a.cam1 = (Real)h->fd_coef[5];
+  fdtd_coefs(h, a.ch, a.ca, a.cb, a.inv_dx, a.kmur, a.cam1);
   a.nt = h->grid.nt;
   a.snap_every = record ? h->rec.snap_every : 0;
   // first step n >= step0 with (n+1) % snap_every == 0, and its snapshot index

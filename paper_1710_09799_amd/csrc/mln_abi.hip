@@ -25,6 +25,44 @@ int mln::set_err(int code, const std::string &msg) {
 }
 
 
+// The Yee update advances E by cb * inv_dx * (H_{i+1/2} - H_{i-1/2}) and H by
+// ch * (E_{i+1} - E_i), so the discrete wave speed depends on the product
+// ch * cb * inv_dx (the squared Courant number over eps_r mu_r).  Rounding the
+// three factors to FP32 independently leaves that product off by up to
+// ~1.8e-7 relative, a systematic phase-velocity error whose effect on E grows
+// with the distance travelled (about 1e-5 after 50 wavelengths).  cb also
+// scales the polarisation term and keeps its rounded value; ch and inv_dx are
+// searched within +-256 ulps of their rounded values for the pair whose
+// product with cb is closest to the FP64 value (typically within 1e-10).
+// inv_dx appears nowhere else; a different ch rescales the carried H, which
+// mln_get_fields undoes.
+void mln::tune_fp32_coefs(mln_handle *h) {
+  const double *c = h->fd_coef;
+  for (int i = 0; i < 6; ++i) h->fc32[i] = (float)c[i];
+  const long double target = (long double)c[0] * c[2] * c[3];
+  const float cb = h->fc32[2];
+  float best_ch = h->fc32[0], best_idx = h->fc32[3];
+  long double best = std::fabs((long double)best_ch * best_idx * cb - target);
+  constexpr int K = 256;
+  float ch = h->fc32[0];
+  for (int i = 0; i < K; ++i) ch = std::nextafter(ch, 0.0f);
+  for (int i = -K; i <= K; ++i, ch = std::nextafter(ch, 2.0f * ch)) {
+    float idx = h->fc32[3];
+    for (int j = 0; j < K; ++j) idx = std::nextafter(idx, 0.0f);
+    for (int j = -K; j <= K; ++j, idx = std::nextafter(idx, 2.0f * idx)) {
+      const long double e = std::fabs((long double)ch * idx * cb - target);
+      if (e < best) {
+        best = e;
+        best_ch = ch;
+        best_idx = idx;
+      }
+    }
+  }
+  h->fc32[0] = best_ch;
+  h->fc32[3] = best_idx;
+  h->h_scale32 = c[0] / (double)best_ch;
+}
+
 namespace {
 
 // Upload the factors of the chosen route in precision Real.  The layout of
@@ -385,6 +423,7 @@ int mln_init(const mln_medium *medium, const mln_grid *grid, const mln_source *s
   h->fd_coef[3] = 1.0 / grid->dx;
   h->fd_coef[4] = (cl * grid->dt - grid->dx) / (cl * grid->dt + grid->dx);
   h->fd_coef[5] = -2.0 * sg / (1.0 + sg);
+  tune_fp32_coefs(h.get());
   // kernel variant and tiling
   if (opt.variant < 0 || opt.variant > 3) return set_err(MLN_EINVAL, "unknown kernel variant");
   const bool rot = h->route == MLN_ROUTE_ROTATION;
@@ -517,6 +556,8 @@ int mln_get_fields(mln_handle *h, double *E, double *H) {
   if (H) {
     HIP_TRY(hipMemcpy(buf.data(), h->H[h->cur].p, buf.size(), hipMemcpyDeviceToHost));
     conv(H, nx - 1);
+    if (h->rs == 4)
+      for (int64_t i = 0; i < nx - 1; ++i) H[i] *= h->h_scale32;
   }
   return MLN_OK;
 }
@@ -670,8 +711,8 @@ int mln_grad(mln_handle *h, const double *dJ_dprobe, mln_grads *out) {
         a.samples = (const double *)h->samples_dev.p;
         a.nx = h->grid.nx; a.mb = h->grid.med_begin; a.me = h->grid.med_end; a.ld = h->ld;
         a.n_hi = n_hi; a.nsteps = k; a.halo = h->halo; a.owned = h->owned;
-        a.ch = h->fd_coef[0]; a.ca = h->fd_coef[1]; a.cb = h->fd_coef[2]; a.inv_dx = h->fd_coef[3];
-        a.kmur = h->fd_coef[4];
+        double cam1;
+        fdtd_coefs(h, a.ch, a.ca, a.cb, a.inv_dx, a.kmur, cam1);
         a.partial = (double *)h->partial.p;
         e = (h->quad && h->W <= 128) ? launch_adj_quad<double>(N, a, h->ntiles, h->W, h->stream)
                     : launch_adj<double>(N, a, h->ntiles, h->W, h->stream);
@@ -690,8 +731,8 @@ int mln_grad(mln_handle *h, const double *dJ_dprobe, mln_grads *out) {
         a.samples = (const double *)h->samples_dev.p;
         a.nx = h->grid.nx; a.mb = h->grid.med_begin; a.me = h->grid.med_end; a.ld = h->ld;
         a.n_hi = n_hi; a.nsteps = k; a.halo = h->halo; a.owned = h->owned;
-        a.ch = (float)h->fd_coef[0]; a.ca = (float)h->fd_coef[1]; a.cb = (float)h->fd_coef[2];
-        a.inv_dx = (float)h->fd_coef[3]; a.kmur = (float)h->fd_coef[4];
+        float cam1;
+        fdtd_coefs(h, a.ch, a.ca, a.cb, a.inv_dx, a.kmur, cam1);
         a.partial = (double *)h->partial.p;
         e = (h->quad && h->W <= 128) ? launch_adj_quad<float>(N, a, h->ntiles, h->W, h->stream)
                     : launch_adj<float>(N, a, h->ntiles, h->W, h->stream);

@@ -168,6 +168,47 @@ def test_vacuum_magic_time_step_exact(orc):
     assert np.max(np.abs(got["probe"] - want)) < 1e-12 * 1.5 * np.abs(s).max()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp32c", "fp32cf"])
+def test_vacuum_magic_time_step_single_precision(orc, precision):
+    """Courant number 1 in single precision: the FP32 coefficients realise
+    the product ch cb / dx = 1 to about 1e-10 (instead of the ~1e-7 of
+    independently rounded factors), so a broadband signal still moves one
+    cell per step with no dispersion beyond the per-step rounding."""
+    c = orc.constants()
+    nx, nt, dx = 300, 700, 1e-7
+    dt = dx * math.sqrt(c["eps0"] * c["mu0"])
+    rng = np.random.default_rng(2)
+    sig = rng.normal(size=nt + 1)
+    med = W.ladder_medium([0.0, 1e-19], [1e-29], density=0.0)
+    prob = W.Problem("vac", med, W.Grid(nx=nx, nt=nt, dx=dx, dt=dt, med_begin=1, med_end=1),
+                     W.Source(sig, 1.5))
+    got = mln.run(prob, precision=precision, snap_every=7)
+    k = np.arange(nt + 1) - (nx - 1)
+    want = np.where(k >= 0, 1.5 * sig[np.clip(k, 0, None)], 0.0)
+    err = np.max(np.abs(got["probe"] - want)) / (1.5 * np.abs(sig).max())
+    print(f"{precision} magic time step probe err {err:.2e}")
+    assert err < 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp32c", "fp32cf"])
+def test_single_precision_fields_match_fp64(precision):
+    """E and H read back through mln_get_fields agree with the FP64 run (the
+    single-precision kernels carry H in units rescaled by their tuned
+    coefficient; the library undoes it on the way out)."""
+    p = W.random_problem(3, 11, nx=400, nt=600)
+    out = {}
+    for prec in ("fp64", precision):
+        s = mln.Solver(p, precision=prec)
+        s.run()
+        out[prec] = s.fields()
+        s.close()
+    (E64, H64), (E32, H32) = out["fp64"], out[precision]
+    eE = np.max(np.abs(E32 - E64)) / np.max(np.abs(E64))
+    eH = np.max(np.abs(H32 - H64)) / np.max(np.abs(H64))
+    print(f"{precision} fields err_E={eE:.2e} err_H={eH:.2e}")
+    assert eE < 1e-5 and eH < 1e-5
+
+
 @pytest.mark.parametrize("mb,me", [(1, 2), (5, 5), (1, 199), (150, 199)])
 def test_medium_edge_cases(orc, mb, me):
     """One-cell medium, empty medium, medium touching both boundaries'
