@@ -215,6 +215,7 @@ def variants(p3, ref64, pop64, headline):
     t, g, nl, _ = time_solver(p2, 1, 1, 1000, precision="fp64", variant="quad", tile=128, steps_per_launch=16)
     var["n2_fp64_two_level"] = {"value": p2.grid.n_med * p2.grid.nt / t, "ms": t * 1e3,
                                 "launch_ms": g * 1e3 / nl}
+    var["n2_large"] = n2_large()
     # batched: 64 independent problems (N = 2 and 3 mixed, 1000..30000 cells,
     # 20000 steps), autotuned tiles, whole run replayed from one HIP graph
     import torch
@@ -258,6 +259,33 @@ def variants(p3, ref64, pop64, headline):
     return var
 
 
+def n2_large_problem():
+    """The two-level medium and pulse on 2^24 cells (medium: the central
+    half), 1000 steps: a shape large enough to fill the chip and to make the
+    state's HBM traffic visible."""
+    from paper_1710_09799_amd import workloads as W
+    return W.two_level(nx=1 << 24, nt=1000, name="two_level_2p24")
+
+
+def n2_large():
+    """Two-level, 2^24 cells, FP64 and FP32: streamed one step per launch
+    (every launch reads and writes the whole state: the HBM-bound form) and
+    temporally blocked (16 steps per launch).  GB/s are algorithmic: every
+    medium cell's state and every cell's E and H read and written once per
+    launch."""
+    p = n2_large_problem()
+    out = {"workload": "two-level, 2^24 cells (medium 2^23), 1000 steps"}
+    for prec, s in (("fp64", 8), ("fp32", 4)):
+        for k in (1, 16):
+            t, g, nl, _ = time_solver(p, 1, 1, 0, precision=prec, variant="quad", tile=128, steps_per_launch=k,
+                                      record_pop=False, record_e=False)
+            launch = g / nl
+            byts = (p.grid.n_med * 3 + p.grid.nx * 2) * s * 2
+            out[f"{prec}_k{k}"] = {"value": p.grid.n_med * p.grid.nt / t, "launch_us": launch * 1e6,
+                                   "alg_GBps": byts / launch / 1e9, "hbm_frac": byts / launch / 8e12}
+    return out
+
+
 def calib_copy():
     """A 1 GiB device-to-device copy: reads and writes 2^30 bytes, the
     reference that maps the HBM counters to bytes."""
@@ -279,13 +307,16 @@ PROFILE_CASES = {
     "n6_fp64": ("six_level", dict(nt=1600), dict(precision="fp64", variant="block", tile=256, steps_per_launch=16)),
     "n6_bf16x6": ("six_level", dict(nt=1600), dict(precision="bf16x6", tile=256, steps_per_launch=16)),
     "n6_bf16x3": ("six_level", dict(nt=1600), dict(precision="bf16x3", tile=256, steps_per_launch=16)),
+    "n2_large_fp64_k1": ("n2_large", {}, dict(precision="fp64", variant="quad", tile=128, steps_per_launch=1)),
+    "n2_large_fp64_k16": ("n2_large", {}, dict(precision="fp64", variant="quad", tile=128, steps_per_launch=16)),
+    "n2_large_fp32_k1": ("n2_large", {}, dict(precision="fp32", variant="quad", tile=128, steps_per_launch=1)),
 }
 
 
 def profile_case(name, steps, warmup, calib):
     from paper_1710_09799_amd import workloads as W
     wl, pkw, kw = PROFILE_CASES[name]
-    p = getattr(W, wl)(**pkw)
+    p = n2_large_problem() if wl == "n2_large" else getattr(W, wl)(**pkw)
     t, g, nl, _ = time_solver(p, steps, warmup, 0, record_pop=False, record_e=False, **kw)
     if calib:
         calib_copy()

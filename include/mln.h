@@ -153,7 +153,11 @@ typedef struct {
                                   (one cell per thread, LDS exchange), 2 wavefront
                                   tile (rotation route; tile/64 cells per lane),
                                   3 quad tile (rotation route, N <= 3; four lanes
-                                  per cell, tile = cells per workgroup)             */
+                                  per cell, tile = cells per workgroup).
+                                  Automatic: quad for N <= 3 on grids below 1e5
+                                  cells (latency-bound sizes), workgroup tile on
+                                  larger ones; N = 4: wavefront tile; N = 6:
+                                  workgroup tile; split-BF16 precisions: quad    */
 } mln_options;
 
 /* Gradients of a scalar objective J with respect to the physical inputs (any
@@ -198,6 +202,11 @@ int mln_reset(mln_handle *h);
 
 /* Current step index (number of completed time steps). */
 int mln_current_step(const mln_handle *h, int64_t *step);
+
+/* The kernel configuration the handle runs: variant (1 workgroup tile, 2
+ * wavefront tile, 3 four lanes per cell; the automatic choice resolved),
+ * cells per tile and time steps per launch.  Any pointer may be NULL. */
+int mln_get_config(const mln_handle *h, int32_t *variant, int32_t *tile, int32_t *steps_per_launch);
 
 /* Copy the current fields to host arrays E[nx] (step n) and H[nx-1]
  * (step n-1/2).  Synchronises the stream. */

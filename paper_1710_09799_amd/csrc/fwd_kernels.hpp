@@ -11,6 +11,7 @@ enum { ROUTE_ROT = 0, ROUTE_DIAG = 1, ROUTE_RODR = 2, ROUTE_PADE = 3 };
 
 constexpr int kMaxTile = 256;      // threads (= cells) per tile workgroup
 constexpr int kMaxQuadTile = 256;  // cells per tile of the four-lanes-per-cell kernel
+constexpr int64_t kQuadMaxAutoCells = 100000;  // automatic variant: quad kernel below this grid size
 constexpr int kMaxStepsPerLaunch = 128;  // time steps fused into one launch (halo <= tile/2 < 128)
 constexpr int kPadeMax = 7;              // highest Pade degree of the per-step Pade route
 constexpr size_t kPadeMaxLds = 160 * 1024;  // LDS of one compute unit

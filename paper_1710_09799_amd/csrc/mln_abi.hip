@@ -428,7 +428,13 @@ int mln_init(const mln_medium *medium, const mln_grid *grid, const mln_source *s
   if (opt.variant < 0 || opt.variant > 3) return set_err(MLN_EINVAL, "unknown kernel variant");
   const bool rot = h->route == MLN_ROUTE_ROTATION;
   int variant = opt.variant;
-  if (variant == 0) variant = !rot ? 1 : (h->f.N <= 3 ? 3 : (h->f.N == 4 && !h->cf ? 2 : 1));
+  // automatic choice: four lanes per cell while the grid is too small to
+  // fill the chip with one cell per thread (the step is latency-bound there,
+  // and four lanes give four times the wavefronts); one cell per thread on
+  // large grids, where the quad's replicated field work costs issue slots
+  // (measured crossover near 1e5 cells at N = 2, 3)
+  if (variant == 0)
+    variant = !rot ? 1 : (h->f.N <= 3 ? (grid->nx < kQuadMaxAutoCells ? 3 : 1) : (h->f.N == 4 && !h->cf ? 2 : 1));
   if (h->mfma) {
     // one cell per thread (1) or four lanes per cell (3, the default)
     if (opt.variant == 0) variant = 3;
@@ -530,6 +536,14 @@ int mln_reset(mln_handle *h) {
 int mln_current_step(const mln_handle *h, int64_t *step) {
   if (!h || !step) return set_err(MLN_EINVAL, "null argument");
   *step = h->step;
+  return MLN_OK;
+}
+
+int mln_get_config(const mln_handle *h, int32_t *variant, int32_t *tile, int32_t *steps_per_launch) {
+  if (!h) return set_err(MLN_EINVAL, "null handle");
+  if (variant) *variant = h->quad ? 3 : (h->wave ? 2 : 1);
+  if (tile) *tile = h->W;
+  if (steps_per_launch) *steps_per_launch = h->halo;
   return MLN_OK;
 }
 

@@ -69,7 +69,7 @@ class _Factors(ctypes.Structure):
 
 
 # every symbol include/mln.h declares
-EXPORTS = ["mln_init", "mln_step", "mln_run", "mln_reset", "mln_current_step", "mln_get_fields",
+EXPORTS = ["mln_init", "mln_step", "mln_run", "mln_reset", "mln_current_step", "mln_get_config", "mln_get_fields",
            "mln_state_bytes", "mln_save_state", "mln_load_state", "mln_bloch_only", "mln_free",
            "mln_strerror", "mln_last_error", "mln_setup_factors", "mln_version", "mln_grad",
            "mln_chain_rule", "mln_init_batch", "mln_batch_tune", "mln_batch_configure",
@@ -97,6 +97,7 @@ def load():
         "mln_run": ([P], ctypes.c_int),
         "mln_reset": ([P], ctypes.c_int),
         "mln_current_step": ([P, i64p], ctypes.c_int),
+        "mln_get_config": ([P, i32p, i32p, i32p], ctypes.c_int),
         "mln_get_fields": ([P, _dp, _dp], ctypes.c_int),
         "mln_state_bytes": ([P, i64p], ctypes.c_int),
         "mln_save_state": ([P, P], ctypes.c_int),
@@ -263,6 +264,13 @@ class Solver:
         v = ctypes.c_int64()
         _check(self._L.mln_current_step(self._h, ctypes.byref(v)))
         return v.value
+
+    def config(self):
+        """The kernel the handle runs: variant ("block", "wave" or "quad"),
+        tile and steps per launch."""
+        v, w, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(self._L.mln_get_config(self._h, ctypes.byref(v), ctypes.byref(w), ctypes.byref(k)))
+        return {"variant": {1: "block", 2: "wave", 3: "quad"}[v.value], "tile": w.value, "steps_per_launch": k.value}
 
     def outputs(self):
         return dict(probe=self.probe, e_snap=self.e_snap, pop=self.pop)

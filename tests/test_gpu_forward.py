@@ -322,6 +322,28 @@ def test_bloch_only_fp32_pade(orc, n, seed, fmax):
     assert np.max(np.abs(dp - ref["dp"])) < 1e-3 * np.max(np.abs(ref["dp"]))
 
 
+def test_automatic_kernel_choice():
+    """Variant 0 resolves to the quad kernel on latency-bound grids and to one
+    cell per thread on large ones; the large-grid choice matches the quad
+    kernel's FP64 result to rounding."""
+    cases = [(W.three_level(nx=20000, nt=10), "fp32c", "quad"),
+             (W.two_level(), "fp64", "quad"),
+             (W.three_level(nx=150000, nt=10), "fp64", "block"),
+             (W.six_level(nx=2000, nt=10), "fp64", "block"),
+             (W.six_level(nx=2000, nt=10), "bf16x6", "quad")]
+    for p, prec, want in cases:
+        s = mln.Solver(p, precision=prec, record_pop=False, record_e=False)
+        cfg = s.config()
+        s.close()
+        assert cfg["variant"] == want, (p.name, prec, cfg)
+    p = W.three_level(nx=150000, nt=600)
+    _print_case("auto_large", nx=p.grid.nx, nt=p.grid.nt)
+    a = mln.run(p, precision="fp64", snap_every=200)
+    b = mln.run(p, precision="fp64", snap_every=200, variant="quad", tile=128, steps_per_launch=20)
+    ee, ep = _errs(a, b)
+    assert ee < 1e-12 and ep < 1e-12, (ee, ep)
+
+
 def test_pade_route_rejects_compensated_state():
     p = W.random_problem(4, 1, nx=100, nt=50)
     for prec in ("fp32c", "fp32cf"):
