@@ -268,16 +268,16 @@ def n2_large_problem():
 
 
 def n2_large():
-    """Two-level, 2^24 cells, FP64 and FP32: streamed one step per launch
-    (every launch reads and writes the whole state: the HBM-bound form) and
-    temporally blocked (16 steps per launch).  GB/s are algorithmic: every
+    """Two-level, 2^24 cells, FP64 and FP32, one cell per thread (tile 256):
+    streamed one step per launch (every launch reads and writes the whole
+    state: the HBM-bound form) and temporally blocked (16 steps per launch).  GB/s are algorithmic: every
     medium cell's state and every cell's E and H read and written once per
     launch."""
     p = n2_large_problem()
     out = {"workload": "two-level, 2^24 cells (medium 2^23), 1000 steps"}
     for prec, s in (("fp64", 8), ("fp32", 4)):
         for k in (1, 16):
-            t, g, nl, _ = time_solver(p, 1, 1, 0, precision=prec, variant="quad", tile=128, steps_per_launch=k,
+            t, g, nl, _ = time_solver(p, 1, 1, 0, precision=prec, variant="block", tile=256, steps_per_launch=k,
                                       record_pop=False, record_e=False)
             launch = g / nl
             byts = (p.grid.n_med * 3 + p.grid.nx * 2) * s * 2
@@ -307,9 +307,10 @@ PROFILE_CASES = {
     "n6_fp64": ("six_level", dict(nt=1600), dict(precision="fp64", variant="block", tile=256, steps_per_launch=16)),
     "n6_bf16x6": ("six_level", dict(nt=1600), dict(precision="bf16x6", tile=256, steps_per_launch=16)),
     "n6_bf16x3": ("six_level", dict(nt=1600), dict(precision="bf16x3", tile=256, steps_per_launch=16)),
-    "n2_large_fp64_k1": ("n2_large", {}, dict(precision="fp64", variant="quad", tile=128, steps_per_launch=1)),
-    "n2_large_fp64_k16": ("n2_large", {}, dict(precision="fp64", variant="quad", tile=128, steps_per_launch=16)),
-    "n2_large_fp32_k1": ("n2_large", {}, dict(precision="fp32", variant="quad", tile=128, steps_per_launch=1)),
+    "n2_large_fp64_k1": ("n2_large", {}, dict(precision="fp64", variant="block", tile=256, steps_per_launch=1)),
+    "n2_large_fp64_k16": ("n2_large", {}, dict(precision="fp64", variant="block", tile=256, steps_per_launch=16)),
+    "n2_large_fp32_k1": ("n2_large", {}, dict(precision="fp32", variant="block", tile=256, steps_per_launch=1)),
+    "n2_large_fp32_k16": ("n2_large", {}, dict(precision="fp32", variant="block", tile=256, steps_per_launch=16)),
 }
 
 
