@@ -50,6 +50,11 @@ def lib():
         L.orc_bloch.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, ctypes.c_double, dp, dp,
                                 ctypes.c_double, i64, i64, ctypes.c_double, dp, dp, dp, dp, dp,
                                 ctypes.c_int]
+        L.orc_grad.restype = ctypes.c_int
+        L.orc_grad.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, ctypes.c_double, dp, dp,
+                               ctypes.c_double, i64, i64, ctypes.c_double, ctypes.c_double, i64, i64,
+                               ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, ctypes.c_double,
+                               dp, dp, dp, dp, dp, dp, dp, ctypes.c_int]
         L.orc_expm.restype = ctypes.c_int
         L.orc_expm.argtypes = [ctypes.c_int, dp, dp]
         L.orc_superop.restype = ctypes.c_int
@@ -161,3 +166,31 @@ def bloch(med, efield, dt, nthreads=0):
         raise RuntimeError(f"oracle bloch failed ({rc})")
     return dict(pop=pop, dp=dp, rho=rho,
                 diag=dict(trace=diag[0], herm=diag[1], min_eig=diag[2], purity=diag[3]))
+
+
+def grad(problem, dJ_dprobe, nthreads=0):
+    """FP64 adjoint of ``run``: gradients of J with respect to the physical
+    inputs, given g[n] = dJ/dprobe[n] (n = 0..nt).  Same conventions as the
+    library's mln_grads: Hermitian inputs (H0, dipole) as N x N complex arrays
+    where, for a < b, d[a, b] = dJ/dRe X_ab + i dJ/dIm X_ab under the Hermitian
+    perturbation of the pair (d[b, a] its conjugate) and d[a, a] = dJ/dX_aa.
+    Stores the whole trajectory: for small problems only."""
+    med, g, src = problem.medium, problem.grid, problem.source
+    n, h0, mu, nj, jumps, rates, deph, relax, rho0 = _medium_args(med)
+    gp = np.ascontiguousarray(np.asarray(dJ_dprobe, dtype=np.float64))
+    if gp.shape != (g.nt + 1,):
+        raise ValueError("dJ_dprobe must have nt + 1 entries")
+    samples = np.ascontiguousarray(src.samples[: g.nt + 1], dtype=np.float64)
+    gh = np.zeros((n, n), dtype=np.complex128)
+    gm = np.zeros((n, n), dtype=np.complex128)
+    gr = np.zeros(max(nj, 1))
+    gd, ga, gn = np.zeros(1), np.zeros(1), np.zeros(1)
+    rc = lib().orc_grad(n, _p(h0), _p(mu), nj, _p(jumps), _p(rates), deph, _p(relax), _p(rho0),
+                        float(med.density), g.nx, g.nt, g.dx, g.dt, g.med_begin, g.med_end,
+                        g.eps_r, g.mu_r, g.sigma, _p(samples), float(src.amplitude), _p(gp),
+                        _p(gh.view(np.float64)), _p(gm.view(np.float64)), _p(gr), _p(gd), _p(ga), _p(gn),
+                        nthreads)
+    if rc:
+        raise RuntimeError(f"oracle adjoint failed ({rc})")
+    return dict(d_h0=gh, d_dipole=gm, d_jump_rate=gr[:nj], d_dephasing=float(gd[0]),
+                d_amplitude=float(ga[0]), d_density=float(gn[0]))

@@ -25,7 +25,11 @@
  *     LU with partial pivoting, no structure exploited;
  *   * the polarisation derivative from Eq. polarization2,
  *     dP/dt = N_a Re Tr{ mu (L0(rho) + G(rho)) }, evaluated on rho^{n+1/2};
- *   * the 1-D Yee FDTD update of Eq. maxwell on the staggered grid of Fig. 1.
+ *   * the 1-D Yee FDTD update of Eq. maxwell on the staggered grid of Fig. 1;
+ *   * the FP64 adjoint of that discrete map (orc_grad): reverse mode through
+ *     every step, matrix-exponential derivatives from the block identity for
+ *     the Frechet derivative, gradients with respect to H0, the dipole
+ *     matrix, the jump and dephasing rates, N_a and the source amplitude.
  *
  * Readings of points the paper leaves open (same on the GPU side, but written
  * independently there):
@@ -555,4 +559,385 @@ int orc_bloch(int n, const double *h0, const double *mu, int n_jump, const doubl
     free(r0);
     medium_free(&m);
     return 0;
+}
+
+/* ----------------------------------------------------------------------- */
+/* FP64 adjoint of orc_run (reverse mode through the steps above)           */
+/*
+ * For J(probe) with g[n] = dJ/dprobe[n], the gradients with respect to the
+ * physical inputs.  Reverse mode over the exact discrete map of orc_run:
+ * the forward pass stores rho before every cell step and the field the cell
+ * saw; the reverse pass walks the steps backwards.  Conventions: for a
+ * complex quantity z the adjoint is Z = dJ/dRe z + i dJ/dIm z, so a linear
+ * map y = A x gives X += A^H Y, and <X, Y> = Re tr(X^H Y).  The derivative
+ * of a matrix exponential enters through the adjoint of its Frechet
+ * derivative, L(A, .)^* = L(A^H, .), evaluated by the block identity
+ * exp([[B, C], [0, B]]) = [[e^B, L(B, C)], [0, e^B]] (Higham, Functions of
+ * Matrices, 2008) with the same generic Pade exponential.  The field-free
+ * generator is linear in H0, the jump rates and the dephasing rate, so their
+ * gradients are inner products of the accumulated dJ/dS with the
+ * superoperators of the derivative maps, built by applying each map to the
+ * basis matrices.  Everything is recomputed the slow, obvious way.
+ */
+
+/* out = L(A^H, G) for n x n complex A, G.  L is linear in G, so G enters the
+ * block scaled to the 1-norm of A (otherwise a large G would set the
+ * scaling of the block exponential and its many squarings) and the result is
+ * scaled back. */
+static int frechet_adj(int n, const cx *A, const cx *G, cx *out)
+{
+    int m = 2 * n;
+    double an = 0.0, gn = 0.0;
+    for (int j = 0; j < n; ++j) {
+        double sa = 0.0, sg = 0.0;
+        for (int i = 0; i < n; ++i) { sa += cabs(A[i * n + j]); sg += cabs(G[i * n + j]); }
+        if (sa > an) an = sa;
+        if (sg > gn) gn = sg;
+    }
+    if (gn == 0.0) {
+        for (int i = 0; i < n * n; ++i) out[i] = 0.0;
+        return 0;
+    }
+    double sc = (an > 0.0 ? an : 1.0) / gn;
+    cx *B = (cx *)calloc((size_t)m * m, sizeof(cx));
+    cx *F = (cx *)malloc(sizeof(cx) * m * m);
+    cx *w = (cx *)malloc(sizeof(cx) * 5 * m * m);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            cx ah = conj(A[j * n + i]);
+            B[i * m + j] = ah;
+            B[(n + i) * m + n + j] = ah;
+            B[i * m + n + j] = sc * G[i * n + j];
+        }
+    int rc = expm_work(m, B, F, w);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) out[i * n + j] = F[i * m + n + j] / sc;
+    free(B); free(F); free(w);
+    return rc;
+}
+
+/* the derivative maps of the field-free generator */
+enum { DM_COMM = 0, DM_JUMP = 1, DM_DEPH = 2 };
+
+/* Y = (d generator / d theta)(X) for: DM_COMM -(i/hbar)[K, X];
+ * DM_JUMP L X L^+ - 1/2 {L^+ L, X}; DM_DEPH -offdiag(X). */
+static void deriv_map(int kind, int n, const cx *K, const cx *X, cx *Y, cx *t1, cx *t2)
+{
+    if (kind == DM_COMM) {
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b) {
+                cx s = 0;
+                for (int k = 0; k < n; ++k) s += K[a * n + k] * X[k * n + b] - X[a * n + k] * K[k * n + b];
+                Y[a * n + b] = -I / ORC_HBAR * s;
+            }
+    } else if (kind == DM_JUMP) {
+        mat_mul(n, K, X, t1);
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b) {
+                cx s = 0;
+                for (int k = 0; k < n; ++k) s += t1[a * n + k] * conj(K[b * n + k]);
+                Y[a * n + b] = s;
+            }
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b) {
+                cx s = 0;
+                for (int k = 0; k < n; ++k) s += conj(K[k * n + a]) * K[k * n + b];
+                t2[a * n + b] = s;
+            }
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b) {
+                cx s = 0;
+                for (int k = 0; k < n; ++k) s += t2[a * n + k] * X[k * n + b] + X[a * n + k] * t2[k * n + b];
+                Y[a * n + b] -= 0.5 * s;
+            }
+    } else {
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b) Y[a * n + b] = (a == b) ? 0.0 : -X[a * n + b];
+    }
+}
+
+/* <GS, dS> where dS is the superoperator of the derivative map */
+static double super_inner(int kind, int n, const cx *K, const cx *GS)
+{
+    int n2 = n * n;
+    cx *X = (cx *)calloc(n2, sizeof(cx)), *Y = (cx *)malloc(sizeof(cx) * n2);
+    cx *t1 = (cx *)malloc(sizeof(cx) * n2), *t2 = (cx *)malloc(sizeof(cx) * n2);
+    double acc = 0.0;
+    for (int q = 0; q < n2; ++q) {
+        memset(X, 0, sizeof(cx) * n2);
+        X[q] = 1.0;
+        deriv_map(kind, n, K, X, Y, t1, t2);
+        for (int p = 0; p < n2; ++p) acc += creal(conj(GS[p * n2 + q]) * Y[p]);
+    }
+    free(X); free(Y); free(t1); free(t2);
+    return acc;
+}
+
+/* gradient of a Hermitian matrix input from the unconstrained adjoint G:
+ * off-diagonal a < b: G_ab + conj(G_ba) (real and imaginary perturbation of
+ * the pair), conjugate below the diagonal; diagonal: Re G_aa */
+static void herm_grad(int n, const cx *G, double *out)
+{
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+            cx v = (a == b) ? creal(G[a * n + a]) : (a < b ? G[a * n + b] + conj(G[b * n + a])
+                                                           : conj(G[b * n + a] + conj(G[a * n + b])));
+            out[2 * (a * n + b)] = creal(v);
+            out[2 * (a * n + b) + 1] = cimag(v);
+        }
+}
+
+int orc_grad(int n, const double *h0, const double *mu, int n_jump, const double *jump,
+             const double *rate, double deph, const double *relax, const double *rho0,
+             double Na, int64_t nx, int64_t nt, double dx, double dt, int64_t mb, int64_t me,
+             double eps_r, double mu_r, double sigma, const double *src, double amp,
+             const double *gprobe, double *g_h0, double *g_mu, double *g_rate, double *g_deph,
+             double *g_amp, double *g_Na, int nthreads)
+{
+    if (n < 2 || nx < 3 || nt < 0 || mb < 1 || me < mb || me > nx - 1) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    medium_t m;
+    if (medium_init(&m, n, h0, mu, n_jump, jump, rate, deph, relax, dt)) return -2;
+    int n2 = n * n;
+    int64_t nmed = me - mb;
+    /* the trajectory: rho before every step, the field each cell saw */
+    size_t need = (size_t)nt * (size_t)(nmed ? nmed : 1) * n2;
+    if (need > ((size_t)1 << 27)) { medium_free(&m); return -3; }  /* 2 GiB of history */
+    cx *hist = (cx *)malloc(sizeof(cx) * (need ? need : 1));
+    double *ehist = (double *)malloc(sizeof(double) * (size_t)(nt ? nt : 1) * (nmed ? nmed : 1));
+    cx *rho = (cx *)malloc(sizeof(cx) * (size_t)(nmed ? nmed : 1) * n2);
+    cx *r0 = load_cx(rho0, n2);
+    for (int64_t c = 0; c < nmed; ++c) memcpy(rho + c * n2, r0, sizeof(cx) * n2);
+    double *E = (double *)calloc(nx, sizeof(double));
+    double *H = (double *)calloc(nx, sizeof(double));
+    double *P = (double *)calloc(nmed ? nmed : 1, sizeof(double));
+    double eps = ORC_EPS0 * eps_r, muu = ORC_MU0 * mu_r;
+    double cl = 1.0 / sqrt(eps * muu);
+    double kmur = (cl * dt - dx) / (cl * dt + dx);
+    double sg = sigma * dt / (2.0 * eps);
+    double ca = (1.0 - sg) / (1.0 + sg), cb = (dt / eps) / (1.0 + sg);
+    double ch = dt / (muu * dx);
+    E[0] = amp * src[0];
+    for (int64_t t = 0; t < nt; ++t) {
+        for (int64_t i = 0; i + 1 < nx; ++i) H[i] += ch * (E[i + 1] - E[i]);
+        memcpy(hist + (size_t)t * nmed * n2, rho, sizeof(cx) * nmed * n2);
+        for (int64_t c = 0; c < nmed; ++c) ehist[t * nmed + c] = E[mb + c];
+#pragma omp parallel
+        {
+            cell_ws_t ws;
+            ws_alloc(&ws, n);
+#pragma omp for schedule(static)
+            for (int64_t c = 0; c < nmed; ++c)
+                P[c] = cell_step(&m, rho + c * n2, E[mb + c], dt, Na, &ws);
+            ws_free(&ws);
+        }
+        double e_nm2 = E[nx - 2], e_nm1 = E[nx - 1];
+        for (int64_t i = 1; i + 1 < nx; ++i) {
+            double dp = (i >= mb && i < me) ? P[i - mb] : 0.0;
+            E[i] = ca * E[i] + cb * (-dp + (H[i] - H[i - 1]) / dx);
+        }
+        E[0] = amp * src[t + 1];
+        E[nx - 1] = e_nm2 + kmur * (E[nx - 2] - e_nm1);
+    }
+
+    /* reverse sweep */
+    double *lE = (double *)calloc(nx, sizeof(double)), *lEo = (double *)calloc(nx, sizeof(double));
+    double *lH = (double *)calloc(nx, sizeof(double));
+    double *lP = (double *)calloc(nmed ? nmed : 1, sizeof(double));
+    double *lEc = (double *)calloc(nmed ? nmed : 1, sizeof(double));
+    cx *lrho = (cx *)calloc((size_t)(nmed ? nmed : 1) * n2, sizeof(cx));
+    cx *mu_cx = m.mu;
+    int nth = 1;
+#ifdef _OPENMP
+    nth = omp_get_max_threads();
+#endif
+    /* per-thread accumulators: dJ/dE0 (n2 x n2), dJ/dS (n2 x n2), dJ/dmu (n x n), dJ/dNa */
+    cx *accE0 = (cx *)calloc((size_t)nth * n2 * n2, sizeof(cx));
+    cx *accS = (cx *)calloc((size_t)nth * n2 * n2, sizeof(cx));
+    cx *accMu = (cx *)calloc((size_t)nth * n2, sizeof(cx));
+    double *accNa = (double *)calloc(nth, sizeof(double));
+    double gamp = 0.0;
+    double alpha = dt / ORC_HBAR;
+    for (int64_t t = nt - 1; t >= 0; --t) {
+        /* lE holds dJ/dE after step t; the probe of step t+1 */
+        lE[nx - 1] += gprobe[t + 1];
+        memset(lEo, 0, sizeof(double) * nx);
+        /* Mur boundary: E[nx-1] = E_old[nx-2] + kmur (E_new[nx-2] - E_old[nx-1]) */
+        double bnd = lE[nx - 1];
+        lE[nx - 2] += kmur * bnd;
+        lEo[nx - 2] += bnd;
+        lEo[nx - 1] -= kmur * bnd;
+        /* source */
+        gamp += lE[0] * src[t + 1];
+        /* interior E update (H after this step's H update) */
+        for (int64_t i = 1; i + 1 < nx; ++i) {
+            double l = lE[i];
+            lEo[i] += ca * l;
+            lH[i] += cb / dx * l;
+            lH[i - 1] -= cb / dx * l;
+            if (i >= mb && i < me) lP[i - mb] = -cb * l;
+        }
+        /* cell steps */
+#pragma omp parallel
+        {
+            int tid = 0;
+#ifdef _OPENMP
+            tid = omp_get_thread_num();
+#endif
+            cx *aE0 = accE0 + (size_t)tid * n2 * n2, *aS = accS + (size_t)tid * n2 * n2;
+            cx *aMu = accMu + (size_t)tid * n2;
+            cx *v = (cx *)malloc(sizeof(cx) * n2), *w = (cx *)malloc(sizeof(cx) * n2);
+            cx *rn = (cx *)malloc(sizeof(cx) * n2), *y = (cx *)malloc(sizeof(cx) * n2);
+            cx *W = (cx *)malloc(sizeof(cx) * n2), *X = (cx *)malloc(sizeof(cx) * n2);
+            cx *t1 = (cx *)malloc(sizeof(cx) * n2), *t2 = (cx *)malloc(sizeof(cx) * n2);
+            cx *lw = (cx *)malloc(sizeof(cx) * n2), *lv = (cx *)malloc(sizeof(cx) * n2);
+            cx *GW = (cx *)malloc(sizeof(cx) * n2), *GX = (cx *)malloc(sizeof(cx) * n2);
+            cx *ex = (cx *)malloc(sizeof(cx) * 5 * n2);
+#pragma omp for schedule(static)
+            for (int64_t c = 0; c < nmed; ++c) {
+                const cx *ro = hist + ((size_t)t * nmed + c) * n2;
+                double Ec = ehist[t * nmed + c];
+                cx *L = lrho + (size_t)c * n2;  /* dJ/drho after this step */
+                /* recompute the step */
+                super_apply(n2, m.E0, ro, v);
+                for (int i = 0; i < n2; ++i) X[i] = (I * alpha * Ec) * mu_cx[i];
+                expm_work(n, X, W, ex);
+                mat_mul(n, W, v, t1);
+                for (int a = 0; a < n; ++a)
+                    for (int b = 0; b < n; ++b) {
+                        cx s = 0;
+                        for (int k = 0; k < n; ++k) s += t1[a * n + k] * conj(W[b * n + k]);
+                        w[a * n + b] = s;
+                    }
+                super_apply(n2, m.E0, w, rn);
+                super_apply(n2, m.S, rn, y);
+                /* P = Na Re <vec mu, S rho_new> */
+                double lp = lP[c];
+                double ptr = 0.0;
+                for (int a = 0; a < n; ++a)
+                    for (int b = 0; b < n; ++b) ptr += creal(mu_cx[a * n + b] * y[b * n + a]);
+                accNa[tid] += lp * ptr;
+                /* dJ/drho_new += lp Na S^H vec(mu); dJ/dS += lp Na vec(mu) rho_new^H */
+                for (int q = 0; q < n2; ++q) {
+                    cx s = 0;
+                    for (int p = 0; p < n2; ++p) s += conj(m.S[p * n2 + q]) * mu_cx[p];
+                    L[q] += lp * Na * s;
+                }
+                for (int p = 0; p < n2; ++p)
+                    for (int q = 0; q < n2; ++q) aS[p * n2 + q] += lp * Na * mu_cx[p] * conj(rn[q]);
+                /* dJ/dmu from P: conj(y_ba) */
+                for (int a = 0; a < n; ++a)
+                    for (int b = 0; b < n; ++b) aMu[a * n + b] += lp * Na * conj(y[b * n + a]);
+                /* rho_new = E0 w */
+                for (int q = 0; q < n2; ++q) {
+                    cx s = 0;
+                    for (int p = 0; p < n2; ++p) s += conj(m.E0[p * n2 + q]) * L[p];
+                    lw[q] = s;
+                }
+                for (int p = 0; p < n2; ++p)
+                    for (int q = 0; q < n2; ++q) aE0[p * n2 + q] += L[p] * conj(w[q]);
+                /* w = W v W^+ : lv = W^+ lw W; GW = lw W v^H + lw^H W v */
+                for (int a = 0; a < n; ++a)
+                    for (int b = 0; b < n; ++b) {
+                        cx s = 0;
+                        for (int k = 0; k < n; ++k) s += conj(W[k * n + a]) * lw[k * n + b];
+                        t1[a * n + b] = s;
+                    }
+                mat_mul(n, t1, W, lv);
+                for (int a = 0; a < n; ++a)
+                    for (int b = 0; b < n; ++b) {
+                        cx s = 0;
+                        for (int k = 0; k < n; ++k) s += W[a * n + k] * conj(v[b * n + k]);
+                        t1[a * n + b] = s;  /* W v^H */
+                    }
+                mat_mul(n, lw, t1, GW);
+                mat_mul(n, W, v, t1);       /* W v */
+                for (int a = 0; a < n; ++a)
+                    for (int b = 0; b < n; ++b) {
+                        cx s = 0;
+                        for (int k = 0; k < n; ++k) s += conj(lw[k * n + a]) * t1[k * n + b];
+                        GW[a * n + b] += s;
+                    }
+                /* W = exp(X), X = i alpha E mu */
+                frechet_adj(n, X, GW, GX);
+                double le = 0.0;
+                for (int i = 0; i < n2; ++i) {
+                    le += creal(conj(GX[i]) * (I * alpha) * mu_cx[i]);
+                    aMu[i] += GX[i] * conj(I * alpha * Ec);
+                }
+                lEc[c] = le;
+                /* v = E0 rho_old */
+                for (int q = 0; q < n2; ++q) {
+                    cx s = 0;
+                    for (int p = 0; p < n2; ++p) s += conj(m.E0[p * n2 + q]) * lv[p];
+                    t2[q] = s;
+                }
+                for (int p = 0; p < n2; ++p)
+                    for (int q = 0; q < n2; ++q) aE0[p * n2 + q] += lv[p] * conj(ro[q]);
+                memcpy(L, t2, sizeof(cx) * n2);
+            }
+            free(v); free(w); free(rn); free(y); free(W); free(X); free(t1); free(t2);
+            free(lw); free(lv); free(GW); free(GX); free(ex);
+        }
+        for (int64_t c = 0; c < nmed; ++c) lEo[mb + c] += lEc[c];
+        /* H update: H_i += ch (E_old[i+1] - E_old[i]) */
+        for (int64_t i = 0; i + 1 < nx; ++i) {
+            lEo[i + 1] += ch * lH[i];
+            lEo[i] -= ch * lH[i];
+        }
+        memcpy(lE, lEo, sizeof(double) * nx);
+    }
+    /* initial field: E[0] = amp src[0] */
+    gamp += lE[0] * src[0];
+
+    /* reduce the per-thread accumulators */
+    for (int th = 1; th < nth; ++th) {
+        for (int i = 0; i < n2 * n2; ++i) {
+            accE0[i] += accE0[(size_t)th * n2 * n2 + i];
+            accS[i] += accS[(size_t)th * n2 * n2 + i];
+        }
+        for (int i = 0; i < n2; ++i) accMu[i] += accMu[(size_t)th * n2 + i];
+        accNa[0] += accNa[th];
+    }
+    /* E0 = exp(S dt/2): dJ/dS += dt/2 L((S dt/2)^H, dJ/dE0) */
+    cx *A = (cx *)malloc(sizeof(cx) * n2 * n2), *GA = (cx *)malloc(sizeof(cx) * n2 * n2);
+    for (int i = 0; i < n2 * n2; ++i) A[i] = m.S[i] * (0.5 * dt);
+    int rc = frechet_adj(n2, A, accE0, GA);
+    for (int i = 0; i < n2 * n2; ++i) accS[i] += 0.5 * dt * GA[i];
+    /* parameters of the field-free generator */
+    cx *K = (cx *)calloc(n2, sizeof(cx));
+    cx *GH = (cx *)calloc(n2, sizeof(cx));
+    for (int a = 0; a < n; ++a)
+        for (int b = a; b < n; ++b) {
+            if (a == b) {
+                memset(K, 0, sizeof(cx) * n2);
+                K[a * n + a] = 1.0;
+                GH[a * n + a] = super_inner(DM_COMM, n, K, accS);
+            } else {
+                memset(K, 0, sizeof(cx) * n2);
+                K[a * n + b] = 1.0; K[b * n + a] = 1.0;
+                double gr = super_inner(DM_COMM, n, K, accS);
+                memset(K, 0, sizeof(cx) * n2);
+                K[a * n + b] = I; K[b * n + a] = -I;
+                double gi = super_inner(DM_COMM, n, K, accS);
+                GH[a * n + b] = gr + I * gi;
+                GH[b * n + a] = gr - I * gi;
+            }
+        }
+    if (g_h0)
+        for (int i = 0; i < n2; ++i) { g_h0[2 * i] = creal(GH[i]); g_h0[2 * i + 1] = cimag(GH[i]); }
+    if (g_rate)
+        for (int j = 0; j < n_jump; ++j) g_rate[j] = super_inner(DM_JUMP, n, m.jump + (size_t)j * n2, accS);
+    if (g_deph) *g_deph = super_inner(DM_DEPH, n, NULL, accS);
+    if (g_mu) herm_grad(n, accMu, g_mu);
+    if (g_amp) *g_amp = gamp;
+    if (g_Na) *g_Na = accNa[0];
+    free(A); free(GA); free(K); free(GH);
+    free(accE0); free(accS); free(accMu); free(accNa);
+    free(lE); free(lEo); free(lH); free(lP); free(lEc); free(lrho);
+    free(hist); free(ehist); free(rho); free(r0); free(E); free(H); free(P);
+    medium_free(&m);
+    return rc ? -4 : 0;
 }
