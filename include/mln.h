@@ -253,16 +253,17 @@ const char *mln_last_error(void);
  * propagation (Sec. 3, 4.1).  Every launch covers one chunk of time steps for
  * all problems: workgroup g is tile t of problem i according to a table on
  * the device, two- and three-level problems share the launch, and the tiles
- * are the four-lanes-per-cell tiles of the rotation route.
+ * are one-cell-per-thread (variant 1, the default) or four-lanes-per-cell
+ * (variant 3) tiles of the rotation route.
  *   media, grids, sources  arrays of n_inst descriptors (as for mln_init);
  *                          every grid has the same dt and nt; N = 2 or 3
  *   records                array of n_inst recordings, or NULL (none)
  *   options                precision MLN_FP64, MLN_FP32, MLN_FP32_COMP or
  *                          MLN_FP32_COMP_FIELDS;
- *                          route MLN_ROUTE_ROTATION; variant 0 or 3;
- *                          ckpt_every 0; tile / steps_per_launch as for
- *                          mln_init (0: 128 cells, 16 steps); stream shared
- *                          by all problems
+ *                          route MLN_ROUTE_ROTATION; variant 0 (= 1), 1 or
+ *                          3; ckpt_every 0; tile / steps_per_launch as for
+ *                          mln_init (0: 256 cells for variant 1, 128 for
+ *                          variant 3; 16 steps); stream shared by all problems
  * Each problem gets its own handle (device state, factors, recording), owned
  * by the batch; mln_batch_instance lends it out (do not mln_free it).
  * Errors: those of mln_init (prefixed with the problem index in
@@ -272,18 +273,21 @@ int mln_init_batch(int32_t n_inst, const mln_medium *media, const mln_grid *grid
                    const mln_source *sources, const mln_record *records,
                    const mln_options *options, mln_batch **out);
 
-/* Autotuner: time every candidate tile shape (cells per tile, steps per
- * launch) on the batch itself over about trial_steps steps (HIP events on
- * the batch's stream), keep the fastest per time step, and reset the batch
- * to step 0.  The chosen shape is returned in *tile and *steps_per_launch
- * (either may be NULL).  Synchronises. */
-int mln_batch_tune(mln_batch *b, int32_t trial_steps, int32_t *tile, int32_t *steps_per_launch);
+/* Autotuner: time every candidate (kernel variant 1 or 3, cells per tile,
+ * steps per launch) on the batch itself over about trial_steps steps (HIP
+ * events on the batch's stream), keep the fastest per time step, and reset
+ * the batch to step 0.  The choice is returned in *variant, *tile and
+ * *steps_per_launch (any may be NULL).  Synchronises. */
+int mln_batch_tune(mln_batch *b, int32_t trial_steps, int32_t *variant, int32_t *tile,
+                   int32_t *steps_per_launch);
 
-/* Set the tile shape explicitly (batch at step 0) / read it back together
- * with the number of workgroups of one launch. */
-int mln_batch_configure(mln_batch *b, int32_t tile, int32_t steps_per_launch);
-int mln_batch_get_config(const mln_batch *b, int32_t *tile, int32_t *steps_per_launch,
-                         int64_t *workgroups);
+/* Set the kernel variant (1: one cell per thread, tile a multiple of 64 in
+ * [64, 256]; 3: four lanes per cell, tile a multiple of 16 in [32, 256]) and
+ * tile shape explicitly (batch at step 0) / read them back together with the
+ * number of workgroups of one launch. */
+int mln_batch_configure(mln_batch *b, int32_t variant, int32_t tile, int32_t steps_per_launch);
+int mln_batch_get_config(const mln_batch *b, int32_t *variant, int32_t *tile,
+                         int32_t *steps_per_launch, int64_t *workgroups);
 
 /* on = 1 (default): mln_batch_run from step 0 replays one HIP graph holding
  * every launch of the run (captured on first use, rebuilt after a change of

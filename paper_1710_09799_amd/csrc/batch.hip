@@ -16,25 +16,38 @@ using namespace mln;
 
 namespace mln {
 
+// quad = true: four lanes per cell (4 W threads per workgroup); false: one
+// cell per thread (W threads).
 template <typename Real>
-hipError_t launch_fwd_quad_batch(bool comp, bool cf, int W, const BatchInst<Real> *inst, const BatchTile *tiles,
-                                 int64_t nblocks, int64_t step0, int nsteps, int slot, hipStream_t st) {
+hipError_t launch_fwd_batch(bool quad, bool comp, bool cf, int W, const BatchInst<Real> *inst,
+                            const BatchTile *tiles, int64_t nblocks, int64_t step0, int nsteps, int slot,
+                            hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
   if (cf && !comp) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)nblocks), block(quad ? 4 * W : W);
   if (comp) {
     if constexpr (std::is_same<Real, float>::value) {
-      if (cf)
-        hipLaunchKernelGGL((fwd_quad_batch_kernel<float, true, true>), dim3((unsigned)nblocks), dim3(4 * W), 0, st,
-                           inst, tiles, step0, nsteps, slot);
+      if (quad && cf)
+        hipLaunchKernelGGL((fwd_quad_batch_kernel<float, true, true>), grid, block, 0, st, inst, tiles, step0,
+                           nsteps, slot);
+      else if (quad)
+        hipLaunchKernelGGL((fwd_quad_batch_kernel<float, true, false>), grid, block, 0, st, inst, tiles, step0,
+                           nsteps, slot);
+      else if (cf)
+        hipLaunchKernelGGL((fwd_block_batch_kernel<float, true, true>), grid, block, 0, st, inst, tiles, step0,
+                           nsteps, slot);
       else
-        hipLaunchKernelGGL((fwd_quad_batch_kernel<float, true, false>), dim3((unsigned)nblocks), dim3(4 * W), 0, st,
-                           inst, tiles, step0, nsteps, slot);
+        hipLaunchKernelGGL((fwd_block_batch_kernel<float, true, false>), grid, block, 0, st, inst, tiles, step0,
+                           nsteps, slot);
     } else {
       return hipErrorInvalidValue;
     }
+  } else if (quad) {
+    hipLaunchKernelGGL((fwd_quad_batch_kernel<Real, false, false>), grid, block, 0, st, inst, tiles, step0, nsteps,
+                       slot);
   } else {
-    hipLaunchKernelGGL((fwd_quad_batch_kernel<Real, false, false>), dim3((unsigned)nblocks), dim3(4 * W), 0, st, inst,
-                       tiles, step0, nsteps, slot);
+    hipLaunchKernelGGL((fwd_block_batch_kernel<Real, false, false>), grid, block, 0, st, inst, tiles, step0, nsteps,
+                       slot);
   }
   return hipGetLastError();
 }
@@ -47,6 +60,7 @@ struct mln_batch {
   bool comp = false, cf = false;     // compensated state / fields
   hipStream_t stream = nullptr;       // the caller's stream
   hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
+  int variant = 3;                    // 3: four lanes per cell, 1: one cell per thread
   int W = 0, halo = 0;
   int64_t nt = 0, step = 0, nblocks = 0;
   int cur = 0;
@@ -69,7 +83,12 @@ struct mln_batch {
 
 namespace {
 
-bool valid_tiling(int W, int K) { return W >= 32 && W <= kMaxQuadTile && W % 16 == 0 && K >= 1 && 2 * K < W; }
+bool valid_tiling(int variant, int W, int K) {
+  if (K < 1 || 2 * K >= W || K > kMaxStepsPerLaunch) return false;
+  if (variant == 3) return W >= 32 && W <= kMaxQuadTile && W % 16 == 0;
+  if (variant == 1) return W >= 64 && W <= kMaxTile && W % 64 == 0;
+  return false;
+}
 
 template <typename Real>
 int upload_tables(mln_batch *b) {
@@ -102,19 +121,24 @@ int upload_tables(mln_batch *b) {
   return MLN_OK;
 }
 
-// Set the tile shape of every problem and rebuild the device tables.
-int configure(mln_batch *b, int W, int K) {
-  if (!valid_tiling(W, K) || K > kMaxStepsPerLaunch)
-    return set_err(MLN_EINVAL, "batch tile must be a multiple of 16 in [32, 256] with 2 steps_per_launch < tile");
+// Set the kernel and tile shape of every problem and rebuild the device tables.
+int configure(mln_batch *b, int variant, int W, int K) {
+  if (!valid_tiling(variant, W, K))
+    return set_err(MLN_EINVAL,
+                   "batch tiling: variant 3 (tile a multiple of 16 in [32, 256]) or 1 (a multiple of 64 in "
+                   "[64, 256]), 2 steps_per_launch < tile, steps_per_launch <= 128");
   int64_t blocks = 0;
   for (mln_handle *h : b->inst) blocks += (h->grid.nx + (W - 2 * K) - 1) / (W - 2 * K);
   if (blocks > 0x7fffffff) return set_err(MLN_EINVAL, "too many workgroups for one launch");
   for (mln_handle *h : b->inst) {
+    h->quad = variant == 3;
+    h->wave = false;
     h->W = W;
     h->halo = K;
     h->owned = W - 2 * K;
     h->ntiles = (h->grid.nx + h->owned - 1) / h->owned;
   }
+  b->variant = variant;
   b->W = W;
   b->halo = K;
   b->drop_graph();
@@ -123,12 +147,13 @@ int configure(mln_batch *b, int W, int K) {
 
 int enqueue(mln_batch *b, int64_t step0, int k, int slot, hipStream_t st) {
   hipError_t e;
+  const bool quad = b->variant == 3;
   if (b->prec == MLN_FP64)
-    e = launch_fwd_quad_batch<double>(false, false, b->W, (const BatchInst<double> *)b->dinst.p,
-                                      (const BatchTile *)b->dtiles.p, b->nblocks, step0, k, slot, st);
+    e = launch_fwd_batch<double>(quad, false, false, b->W, (const BatchInst<double> *)b->dinst.p,
+                                 (const BatchTile *)b->dtiles.p, b->nblocks, step0, k, slot, st);
   else
-    e = launch_fwd_quad_batch<float>(b->comp, b->cf, b->W, (const BatchInst<float> *)b->dinst.p,
-                                     (const BatchTile *)b->dtiles.p, b->nblocks, step0, k, slot, st);
+    e = launch_fwd_batch<float>(quad, b->comp, b->cf, b->W, (const BatchInst<float> *)b->dinst.p,
+                                (const BatchTile *)b->dtiles.p, b->nblocks, step0, k, slot, st);
   if (e != hipSuccess) return set_err(MLN_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
   return MLN_OK;
 }
@@ -204,12 +229,15 @@ int mln_init_batch(int32_t n_inst, const mln_medium *media, const mln_grid *grid
       opt.precision != MLN_FP32_COMP_FIELDS)
     return set_err(MLN_ENOTSUPPORTED, "batched launch: FP64, FP32 or compensated FP32");
   if (opt.route != MLN_ROUTE_ROTATION) return set_err(MLN_ENOTSUPPORTED, "batched launch: rotation route only");
-  if (opt.variant != 0 && opt.variant != 3)
-    return set_err(MLN_ENOTSUPPORTED, "batched launch: four-lanes-per-cell tiles only");
+  if (opt.variant != 0 && opt.variant != 1 && opt.variant != 3)
+    return set_err(MLN_ENOTSUPPORTED, "batched launch: one-cell-per-thread or four-lanes-per-cell tiles");
   if (opt.ckpt_every != 0) return set_err(MLN_ENOTSUPPORTED, "batched launch: no checkpoints");
-  const int W = opt.tile > 0 ? opt.tile : 128;
+  const int variant = opt.variant == 0 ? 1 : opt.variant;
+  const int W = opt.tile > 0 ? opt.tile : (variant == 3 ? 128 : 256);
   const int K = opt.steps_per_launch > 0 ? opt.steps_per_launch : 16;
-  if (!valid_tiling(W, K)) return set_err(MLN_EINVAL, "batch tile must be a multiple of 16 in [32, 256], 2 k < tile");
+  if (!valid_tiling(variant, W, K))
+    return set_err(MLN_EINVAL, "batch tiling: variant 3 (tile a multiple of 16 in [32, 256]) or 1 (a multiple "
+                               "of 64 in [64, 256]), 2 steps_per_launch < tile, steps_per_launch <= 128");
   for (int32_t i = 0; i < n_inst; ++i) {
     if (media[i].n_levels != 2 && media[i].n_levels != 3)
       return set_err(MLN_ENOTSUPPORTED, "batched launch: N = 2 or 3 levels");
@@ -223,7 +251,7 @@ int mln_init_batch(int32_t n_inst, const mln_medium *media, const mln_grid *grid
   b->stream = (hipStream_t)opt.stream;
   b->nt = grids[0].nt;
   mln_options o = opt;
-  o.variant = 3;
+  o.variant = variant;
   o.tile = W;
   o.steps_per_launch = K;
   for (int32_t i = 0; i < n_inst; ++i) {
@@ -235,20 +263,22 @@ int mln_init_batch(int32_t n_inst, const mln_medium *media, const mln_grid *grid
     }
     b->inst.push_back(h);
   }
-  int rc = configure(b.get(), W, K);
+  int rc = configure(b.get(), variant, W, K);
   if (rc) return rc;
   *out = b.release();
   return MLN_OK;
 }
 
-int mln_batch_configure(mln_batch *b, int32_t tile, int32_t steps_per_launch) {
+int mln_batch_configure(mln_batch *b, int32_t variant, int32_t tile, int32_t steps_per_launch) {
   if (!b) return set_err(MLN_EINVAL, "null batch");
   if (b->step != 0) return set_err(MLN_ESTATE, "configure a batch at step 0 (mln_batch_reset)");
-  return configure(b, tile, steps_per_launch);
+  return configure(b, variant, tile, steps_per_launch);
 }
 
-int mln_batch_get_config(const mln_batch *b, int32_t *tile, int32_t *steps_per_launch, int64_t *workgroups) {
+int mln_batch_get_config(const mln_batch *b, int32_t *variant, int32_t *tile, int32_t *steps_per_launch,
+                         int64_t *workgroups) {
   if (!b) return set_err(MLN_EINVAL, "null batch");
+  if (variant) *variant = b->variant;
   if (tile) *tile = b->W;
   if (steps_per_launch) *steps_per_launch = b->halo;
   if (workgroups) *workgroups = b->nblocks;
@@ -303,24 +333,27 @@ int mln_batch_run(mln_batch *b) {
   return MLN_OK;
 }
 
-int mln_batch_tune(mln_batch *b, int32_t trial_steps, int32_t *tile, int32_t *steps_per_launch) {
+int mln_batch_tune(mln_batch *b, int32_t trial_steps, int32_t *variant, int32_t *tile, int32_t *steps_per_launch) {
   if (!b) return set_err(MLN_EINVAL, "null batch");
   if (trial_steps < 1) return set_err(MLN_EINVAL, "trial_steps must be >= 1");
-  static const int cand[][2] = {{64, 8},   {64, 16},  {96, 16},  {128, 8},  {128, 16}, {128, 32},
-                                {192, 16}, {192, 32}, {256, 16}, {256, 32}, {256, 64}};
+  // (variant, cells per tile, steps per launch)
+  static const int cand[][3] = {{3, 64, 8},   {3, 64, 16},  {3, 96, 16},  {3, 128, 8},  {3, 128, 16},
+                                {3, 128, 32}, {3, 192, 16}, {3, 192, 32}, {3, 256, 16}, {3, 256, 32},
+                                {3, 256, 64}, {1, 128, 16}, {1, 128, 32}, {1, 192, 16}, {1, 192, 32},
+                                {1, 256, 16}, {1, 256, 32}, {1, 256, 64}};
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   double best = INFINITY;
-  int bw = b->W, bk = b->halo, rc = MLN_OK;
+  int bv = b->variant, bw = b->W, bk = b->halo, rc = MLN_OK;
   const int64_t nt = b->nt;
   for (const auto &c : cand) {
-    if (!valid_tiling(c[0], c[1])) continue;
+    if (!valid_tiling(c[0], c[1], c[2])) continue;
     // whole launches only, at least two, and within the run length
-    int64_t steps = std::max<int64_t>(2 * c[1], (trial_steps + c[1] - 1) / c[1] * c[1]);
-    if (steps + c[1] > nt) continue;
-    if ((rc = configure(b, c[0], c[1])) || (rc = mln_batch_reset(b))) break;
-    if ((rc = step_eager(b, c[1]))) break;  // warm-up launch
+    int64_t steps = std::max<int64_t>(2 * c[2], (trial_steps + c[2] - 1) / c[2] * c[2]);
+    if (steps + c[2] > nt) continue;
+    if ((rc = configure(b, c[0], c[1], c[2])) || (rc = mln_batch_reset(b))) break;
+    if ((rc = step_eager(b, c[2]))) break;  // warm-up launch
     if (hipEventRecord(e0, b->stream) != hipSuccess) { rc = set_err(MLN_EHIP, "event record"); break; }
     if ((rc = step_eager(b, steps))) break;
     if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
@@ -332,14 +365,16 @@ int mln_batch_tune(mln_batch *b, int32_t trial_steps, int32_t *tile, int32_t *st
     const double per_step = ms / (double)steps;
     if (per_step < best) {
       best = per_step;
-      bw = c[0];
-      bk = c[1];
+      bv = c[0];
+      bw = c[1];
+      bk = c[2];
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
-  if ((rc = configure(b, bw, bk)) || (rc = mln_batch_reset(b))) return rc;
+  if ((rc = configure(b, bv, bw, bk)) || (rc = mln_batch_reset(b))) return rc;
+  if (variant) *variant = bv;
   if (tile) *tile = bw;
   if (steps_per_launch) *steps_per_launch = bk;
   return MLN_OK;

@@ -5,21 +5,19 @@
 // factors, grid, recording) live in device memory too, one copy per
 // ping-pong slot, so a launch carries only the step range and the slot.
 // Two- and three-level problems share a launch: the workgroup branches once,
-// uniformly, to the four-lanes-per-cell tile of its level count.  All problems
-// advance in lockstep with one time step, so the launch sequence of a whole
-// run is fixed and can be captured in a HIP graph.
+// uniformly, to the tile of its level count -- four lanes per cell, or one
+// cell per thread (the better choice once the batch fills the chip).  All
+// problems advance in lockstep with one time step, so the launch sequence of
+// a whole run is fixed and can be captured in a HIP graph.
 #pragma once
 
 #include "fwd_quad.hpp"
 
 namespace mln {
 
-template <typename Real, bool COMP, bool CF>
-__global__ void __launch_bounds__(1024)
-    fwd_quad_batch_kernel(const BatchInst<Real> *__restrict__ inst, const BatchTile *__restrict__ tiles,
-                          int64_t step0, int nsteps, int slot) {
-  const BatchTile bt = tiles[blockIdx.x];
-  const BatchInst<Real> &bi = inst[bt.inst];
+// The arguments of this workgroup's problem for the launch's step range.
+template <typename Real>
+__device__ __forceinline__ FwdArgs<Real> batch_args(const BatchInst<Real> &bi, int64_t step0, int nsteps, int slot) {
   FwdArgs<Real> a = bi.a[slot];
   a.step0 = step0;
   a.nsteps = nsteps;
@@ -30,10 +28,33 @@ __global__ void __launch_bounds__(1024)
     a.snap_next = (k + 1) * a.snap_every - 1;
     a.snap_i0 = k;
   }
+  return a;
+}
+
+template <typename Real, bool COMP, bool CF>
+__global__ void __launch_bounds__(1024)
+    fwd_quad_batch_kernel(const BatchInst<Real> *__restrict__ inst, const BatchTile *__restrict__ tiles,
+                          int64_t step0, int nsteps, int slot) {
+  const BatchTile bt = tiles[blockIdx.x];
+  const BatchInst<Real> &bi = inst[bt.inst];
+  const FwdArgs<Real> a = batch_args(bi, step0, nsteps, slot);
   if (bi.n_levels == 2)
     quad_tile<2, Real, COMP, CF>(a, bt.tile);
   else
     quad_tile<3, Real, COMP, CF>(a, bt.tile);
+}
+
+template <typename Real, bool COMP, bool CF>
+__global__ void __launch_bounds__(kMaxTile)
+    fwd_block_batch_kernel(const BatchInst<Real> *__restrict__ inst, const BatchTile *__restrict__ tiles,
+                           int64_t step0, int nsteps, int slot) {
+  const BatchTile bt = tiles[blockIdx.x];
+  const BatchInst<Real> &bi = inst[bt.inst];
+  const FwdArgs<Real> a = batch_args(bi, step0, nsteps, slot);
+  if (bi.n_levels == 2)
+    block_tile<2, Real, ROUTE_ROT, COMP, CF>(a, bt.tile);
+  else
+    block_tile<3, Real, ROUTE_ROT, COMP, CF>(a, bt.tile);
 }
 
 }  // namespace mln

@@ -518,9 +518,10 @@ __device__ __forceinline__ Real cell_step(const FacDev<Real> &f, const Real *sF,
   }
 }
 
+// One tile (one cell per thread, W = blockDim.x cells) of the forward step.
 // COMP: compensated (float-float) state; CF: E and H as float-float pairs too.
-template <int N, typename Real, int ROUTE, bool COMP, bool CF = false>
-__global__ void __launch_bounds__(kMaxTile) fwd_tile_kernel(FwdArgs<Real> a) {
+template <int N, typename Real, int ROUTE, bool COMP, bool CF>
+__device__ __forceinline__ void block_tile(const FwdArgs<Real> &a, int64_t tile) {
   static_assert(COMP || !CF, "compensated fields come with the compensated state");
   constexpr int D = N * N - 1;
   constexpr int DL = COMP ? D : 1;
@@ -537,7 +538,7 @@ __global__ void __launch_bounds__(kMaxTile) fwd_tile_kernel(FwdArgs<Real> a) {
   }
   const int lid = threadIdx.x;
   const int W = blockDim.x;
-  const int64_t base = (int64_t)blockIdx.x * a.owned - a.halo;
+  const int64_t base = tile * a.owned - a.halo;
   const int64_t g = base + lid;
   const bool in_dom = g >= 0 && g < a.nx;
   const bool is_med = g >= a.mb && g < a.me;
@@ -653,6 +654,11 @@ __global__ void __launch_bounds__(kMaxTile) fwd_tile_kernel(FwdArgs<Real> a) {
       }
     }
   }
+}
+
+template <int N, typename Real, int ROUTE, bool COMP, bool CF = false>
+__global__ void __launch_bounds__(kMaxTile) fwd_tile_kernel(FwdArgs<Real> a) {
+  block_tile<N, Real, ROUTE, COMP, CF>(a, blockIdx.x);
 }
 
 // Prescribed-field mode: one thread per medium cell, no FDTD.

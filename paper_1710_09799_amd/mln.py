@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libmln.so")
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32c": 2, "bf16x6": 3, "bf16x3": 4, "fp32cf": 5}
 ROUTES = {"rotation": 0, "diag": 1, "rodrigues": 2, "pade": 3}
 VARIANTS = {"auto": 0, "block": 1, "wave": 2, "quad": 3}
+_VARIANT_NAMES = {1: "block", 2: "wave", 3: "quad"}
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -115,9 +116,9 @@ def load():
         "mln_init_batch": ([ctypes.c_int32, ctypes.POINTER(_Medium), ctypes.POINTER(_Grid),
                             ctypes.POINTER(_Source), ctypes.POINTER(_Record), ctypes.POINTER(_Options),
                             ctypes.POINTER(P)], ctypes.c_int),
-        "mln_batch_tune": ([P, ctypes.c_int32, i32p, i32p], ctypes.c_int),
-        "mln_batch_configure": ([P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
-        "mln_batch_get_config": ([P, i32p, i32p, i64p], ctypes.c_int),
+        "mln_batch_tune": ([P, ctypes.c_int32, i32p, i32p, i32p], ctypes.c_int),
+        "mln_batch_configure": ([P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+        "mln_batch_get_config": ([P, i32p, i32p, i32p, i64p], ctypes.c_int),
         "mln_batch_use_graph": ([P, ctypes.c_int32], ctypes.c_int),
         "mln_batch_step": ([P, ctypes.c_int64], ctypes.c_int),
         "mln_batch_run": ([P], ctypes.c_int),
@@ -270,7 +271,7 @@ class Solver:
         tile and steps per launch."""
         v, w, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(self._L.mln_get_config(self._h, ctypes.byref(v), ctypes.byref(w), ctypes.byref(k)))
-        return {"variant": {1: "block", 2: "wave", 3: "quad"}[v.value], "tile": w.value, "steps_per_launch": k.value}
+        return {"variant": _VARIANT_NAMES[v.value], "tile": w.value, "steps_per_launch": k.value}
 
     def outputs(self):
         return dict(probe=self.probe, e_snap=self.e_snap, pop=self.pop)
@@ -341,7 +342,7 @@ class Batch:
     """
 
     def __init__(self, problems, precision="fp32c", snap_every=0, steps_per_launch=0, tile=0,
-                 record_probe=True, record_pop=True, record_e=True, graph=True):
+                 record_probe=True, record_pop=True, record_e=True, graph=True, variant="auto"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("Batch needs a HIP device")
@@ -374,24 +375,27 @@ class Batch:
             recs[i] = _Record(snap_every, _dptr(o["pop"]), _dptr(o["e_snap"]), _dptr(o["probe"]), 1)
         self.stream = torch.cuda.current_stream()
         opt = _Options(PRECISIONS[precision], ROUTES["rotation"], steps_per_launch, tile,
-                       ctypes.c_void_p(self.stream.cuda_stream), 0, VARIANTS["quad"])
+                       ctypes.c_void_p(self.stream.cuda_stream), 0, VARIANTS[variant])
         h = ctypes.c_void_p()
         _check(L.mln_init_batch(n, meds, grids, srcs, recs, ctypes.byref(opt), ctypes.byref(h)))
         self._h = h
         self.use_graph(graph)
 
     def tune(self, trial_steps=256):
-        w, k = ctypes.c_int32(), ctypes.c_int32()
-        _check(self._L.mln_batch_tune(self._h, int(trial_steps), ctypes.byref(w), ctypes.byref(k)))
-        return w.value, k.value
+        """Autotune (kernel variant, tile, steps per launch); returns them."""
+        v, w, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(self._L.mln_batch_tune(self._h, int(trial_steps), ctypes.byref(v), ctypes.byref(w),
+                                      ctypes.byref(k)))
+        return _VARIANT_NAMES[v.value], w.value, k.value
 
-    def configure(self, tile, steps_per_launch):
-        _check(self._L.mln_batch_configure(self._h, int(tile), int(steps_per_launch)))
+    def configure(self, variant, tile, steps_per_launch):
+        _check(self._L.mln_batch_configure(self._h, VARIANTS[variant], int(tile), int(steps_per_launch)))
 
     def config(self):
-        w, k, nb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
-        _check(self._L.mln_batch_get_config(self._h, ctypes.byref(w), ctypes.byref(k), ctypes.byref(nb)))
-        return dict(tile=w.value, steps_per_launch=k.value, workgroups=nb.value)
+        v, w, k, nb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(self._L.mln_batch_get_config(self._h, ctypes.byref(v), ctypes.byref(w), ctypes.byref(k),
+                                            ctypes.byref(nb)))
+        return dict(variant=_VARIANT_NAMES[v.value], tile=w.value, steps_per_launch=k.value, workgroups=nb.value)
 
     def use_graph(self, on):
         _check(self._L.mln_batch_use_graph(self._h, 1 if on else 0))

@@ -1,11 +1,11 @@
 """Batched lockstep launch (mln_init_batch): many two- and three-level
 problems of different lengths in one launch per chunk of steps, its HIP graph
-and its tile autotuner.
+and its autotuner (kernel variant and tile shape).
 
 The batched launch runs the same per-tile arithmetic as the single-problem
-four-lanes-per-cell kernel, so with equal tile shapes the recordings of each
-problem agree with a single-problem run to the last bit; every problem is
-also checked against the FP64 oracle.
+kernels (four lanes per cell or one cell per thread), so with equal kernel
+and tile shape the recordings of each problem agree with a single-problem run
+to the last bit; every problem is also checked against the FP64 oracle.
 """
 import ctypes
 
@@ -41,15 +41,17 @@ def sweep_ref(orc):
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32c", 1e-5), ("fp32cf", 1e-5), ("fp32", 1e-3)])
-@pytest.mark.parametrize("tile,k", [(128, 16), (64, 8)])
-def test_batch_equals_single_runs_and_oracle(sweep_ref, precision, tol, tile, k):
+@pytest.mark.parametrize("variant,tile,k", [("quad", 128, 16), ("quad", 64, 8), ("block", 256, 32),
+                                            ("block", 128, 16), ("block", 64, 8)])
+def test_batch_equals_single_runs_and_oracle(sweep_ref, precision, tol, variant, tile, k):
     probs, refs = sweep_ref
-    print(f"[case] batch {precision} tile={tile} k={k}", flush=True)
-    b = mln.Batch(probs, precision=precision, snap_every=100, tile=tile, steps_per_launch=k)
+    print(f"[case] batch {precision} {variant} tile={tile} k={k}", flush=True)
+    b = mln.Batch(probs, precision=precision, snap_every=100, tile=tile, steps_per_launch=k, variant=variant)
+    assert b.config()["variant"] == variant
     outs = [_np(o) for o in b.run()]
     b.close()
     for i, p in enumerate(probs):
-        single = mln.run(p, precision=precision, variant="quad", tile=tile, steps_per_launch=k, snap_every=100)
+        single = mln.run(p, precision=precision, variant=variant, tile=tile, steps_per_launch=k, snap_every=100)
         for key in ("probe", "e_snap", "pop"):
             assert np.array_equal(outs[i][key], single[key]), (i, key)
         ee, ep = _errs(outs[i], refs[i])
@@ -95,11 +97,11 @@ def test_stepping_in_chunks_equals_run(sweep_ref):
 def test_autotuner_picks_a_valid_shape(sweep_ref):
     probs, refs = sweep_ref
     b = mln.Batch(probs, precision="fp32c", snap_every=100)
-    w, k = b.tune(trial_steps=64)
+    v, w, k = b.tune(trial_steps=64)
     cfg = b.config()
-    print("tuned", w, k, cfg)
-    assert cfg["tile"] == w and cfg["steps_per_launch"] == k
-    assert 32 <= w <= 256 and w % 16 == 0 and 2 * k < w
+    print("tuned", v, w, k, cfg)
+    assert cfg["variant"] == v and cfg["tile"] == w and cfg["steps_per_launch"] == k
+    assert v in ("quad", "block") and 32 <= w <= 256 and w % (16 if v == "quad" else 64) == 0 and 2 * k < w
     assert cfg["workgroups"] == sum(-(-p.grid.nx // (w - 2 * k)) for p in probs)
     outs = [_np(o) for o in b.run()]
     b.close()
@@ -125,6 +127,12 @@ def test_batch_errors():
     with pytest.raises(mln.MLNError) as e:
         mln.Batch(probs, tile=100)
     assert e.value.code == -1
+    with pytest.raises(mln.MLNError) as e:
+        mln.Batch(probs, variant="block", tile=96)
+    assert e.value.code == -1
+    with pytest.raises(mln.MLNError) as e:
+        mln.Batch(probs, variant="wave")
+    assert e.value.code == -8
     # a problem stepped on its own leaves the lockstep
     b = mln.Batch(probs, precision="fp64")
     L = mln.load()
@@ -159,8 +167,8 @@ def test_full_sweep_64_instances(full_sweep, precision):
     probs, refs = full_sweep
     nt = probs[0].grid.nt
     b = mln.Batch(probs, precision=precision, snap_every=nt)
-    w, k = b.tune(trial_steps=256)
-    print("tuned", w, k, b.config(), flush=True)
+    v, w, k = b.tune(trial_steps=256)
+    print("tuned", v, w, k, b.config(), flush=True)
     outs = [_np(o) for o in b.run()]
     b.close()
     for o in outs:
@@ -169,3 +177,27 @@ def test_full_sweep_64_instances(full_sweep, precision):
         ee, ep = _errs(outs[i], ref)
         print(f"{precision} inst {i} N={probs[i].medium.n_levels} nx={probs[i].grid.nx} err_E={ee:.3e} err_pop={ep:.3e}")
         assert ee < 1e-5 and ep < 1e-5
+
+
+def test_full_sweep_compensated_fields_vs_fp64():
+    """All 64 problems of the full-size sweep: the compensated-fields batch
+    against the FP64 batch at the FP32 tolerance.  (The compensated state
+    with plain FP32 fields, and plain FP32, are printed for reference: their
+    field rounding accumulates over the longest propagation paths, to about
+    5e-5 on the 30000-cell problems, which is why the compensated-fields mode
+    exists.)"""
+    probs = W.batched_sweep()
+    nt = probs[0].grid.nt
+    res = {}
+    for prec in ("fp64", "fp32cf", "fp32c", "fp32"):
+        b = mln.Batch(probs, precision=prec, snap_every=nt, variant="block", tile=256, steps_per_launch=16)
+        res[prec] = [_np(o) for o in b.run()]
+        b.close()
+    for prec in ("fp32cf", "fp32c", "fp32"):
+        errs = [_errs(res[prec][i], res["fp64"][i]) for i in range(len(probs))]
+        print(f"{prec}: worst over 64 problems err_E={max(e[0] for e in errs):.2e} "
+              f"err_pop={max(e[1] for e in errs):.2e}")
+        if prec == "fp32cf":
+            for i in range(len(probs)):
+                ee, ep = _errs(res[prec][i], res["fp64"][i])
+                assert ee < 1e-5 and ep < 1e-5, (i, probs[i].grid.nx, ee, ep)
