@@ -208,6 +208,22 @@ int mln_current_step(const mln_handle *h, int64_t *step);
  * cells per tile and time steps per launch.  Any pointer may be NULL. */
 int mln_get_config(const mln_handle *h, int32_t *variant, int32_t *tile, int32_t *steps_per_launch);
 
+/* Change the kernel configuration (same meaning and rules as the variant,
+ * tile and steps_per_launch options of mln_init; 0 = automatic / default)
+ * of a handle at step 0.  On error the configuration is unchanged.
+ * Errors: MLN_ESTATE (not at step 0), MLN_EINVAL, MLN_ENOTSUPPORTED. */
+int mln_configure(mln_handle *h, int32_t variant, int32_t tile, int32_t steps_per_launch);
+
+/* Autotuner for one problem: time every kernel configuration the handle's
+ * level count, precision and route allow (variants 1-3, several tile shapes)
+ * on the problem itself, about trial_steps steps each from step 0 with
+ * nothing recorded (HIP events on the handle's stream), keep the fastest per
+ * time step and return the handle to step 0 with it.  The choice is returned
+ * in *variant, *tile and *steps_per_launch (any may be NULL).  Candidates
+ * that need more steps than the run has are skipped.  Synchronises.
+ * Errors: MLN_ESTATE (not at step 0), MLN_EINVAL, MLN_EHIP. */
+int mln_tune(mln_handle *h, int32_t trial_steps, int32_t *variant, int32_t *tile, int32_t *steps_per_launch);
+
 /* Copy the current fields to host arrays E[nx] (step n) and H[nx-1]
  * (step n-1/2).  Synchronises the stream. */
 int mln_get_fields(mln_handle *h, double *E, double *H);

@@ -230,6 +230,58 @@ int forward_steps(mln_handle *h, int64_t n, bool record, void *tape, int64_t tap
   return MLN_OK;
 }
 
+// Choose and validate the forward kernel (variant 0: automatic) and its
+// tiling (0: defaults); sets the tile bookkeeping of the handle.
+int set_kernel(mln_handle *h, int variant_req, int tile, int steps_per_launch) {
+  if (variant_req < 0 || variant_req > 3) return set_err(MLN_EINVAL, "unknown kernel variant");
+  const bool rot = h->route == MLN_ROUTE_ROTATION;
+  int variant = variant_req;
+  // automatic choice: four lanes per cell while the grid is too small to
+  // fill the chip with one cell per thread (the step is latency-bound there,
+  // and four lanes give four times the wavefronts); one cell per thread on
+  // large grids, where the quad's replicated field work costs issue slots
+  // (measured crossover near 1e5 cells at N = 2, 3)
+  if (variant == 0)
+    variant = !rot ? 1 : (h->f.N <= 3 ? (h->grid.nx < kQuadMaxAutoCells ? 3 : 1) : (h->f.N == 4 && !h->cf ? 2 : 1));
+  if (h->mfma) {
+    // one cell per thread (1) or four lanes per cell (3, the default)
+    if (variant_req == 0) variant = 3;
+    if (variant != 1 && variant != 3)
+      return set_err(MLN_ENOTSUPPORTED, "the split-BF16 MFMA kernels are workgroup-tile or four-lanes-per-cell kernels");
+  }
+  h->wave = variant == 2;
+  if (h->wave && h->cf)
+    return set_err(MLN_ENOTSUPPORTED, "the wavefront kernel keeps E and H in plain precision");
+  h->quad = variant == 3;
+  if ((h->wave || h->quad) && !rot)
+    return set_err(MLN_ENOTSUPPORTED, "the wavefront and quad kernels implement the rotation route");
+  if (h->quad && h->f.N > 3 && !h->mfma)
+    return set_err(MLN_ENOTSUPPORTED, "the quad kernel is built for N <= 3 (N = 4, 6: split-BF16 precisions)");
+  // the per-step Pade route for N >= 4 keeps the tile's states in LDS and is
+  // bound by arithmetic: smaller tiles, short halos
+  const bool pade_wave = h->route == MLN_ROUTE_PADE && h->f.N >= 4;
+  h->W = tile > 0 ? tile : ((h->quad && !h->mfma) || pade_wave ? 128 : kMaxTile);
+  if (h->quad) {
+    if (h->W > kMaxQuadTile || h->W < 32 || h->W % 16)
+      return set_err(MLN_EINVAL, "quad kernel tile must be a multiple of 16 in [32, 256]");
+  } else if (h->W > kMaxTile || h->W < 64 || h->W % 64) {
+    return set_err(MLN_EINVAL, "tile must be a multiple of 64 in [64, 256]");
+  }
+  if (h->wave && (h->W == 192 || (h->f.N == 6 && h->W != 64)))
+    return set_err(MLN_ENOTSUPPORTED, "wavefront kernel tiles: 64, 128 or 256 cells (64 for N = 6)");
+  int K = steps_per_launch > 0
+              ? steps_per_launch
+              : (pade_wave ? 8 : (h->wave ? h->W / 8 : (h->mfma ? 16 : (h->quad ? h->W / 4 : 32))));
+  if (2 * K >= h->W || K > kMaxStepsPerLaunch)
+    return set_err(MLN_EINVAL, "steps_per_launch must be below tile/2 (and at most 128)");
+  if (pade_wave && pade_lds_bytes(h->f.N, h->rs, h->W) > kPadeMaxLds)
+    return set_err(MLN_EINVAL, "tile too large for the LDS of the per-step Pade kernel");
+  h->halo = K;
+  h->owned = h->W - 2 * K;
+  h->ntiles = (h->grid.nx + h->owned - 1) / h->owned;
+  return MLN_OK;
+}
+
 int validate_grid(const mln_grid *g, const mln_source *s) {
   if (!g || !s) return set_err(MLN_EINVAL, "null grid or source");
   if (g->nx < 3) return set_err(MLN_EINVAL, "nx must be >= 3");
@@ -424,53 +476,8 @@ int mln_init(const mln_medium *medium, const mln_grid *grid, const mln_source *s
   h->fd_coef[4] = (cl * grid->dt - grid->dx) / (cl * grid->dt + grid->dx);
   h->fd_coef[5] = -2.0 * sg / (1.0 + sg);
   tune_fp32_coefs(h.get());
-  // kernel variant and tiling
-  if (opt.variant < 0 || opt.variant > 3) return set_err(MLN_EINVAL, "unknown kernel variant");
-  const bool rot = h->route == MLN_ROUTE_ROTATION;
-  int variant = opt.variant;
-  // automatic choice: four lanes per cell while the grid is too small to
-  // fill the chip with one cell per thread (the step is latency-bound there,
-  // and four lanes give four times the wavefronts); one cell per thread on
-  // large grids, where the quad's replicated field work costs issue slots
-  // (measured crossover near 1e5 cells at N = 2, 3)
-  if (variant == 0)
-    variant = !rot ? 1 : (h->f.N <= 3 ? (grid->nx < kQuadMaxAutoCells ? 3 : 1) : (h->f.N == 4 && !h->cf ? 2 : 1));
-  if (h->mfma) {
-    // one cell per thread (1) or four lanes per cell (3, the default)
-    if (opt.variant == 0) variant = 3;
-    if (variant != 1 && variant != 3)
-      return set_err(MLN_ENOTSUPPORTED, "the split-BF16 MFMA kernels are workgroup-tile or four-lanes-per-cell kernels");
-  }
-  h->wave = variant == 2;
-  if (h->wave && h->cf)
-    return set_err(MLN_ENOTSUPPORTED, "the wavefront kernel keeps E and H in plain precision");
-  h->quad = variant == 3;
-  if ((h->wave || h->quad) && !rot)
-    return set_err(MLN_ENOTSUPPORTED, "the wavefront and quad kernels implement the rotation route");
-  if (h->quad && h->f.N > 3 && !h->mfma)
-    return set_err(MLN_ENOTSUPPORTED, "the quad kernel is built for N <= 3 (N = 4, 6: split-BF16 precisions)");
-  // the per-step Pade route for N >= 4 keeps the tile's states in LDS and is
-  // bound by arithmetic: smaller tiles, short halos
-  const bool pade_wave = h->route == MLN_ROUTE_PADE && h->f.N >= 4;
-  h->W = opt.tile > 0 ? opt.tile : ((h->quad && !h->mfma) || pade_wave ? 128 : kMaxTile);
-  if (h->quad) {
-    if (h->W > kMaxQuadTile || h->W < 32 || h->W % 16)
-      return set_err(MLN_EINVAL, "quad kernel tile must be a multiple of 16 in [32, 256]");
-  } else if (h->W > kMaxTile || h->W < 64 || h->W % 64) {
-    return set_err(MLN_EINVAL, "tile must be a multiple of 64 in [64, 256]");
-  }
-  if (h->wave && (h->W == 192 || (h->f.N == 6 && h->W != 64)))
-    return set_err(MLN_ENOTSUPPORTED, "wavefront kernel tiles: 64, 128 or 256 cells (64 for N = 6)");
-  int K = opt.steps_per_launch > 0
-              ? opt.steps_per_launch
-              : (pade_wave ? 8 : (h->wave ? h->W / 8 : (h->mfma ? 16 : (h->quad ? h->W / 4 : 32))));
-  if (2 * K >= h->W || K > kMaxStepsPerLaunch)
-    return set_err(MLN_EINVAL, "steps_per_launch must be below tile/2 (and at most 128)");
-  if (pade_wave && pade_lds_bytes(h->f.N, h->rs, h->W) > kPadeMaxLds)
-    return set_err(MLN_EINVAL, "tile too large for the LDS of the per-step Pade kernel");
-  h->halo = K;
-  h->owned = h->W - 2 * K;
-  h->ntiles = (grid->nx + h->owned - 1) / h->owned;
+  rc = set_kernel(h.get(), opt.variant, opt.tile, opt.steps_per_launch);
+  if (rc) return rc;
   h->nmed = grid->med_end - grid->med_begin;
   h->ld = std::max<int64_t>(1, (h->nmed + 63) / 64 * 64);
   // recording
@@ -536,6 +543,80 @@ int mln_reset(mln_handle *h) {
 int mln_current_step(const mln_handle *h, int64_t *step) {
   if (!h || !step) return set_err(MLN_EINVAL, "null argument");
   *step = h->step;
+  return MLN_OK;
+}
+
+namespace {
+struct KernelChoice {
+  bool quad, wave;
+  int W, halo, owned;
+  int64_t ntiles;
+};
+KernelChoice save_kernel(const mln_handle *h) { return {h->quad, h->wave, h->W, h->halo, h->owned, h->ntiles}; }
+void restore_kernel(mln_handle *h, const KernelChoice &k) {
+  h->quad = k.quad;
+  h->wave = k.wave;
+  h->W = k.W;
+  h->halo = k.halo;
+  h->owned = k.owned;
+  h->ntiles = k.ntiles;
+}
+}  // namespace
+
+int mln_configure(mln_handle *h, int32_t variant, int32_t tile, int32_t steps_per_launch) {
+  if (!h) return set_err(MLN_EINVAL, "null handle");
+  if (h->step != 0) return set_err(MLN_ESTATE, "configure a handle at step 0 (mln_reset)");
+  const KernelChoice old = save_kernel(h);
+  int rc = set_kernel(h, variant, tile, steps_per_launch);
+  if (rc) restore_kernel(h, old);
+  return rc;
+}
+
+int mln_tune(mln_handle *h, int32_t trial_steps, int32_t *variant, int32_t *tile, int32_t *steps_per_launch) {
+  if (!h) return set_err(MLN_EINVAL, "null handle");
+  if (h->step != 0) return set_err(MLN_ESTATE, "tune a handle at step 0 (mln_reset)");
+  if (trial_steps < 1) return set_err(MLN_EINVAL, "trial_steps must be >= 1");
+  // (variant, cells per tile, steps per launch); candidates the handle's
+  // precision, route or level count does not allow are skipped
+  static const int cand[][3] = {{3, 64, 8},   {3, 128, 16}, {3, 128, 20}, {3, 128, 32}, {3, 256, 16},
+                                {3, 256, 32}, {1, 64, 8},   {1, 128, 8},  {1, 128, 16}, {1, 128, 32},
+                                {1, 256, 8},  {1, 256, 16}, {1, 256, 32}, {2, 64, 8},   {2, 128, 16},
+                                {2, 256, 32}};
+  const KernelChoice start = save_kernel(h);
+  KernelChoice best_k = start;
+  double best = INFINITY;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int rc = MLN_OK;
+  for (const auto &c : cand) {
+    if (set_kernel(h, c[0], c[1], c[2]) != MLN_OK) continue;
+    // one warm-up launch, then whole launches, all within the run length
+    const int64_t steps = std::max<int64_t>(2 * c[2], (trial_steps + c[2] - 1) / c[2] * c[2]);
+    if (steps + c[2] > h->grid.nt) continue;
+    if ((rc = reset_state(h)) || (rc = forward_steps(h, c[2], false, nullptr, 0, false))) break;
+    if (hipEventRecord(e0, h->stream) != hipSuccess) { rc = set_err(MLN_EHIP, "event record"); break; }
+    if ((rc = forward_steps(h, steps, false, nullptr, 0, false))) break;
+    if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      rc = set_err(MLN_EHIP, "event synchronize");
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms / (double)steps < best) {
+      best = ms / (double)steps;
+      best_k = save_kernel(h);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  restore_kernel(h, rc ? start : best_k);
+  const int rc2 = reset_state(h);
+  if (rc) return rc;
+  if (rc2) return rc2;
+  if (variant) *variant = h->quad ? 3 : (h->wave ? 2 : 1);
+  if (tile) *tile = h->W;
+  if (steps_per_launch) *steps_per_launch = h->halo;
   return MLN_OK;
 }
 

@@ -70,7 +70,8 @@ class _Factors(ctypes.Structure):
 
 
 # every symbol include/mln.h declares
-EXPORTS = ["mln_init", "mln_step", "mln_run", "mln_reset", "mln_current_step", "mln_get_config", "mln_get_fields",
+EXPORTS = ["mln_init", "mln_step", "mln_run", "mln_reset", "mln_current_step", "mln_get_config", "mln_configure", "mln_tune",
+           "mln_get_fields",
            "mln_state_bytes", "mln_save_state", "mln_load_state", "mln_bloch_only", "mln_free",
            "mln_strerror", "mln_last_error", "mln_setup_factors", "mln_version", "mln_grad",
            "mln_chain_rule", "mln_init_batch", "mln_batch_tune", "mln_batch_configure",
@@ -99,6 +100,8 @@ def load():
         "mln_reset": ([P], ctypes.c_int),
         "mln_current_step": ([P, i64p], ctypes.c_int),
         "mln_get_config": ([P, i32p, i32p, i32p], ctypes.c_int),
+        "mln_configure": ([P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+        "mln_tune": ([P, ctypes.c_int32, i32p, i32p, i32p], ctypes.c_int),
         "mln_get_fields": ([P, _dp, _dp], ctypes.c_int),
         "mln_state_bytes": ([P, i64p], ctypes.c_int),
         "mln_save_state": ([P, P], ctypes.c_int),
@@ -272,6 +275,17 @@ class Solver:
         v, w, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(self._L.mln_get_config(self._h, ctypes.byref(v), ctypes.byref(w), ctypes.byref(k)))
         return {"variant": _VARIANT_NAMES[v.value], "tile": w.value, "steps_per_launch": k.value}
+
+    def configure(self, variant="auto", tile=0, steps_per_launch=0):
+        """Change the kernel configuration (at step 0)."""
+        _check(self._L.mln_configure(self._h, VARIANTS[variant], int(tile), int(steps_per_launch)))
+
+    def tune(self, trial_steps=256):
+        """Autotune the kernel configuration on this problem (at step 0); the
+        handle keeps the fastest.  Returns config()."""
+        v, w, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(self._L.mln_tune(self._h, int(trial_steps), ctypes.byref(v), ctypes.byref(w), ctypes.byref(k)))
+        return self.config()
 
     def outputs(self):
         return dict(probe=self.probe, e_snap=self.e_snap, pop=self.pop)

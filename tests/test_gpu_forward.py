@@ -344,6 +344,39 @@ def test_automatic_kernel_choice():
     assert ee < 1e-12 and ep < 1e-12, (ee, ep)
 
 
+def test_single_problem_autotuner_and_configure():
+    """mln_tune times the allowed configurations on the problem and keeps the
+    fastest; the tuned run agrees with the default one to rounding (FP64);
+    mln_configure rejects invalid shapes and leaves the configuration
+    unchanged, and works only at step 0."""
+    for p, prec, bad in ((W.three_level(nx=20000, nt=1200), "fp32c", None),
+                         (W.two_level(nx=1 << 20, nt=300), "fp64", "quad"),
+                         (W.six_level(nx=3000, nt=400), "bf16x6", "wave")):
+        s = mln.Solver(p, precision=prec, snap_every=p.grid.nt // 2)
+        cfg = s.tune(trial_steps=64)
+        print("tuned", p.name, prec, cfg, flush=True)
+        assert s.current_step() == 0
+        if bad:
+            assert cfg["variant"] != bad
+        tuned = {k: v.cpu().numpy().copy() for k, v in s.run().items() if v is not None}
+        s.reset()
+        s.configure("auto")
+        ref = {k: v.cpu().numpy().copy() for k, v in s.run().items() if v is not None}
+        ee, ep = _errs(tuned, ref)
+        tol = 1e-12 if prec == "fp64" else 1e-4
+        assert ee < tol and ep < tol, (ee, ep)
+        before = s.config()
+        s.reset()
+        with pytest.raises(mln.MLNError) as e:
+            s.configure("quad", tile=100)
+        assert e.value.code == -1 and s.config() == before
+        s.step(5)
+        with pytest.raises(mln.MLNError) as e:
+            s.configure("block")
+        assert e.value.code == -10
+        s.close()
+
+
 def test_pade_route_rejects_compensated_state():
     p = W.random_problem(4, 1, nx=100, nt=50)
     for prec in ("fp32c", "fp32cf"):
