@@ -209,3 +209,24 @@ def test_grad_state_errors():
     with pytest.raises(mln.MLNError) as e:
         s2.grad(np.zeros(101))
     assert e.value.code == -10
+
+
+@pytest.mark.slow
+def test_adjoint_case_full_size():
+    """The adjoint workload at full size (three-level ladder, 10000 cells,
+    50000 steps, checkpoints every 500): the FP64 gradient of the transmitted
+    energy against central differences with the h = 1e-6 relative step (FP64
+    forward runs), and the compensated-FP32 gradient (the measured
+    configuration) against the FP64 one."""
+    prob = W.adjoint_case()
+    print("[case] adjoint case full size", flush=True)
+    J, g64 = _grad(prob, "fp64", ckpt=500)
+    ga = grads_to_ladder(g64, 3)
+    fd, scale = _fd_ladder(prob, _run_J)
+    _compare(ga, fd, scale, 1e-6, 1e-5)
+    _, g32 = _grad(prob, "fp32c", ckpt=500)
+    a = grads_to_ladder(g32, 3) * scale
+    b = ga * scale
+    rel = np.abs(a - b) / np.max(np.abs(b))
+    print("fp32c vs fp64 gradient, relative to the largest:", rel)
+    assert np.max(rel) < 1e-3

@@ -164,3 +164,26 @@ def test_wave_kernel_rejects_compensated_fields():
     with pytest.raises(mln.MLNError) as e:
         mln.Solver(p, precision="fp32cf", variant="wave", tile=64, steps_per_launch=8)
     assert e.value.code == -8
+
+
+@pytest.mark.slow
+def test_six_level_full_size():
+    """The six-level workload at full size (50000 cells, 200000 steps) in the
+    benchmark's launch configurations.  The oracle cannot run it; the FP64 GPU
+    path (matched to the oracle to 1e-10 on the reduced six-level shape) is
+    the reference: split-BF16 (six products) within its 1e-4 bound and
+    compensated fields within 1e-5 on the probe; populations of every run in
+    [0, 1] and summing to one."""
+    p = W.six_level()
+    nt = p.grid.nt
+    kw = dict(tile=256, steps_per_launch=16, snap_every=nt // 2, record_e=False)
+    ref = mln.run(p, precision="fp64", variant="block", **kw)
+    for prec, tol in (("bf16x6", 1e-4), ("fp32cf", 1e-5)):
+        got = mln.run(p, precision=prec, **kw)
+        err = np.max(np.abs(got["probe"] - ref["probe"])) / np.max(np.abs(ref["probe"]))
+        print(f"six-level full size {prec}: probe deviation from FP64 {err:.2e}")
+        assert err < tol
+        for out in (got, ref):
+            pop = out["pop"]
+            assert np.all(np.isfinite(pop)) and pop.min() > -1e-6 and pop.max() < 1 + 1e-6
+            assert np.max(np.abs(pop.sum(axis=1) - 1.0)) < 1e-6
