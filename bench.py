@@ -409,6 +409,17 @@ def main():
                      "kernel": f"fwd_quad_kernel<3,float,{args.precision}>", "launch_us": launch_s * 1e6,
                      "flop_per_update": fl, "updates_per_launch": p.grid.n_med * K},
     }
+    # the latency floor of a step at the headline's launch shape: one LDS
+    # exchange and one workgroup barrier, without and with a 128-long chain of
+    # dependent FMAs (about the length of the kernel's per-step chain)
+    from paper_1710_09799_amd import mln
+    wg = -(-p.grid.nx // (kw["tile"] - 2 * K))
+    res["step_latency"] = {"kernel_us_per_step": launch_s * 1e6 / K,
+                           "floor_exchange_barrier_us": mln.step_floor(wg, 4 * kw["tile"], 4000, 0),
+                           "floor_exchange_barrier_chain128_us": mln.step_floor(wg, 4 * kw["tile"], 4000, 128),
+                           "launch_shape": f"{wg} workgroups x {4 * kw['tile']} lanes"}
+    # the vector FMA rate the kernels can reach (plain instructions, measured)
+    res["measured_fma_tflops"] = {"fp32": mln.fma_rate(False), "fp64": mln.fma_rate(True)}
     if not args.no_variants:
         t64, g64, nl64, out64 = time_solver(p, 1, 1, 10000, keep=True, precision="fp64", variant="quad",
                                             tile=kw["tile"], steps_per_launch=K)

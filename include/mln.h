@@ -361,6 +361,23 @@ int mln_chain_rule(const mln_medium *medium, double dt, const double *gA, const 
 /* Library version (major*10000 + minor*100 + patch). */
 int mln_version(void);
 
+/* Diagnostic for the measurement (no problem involved): the time per step,
+ * in microseconds, of `workgroups` workgroups of `threads` lanes (a multiple
+ * of 64 up to 1024) that per step write one value per lane to LDS, pass one
+ * workgroup barrier, read two neighbours back and run a chain of `chain` (0,
+ * 32, 64 or 128) dependent FP32 FMAs -- the floor under any tile kernel's
+ * step at that launch shape.  Runs `steps` and 2 `steps` steps on the
+ * default stream and reports the difference per step (launch overhead
+ * removed).  Allocates a small device buffer; synchronises. */
+int mln_measure_step_floor(int32_t workgroups, int32_t threads, int32_t steps, int32_t chain,
+                           double *us_per_step);
+
+/* Diagnostic: the vector FMA rate of the device in TFLOP/s (fp64 = 0: FP32,
+ * else FP64), from 16 independent chains of plain (not packed) FMAs per lane
+ * on 32 workgroups of 256 lanes per compute unit; the peak the kernels'
+ * vector code can reach at the clock under load.  Synchronises. */
+int mln_measure_fma_rate(int32_t fp64, double *tflops);
+
 #ifdef __cplusplus
 }
 #endif

@@ -76,7 +76,8 @@ EXPORTS = ["mln_init", "mln_step", "mln_run", "mln_reset", "mln_current_step", "
            "mln_strerror", "mln_last_error", "mln_setup_factors", "mln_version", "mln_grad",
            "mln_chain_rule", "mln_init_batch", "mln_batch_tune", "mln_batch_configure",
            "mln_batch_get_config", "mln_batch_use_graph", "mln_batch_step", "mln_batch_run",
-           "mln_batch_reset", "mln_batch_instance", "mln_batch_free"]
+           "mln_batch_reset", "mln_batch_instance", "mln_batch_free", "mln_measure_step_floor",
+           "mln_measure_fma_rate"]
 
 _lib = None
 
@@ -128,6 +129,9 @@ def load():
         "mln_batch_reset": ([P], ctypes.c_int),
         "mln_batch_instance": ([P, ctypes.c_int32, ctypes.POINTER(P)], ctypes.c_int),
         "mln_batch_free": ([P], None),
+        "mln_measure_step_floor": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+        "mln_measure_fma_rate": ([ctypes.c_int32, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -446,3 +450,20 @@ def run(problem, **kw):
     res = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
     s.close()
     return res
+
+
+def step_floor(workgroups, threads, steps=2000, chain=0):
+    """mln_measure_step_floor: microseconds per step of an LDS exchange, a
+    workgroup barrier and `chain` dependent FMAs at this launch shape."""
+    L = load()
+    us = ctypes.c_double()
+    _check(L.mln_measure_step_floor(int(workgroups), int(threads), int(steps), int(chain), ctypes.byref(us)))
+    return us.value
+
+
+def fma_rate(fp64=False):
+    """mln_measure_fma_rate: achieved plain-FMA TFLOP/s (FP32 or FP64)."""
+    L = load()
+    v = ctypes.c_double()
+    _check(L.mln_measure_fma_rate(1 if fp64 else 0, ctypes.byref(v)))
+    return v.value
