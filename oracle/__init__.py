@@ -55,6 +55,13 @@ def lib():
                                ctypes.c_double, i64, i64, ctypes.c_double, ctypes.c_double, i64, i64,
                                ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, ctypes.c_double,
                                dp, dp, dp, dp, dp, dp, dp, ctypes.c_int]
+        L.orc_pstd_run.restype = ctypes.c_int
+        L.orc_pstd_run.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, ctypes.c_double, dp, dp,
+                                   ctypes.c_double, i64, i64, ctypes.c_double, ctypes.c_double, i64, i64,
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, ctypes.c_double,
+                                   dp, dp, i64, dp, dp, dp, dp, ctypes.c_int]
+        L.orc_spectral_derivative.restype = None
+        L.orc_spectral_derivative.argtypes = [i64, ctypes.c_double, dp, ctypes.c_double, dp]
         L.orc_expm.restype = ctypes.c_int
         L.orc_expm.argtypes = [ctypes.c_int, dp, dp]
         L.orc_superop.restype = ctypes.c_int
@@ -194,3 +201,38 @@ def grad(problem, dJ_dprobe, nthreads=0):
         raise RuntimeError(f"oracle adjoint failed ({rc})")
     return dict(d_h0=gh, d_dipole=gm, d_jump_rate=gr[:nj], d_dephasing=float(gd[0]),
                 d_amplitude=float(ga[0]), d_density=float(gn[0]))
+
+
+def pstd_run(problem, snap_every=0, nthreads=0, nt=None, e_init=None, h_init=None, hard_source=False):
+    """Coupled run with the pseudo-spectral field solver on a periodic grid
+    (see orc_pstd_run).  e_init / h_init (nx values each; H[i] sits at
+    (i + 1/2) dx) replace the zero initial fields and the initial source
+    sample; hard_source=True forces cell 0 to the source as run() does.  Returns 'probe', 'e_snap',
+    'pop' as run() does, and 'h' (the final H)."""
+    med, g, src = problem.medium, problem.grid, problem.source
+    nt = g.nt if nt is None else nt
+    n, h0, mu, nj, jumps, rates, deph, relax, rho0 = _medium_args(med)
+    nsnap = nt // snap_every if snap_every > 0 else 0
+    probe = np.zeros(nt + 1)
+    e_snap = np.zeros((max(nsnap, 1), g.nx))
+    pop = np.zeros((max(nsnap, 1), n, max(g.n_med, 1)))
+    hfin = np.zeros(g.nx)
+    samples = np.ascontiguousarray(src.samples[: nt + 1], dtype=np.float64)
+    ei = None if e_init is None else np.ascontiguousarray(e_init, dtype=np.float64)
+    hi = None if h_init is None else np.ascontiguousarray(h_init, dtype=np.float64)
+    rc = lib().orc_pstd_run(n, _p(h0), _p(mu), nj, _p(jumps), _p(rates), deph, _p(relax), _p(rho0),
+                            float(med.density), g.nx, nt, g.dx, g.dt, g.med_begin, g.med_end,
+                            g.eps_r, g.mu_r, g.sigma, _p(samples) if hard_source else None,
+                            float(src.amplitude), _p(ei), _p(hi),
+                            snap_every, _p(e_snap), _p(pop), _p(probe), _p(hfin), nthreads)
+    if rc:
+        raise RuntimeError(f"oracle pstd run failed ({rc})")
+    return dict(probe=probe, e_snap=e_snap[:nsnap], pop=pop[:nsnap, :, : g.n_med], h=hfin)
+
+
+def spectral_derivative(f, dx, shift):
+    """d/dx of the periodic band-limited interpolant of f at x_i + shift."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.zeros_like(f)
+    lib().orc_spectral_derivative(len(f), float(dx), _p(f), float(shift), _p(out))
+    return out

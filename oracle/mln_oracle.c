@@ -29,7 +29,10 @@
  *   * the FP64 adjoint of that discrete map (orc_grad): reverse mode through
  *     every step, matrix-exponential derivatives from the block identity for
  *     the Frechet derivative, gradients with respect to H0, the dipole
- *     matrix, the jump and dephasing rates, N_a and the source amplitude.
+ *     matrix, the jump and dephasing rates, N_a and the source amplitude;
+ *   * a pseudo-spectral (PSTD) field solver on a periodic grid
+ *     (orc_pstd_run): the same leapfrog and medium step with the spatial
+ *     derivatives taken from direct DFT sums.
  *
  * Readings of points the paper leaves open (same on the GPU side, but written
  * independently there):
@@ -940,4 +943,130 @@ int orc_grad(int n, const double *h0, const double *mu, int n_jump, const double
     free(hist); free(ehist); free(rho); free(r0); free(E); free(H); free(P);
     medium_free(&m);
     return rc ? -4 : 0;
+}
+
+/* ----------------------------------------------------------------------- */
+/* pseudo-spectral time-domain (PSTD) field solver                          */
+/*
+ * The paper notes that its Liouville treatment combines with a PSTD field
+ * solver as well as with FDTD (Introduction; Sec. 4).  Reading taken here:
+ * the staggered leapfrog of the Yee scheme in time (E at integer steps, H at
+ * half steps), the spatial derivatives spectral on a periodic grid of nx
+ * cells, the half-cell staggering of H realised by the shift factor
+ * exp(+-i kappa dx/2) of every Fourier mode, the Nyquist mode of an even nx
+ * dropped.  A run is an initial-value problem: E at step 0 and H at step
+ * -1/2 are given (e_init, h_init), the grid is periodic with no absorbing
+ * boundary, the probe is cell nx - 1, and the medium coupling is exactly as
+ * in orc_run.  A hard source at cell 0 (src != NULL) is optional: a sample
+ * forced on a spectral grid radiates both ways and leaves a jump in H whose
+ * Gibbs error spoils the method's convergence, so it serves comparisons
+ * only.  The derivatives are direct DFT sums (O(nx^2) per derivative): the
+ * definition, no FFT.
+ */
+
+/* out[j] = d/dx of the periodic band-limited interpolant of f (samples at
+ * x_i = i dx), evaluated at x_j + shift (shift = +dx/2 or -dx/2). */
+static void spectral_derivative(int64_t nx, double dx, const double *f, double shift, double *out,
+                                double *re, double *im)
+{
+    const double tw = 2.0 * 3.14159265358979323846 / (double)nx;
+    int64_t kmax = (nx - 1) / 2;  /* modes -kmax..kmax; the Nyquist mode is dropped */
+    for (int64_t k = 0; k <= kmax; ++k) {
+        double sr = 0.0, si = 0.0;
+        for (int64_t i = 0; i < nx; ++i) {
+            double a = tw * (double)((k * i) % nx);
+            sr += f[i] * cos(a);
+            si -= f[i] * sin(a);
+        }
+        re[k] = sr;
+        im[k] = si;
+    }
+    for (int64_t j = 0; j < nx; ++j) {
+        double acc = 0.0;
+        for (int64_t k = 1; k <= kmax; ++k) {
+            /* the pair (k, -k) of a real signal: 2 Re{ i kappa e^{i kappa (x_j + shift)} F_k } / nx */
+            double kappa = tw * (double)k / dx;
+            double ph = tw * (double)((k * j) % nx) + kappa * shift;
+            double c = cos(ph), s = sin(ph);
+            /* i kappa (re + i im)(c + i s) -> real part: -kappa (re s + im c) */
+            acc += -kappa * (re[k] * s + im[k] * c);
+        }
+        out[j] = 2.0 * acc / (double)nx;
+    }
+}
+
+int orc_pstd_run(int n, const double *h0, const double *mu, int n_jump, const double *jump,
+                 const double *rate, double deph, const double *relax, const double *rho0,
+                 double Na, int64_t nx, int64_t nt, double dx, double dt, int64_t mb, int64_t me,
+                 double eps_r, double mu_r, double sigma, const double *src, double amp,
+                 const double *e_init, const double *h_init,
+                 int64_t snap_every, double *e_snap, double *pop_snap, double *probe, double *h_final,
+                 int nthreads)
+{
+    if (n < 2 || nx < 3 || nt < 0 || mb < 1 || me < mb || me > nx - 1) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    medium_t m;
+    if (medium_init(&m, n, h0, mu, n_jump, jump, rate, deph, relax, dt)) return -2;
+    int n2 = n * n;
+    int64_t nmed = me - mb;
+    cx *rho = (cx *)malloc(sizeof(cx) * (size_t)(nmed ? nmed : 1) * n2);
+    cx *r0 = load_cx(rho0, n2);
+    for (int64_t c = 0; c < nmed; ++c) memcpy(rho + c * n2, r0, sizeof(cx) * n2);
+    double *E = (double *)calloc(nx, sizeof(double));
+    double *H = (double *)calloc(nx, sizeof(double));
+    double *D = (double *)calloc(nx, sizeof(double));
+    double *re = (double *)calloc(nx, sizeof(double)), *im = (double *)calloc(nx, sizeof(double));
+    double *P = (double *)calloc(nmed ? nmed : 1, sizeof(double));
+    double eps = ORC_EPS0 * eps_r, muu = ORC_MU0 * mu_r;
+    double sg = sigma * dt / (2.0 * eps);
+    double ca = (1.0 - sg) / (1.0 + sg), cb = (dt / eps) / (1.0 + sg);
+    double chp = dt / muu;
+    if (e_init) memcpy(E, e_init, sizeof(double) * nx);
+    if (h_init) memcpy(H, h_init, sizeof(double) * nx);
+    if (!e_init && src) E[0] = amp * src[0];
+    if (probe) probe[0] = E[nx - 1];
+    for (int64_t t = 0; t < nt; ++t) {
+        /* H at x_i + dx/2 */
+        spectral_derivative(nx, dx, E, 0.5 * dx, D, re, im);
+        for (int64_t i = 0; i < nx; ++i) H[i] += chp * D[i];
+#pragma omp parallel
+        {
+            cell_ws_t ws;
+            ws_alloc(&ws, n);
+#pragma omp for schedule(static)
+            for (int64_t c = 0; c < nmed; ++c)
+                P[c] = cell_step(&m, rho + c * n2, E[mb + c], dt, Na, &ws);
+            ws_free(&ws);
+        }
+        /* dH/dx at x_i: the samples of H sit half a cell to the right */
+        spectral_derivative(nx, dx, H, -0.5 * dx, D, re, im);
+        for (int64_t i = 0; i < nx; ++i) {
+            double dp = (i >= mb && i < me) ? P[i - mb] : 0.0;
+            E[i] = ca * E[i] + cb * (-dp + D[i]);
+        }
+        if (src) E[0] = amp * src[t + 1];
+        if (probe) probe[t + 1] = E[nx - 1];
+        if (snap_every > 0 && (t + 1) % snap_every == 0) {
+            int64_t s = (t + 1) / snap_every - 1;
+            if (e_snap) memcpy(e_snap + s * nx, E, sizeof(double) * nx);
+            if (pop_snap)
+                for (int64_t c = 0; c < nmed; ++c)
+                    for (int a = 0; a < n; ++a)
+                        pop_snap[(s * n + a) * nmed + c] = creal(rho[c * n2 + a * n + a]);
+        }
+    }
+    if (h_final) memcpy(h_final, H, sizeof(double) * nx);
+    free(rho); free(r0); free(E); free(H); free(D); free(re); free(im); free(P);
+    medium_free(&m);
+    return 0;
+}
+
+/* exported for the pins: the spectral derivative itself */
+void orc_spectral_derivative(int64_t nx, double dx, const double *f, double shift, double *out)
+{
+    double *re = (double *)calloc(nx, sizeof(double)), *im = (double *)calloc(nx, sizeof(double));
+    spectral_derivative(nx, dx, f, shift, out, re, im);
+    free(re); free(im);
 }

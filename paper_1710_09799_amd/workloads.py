@@ -29,6 +29,8 @@ HBAR = 1.054571817e-34
 C0 = 299792458.0
 E_CHARGE = 1.602176634e-19
 H_PLANCK = 6.62607015e-34
+EPS0 = 8.8541878128e-12
+MU0 = 1.25663706212e-6
 
 
 @dataclasses.dataclass
@@ -138,6 +140,28 @@ def sech_pulse(nt, dt, omega, tau, t0):
 def gauss_pulse(nt, dt, omega, sigma_t, t0):
     t = np.arange(nt + 1, dtype=np.float64) * dt
     return np.exp(-0.5 * ((t - t0) / sigma_t) ** 2) * np.sin(omega * (t - t0))
+
+
+def moving_pulse(nx, dx, dt, x0, sigma_x, omega, amplitude, eps_r=1.0, mu_r=1.0):
+    """Initial fields of a Gaussian-envelope pulse moving towards larger x on
+    a periodic grid of nx cells: E at x_i = i dx and time 0, H at
+    x_i + dx/2 and time -dt/2, from the vacuum relation H = -sqrt(eps/mu) E
+    of such a wave (the fields of a pulse in the staggered leapfrog, whose
+    own dispersion differs from c by O((omega dt)^2)).  x0 is the centre,
+    sigma_x the envelope's standard deviation, omega the carrier frequency.
+    Returns (E, H), two float64 arrays of nx values."""
+    eps, mu = EPS0 * eps_r, MU0 * mu_r
+    c = 1.0 / math.sqrt(eps * mu)
+    L = nx * dx
+
+    def field(x):
+        u = (x - x0 + 0.5 * L) % L - 0.5 * L  # periodic distance from the centre
+        return amplitude * np.exp(-0.5 * (u / sigma_x) ** 2) * np.sin(omega / c * u)
+
+    x = np.arange(nx, dtype=np.float64) * dx
+    e = field(x)
+    h = -math.sqrt(eps / mu) * field(x + 0.5 * dx + 0.5 * c * dt)
+    return e, h
 
 
 def cw_wave(nt, dt, omega):
