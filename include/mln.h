@@ -321,6 +321,72 @@ int mln_batch_reset(mln_batch *b);
 int mln_batch_instance(mln_batch *b, int32_t i, mln_handle **h);
 void mln_batch_free(mln_batch *b);
 
+/* ---- pseudo-spectral (PSTD) field solver ------------------------------- */
+/* The paper names PSTD as a field solver that its Liouville treatment combines
+ * with, as well as FDTD (Introduction; Sec. 4).  Here: the staggered leapfrog
+ * of the Yee scheme in time (E at steps n, H at n + 1/2), the spatial
+ * derivatives spectral on a periodic grid of nx cells -- every Fourier mode
+ * of wavenumber kappa multiplied by i kappa exp(+-i kappa dx / 2), the sign
+ * giving the half-cell offset of H (x_i + dx/2) from E (x_i = i dx), the
+ * Nyquist mode dropped -- and the medium advanced by the rotation route in
+ * FP64, exactly as the Yee kernels do (Sec. 4.1, Eq. maxwell with the
+ * derivatives replaced).
+ *
+ * A run is an initial-value problem: E at step 0 and H at step -1/2 are
+ * given; there is no source and no absorbing boundary (the grid is a ring);
+ * the probe is E at cell nx - 1, with probe[0] = E at step 0.  n_inst
+ * independent problems share the grid and advance together, one workgroup
+ * each; they may differ in medium (same level count) and initial fields.
+ *
+ *   media    n_inst media, all with the same n_levels N in {2, 3, 4, 6}
+ *   grid     nx a power of two, 64 <= nx <= 4096, 4096, 2048, 1024 for
+ *            N = 2, 3, 4, 6; nt >= 0; medium cells [med_begin, med_end) with
+ *            1 <= med_begin <= med_end <= nx - 1; eps_r, mu_r, sigma as on
+ *            the Yee grid (conductivity semi-implicit).  Stability needs
+ *            c dt kappa_max / 2 < 1 with kappa_max = 2 pi (nx/2 - 1) / (nx dx),
+ *            c = 1 / sqrt(eps mu): else MLN_ECOURANT
+ *   e_init   n_inst x nx host array (row i: instance i), or NULL for zero
+ *   h_init   n_inst x nx host array of H at step -1/2, or NULL for zero
+ *   records  n_inst records (all with the same snap_every), or NULL: per
+ *            instance probe_out (nt + 1), e_out (nsnap x nx) and pop_out
+ *            (nsnap x N x nmed) as in mln_init, nsnap = nt / snap_every
+ *   stream   hipStream_t for all device work, NULL = the default stream
+ * Inputs are copied; the record buffers stay owned by the caller.  Errors:
+ * MLN_EINVAL (null or out-of-range arguments, non-finite initial fields,
+ * mixed level counts or snap_every), MLN_ENOTSUPPORTED (N or nx outside the
+ * built set), MLN_ECOURANT, the medium errors of mln_init, MLN_ENOMEM and
+ * MLN_EHIP.  On error *out is set to NULL. */
+typedef struct mln_pstd mln_pstd;
+int mln_pstd_init(int32_t n_inst, const mln_medium *media, const mln_grid *grid, const double *e_init,
+                  const double *h_init, const mln_record *records, void *stream, mln_pstd **out);
+
+/* Time steps fused into one launch (default 256; >= 1). */
+int mln_pstd_configure(mln_pstd *p, int32_t steps_per_launch);
+
+/* Launch shape: threads per workgroup (nx / cells_per_thread), cells per
+ * thread and steps per launch.  Any pointer may be NULL. */
+int mln_pstd_get_config(const mln_pstd *p, int32_t *threads, int32_t *cells_per_thread,
+                        int32_t *steps_per_launch);
+
+/* Advance n_steps (clamped to the steps left), enqueued on the stream;
+ * returns without waiting.  Allocates nothing. */
+int mln_pstd_step(mln_pstd *p, int64_t n_steps);
+
+/* Advance to step nt, wait, copy host-side records and check every probe for
+ * NaN/Inf (MLN_ENONFINITE). */
+int mln_pstd_run(mln_pstd *p);
+
+/* Back to the initial fields and medium state (step 0).  Synchronises. */
+int mln_pstd_reset(mln_pstd *p);
+
+int mln_pstd_current_step(const mln_pstd *p, int64_t *step);
+
+/* E (at the current step) and H (half a step earlier) of instance `inst`
+ * into host arrays of nx values (either may be NULL).  Synchronises. */
+int mln_pstd_get_fields(mln_pstd *p, int32_t inst, double *E, double *H);
+
+void mln_pstd_free(mln_pstd *p);
+
 /* ---- one-time factors (host only, no GPU needed) ---------------------- */
 
 /* The FP64 quantities built once per medium and time step.  D = N^2-1,

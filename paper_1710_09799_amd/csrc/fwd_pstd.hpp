@@ -1,0 +1,285 @@
+// fwd_pstd.hpp -- the coupled time step with a pseudo-spectral (PSTD) field
+// solver on a periodic grid (the paper names PSTD as a field solver its
+// Liouville treatment combines with: Introduction, Sec. 4).
+//
+// One workgroup advances one problem of nx cells (nx a power of two); a
+// launch of n_inst workgroups advances n_inst independent problems that share
+// the grid.  Per step, in the staggered leapfrog of the Yee kernels:
+//   H^{n+1/2} = H^{n-1/2} + (dt / mu) D+ E^n      D+ = d/dx at x_i + dx/2
+//   P         = Liouville cell step with E^n        (rotation route, Sec. 4.1)
+//   E^{n+1}   = ca E^n + cb (-P + D- H^{n+1/2})     D- = d/dx at x_i
+// D+ and D- multiply the Fourier mode of wavenumber kappa by
+// i kappa exp(+-i kappa dx / 2) (H sits half a cell to the right of E); the
+// Nyquist mode is dropped.
+//
+// Layout (all of it in one workgroup's registers and LDS):
+//   * thread t owns cells t + c T, c < C (T = nx / C threads): E^n and the
+//     Bloch state of those cells live in registers for the whole launch;
+//   * H lives in Fourier space for the whole launch, each mode pair
+//     (k, M - k), M = nx / 2, in the registers of one thread, so a step takes
+//     one forward and one inverse FFT; H returns to real space at the end of
+//     the launch;
+//   * a real signal f of length nx is packed into M complex values
+//     z_j = f_{2j} + i f_{2j+1} (the half-length transform of real data):
+//     the packed buffer is simply the nx reals in cell order;
+//   * forward FFT: radix-2 decimation in frequency, natural order in,
+//     bit-reversed order out; the mode-wise step works in bit-reversed order;
+//     inverse FFT: decimation in time, bit-reversed order in, natural order
+//     out, so no permutation pass is needed;
+//   * one LDS table tab[k] = exp(-i pi k / nx), k < M, holds every twiddle,
+//     the unpacking factors exp(-2 pi i k / nx) and the half-cell shifts.
+#pragma once
+
+#include "fwd_impl.hpp"
+
+namespace mln {
+
+constexpr int kPstdMaxThreads = 512;
+constexpr int kPstdMinCells = 64;
+
+struct PstdInst {
+  FacDev<double> fac;
+  double *E;        // nx: E_i at x_i = i dx (updated in place)
+  double *H;        // nx: H_i at x_i + dx / 2 (updated in place)
+  double *z;        // D x ld: rotation-route state of the medium cells (in place)
+  double *probe;    // nt + 1 samples of E_{nx-1}, or null
+  double *e_out;    // snapshots x nx, or null
+  double *pop_out;  // snapshots x N x nmed, or null
+};
+
+struct PstdArgs {
+  const PstdInst *inst;
+  const double2 *tab;  // M values exp(-i pi k / nx)
+  int64_t nx, mb, me, ld;
+  int log2m;           // M = nx / 2 = 2^log2m
+  int nsteps;
+  int64_t step0;
+  int64_t snap_every, snap_next, snap_i0;
+  double ca, cb;
+  double ah;           // (dt / mu) 2 pi / (nx dx): H-update factor per unit of k
+  double be;           // (cb / M) 2 pi / (nx dx): E-update factor per unit of k
+  int64_t opaque0;     // 0 at run time (keeps per-step factor loads inside the loop)
+};
+
+__device__ __forceinline__ double2 c_add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 c_sub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 c_mul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ double2 c_mulc(double2 a, double2 b) {
+  return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ double2 c_conj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 c_scale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+// i * a
+__device__ __forceinline__ double2 c_i(double2 a) { return make_double2(-a.y, a.x); }
+
+// exp(-i pi idx / nx) for 0 <= idx < nx = 2 M from the table of the first M
+// values: exp(-i pi (idx - M) / nx) exp(-i pi / 2) for idx >= M.
+__device__ __forceinline__ double2 pstd_tw(const double2 *tab, int idx, int M) {
+  if (idx < M) return tab[idx];
+  const double2 t = tab[idx - M];
+  return make_double2(t.y, -t.x);
+}
+
+// Position of mode k in the bit-reversed output of the forward transform.
+__device__ __forceinline__ int pstd_pos(int k, int lm) { return (int)(__brev((unsigned)k) >> (32 - lm)); }
+
+// Unnormalised forward DFT of length M = 2^lm in place (exp(-2 pi i j k / M)):
+// natural order in, bit-reversed order out.  Ends with a barrier.
+__device__ __forceinline__ void pstd_fft_dif(double2 *buf, const double2 *tab, int lm) {
+  const int M = 1 << lm;
+  for (int lh = lm - 1; lh >= 0; --lh) {
+    const int half = 1 << lh;
+    for (int b = threadIdx.x; b < M / 2; b += blockDim.x) {
+      const int j = b & (half - 1);
+      const int i0 = ((b >> lh) << (lh + 1)) | j;
+      const double2 u = buf[i0], v = buf[i0 + half];
+      buf[i0] = c_add(u, v);
+      // exp(-2 pi i j / (2 half)) = exp(-i pi (j 2^(lm + 1 - lh)) / nx)
+      buf[i0 + half] = c_mul(c_sub(u, v), pstd_tw(tab, j << (lm + 1 - lh), M));
+    }
+    __syncthreads();
+  }
+}
+
+// Unnormalised inverse DFT of length M in place (exp(+2 pi i j k / M)):
+// bit-reversed order in, natural order out.  Ends with a barrier.
+__device__ __forceinline__ void pstd_fft_dit_inv(double2 *buf, const double2 *tab, int lm) {
+  const int M = 1 << lm;
+  for (int lh = 0; lh < lm; ++lh) {
+    const int half = 1 << lh;
+    for (int b = threadIdx.x; b < M / 2; b += blockDim.x) {
+      const int j = b & (half - 1);
+      const int i0 = ((b >> lh) << (lh + 1)) | j;
+      const double2 u = buf[i0];
+      const double2 v = c_mulc(buf[i0 + half], pstd_tw(tab, j << (lm + 1 - lh), M));
+      buf[i0] = c_add(u, v);
+      buf[i0 + half] = c_sub(u, v);
+    }
+    __syncthreads();
+  }
+}
+
+// Modes k and M - k of the length-nx DFT F of a real signal from its packed
+// transform Z: with w = exp(-2 pi i k / nx), S = (Z_k + conj Z_{M-k}) / 2 and
+// Dd = (Z_k - conj Z_{M-k}) / 2, F_k = S - i w Dd and conj F_{M-k} = S + i w Dd.
+__device__ __forceinline__ void pstd_unpack(double2 Zk, double2 Zm, double2 w, double2 &Fk, double2 &Fm) {
+  const double2 S = c_scale(c_add(Zk, c_conj(Zm)), 0.5);
+  const double2 Dd = c_scale(c_sub(Zk, c_conj(Zm)), 0.5);
+  const double2 iwD = c_i(c_mul(w, Dd));
+  Fk = c_sub(S, iwD);
+  Fm = c_conj(c_add(S, iwD));
+}
+
+// Inverse of pstd_unpack: the packed spectrum of a real signal from its DFT
+// modes k and M - k (even part Xe, odd part Xo: Z_k = Xe + i Xo,
+// Z_{M-k} = conj Xe + i conj Xo).
+__device__ __forceinline__ void pstd_pack(double2 Gk, double2 Gm, double2 w, double2 &Zk, double2 &Zm) {
+  const double2 Xe = c_scale(c_add(Gk, c_conj(Gm)), 0.5);
+  const double2 Xo = c_scale(c_mulc(c_sub(Gk, c_conj(Gm)), w), 0.5);
+  Zk = c_add(Xe, c_i(Xo));
+  Zm = c_add(c_conj(Xe), c_i(c_conj(Xo)));
+}
+
+// N levels, C cells per thread (blockDim.x = nx / C threads).
+template <int N, int C>
+__global__ void __launch_bounds__(kPstdMaxThreads) fwd_pstd_kernel(PstdArgs a) {
+  constexpr int D = N * N - 1;
+  constexpr int R = (C + 3) / 4;  // mode pairs per thread: (M / 2) / T rounded up
+  using L = RotLds<N, double, false>;
+  extern __shared__ double2 pstd_lds[];
+  __shared__ double sF[L::size];
+  __shared__ double sP[N * D + N];
+  const int lm = a.log2m, M = 1 << lm;
+  double2 *tab = pstd_lds;
+  double2 *buf = pstd_lds + M;
+  double *bufd = reinterpret_cast<double *>(buf);  // the packed buffer as nx reals
+  const PstdInst in = a.inst[blockIdx.x];
+  const int T = blockDim.x, t = threadIdx.x;
+  const int64_t nx = a.nx, nmed = a.me - a.mb;
+
+  L::stage(in.fac, sF);
+  L::stage_pop(in.fac, sP);
+  for (int i = t; i < M; i += T) tab[i] = a.tab[i];
+
+  double E[C];
+  double z[C][D];
+  double zl[1] = {0.0};
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int64_t i = t + (int64_t)c * T;
+    E[c] = in.E[i];
+    const bool med = i >= a.mb && i < a.me;
+#pragma unroll
+    for (int j = 0; j < D; ++j) z[c][j] = med ? in.z[j * a.ld + (i - a.mb)] : 0.0;
+    bufd[i] = in.H[i];
+  }
+  __syncthreads();
+
+  // H into Fourier space: modes k and M - k of the pairs this thread owns;
+  // the k = 0 slot (DC and Nyquist modes, which no update touches) is kept
+  // as packed for the way back.
+  pstd_fft_dif(buf, tab, lm);
+  double2 hk[R], hm[R];
+  double2 h0 = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int k = 1 + t + r * T;
+    hk[r] = hm[r] = make_double2(0.0, 0.0);
+    if (k <= M / 2)
+      pstd_unpack(buf[pstd_pos(k, lm)], buf[pstd_pos(M - k, lm)], pstd_tw(tab, 2 * k, M), hk[r], hm[r]);
+  }
+  if (t == 0) h0 = buf[0];
+  __syncthreads();
+
+  int64_t snap_next = a.snap_next, si = a.snap_i0;
+  for (int s = 0; s < a.nsteps; ++s) {
+    const int64_t n = a.step0 + s;
+    const bool snap = n == snap_next;
+    int ts = t;  // per-step copy: addresses are recomputed, not held across steps
+    asm volatile("" : "+v"(ts));
+#pragma unroll
+    for (int c = 0; c < C; ++c) bufd[ts + c * T] = E[c];
+    __syncthreads();
+    pstd_fft_dif(buf, tab, lm);
+    // Mode-wise: H += (dt / mu) i kappa e^{+i kappa dx / 2} F(E^n); then the
+    // packed spectrum of (cb / M) D- H for the inverse transform.  With
+    // e = tab[k] = exp(-i pi k / nx): e^{+i kappa_k dx / 2} = conj e and
+    // e^{+i kappa_{M-k} dx / 2} = i e.
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int k = 1 + t + r * T;
+      if (k <= M / 2) {
+        const int pk = pstd_pos(k, lm), pm = pstd_pos(M - k, lm);
+        const double2 w = pstd_tw(tab, 2 * k, M);
+        const double2 e = tab[k];
+        double2 Fk, Fm;
+        pstd_unpack(buf[pk], buf[pm], w, Fk, Fm);
+        const double kk = (double)k, km = (double)(M - k);
+        hk[r] = c_add(hk[r], c_scale(c_i(c_mul(c_conj(e), Fk)), a.ah * kk));
+        hm[r] = c_sub(hm[r], c_scale(c_mul(e, Fm), a.ah * km));
+        const double2 Gk = c_scale(c_i(c_mul(e, hk[r])), a.be * kk);
+        const double2 Gm = c_scale(c_mul(c_conj(e), hm[r]), a.be * km);
+        double2 Zk, Zm;
+        pstd_pack(Gk, Gm, w, Zk, Zm);
+        buf[pk] = Zk;
+        buf[pm] = Zm;
+      }
+    }
+    if (t == 0) buf[0] = make_double2(0.0, 0.0);
+    __syncthreads();
+    pstd_fft_dit_inv(buf, tab, lm);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int64_t i = ts + (int64_t)c * T;
+      double P = 0.0;
+      if (i >= a.mb && i < a.me) {
+        const int64_t cm = i - a.mb;
+        double *pp = (snap && in.pop_out) ? in.pop_out + si * N * nmed + cm : nullptr;
+        P = cell_step<N, double, ROUTE_ROT, false>(in.fac, sF, sP, E[c], z[c], zl, pp, nmed, a.opaque0 * s);
+      }
+      E[c] = a.ca * E[c] - a.cb * P + bufd[i];
+      if (i == nx - 1 && in.probe) in.probe[n + 1] = E[c];
+      if (snap && in.e_out) in.e_out[si * nx + i] = E[c];
+    }
+    if (snap) {
+      snap_next += a.snap_every;
+      ++si;
+    }
+    __syncthreads();  // the packed buffer is read before the next step writes it
+  }
+
+  // H back to real space
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int k = 1 + t + r * T;
+    if (k <= M / 2) {
+      double2 Zk, Zm;
+      pstd_pack(hk[r], hm[r], pstd_tw(tab, 2 * k, M), Zk, Zm);
+      buf[pstd_pos(k, lm)] = Zk;
+      buf[pstd_pos(M - k, lm)] = Zm;
+    }
+  }
+  if (t == 0) buf[0] = h0;
+  __syncthreads();
+  pstd_fft_dit_inv(buf, tab, lm);
+  const double inv_m = 1.0 / (double)M;
+  // a fresh copy of the thread index, so that the write-back addresses are
+  // computed here rather than kept live from the loads at entry
+  int tb = t;
+  asm volatile("" : "+v"(tb));
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int64_t i = tb + (int64_t)c * T;
+    in.H[i] = bufd[i] * inv_m;
+    in.E[i] = E[c];
+    if (i >= a.mb && i < a.me) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) in.z[j * a.ld + (i - a.mb)] = z[c][j];
+    }
+  }
+}
+
+}  // namespace mln

@@ -137,6 +137,13 @@ inline void fdtd_coefs(const mln_handle *h, float &ch, float &ca, float &cb, flo
   inv_dx = h->fc32[3]; kmur = h->fc32[4]; cam1 = h->fc32[5];
 }
 
+// Upload the factors of `route` (FP64 Factors f at time step dt) in precision
+// Real into fac (factor block), pop and popc (FP64 population maps); fd then
+// points into them.
+template <typename Real>
+int upload_factors(const Factors &f, int route, double dt, DevBuf &fac, DevBuf &pop, DevBuf &popc,
+                   FacDev<Real> &fd);
+
 // Fill h->fc32 and h->h_scale32 from h->fd_coef.
 void tune_fp32_coefs(mln_handle *h);
 

@@ -63,13 +63,11 @@ void mln::tune_fp32_coefs(mln_handle *h) {
   h->h_scale32 = c[0] / (double)best_ch;
 }
 
-namespace {
-
 // Upload the factors of the chosen route in precision Real.  The layout of
 // the device block is a concatenation of arrays; FacDev points into it.
 template <typename Real>
-int upload_factors(mln_handle *h, FacDev<Real> &fd) {
-  const Factors &f = h->f;
+int mln::upload_factors(const Factors &f, int route, double dt, DevBuf &fac, DevBuf &pop, DevBuf &popc,
+                        FacDev<Real> &fd) {
   const int D = f.D, q = f.q;
   std::vector<Real> blk;
   auto push = [&](const std::vector<double> &v) {
@@ -78,16 +76,16 @@ int upload_factors(mln_handle *h, FacDev<Real> &fd) {
     while (blk.size() % 16) blk.push_back(0);
     return off;
   };
-  const bool rot = h->route == MLN_ROUTE_ROTATION;
+  const bool rot = route == MLN_ROUTE_ROTATION;
   std::vector<double> Km = rot ? f.K : f.A;
   for (int i = 0; i < D; ++i) Km[i * D + i] -= 1.0;
   std::vector<double> thdt(q), rre(D * D), rim(D * D), lamdt(D);
-  for (int p = 0; p < q; ++p) thdt[p] = f.theta[p] * h->grid.dt;
+  for (int p = 0; p < q; ++p) thdt[p] = f.theta[p] * dt;
   for (int i = 0; i < D * D; ++i) {
     rre[i] = f.R[i].real();
     rim[i] = f.R[i].imag();
   }
-  for (int k = 0; k < D; ++k) lamdt[k] = f.lam[k].imag() * h->grid.dt;
+  for (int k = 0; k < D; ++k) lamdt[k] = f.lam[k].imag() * dt;
   size_t oK = push(Km), oc = push(rot ? f.rz : f.c), ow = push(rot ? f.wz : f.w);
   size_t oth = push(thdt), orr = push(rre), ori = push(rim), ol = push(lamdt);
   size_t oS = push(f.S), oS2 = push(f.S2);
@@ -97,13 +95,13 @@ int upload_factors(mln_handle *h, FacDev<Real> &fd) {
   // factors of order one (powers of E itself overflow single precision)
   std::vector<double> Up;
   double unorm = 0.0;
-  if (h->route == MLN_ROUTE_PADE) {
+  if (route == MLN_ROUTE_PADE) {
     for (int j = 0; j < D; ++j) {
       double cs = 0.0;
-      for (int i = 0; i < D; ++i) cs += std::fabs(f.U[i * D + j] * h->grid.dt);
+      for (int i = 0; i < D; ++i) cs += std::fabs(f.U[i * D + j] * dt);
       unorm = std::max(unorm, cs);
     }
-    const double vs = unorm > 0.0 ? h->grid.dt / unorm : 0.0;
+    const double vs = unorm > 0.0 ? dt / unorm : 0.0;
     std::vector<double> V(D * D), P(D * D);
     for (int i = 0; i < D * D; ++i) V[i] = P[i] = f.U[i] * vs;
     Up.assign((size_t)kPadeMax * D * D, 0.0);
@@ -125,9 +123,9 @@ int upload_factors(mln_handle *h, FacDev<Real> &fd) {
   };
   const std::vector<double> &cvec = rot ? f.rz : f.c;
   size_t oKl = push(lo_of(Km)), ocl = push(lo_of(cvec)), otl = push(lo_of(thdt));
-  HIP_TRY(h->fac.alloc(blk.size() * sizeof(Real)));
-  HIP_TRY(hipMemcpy(h->fac.p, blk.data(), blk.size() * sizeof(Real), hipMemcpyHostToDevice));
-  const Real *b = (const Real *)h->fac.p;
+  HIP_TRY(fac.alloc(blk.size() * sizeof(Real)));
+  HIP_TRY(hipMemcpy(fac.p, blk.data(), blk.size() * sizeof(Real), hipMemcpyHostToDevice));
+  const Real *b = (const Real *)fac.p;
   fd.Km = b + oK;
   fd.cz = b + oc;
   fd.wz = b + ow;
@@ -145,14 +143,26 @@ int upload_factors(mln_handle *h, FacDev<Real> &fd) {
   fd.unorm = (Real)unorm;
   fd.p0 = (Real)(rot ? f.pr : f.p0);
   const std::vector<double> &pm = rot ? f.popz : f.popd;
-  HIP_TRY(h->pop.alloc(pm.size() * sizeof(double)));
-  HIP_TRY(hipMemcpy(h->pop.p, pm.data(), pm.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(pop.alloc(pm.size() * sizeof(double)));
+  HIP_TRY(hipMemcpy(pop.p, pm.data(), pm.size() * sizeof(double), hipMemcpyHostToDevice));
   const std::vector<double> &pc = rot ? f.popcy : f.popc;
-  HIP_TRY(h->popc.alloc(pc.size() * sizeof(double)));
-  HIP_TRY(hipMemcpy(h->popc.p, pc.data(), pc.size() * sizeof(double), hipMemcpyHostToDevice));
-  fd.pop = (const double *)h->pop.p;
-  fd.popc = (const double *)h->popc.p;
+  HIP_TRY(popc.alloc(pc.size() * sizeof(double)));
+  HIP_TRY(hipMemcpy(popc.p, pc.data(), pc.size() * sizeof(double), hipMemcpyHostToDevice));
+  fd.pop = (const double *)pop.p;
+  fd.popc = (const double *)popc.p;
   return MLN_OK;
+}
+
+template int mln::upload_factors<double>(const Factors &, int, double, DevBuf &, DevBuf &, DevBuf &,
+                                         FacDev<double> &);
+template int mln::upload_factors<float>(const Factors &, int, double, DevBuf &, DevBuf &, DevBuf &,
+                                        FacDev<float> &);
+
+namespace {
+
+template <typename Real>
+int upload_factors(mln_handle *h, FacDev<Real> &fd) {
+  return mln::upload_factors<Real>(h->f, h->route, h->grid.dt, h->fac, h->pop, h->popc, fd);
 }
 
 template <typename Real>

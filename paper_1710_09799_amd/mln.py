@@ -77,7 +77,9 @@ EXPORTS = ["mln_init", "mln_step", "mln_run", "mln_reset", "mln_current_step", "
            "mln_chain_rule", "mln_init_batch", "mln_batch_tune", "mln_batch_configure",
            "mln_batch_get_config", "mln_batch_use_graph", "mln_batch_step", "mln_batch_run",
            "mln_batch_reset", "mln_batch_instance", "mln_batch_free", "mln_measure_step_floor",
-           "mln_measure_fma_rate"]
+           "mln_measure_fma_rate", "mln_pstd_init", "mln_pstd_configure", "mln_pstd_get_config",
+           "mln_pstd_step", "mln_pstd_run", "mln_pstd_reset", "mln_pstd_current_step", "mln_pstd_get_fields",
+           "mln_pstd_free"]
 
 _lib = None
 
@@ -132,6 +134,16 @@ def load():
         "mln_measure_step_floor": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "mln_measure_fma_rate": ([ctypes.c_int32, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+        "mln_pstd_init": ([ctypes.c_int32, ctypes.POINTER(_Medium), ctypes.POINTER(_Grid), _dp, _dp,
+                           ctypes.POINTER(_Record), P, ctypes.POINTER(P)], ctypes.c_int),
+        "mln_pstd_configure": ([P, ctypes.c_int32], ctypes.c_int),
+        "mln_pstd_get_config": ([P, i32p, i32p, i32p], ctypes.c_int),
+        "mln_pstd_step": ([P, ctypes.c_int64], ctypes.c_int),
+        "mln_pstd_run": ([P], ctypes.c_int),
+        "mln_pstd_reset": ([P], ctypes.c_int),
+        "mln_pstd_current_step": ([P, i64p], ctypes.c_int),
+        "mln_pstd_get_fields": ([P, ctypes.c_int32, _dp, _dp], ctypes.c_int),
+        "mln_pstd_free": ([P], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -441,6 +453,117 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Pstd:
+    """Problems on a periodic grid with the pseudo-spectral field solver
+    (mln_pstd_init): all share problems[0].grid and differ in medium (same
+    level count) and initial fields.  e_init / h_init: E at step 0 and H at
+    step -1/2, shape (nx,) for all problems or (n, nx), None for zero.  The
+    problems' sources are not used (a PSTD run has none).  outputs(i) gives
+    problem i's recordings as torch float64 device tensors."""
+
+    def __init__(self, problems, e_init=None, h_init=None, snap_every=0, steps_per_launch=0,
+                 record_probe=True, record_pop=True, record_e=True):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("Pstd needs a HIP device")
+        L = load()
+        self._L = L
+        self.problems = list(problems)
+        n = len(self.problems)
+        g = self.problems[0].grid
+        self.grid = g
+        dev = torch.device("cuda")
+
+        def rows(a):
+            if a is None:
+                return None
+            a = np.asarray(a, dtype=np.float64)
+            a = np.broadcast_to(a, (n, g.nx)) if a.ndim == 1 else a
+            if a.shape != (n, g.nx):
+                raise ValueError(f"initial fields need shape ({g.nx},) or ({n}, {g.nx})")
+            return np.ascontiguousarray(a)
+
+        self._e0, self._h0 = rows(e_init), rows(h_init)
+        nsnap = g.nt // snap_every if snap_every > 0 else 0
+        meds = (_Medium * n)()
+        recs = (_Record * n)()
+        self._keep = []
+        self._out = []
+        for i, p in enumerate(self.problems):
+            o = dict(probe=torch.zeros(g.nt + 1, dtype=torch.float64, device=dev) if record_probe else None,
+                     e_snap=(torch.zeros((nsnap, g.nx), dtype=torch.float64, device=dev)
+                             if (record_e and nsnap) else None),
+                     pop=(torch.zeros((nsnap, p.medium.n_levels, g.n_med), dtype=torch.float64, device=dev)
+                          if (record_pop and nsnap) else None))
+            self._out.append(o)
+            ma = _MediumArgs(p.medium)
+            self._keep.append(ma)
+            meds[i] = ma.s
+            recs[i] = _Record(snap_every, _dptr(o["pop"]), _dptr(o["e_snap"]), _dptr(o["probe"]), 1)
+        grid = _Grid(g.nx, g.nt, g.dx, g.dt, g.med_begin, g.med_end, g.eps_r, g.mu_r, g.sigma)
+        self.stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(L.mln_pstd_init(n, meds, ctypes.byref(grid), _ptr(self._e0), _ptr(self._h0), recs,
+                               ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        if steps_per_launch:
+            self.configure(steps_per_launch)
+
+    def configure(self, steps_per_launch):
+        _check(self._L.mln_pstd_configure(self._h, int(steps_per_launch)))
+
+    def config(self):
+        t, c, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(self._L.mln_pstd_get_config(self._h, ctypes.byref(t), ctypes.byref(c), ctypes.byref(k)))
+        return dict(threads=t.value, cells_per_thread=c.value, steps_per_launch=k.value)
+
+    def step(self, n):
+        _check(self._L.mln_pstd_step(self._h, int(n)))
+
+    def run(self):
+        _check(self._L.mln_pstd_run(self._h))
+        return self._out
+
+    def reset(self):
+        _check(self._L.mln_pstd_reset(self._h))
+
+    def current_step(self):
+        s = ctypes.c_int64()
+        _check(self._L.mln_pstd_current_step(self._h, ctypes.byref(s)))
+        return s.value
+
+    def fields(self, i=0):
+        E = np.zeros(self.grid.nx)
+        H = np.zeros(self.grid.nx)
+        _check(self._L.mln_pstd_get_fields(self._h, int(i), _ptr(E), _ptr(H)))
+        return E, H
+
+    def outputs(self, i):
+        return self._out[i]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.mln_pstd_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pstd_run(problem, e_init=None, h_init=None, snap_every=0, **kw):
+    """Convenience: one PSTD problem run to the end; outputs as numpy arrays
+    plus the final fields 'e' and 'h'."""
+    s = Pstd([problem], e_init=e_init, h_init=h_init, snap_every=snap_every, **kw)
+    out = s.run()
+    res = {k: (v.cpu().numpy() if v is not None else None) for k, v in out[0].items()}
+    res["e"], res["h"] = s.fields(0)
+    s.close()
+    return res
 
 
 def run(problem, **kw):

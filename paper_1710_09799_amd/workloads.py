@@ -204,6 +204,44 @@ def three_level(nx=20000, nt=100000, name="three_level_ladder_pi_gauss"):
     return Problem(name, med, grid, src)
 
 
+# A spectral grid resolves a wave with far fewer cells than the Yee grid.
+DX_PSTD = LAMBDA0 / 8.0
+DT_PSTD = 0.5 * DX_PSTD / C0  # Courant number 0.5 (PSTD leapfrog limit ~2/pi)
+
+
+def pstd_three_level(nx=2048, nt=8192, name="pstd_three_level_ring"):
+    """The three-level ladder medium of three_level() on a periodic grid for
+    the pseudo-spectral solver: nx cells of lambda0/8 (a ring nx/8
+    wavelengths long), the medium in cells [nx/4, 3nx/4), a Gaussian pi pulse
+    of 50 fs envelope FWHM as the initial field, centred at nx/8 and moving
+    towards the medium; nt steps at Courant number 0.5 (nt = 4 nx is two
+    round trips).  Returns (problem, e_init, h_init)."""
+    mu01 = 1e-29
+    med = ladder_medium([0.0, HBAR * OMEGA0, 2.1 * HBAR * OMEGA0], [mu01, 0.8e-29],
+                        density=1e24, decay=1e12, dephasing=5e12)
+    sig = 50e-15 / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+    amp = math.pi * HBAR / (mu01 * sig * math.sqrt(2.0 * math.pi))
+    grid = Grid(nx=nx, nt=nt, dx=DX_PSTD, dt=DT_PSTD, med_begin=nx // 4, med_end=3 * nx // 4)
+    e0, h0 = moving_pulse(nx, DX_PSTD, DT_PSTD, (nx // 8) * DX_PSTD, C0 * sig, OMEGA0, amp)
+    return Problem(name, med, grid, Source(np.zeros(nt + 1), 0.0)), e0, h0
+
+
+def pstd_random(n, seed, nx=64, nt=200, med=None, density=1e25):
+    """Short PSTD run on a ring of nx cells of lambda0/8: random N-level
+    medium (random_medium with the given density) in cells [med) (default
+    [nx/4, 3nx/4)), a Gaussian pulse (envelope ~8 cells, random amplitude
+    near a pi pulse) centred at nx/8 moving towards it.  Returns (problem,
+    e_init, h_init)."""
+    rng = np.random.default_rng(seed + 11)
+    medium = random_medium(n, seed, density=density)
+    b, e = (nx // 4, 3 * nx // 4) if med is None else med
+    grid = Grid(nx=nx, nt=nt, dx=DX_PSTD, dt=DT_PSTD, med_begin=b, med_end=e)
+    sig_x = 8.0 * DX_PSTD * float(rng.uniform(0.8, 1.2))
+    amp = float(rng.uniform(2e9, 6e9))
+    e0, h0 = moving_pulse(nx, DX_PSTD, DT_PSTD, (nx // 8) * DX_PSTD, sig_x, OMEGA0, amp)
+    return Problem(f"pstd_random_n{n}_s{seed}", medium, grid, Source(np.zeros(nt + 1), 0.0)), e0, h0
+
+
 def six_level(nx=50000, nt=200000, seed=1710, name="six_level_qcl_cw"):
     """N=6 QCL-like region: energies U[0,60] meV (sorted), tridiagonal real
     dipoles U[1,5] nm*e, one Lindblad channel |a><b| per pair a<b with

@@ -1,0 +1,149 @@
+"""Pseudo-spectral (PSTD) field solver on the GPU (mln_pstd_*): element-by-
+element parity with the FP64 oracle's PSTD run (direct DFT derivatives,
+density-matrix medium) for N = 2, 3, 4, 6 and every cells-per-thread shape
+of the one-workgroup kernel, with launch chunks that do not divide the run,
+snapshots across launches, media that start and end at arbitrary cells,
+batches of different media and initial fields, and the exact single-mode
+vacuum solution of the leapfrog at the largest grid."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1710_09799_amd import mln
+from paper_1710_09799_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10  # FP64 throughout: FFT vs direct DFT sums differ by rounding only
+
+
+def _check(got, ref, h_final=None):
+    # E errors relative to the largest field anywhere (the probe cell can sit
+    # far from the pulse, where E is rounding noise of the pulse's size)
+    scale = max(np.max(np.abs(ref["probe"])), np.max(np.abs(ref["e_snap"])))
+    errs = {"probe": np.max(np.abs(got["probe"] - ref["probe"])) / scale}
+    if ref["e_snap"] is not None and ref["e_snap"].size:
+        errs["e_snap"] = np.max(np.abs(got["e_snap"] - ref["e_snap"])) / scale
+    if ref["pop"] is not None and ref["pop"].size:
+        errs["pop"] = np.max(np.abs(got["pop"] - ref["pop"]))
+    if h_final is not None:
+        errs["h"] = np.max(np.abs(h_final - ref["h"])) / np.max(np.abs(ref["h"]))
+    print("  errors", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v < TOL, (k, v)
+
+
+# (N, nx, nt, steps per launch, medium range or None): nx 64..512 run one
+# cell per thread, 1024 two, 2048 four, 4096 eight; on the large grids the
+# medium sits under the initial pulse so that the few steps the oracle can
+# afford still couple it strongly
+CASES = [
+    (2, 64, 200, 64, None), (3, 64, 200, 37, None), (4, 64, 120, 50, None), (6, 64, 80, 33, None),
+    (2, 512, 120, 256, (40, 301)), (3, 256, 150, 41, (17, 200)),
+    (2, 1024, 40, 13, (100, 250)), (3, 1024, 40, 9, (101, 233)), (6, 1024, 12, 5, (110, 150)),
+    (2, 2048, 24, 7, (230, 420)), (3, 2048, 24, 10, (231, 399)), (4, 2048, 16, 6, (240, 300)),
+    (2, 4096, 12, 5, (490, 700)), (3, 4096, 12, 4, (500, 611)),
+]
+
+
+@pytest.mark.parametrize("n,nx,nt,spl,med", CASES)
+def test_pstd_matches_oracle(orc, n, nx, nt, spl, med):
+    print(f"[case] pstd N={n} nx={nx} nt={nt} spl={spl} med={med}", flush=True)
+    p, e0, h0 = W.pstd_random(n, 3 + n, nx=nx, nt=nt, med=med)
+    se = max(1, nt // 4)
+    ref = orc.pstd_run(p, snap_every=se, e_init=e0, h_init=h0)
+    s = mln.Pstd([p], e_init=e0, h_init=h0, snap_every=se, steps_per_launch=spl)
+    cfg = s.config()
+    assert cfg["threads"] * cfg["cells_per_thread"] == nx and cfg["threads"] <= 512
+    out = {k: (v.cpu().numpy() if v is not None else None) for k, v in s.run()[0].items()}
+    e, h = s.fields(0)
+    s.close()
+    _check(out, ref, h_final=h)
+    assert np.array_equal(out["probe"][-1], e[-1])
+
+
+def test_pstd_batch_of_media_and_fields(orc):
+    """Three problems with different media and initial fields in one launch;
+    each matches its own oracle run."""
+    nx, nt = 256, 160
+    items = [W.pstd_random(3, seed, nx=nx, nt=nt, med=(30 + 7 * seed, 180 + 5 * seed)) for seed in (1, 2, 3)]
+    # one grid for all: the medium range of the first problem
+    g = items[0][0].grid
+    probs = [W.Problem(p.name, p.medium, g, p.source) for p, _, _ in items]
+    e0 = np.stack([it[1] for it in items])
+    h0 = np.stack([it[2] * (1.0 + 0.1 * i) for i, it in enumerate(items)])
+    s = mln.Pstd(probs, e_init=e0, h_init=h0, snap_every=40, steps_per_launch=50)
+    outs = [{k: (v.cpu().numpy() if v is not None else None) for k, v in o.items()} for o in s.run()]
+    fields = [s.fields(i) for i in range(3)]
+    s.close()
+    for i, p in enumerate(probs):
+        print(f"[case] batch instance {i}", flush=True)
+        ref = orc.pstd_run(p, snap_every=40, e_init=e0[i], h_init=h0[i])
+        _check(outs[i], ref, h_final=fields[i][1])
+
+
+def test_pstd_reset_repeats_bitwise_and_chunking_changes_rounding_only():
+    """A reset run with the same launch chunks repeats bit for bit.  Other
+    chunks (steps in pieces, another steps-per-launch) agree to rounding: H
+    returns to real space at the end of every launch, so the chunking only
+    moves where that rounding happens."""
+    p, e0, h0 = W.pstd_random(2, 9, nx=128, nt=300)
+    s = mln.Pstd([p], e_init=e0, h_init=h0, snap_every=30, steps_per_launch=64)
+
+    def grab():
+        return {k: v.cpu().numpy().copy() for k, v in s.outputs(0).items()}, s.fields(0)
+
+    s.run()
+    first, f1 = grab()
+    s.reset()
+    assert s.current_step() == 0
+    s.run()
+    again, f2 = grab()
+    for k in first:
+        assert np.array_equal(first[k], again[k]), k
+    assert np.array_equal(f1[0], f2[0]) and np.array_equal(f1[1], f2[1])
+    s.reset()
+    s.step(37)
+    s.step(101)
+    assert s.current_step() == 138
+    s.configure(17)
+    s.run()
+    pieces, f3 = grab()
+    s.close()
+    scale = np.max(np.abs(first["e_snap"]))
+    assert np.max(np.abs(pieces["e_snap"] - first["e_snap"])) < 1e-12 * scale
+    assert np.max(np.abs(pieces["probe"] - first["probe"])) < 1e-12 * scale
+    assert np.max(np.abs(pieces["pop"] - first["pop"])) < 1e-12
+    assert np.max(np.abs(f3[1] - f1[1])) < 1e-12 * np.max(np.abs(f1[1]))
+
+
+@pytest.mark.parametrize("m", [1, 37, 1000])
+def test_pstd_single_mode_exact_at_the_largest_grid(orc, m):
+    """Vacuum (a medium of zero density), E = A cos(kappa x) with its exact
+    leapfrog partner H: after nt steps E = A cos(kappa x - omega nt dt) with
+    sin(omega dt / 2) = c kappa dt / 2, at nx = 4096 and 2000 steps."""
+    c = orc.constants()
+    nx, nt = 4096, 2000
+    dx = W.DX_PSTD
+    c0 = 1.0 / math.sqrt(c["eps0"] * c["mu0"])
+    dt = 0.5 * dx / c0
+    kap = 2 * math.pi * m / (nx * dx)
+    w = 2.0 / dt * math.asin(c0 * kap * dt / 2.0)
+    A = 2.0e9
+    B = -dt * A * kap / (2.0 * c["mu0"] * math.sin(w * dt / 2.0))
+    x = np.arange(nx) * dx
+    e0 = A * np.cos(kap * x)
+    h0 = B * np.cos(kap * (x + 0.5 * dx) + w * dt / 2.0)
+    med = W.ladder_medium([0.0, 1e-19], [1e-29], density=0.0)
+    p = W.Problem("vac", med, W.Grid(nx=nx, nt=nt, dx=dx, dt=dt, med_begin=1, med_end=2),
+                  W.Source(np.zeros(nt + 1), 0.0))
+    out = mln.pstd_run(p, e_init=e0, h_init=h0, snap_every=nt)
+    want_e = A * np.cos(kap * x - w * nt * dt)
+    want_h = B * np.cos(kap * (x + 0.5 * dx) - w * (nt - 0.5) * dt)
+    err_e = np.max(np.abs(out["e_snap"][0] - want_e)) / A
+    err_h = np.max(np.abs(out["h"] - want_h)) / abs(B)
+    print(f"[case] single mode m={m}: err_E={err_e:.2e} err_H={err_h:.2e}", flush=True)
+    assert err_e < 1e-9 and err_h < 1e-9
+    n = np.arange(nt + 1)
+    assert np.max(np.abs(out["probe"] - A * np.cos(kap * x[-1] - w * n * dt))) < 1e-9 * A
