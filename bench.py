@@ -276,6 +276,52 @@ def variants(p3, ref64, pop64, headline):
     return var
 
 
+def pstd_ring():
+    """Pseudo-spectral field solver (one workgroup per problem): the
+    three-level ladder on a periodic ring of 2048 cells of lambda0/8 (medium
+    1024 cells), 8192 steps, alone and as a batch of 256 problems (one per
+    compute unit, densities 0.5e24 .. 1.5e24 /m^3); the field-only step time
+    (one medium cell) separates the FFT pair from the Liouville step."""
+    import torch
+    from paper_1710_09799_amd import mln
+    from paper_1710_09799_amd import workloads as W
+    p, e0, h0 = W.pstd_three_level()
+    g = p.grid
+
+    def timed(s, steps):
+        s.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    out = {"workload": "three-level ladder on a periodic ring, 2048 cells of lambda0/8 (medium 1024), "
+                       "8192 steps, Courant 0.5, pi pulse 50 fs FWHM as the initial field", "precision": "fp64"}
+    s = mln.Pstd([p], e_init=e0, h_init=h0, steps_per_launch=256, record_pop=False, record_e=False)
+    timed(s, 256)
+    t = timed(s, g.nt)
+    out["single"] = {"value": g.n_med * g.nt / t, "us_per_step": t / g.nt * 1e6, **s.config()}
+    s.close()
+    g1 = W.Grid(nx=g.nx, nt=g.nt, dx=g.dx, dt=g.dt, med_begin=1, med_end=2)
+    s = mln.Pstd([W.Problem("fields", p.medium, g1, p.source)], e_init=e0, h_init=h0, steps_per_launch=256,
+                 record_pop=False, record_e=False)
+    timed(s, 256)
+    out["single"]["fields_only_us_per_step"] = timed(s, g.nt) / g.nt * 1e6
+    s.close()
+    n = 256
+    probs = [W.Problem(p.name, W.ladder_medium([0.0, W.HBAR * W.OMEGA0, 2.1 * W.HBAR * W.OMEGA0],
+                                               [1e-29, 0.8e-29], density=1e24 * (0.5 + i / n),
+                                               decay=1e12, dephasing=5e12), g, p.source) for i in range(n)]
+    s = mln.Pstd(probs, e_init=e0, h_init=h0, steps_per_launch=256, record_pop=False, record_e=False)
+    timed(s, 256)
+    nt = 2048
+    t = timed(s, nt)
+    out["batch_256"] = {"value": n * g.n_med * nt / t, "us_per_step": t / nt * 1e6, "steps": nt}
+    s.close()
+    return out
+
+
 def n2_large_problem():
     """The two-level medium and pulse on 2^24 cells (medium: the central
     half), 1000 steps: a shape large enough to fill the chip and to make the
@@ -328,12 +374,49 @@ PROFILE_CASES = {
     "n2_large_fp64_k16": ("n2_large", {}, dict(precision="fp64", variant="block", tile=256, steps_per_launch=16)),
     "n2_large_fp32_k1": ("n2_large", {}, dict(precision="fp32", variant="block", tile=256, steps_per_launch=1)),
     "n2_large_fp32_k16": ("n2_large", {}, dict(precision="fp32", variant="block", tile=256, steps_per_launch=16)),
+    # pseudo-spectral ring (2048 cells, 2048 of its 8192 steps): the problem
+    # alone, its field part alone (one medium cell), and 256 problems at once
+    "pstd_n3_ring": ("pstd", dict(batch=1, med=True), dict(steps_per_launch=256)),
+    "pstd_n3_ring_fields": ("pstd", dict(batch=1, med=False), dict(steps_per_launch=256)),
+    "pstd_n3_ring_batch256": ("pstd", dict(batch=256, med=True), dict(steps_per_launch=256)),
 }
+
+
+def profile_pstd(name, batch, med, steps_per_launch, steps, warmup):
+    import torch
+    from paper_1710_09799_amd import mln
+    from paper_1710_09799_amd import workloads as W
+    p, e0, h0 = W.pstd_three_level(nt=2048)
+    g = p.grid
+    if not med:
+        g = W.Grid(nx=g.nx, nt=g.nt, dx=g.dx, dt=g.dt, med_begin=1, med_end=2)
+    probs = [W.Problem(p.name, W.ladder_medium([0.0, W.HBAR * W.OMEGA0, 2.1 * W.HBAR * W.OMEGA0],
+                                               [1e-29, 0.8e-29], density=1e24 * (0.5 + i / batch),
+                                               decay=1e12, dephasing=5e12), g, p.source) for i in range(batch)]
+    s = mln.Pstd(probs, e_init=e0, h_init=h0, steps_per_launch=steps_per_launch, record_pop=False,
+                 record_e=False)
+    ts = []
+    for r in range(warmup + steps):
+        s.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(g.nt)
+        torch.cuda.synchronize()
+        if r >= warmup:
+            ts.append(time.perf_counter() - t0)
+    s.close()
+    t = min(ts)
+    print(json.dumps({"profile_case": name, "nx": g.nx, "nt": g.nt, "n_med": g.n_med, "problems": batch,
+                      "launches_per_run": -(-g.nt // steps_per_launch), "ms_per_run": t * 1e3,
+                      "us_per_step": t / g.nt * 1e6, "cell_updates_per_s": batch * g.n_med * g.nt / t}))
 
 
 def profile_case(name, steps, warmup, calib):
     from paper_1710_09799_amd import workloads as W
     wl, pkw, kw = PROFILE_CASES[name]
+    if wl == "pstd":
+        profile_pstd(name, pkw["batch"], pkw["med"], kw["steps_per_launch"], steps, warmup)
+        return
     p = n2_large_problem() if wl == "n2_large" else getattr(W, wl)(**pkw)
     t, g, nl, _ = time_solver(p, steps, warmup, 0, record_pop=False, record_e=False, **kw)
     if calib:
@@ -433,6 +516,7 @@ def main():
         var = {"n3_fp64_quad": {"value": n_upd / t64, "ms": t64 * 1e3, "launch_ms": g64 * 1e3 / nl64}}
         var[f"n3_speedup_{args.precision}_vs_fp64"] = value / var["n3_fp64_quad"]["value"]
         var.update(variants(p, e64, out64["pop"], args.precision))
+        var["pstd_ring"] = pstd_ring()
         res["variants"] = var
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)

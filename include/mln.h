@@ -360,8 +360,14 @@ typedef struct mln_pstd mln_pstd;
 int mln_pstd_init(int32_t n_inst, const mln_medium *media, const mln_grid *grid, const double *e_init,
                   const double *h_init, const mln_record *records, void *stream, mln_pstd **out);
 
-/* Time steps fused into one launch (default 256; >= 1). */
-int mln_pstd_configure(mln_pstd *p, int32_t steps_per_launch);
+/* Launch shape: time steps fused into one launch (0 = 256) and the most
+ * threads a workgroup may have (0 = automatic, 256 or 512; a grid of nx
+ * cells then runs min(nx, max_threads) threads of nx / threads cells each).
+ * 256 threads hold every built grid size in registers; 512 build up to half
+ * as many cells per thread (MLN_ENOTSUPPORTED beyond).  Automatic: 512
+ * where built, which steps one problem fastest; 256 lets two workgroups
+ * share a compute unit, which can serve batches of small grids better. */
+int mln_pstd_configure(mln_pstd *p, int32_t steps_per_launch, int32_t max_threads);
 
 /* Launch shape: threads per workgroup (nx / cells_per_thread), cells per
  * thread and steps per launch.  Any pointer may be NULL. */

@@ -34,7 +34,6 @@
 
 namespace mln {
 
-constexpr int kPstdMaxThreads = 512;
 constexpr int kPstdMinCells = 64;
 
 struct PstdInst {
@@ -86,37 +85,93 @@ __device__ __forceinline__ double2 pstd_tw(const double2 *tab, int idx, int M) {
 // Position of mode k in the bit-reversed output of the forward transform.
 __device__ __forceinline__ int pstd_pos(int k, int lm) { return (int)(__brev((unsigned)k) >> (32 - lm)); }
 
+// The mode pairs (k, M - k), k = 1 .. M/2, are numbered u = 0 .. M/2 - 1 by
+// the position of k: u = 0 is k = M/2 (position 1, its own partner), u > 0
+// the even position 2u (k = rev(2u) < M/2).  Consecutive threads then touch
+// consecutive positions (and the partners, whose positions are those of k
+// with the low bits inverted, nearly so) instead of positions M/2 apart,
+// which would put a whole wavefront on the same LDS banks.
+__device__ __forceinline__ int pstd_pair_pos(int u) { return u ? 2 * u : 1; }
+__device__ __forceinline__ int pstd_pair_k(int u, int lm) { return pstd_pos(pstd_pair_pos(u), lm); }
+
+// -i * a
+__device__ __forceinline__ double2 c_mi(double2 a) { return make_double2(a.y, -a.x); }
+
 // Unnormalised forward DFT of length M = 2^lm in place (exp(-2 pi i j k / M)):
-// natural order in, bit-reversed order out.  Ends with a barrier.
+// natural order in, bit-reversed order out.  The radix-2 stages of
+// decimation in frequency (span half = M/2 down to 1) run two at a time:
+// one pass over groups i0 + {0, h, 2h, 3h}, i0 mod 4h = j < h, applies the
+// stage of span 2h (twiddles W_4h^j and W_4h^(j+h) = -i W_4h^j) and then
+// the stage of span h (twiddle W_2h^j = (W_4h^j)^2), W_L = exp(-2 pi i / L).
+// An odd stage count leaves the span-1 stage (twiddle 1) for last.  Ends
+// with a barrier.
 __device__ __forceinline__ void pstd_fft_dif(double2 *buf, const double2 *tab, int lm) {
   const int M = 1 << lm;
-  for (int lh = lm - 1; lh >= 0; --lh) {
-    const int half = 1 << lh;
+  int lh = lm - 1;
+  for (; lh >= 1; lh -= 2) {
+    const int lq = lh - 1, h = 1 << lq;
+    for (int q = threadIdx.x; q < M / 4; q += blockDim.x) {
+      const int j = q & (h - 1);
+      const int i0 = ((q >> lq) << (lq + 2)) | j;
+      const double2 a0 = buf[i0], a1 = buf[i0 + h], a2 = buf[i0 + 2 * h], a3 = buf[i0 + 3 * h];
+      // W_4h^j = exp(-i pi (j 2^(lm - lq)) / nx), an index below M
+      const double2 w1 = tab[j << (lm - lq)];
+      const double2 w2 = c_mul(w1, w1);
+      const double2 b0 = c_add(a0, a2), b1 = c_add(a1, a3);
+      const double2 b2 = c_mul(c_sub(a0, a2), w1);
+      const double2 b3 = c_mi(c_mul(c_sub(a1, a3), w1));
+      buf[i0] = c_add(b0, b1);
+      buf[i0 + h] = c_mul(c_sub(b0, b1), w2);
+      buf[i0 + 2 * h] = c_add(b2, b3);
+      buf[i0 + 3 * h] = c_mul(c_sub(b2, b3), w2);
+    }
+    __syncthreads();
+  }
+  if (lh == 0) {
     for (int b = threadIdx.x; b < M / 2; b += blockDim.x) {
-      const int j = b & (half - 1);
-      const int i0 = ((b >> lh) << (lh + 1)) | j;
-      const double2 u = buf[i0], v = buf[i0 + half];
-      buf[i0] = c_add(u, v);
-      // exp(-2 pi i j / (2 half)) = exp(-i pi (j 2^(lm + 1 - lh)) / nx)
-      buf[i0 + half] = c_mul(c_sub(u, v), pstd_tw(tab, j << (lm + 1 - lh), M));
+      const double2 u = buf[2 * b], v = buf[2 * b + 1];
+      buf[2 * b] = c_add(u, v);
+      buf[2 * b + 1] = c_sub(u, v);
     }
     __syncthreads();
   }
 }
 
 // Unnormalised inverse DFT of length M in place (exp(+2 pi i j k / M)):
-// bit-reversed order in, natural order out.  Ends with a barrier.
+// bit-reversed order in, natural order out.  Decimation in time, spans
+// 1, 2, ..., M/2: the span-1 stage alone first when the stage count is odd,
+// then two stages per pass (span h with twiddle conj W_2h^j, then span 2h
+// with conj W_4h^j and conj W_4h^(j+h) = i conj W_4h^j).  Ends with a
+// barrier.
 __device__ __forceinline__ void pstd_fft_dit_inv(double2 *buf, const double2 *tab, int lm) {
   const int M = 1 << lm;
-  for (int lh = 0; lh < lm; ++lh) {
-    const int half = 1 << lh;
+  int lh = 0;
+  if (lm & 1) {
     for (int b = threadIdx.x; b < M / 2; b += blockDim.x) {
-      const int j = b & (half - 1);
-      const int i0 = ((b >> lh) << (lh + 1)) | j;
-      const double2 u = buf[i0];
-      const double2 v = c_mulc(buf[i0 + half], pstd_tw(tab, j << (lm + 1 - lh), M));
-      buf[i0] = c_add(u, v);
-      buf[i0 + half] = c_sub(u, v);
+      const double2 u = buf[2 * b], v = buf[2 * b + 1];
+      buf[2 * b] = c_add(u, v);
+      buf[2 * b + 1] = c_sub(u, v);
+    }
+    __syncthreads();
+    lh = 1;
+  }
+  for (; lh + 1 < lm; lh += 2) {
+    const int h = 1 << lh;
+    for (int q = threadIdx.x; q < M / 4; q += blockDim.x) {
+      const int j = q & (h - 1);
+      const int i0 = ((q >> lh) << (lh + 2)) | j;
+      const double2 a0 = buf[i0], a1 = buf[i0 + h], a2 = buf[i0 + 2 * h], a3 = buf[i0 + 3 * h];
+      const double2 u1 = c_conj(tab[j << (lm - lh)]);
+      const double2 v = c_mul(u1, u1);
+      const double2 t1 = c_mul(a1, v), t3 = c_mul(a3, v);
+      const double2 b0 = c_add(a0, t1), b1 = c_sub(a0, t1);
+      const double2 b2 = c_add(a2, t3), b3 = c_sub(a2, t3);
+      const double2 s2 = c_mul(b2, u1);
+      const double2 s3 = c_i(c_mul(b3, u1));
+      buf[i0] = c_add(b0, s2);
+      buf[i0 + 2 * h] = c_sub(b0, s2);
+      buf[i0 + h] = c_add(b1, s3);
+      buf[i0 + 3 * h] = c_sub(b1, s3);
     }
     __syncthreads();
   }
@@ -143,9 +198,11 @@ __device__ __forceinline__ void pstd_pack(double2 Gk, double2 Gm, double2 w, dou
   Zm = c_add(c_conj(Xe), c_i(c_conj(Xo)));
 }
 
-// N levels, C cells per thread (blockDim.x = nx / C threads).
-template <int N, int C>
-__global__ void __launch_bounds__(kPstdMaxThreads) fwd_pstd_kernel(PstdArgs a) {
+// N levels, C cells per thread (blockDim.x = nx / C <= TMAX threads).  With
+// TMAX = 256 a workgroup is one wavefront per SIMD, which may hold up to 512
+// registers per lane (VGPRs and AGPRs); with 512, two per SIMD share them.
+template <int N, int C, int TMAX>
+__global__ void __launch_bounds__(TMAX) fwd_pstd_kernel(PstdArgs a) {
   constexpr int D = N * N - 1;
   constexpr int R = (C + 3) / 4;  // mode pairs per thread: (M / 2) / T rounded up
   using L = RotLds<N, double, false>;
@@ -186,10 +243,12 @@ __global__ void __launch_bounds__(kPstdMaxThreads) fwd_pstd_kernel(PstdArgs a) {
   double2 h0 = make_double2(0.0, 0.0);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int k = 1 + t + r * T;
+    const int u = t + r * T;
     hk[r] = hm[r] = make_double2(0.0, 0.0);
-    if (k <= M / 2)
-      pstd_unpack(buf[pstd_pos(k, lm)], buf[pstd_pos(M - k, lm)], pstd_tw(tab, 2 * k, M), hk[r], hm[r]);
+    if (u < M / 2) {
+      const int k = pstd_pair_k(u, lm);
+      pstd_unpack(buf[pstd_pair_pos(u)], buf[pstd_pos(M - k, lm)], pstd_tw(tab, 2 * k, M), hk[r], hm[r]);
+    }
   }
   if (t == 0) h0 = buf[0];
   __syncthreads();
@@ -210,9 +269,10 @@ __global__ void __launch_bounds__(kPstdMaxThreads) fwd_pstd_kernel(PstdArgs a) {
     // e^{+i kappa_{M-k} dx / 2} = i e.
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int k = 1 + t + r * T;
-      if (k <= M / 2) {
-        const int pk = pstd_pos(k, lm), pm = pstd_pos(M - k, lm);
+      const int u = t + r * T;
+      if (u < M / 2) {
+        const int k = pstd_pair_k(u, lm);
+        const int pk = pstd_pair_pos(u), pm = pstd_pos(M - k, lm);
         const double2 w = pstd_tw(tab, 2 * k, M);
         const double2 e = tab[k];
         double2 Fk, Fm;
@@ -254,11 +314,12 @@ __global__ void __launch_bounds__(kPstdMaxThreads) fwd_pstd_kernel(PstdArgs a) {
   // H back to real space
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int k = 1 + t + r * T;
-    if (k <= M / 2) {
+    const int u = t + r * T;
+    if (u < M / 2) {
+      const int k = pstd_pair_k(u, lm);
       double2 Zk, Zm;
       pstd_pack(hk[r], hm[r], pstd_tw(tab, 2 * k, M), Zk, Zm);
-      buf[pstd_pos(k, lm)] = Zk;
+      buf[pstd_pair_pos(u)] = Zk;
       buf[pstd_pos(M - k, lm)] = Zm;
     }
   }

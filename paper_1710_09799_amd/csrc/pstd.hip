@@ -18,51 +18,66 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
-// Largest cells-per-thread count built for N levels: one thread holds C
-// cells of E and of the D-component state in registers (256 VGPRs at 512
-// threads); beyond these counts the state no longer fits.
-int pstd_max_cells(int N) {
+// Largest cells-per-thread count built for N levels and TMAX threads per
+// workgroup: a thread holds C cells of E and of the D-component state in
+// registers (256 VGPRs per lane at 512 threads, 512 VGPRs and AGPRs at 256).
+int pstd_max_cells(int N, int tmax) {
   switch (N) {
-    case 2: return 8;
-    case 3: return 8;
-    case 4: return 4;
-    case 6: return 2;
+    case 2: return tmax == 256 ? 16 : 8;
+    case 3: return tmax == 256 ? 16 : 8;
+    case 4: return tmax == 256 ? 8 : 4;
+    case 6: return tmax == 256 ? 4 : 2;
     default: return 0;
   }
 }
 
-template <int N, int C>
+template <int N, int C, int TMAX>
 hipError_t launch_n(const PstdArgs &a, int n_inst, int threads, size_t lds, hipStream_t st) {
-  hipError_t e = hipFuncSetAttribute((const void *)fwd_pstd_kernel<N, C>,
+  hipError_t e = hipFuncSetAttribute((const void *)fwd_pstd_kernel<N, C, TMAX>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((fwd_pstd_kernel<N, C>), dim3((unsigned)n_inst), dim3(threads), lds, st, a);
+  hipLaunchKernelGGL((fwd_pstd_kernel<N, C, TMAX>), dim3((unsigned)n_inst), dim3(threads), lds, st, a);
   return hipGetLastError();
 }
 
-template <int N>
+template <int N, int TMAX>
 hipError_t launch_c(int C, const PstdArgs &a, int n_inst, int threads, size_t lds, hipStream_t st) {
+  constexpr int cmax = N == 2 ? (TMAX == 256 ? 16 : 8)
+                     : N == 3 ? (TMAX == 256 ? 16 : 8)
+                     : N == 4 ? (TMAX == 256 ? 8 : 4)
+                              : (TMAX == 256 ? 4 : 2);
   switch (C) {
-    case 1: return launch_n<N, 1>(a, n_inst, threads, lds, st);
-    case 2: return launch_n<N, 2>(a, n_inst, threads, lds, st);
+    case 1: return launch_n<N, 1, TMAX>(a, n_inst, threads, lds, st);
+    case 2: return launch_n<N, 2, TMAX>(a, n_inst, threads, lds, st);
     case 4:
-      if constexpr (N <= 4) return launch_n<N, 4>(a, n_inst, threads, lds, st);
+      if constexpr (cmax >= 4) return launch_n<N, 4, TMAX>(a, n_inst, threads, lds, st);
       break;
     case 8:
-      if constexpr (N <= 3) return launch_n<N, 8>(a, n_inst, threads, lds, st);
+      if constexpr (cmax >= 8) return launch_n<N, 8, TMAX>(a, n_inst, threads, lds, st);
+      break;
+    case 16:
+      if constexpr (cmax >= 16) return launch_n<N, 16, TMAX>(a, n_inst, threads, lds, st);
       break;
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_pstd(int N, int C, const PstdArgs &a, int n_inst, int threads, size_t lds, hipStream_t st) {
+template <int TMAX>
+hipError_t launch_t(int N, int C, const PstdArgs &a, int n_inst, int threads, size_t lds, hipStream_t st) {
   switch (N) {
-    case 2: return launch_c<2>(C, a, n_inst, threads, lds, st);
-    case 3: return launch_c<3>(C, a, n_inst, threads, lds, st);
-    case 4: return launch_c<4>(C, a, n_inst, threads, lds, st);
-    case 6: return launch_c<6>(C, a, n_inst, threads, lds, st);
+    case 2: return launch_c<2, TMAX>(C, a, n_inst, threads, lds, st);
+    case 3: return launch_c<3, TMAX>(C, a, n_inst, threads, lds, st);
+    case 4: return launch_c<4, TMAX>(C, a, n_inst, threads, lds, st);
+    case 6: return launch_c<6, TMAX>(C, a, n_inst, threads, lds, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_pstd(int N, int C, int tmax, const PstdArgs &a, int n_inst, int threads, size_t lds,
+                       hipStream_t st) {
+  if (threads > tmax) return hipErrorInvalidValue;
+  return tmax == 256 ? launch_t<256>(N, C, a, n_inst, threads, lds, st)
+                     : launch_t<512>(N, C, a, n_inst, threads, lds, st);
 }
 
 }  // namespace
@@ -78,7 +93,7 @@ struct mln_pstd {
   };
   int N = 0, n_inst = 0;
   mln_grid grid{};
-  int C = 1, threads = 0, log2m = 0;
+  int C = 1, threads = 0, tmax = 256, log2m = 0;
   size_t lds = 0;
   hipStream_t stream = nullptr;
   int64_t nmed = 0, ld = 0, step = 0;
@@ -135,11 +150,33 @@ int pstd_steps(mln_pstd *p, int64_t n) {
       a.snap_next = (q + 1) * a.snap_every - 1;
       a.snap_i0 = q;
     }
-    hipError_t e = launch_pstd(p->N, p->C, a, p->n_inst, p->threads, p->lds, p->stream);
+    hipError_t e = launch_pstd(p->N, p->C, p->tmax, a, p->n_inst, p->threads, p->lds, p->stream);
     if (e != hipSuccess) return set_err(MLN_EHIP, std::string("PSTD launch: ") + hipGetErrorString(e));
     p->step += k;
     n -= k;
   }
+  return MLN_OK;
+}
+
+// Threads per workgroup: at most tmax (256 or 512), fewer on grids below
+// that; C = nx / threads cells per thread.  Automatic (0): 512 where that
+// shape is built (one problem steps fastest with the medium spread over more
+// threads), except N = 6, whose 35-component state fits one thread's
+// registers only at 256.  For batches of small grids 256 can be faster: two
+// workgroups then share a compute unit.
+int set_shape(mln_pstd *p, int tmax) {
+  if (tmax == 0) tmax = (p->N < 6 && p->grid.nx <= 512 * pstd_max_cells(p->N, 512)) ? 512 : 256;
+  if (tmax != 256 && tmax != 512) return set_err(MLN_EINVAL, "PSTD threads per workgroup: 0, 256 or 512");
+  const int64_t nx = p->grid.nx;
+  const int threads = (int)std::min<int64_t>(nx, tmax);
+  const int C = (int)(nx / threads);
+  if (C > pstd_max_cells(p->N, tmax))
+    return set_err(MLN_ENOTSUPPORTED, "PSTD grid of " + std::to_string((long long)nx) + " cells needs " +
+                                          std::to_string(C) + " cells per thread at " + std::to_string(tmax) +
+                                          " threads: more than are built for N = " + std::to_string(p->N));
+  p->tmax = tmax;
+  p->threads = threads;
+  p->C = C;
   return MLN_OK;
 }
 
@@ -171,15 +208,12 @@ int mln_pstd_init(int32_t n_inst, const mln_medium *media, const mln_grid *grid,
   if (!(cl * kap_max * g.dt / 2.0 < 1.0))
     return set_err(MLN_ECOURANT, "PSTD leapfrog unstable: c dt kappa_max / 2 >= 1");
   const int N = media[0].n_levels;
-  const int cmax = pstd_max_cells(N);
-  if (cmax == 0) return set_err(MLN_ENOTSUPPORTED, "PSTD kernels are built for N = 2, 3, 4 and 6");
+  if (pstd_max_cells(N, 256) == 0) return set_err(MLN_ENOTSUPPORTED, "PSTD kernels are built for N = 2, 3, 4 and 6");
   for (int i = 1; i < n_inst; ++i)
     if (media[i].n_levels != N) return set_err(MLN_EINVAL, "all PSTD instances need the same level count");
-  int C = 1;
-  while (nx / C > kPstdMaxThreads) C *= 2;
-  if (C > cmax)
+  if (nx > 256 * pstd_max_cells(N, 256))
     return set_err(MLN_ENOTSUPPORTED, "PSTD grid too large for N = " + std::to_string(N) + ": nx <= " +
-                                          std::to_string((long long)kPstdMaxThreads * cmax));
+                                          std::to_string(256 * pstd_max_cells(N, 256)));
   int64_t se = 0;
   if (records) {
     se = records[0].snap_every;
@@ -196,11 +230,12 @@ int mln_pstd_init(int32_t n_inst, const mln_medium *media, const mln_grid *grid,
       if (!std::isfinite(h_init[i])) return set_err(MLN_EINVAL, "non-finite initial H");
 
   std::unique_ptr<mln_pstd> p(new mln_pstd());
+  int rc0 = 0;
   p->N = N;
   p->n_inst = n_inst;
   p->grid = g;
-  p->C = C;
-  p->threads = (int)(nx / C);
+  rc0 = set_shape(p.get(), 0);
+  if (rc0) return rc0;
   p->log2m = 0;
   while ((int64_t(1) << p->log2m) < M) ++p->log2m;
   p->lds = (size_t)2 * M * sizeof(double2);
@@ -285,10 +320,12 @@ int mln_pstd_init(int32_t n_inst, const mln_medium *media, const mln_grid *grid,
   return MLN_OK;
 }
 
-int mln_pstd_configure(mln_pstd *p, int32_t steps_per_launch) {
+int mln_pstd_configure(mln_pstd *p, int32_t steps_per_launch, int32_t max_threads) {
   if (!p) return set_err(MLN_EINVAL, "null handle");
-  if (steps_per_launch < 1) return set_err(MLN_EINVAL, "steps_per_launch must be >= 1");
-  p->spl = steps_per_launch;
+  if (steps_per_launch < 0) return set_err(MLN_EINVAL, "steps_per_launch must be >= 0");
+  const int rc = set_shape(p, max_threads);
+  if (rc) return rc;
+  p->spl = steps_per_launch ? steps_per_launch : 256;
   return MLN_OK;
 }
 
@@ -333,7 +370,8 @@ int mln_pstd_current_step(const mln_pstd *p, int64_t *step) {
   return MLN_OK;
 }
 
-int mln_pstd_get_config(const mln_pstd *p, int32_t *threads, int32_t *cells_per_thread, int32_t *steps_per_launch) {
+int mln_pstd_get_config(const mln_pstd *p, int32_t *threads, int32_t *cells_per_thread,
+                        int32_t *steps_per_launch) {
   if (!p) return set_err(MLN_EINVAL, "null handle");
   if (threads) *threads = p->threads;
   if (cells_per_thread) *cells_per_thread = p->C;

@@ -136,7 +136,7 @@ def load():
         "mln_measure_fma_rate": ([ctypes.c_int32, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "mln_pstd_init": ([ctypes.c_int32, ctypes.POINTER(_Medium), ctypes.POINTER(_Grid), _dp, _dp,
                            ctypes.POINTER(_Record), P, ctypes.POINTER(P)], ctypes.c_int),
-        "mln_pstd_configure": ([P, ctypes.c_int32], ctypes.c_int),
+        "mln_pstd_configure": ([P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
         "mln_pstd_get_config": ([P, i32p, i32p, i32p], ctypes.c_int),
         "mln_pstd_step": ([P, ctypes.c_int64], ctypes.c_int),
         "mln_pstd_run": ([P], ctypes.c_int),
@@ -463,7 +463,7 @@ class Pstd:
     problems' sources are not used (a PSTD run has none).  outputs(i) gives
     problem i's recordings as torch float64 device tensors."""
 
-    def __init__(self, problems, e_init=None, h_init=None, snap_every=0, steps_per_launch=0,
+    def __init__(self, problems, e_init=None, h_init=None, snap_every=0, steps_per_launch=0, max_threads=0,
                  record_probe=True, record_pop=True, record_e=True):
         import torch
         if not torch.cuda.is_available():
@@ -508,11 +508,13 @@ class Pstd:
         _check(L.mln_pstd_init(n, meds, ctypes.byref(grid), _ptr(self._e0), _ptr(self._h0), recs,
                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
         self._h = h
-        if steps_per_launch:
-            self.configure(steps_per_launch)
+        if steps_per_launch or max_threads:
+            self.configure(steps_per_launch, max_threads)
 
-    def configure(self, steps_per_launch):
-        _check(self._L.mln_pstd_configure(self._h, int(steps_per_launch)))
+    def configure(self, steps_per_launch=0, max_threads=0):
+        """Steps per launch (0 = 256) and the most threads per workgroup
+        (0 = automatic, 256 or 512)."""
+        _check(self._L.mln_pstd_configure(self._h, int(steps_per_launch), int(max_threads)))
 
     def config(self):
         t, c, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
