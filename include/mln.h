@@ -228,6 +228,30 @@ int mln_tune(mln_handle *h, int32_t trial_steps, int32_t *variant, int32_t *tile
  * (step n-1/2).  Synchronises the stream. */
 int mln_get_fields(mln_handle *h, double *E, double *H);
 
+/* The physical state after the completed steps (mln_current_step), host
+ * arrays; any pointer may be NULL.  Synchronises.
+ *   E         nx values, E at the current step (Sec. 2, Fig. 1)
+ *   H         nx - 1 values, H_{i+1/2} half a step earlier
+ *   rho_diag  N x nmed populations rho_aa = 1/N + (1/2) sum_l d_l (s_l)_aa
+ *             (Eq. comp_rho) of every medium cell, row a = level
+ * The device carries each cell's state after the first L1 half step of the
+ * next step (Sec. 4.1); the Bloch vector is recovered in FP64 as
+ * d = A0^-1 (d' - b0). */
+int mln_get_state(const mln_handle *h, double *E, double *H, double *rho_diag);
+
+/* The Bloch vectors d (Sec. 3: rho = 1/N + (1/2) sum_l d_l s_l, generators
+ * as mln_setup_factors returns them) of every medium cell after the
+ * completed steps: D x nmed host array, row l = component.  Synchronises. */
+int mln_get_bloch(const mln_handle *h, double *d);
+
+/* Replace the state at the current step (the step counter is unchanged):
+ * E (nx), H (nx - 1) and Bloch vectors d (D x nmed, as
+ * mln_get_bloch returns them), host arrays; NULL leaves that part as it is.
+ * The values are converted to the handle's precision; d is not checked for
+ * positivity.  Invalidates the checkpoints of mln_grad until the next run
+ * from step 0.  MLN_EINVAL on non-finite input.  Synchronises. */
+int mln_set_state(mln_handle *h, const double *E, const double *H, const double *d);
+
 /* Opaque full-state checkpoint (fields, Bloch state, step counter).
  * mln_state_bytes gives the size; save/load copy to/from a host buffer and
  * synchronise.  A loaded state continues bit-identically. */

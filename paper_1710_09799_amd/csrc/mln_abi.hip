@@ -667,6 +667,197 @@ int mln_get_fields(mln_handle *h, double *E, double *H) {
   return MLN_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Inverse of a D x D row-major matrix by Gauss-Jordan elimination with
+// partial pivoting (FP64; false if singular).
+bool invert(int D, const std::vector<double> &A, std::vector<double> &inv) {
+  std::vector<double> a(A);
+  inv.assign((size_t)D * D, 0.0);
+  for (int i = 0; i < D; ++i) inv[(size_t)i * D + i] = 1.0;
+  for (int c = 0; c < D; ++c) {
+    int pr = c;
+    for (int r = c + 1; r < D; ++r)
+      if (std::fabs(a[(size_t)r * D + c]) > std::fabs(a[(size_t)pr * D + c])) pr = r;
+    if (a[(size_t)pr * D + c] == 0.0) return false;
+    for (int k = 0; k < D; ++k) {
+      std::swap(a[(size_t)c * D + k], a[(size_t)pr * D + k]);
+      std::swap(inv[(size_t)c * D + k], inv[(size_t)pr * D + k]);
+    }
+    const double piv = 1.0 / a[(size_t)c * D + c];
+    for (int k = 0; k < D; ++k) {
+      a[(size_t)c * D + k] *= piv;
+      inv[(size_t)c * D + k] *= piv;
+    }
+    for (int r = 0; r < D; ++r) {
+      if (r == c) continue;
+      const double f = a[(size_t)r * D + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < D; ++k) {
+        a[(size_t)r * D + k] -= f * a[(size_t)c * D + k];
+        inv[(size_t)r * D + k] -= f * inv[(size_t)c * D + k];
+      }
+    }
+  }
+  return true;
+}
+
+// Bloch vectors d (D x nmed, component-major) of the state after the
+// completed steps.  The device carries, per cell, the state after the first
+// L1 half step of the next step, d' = A0 d + b0 (Sec. 4.1): in T-coordinates
+// as the deviation y = T^T d' - zr (rotation route, compensated FP32 as
+// high + low rows) or as d' itself (other routes).  d = A0^-1 (d' - b0).
+int read_bloch(mln_handle *h, std::vector<double> &d) {
+  const Factors &f = h->f;
+  const int D = f.D;
+  const int64_t nm = h->nmed, ld = h->ld;
+  const int rows = h->comp ? 2 * D : D;
+  std::vector<unsigned char> raw((size_t)rows * ld * h->rs);
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (nm > 0) HIP_TRY(hipMemcpy(raw.data(), h->z[h->cur].p, raw.size(), hipMemcpyDeviceToHost));
+  auto at = [&](int row, int64_t c) {
+    return h->rs == 8 ? ((const double *)raw.data())[row * ld + c] : (double)((const float *)raw.data())[row * ld + c];
+  };
+  std::vector<double> inv;
+  if (!invert(D, f.A0, inv)) return set_err(MLN_ENUMERIC, "half-step propagator is singular");
+  const bool rot = h->route == MLN_ROUTE_ROTATION;
+  d.assign((size_t)D * nm, 0.0);
+  std::vector<double> zp(D), dp(D);
+  for (int64_t c = 0; c < nm; ++c) {
+    for (int j = 0; j < D; ++j) zp[j] = at(j, c) + (h->comp ? at(D + j, c) : 0.0) + (rot ? f.zr[j] : 0.0);
+    for (int i = 0; i < D; ++i) {
+      double acc = 0.0;
+      if (rot)
+        for (int j = 0; j < D; ++j) acc += f.T[(size_t)i * D + j] * zp[j];
+      else
+        acc = zp[i];
+      dp[i] = acc - f.b0[i];
+    }
+    for (int i = 0; i < D; ++i) {
+      double acc = 0.0;
+      for (int j = 0; j < D; ++j) acc += inv[(size_t)i * D + j] * dp[j];
+      d[(size_t)i * nm + c] = acc;
+    }
+  }
+  return MLN_OK;
+}
+
+// Write n real values into a device buffer of the kernels' precision (with
+// the compensated fields, the high parts then the low parts).
+template <typename T>
+void to_real(const double *src, int64_t n, int64_t stride, bool split, double scale, std::vector<unsigned char> &out,
+             int64_t at) {
+  T *o = (T *)out.data();
+  for (int64_t i = 0; i < n; ++i) {
+    const double v = src[i] * scale;
+    o[at + i] = (T)v;
+    if (split) o[at + stride + i] = (T)(v - (double)(T)v);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int mln_get_state(const mln_handle *hc, double *E, double *H, double *rho_diag) {
+  mln_handle *h = const_cast<mln_handle *>(hc);
+  if (!h) return set_err(MLN_EINVAL, "null handle");
+  int rc = mln_get_fields(h, E, H);
+  if (rc || !rho_diag) return rc;
+  std::vector<double> d;
+  rc = read_bloch(h, d);
+  if (rc) return rc;
+  // rho_aa = 1/N + (1/2) sum_l d_l (s_l)_aa (Eq. comp_rho)
+  const Factors &f = h->f;
+  const int N = f.N, D = f.D;
+  const int64_t nm = h->nmed;
+  for (int a = 0; a < N; ++a)
+    for (int64_t c = 0; c < nm; ++c) {
+      double acc = 1.0 / N;
+      for (int l = 0; l < D; ++l) acc += 0.5 * d[(size_t)l * nm + c] * f.gen[((size_t)l * N + a) * N + a].real();
+      rho_diag[(size_t)a * nm + c] = acc;
+    }
+  return MLN_OK;
+}
+
+int mln_get_bloch(const mln_handle *hc, double *d) {
+  mln_handle *h = const_cast<mln_handle *>(hc);
+  if (!h || !d) return set_err(MLN_EINVAL, "null argument");
+  std::vector<double> v;
+  int rc = read_bloch(h, v);
+  if (rc) return rc;
+  std::copy(v.begin(), v.end(), d);
+  return MLN_OK;
+}
+
+int mln_set_state(mln_handle *h, const double *E, const double *H, const double *d) {
+  if (!h) return set_err(MLN_EINVAL, "null handle");
+  const int64_t nx = h->grid.nx, nm = h->nmed, ld = h->ld;
+  const Factors &f = h->f;
+  const int D = f.D;
+  for (int64_t i = 0; E && i < nx; ++i)
+    if (!std::isfinite(E[i])) return set_err(MLN_EINVAL, "non-finite E");
+  for (int64_t i = 0; H && i < nx - 1; ++i)
+    if (!std::isfinite(H[i])) return set_err(MLN_EINVAL, "non-finite H");
+  for (int64_t i = 0; d && i < (int64_t)D * nm; ++i)
+    if (!std::isfinite(d[i])) return set_err(MLN_EINVAL, "non-finite Bloch vector");
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  const bool f32 = h->rs == 4;
+  if (E || H) {
+    const int parts = h->cf ? 2 : 1;
+    std::vector<unsigned char> buf((size_t)h->rs * nx * parts, 0);
+    if (E) {
+      if (f32) to_real<float>(E, nx, nx, h->cf, 1.0, buf, 0);
+      else to_real<double>(E, nx, nx, false, 1.0, buf, 0);
+      HIP_TRY(hipMemcpy(h->E[h->cur].p, buf.data(), buf.size(), hipMemcpyHostToDevice));
+    }
+    if (H) {
+      std::fill(buf.begin(), buf.end(), 0);
+      if (f32) to_real<float>(H, nx - 1, nx, h->cf, 1.0 / h->h_scale32, buf, 0);
+      else to_real<double>(H, nx - 1, nx, false, 1.0, buf, 0);
+      HIP_TRY(hipMemcpy(h->H[h->cur].p, buf.data(), buf.size(), hipMemcpyHostToDevice));
+    }
+  }
+  if (d && nm > 0) {
+    // d' = A0 d + b0; rotation route: y = T^T d' - zr
+    const bool rot = h->route == MLN_ROUTE_ROTATION;
+    const int rows = h->comp ? 2 * D : D;
+    std::vector<double> st((size_t)rows * ld, 0.0), dp(D);
+    for (int64_t c = 0; c < nm; ++c) {
+      for (int i = 0; i < D; ++i) {
+        double acc = f.b0[i];
+        for (int j = 0; j < D; ++j) acc += f.A0[(size_t)i * D + j] * d[(size_t)j * nm + c];
+        dp[i] = acc;
+      }
+      for (int j = 0; j < D; ++j) {
+        double v = dp[j];
+        if (rot) {
+          v = -f.zr[j];
+          for (int i = 0; i < D; ++i) v += f.T[(size_t)i * D + j] * dp[i];
+        }
+        st[(size_t)j * ld + c] = v;
+      }
+    }
+    std::vector<unsigned char> buf((size_t)rows * ld * h->rs, 0);
+    if (f32) {
+      float *o = (float *)buf.data();
+      for (int j = 0; j < D; ++j)
+        for (int64_t c = 0; c < nm; ++c) {
+          const double v = st[(size_t)j * ld + c];
+          o[(size_t)j * ld + c] = (float)v;
+          if (h->comp) o[(size_t)(D + j) * ld + c] = (float)(v - (double)(float)v);
+        }
+    } else {
+      std::memcpy(buf.data(), st.data(), (size_t)D * ld * sizeof(double));
+    }
+    HIP_TRY(hipMemcpy(h->z[h->cur].p, buf.data(), buf.size(), hipMemcpyHostToDevice));
+  }
+  h->ckpt_ok = false;  // checkpoints of the run so far no longer lead here
+  return MLN_OK;
+}
+
 int mln_state_bytes(const mln_handle *h, int64_t *bytes) {
   if (!h || !bytes) return set_err(MLN_EINVAL, "null argument");
   *bytes = (int64_t)(sizeof(int64_t) + h->E[0].bytes + h->H[0].bytes + h->z[0].bytes);

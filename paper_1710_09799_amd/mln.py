@@ -71,7 +71,7 @@ class _Factors(ctypes.Structure):
 
 # every symbol include/mln.h declares
 EXPORTS = ["mln_init", "mln_step", "mln_run", "mln_reset", "mln_current_step", "mln_get_config", "mln_configure", "mln_tune",
-           "mln_get_fields",
+           "mln_get_fields", "mln_get_state", "mln_get_bloch", "mln_set_state",
            "mln_state_bytes", "mln_save_state", "mln_load_state", "mln_bloch_only", "mln_free",
            "mln_strerror", "mln_last_error", "mln_setup_factors", "mln_version", "mln_grad",
            "mln_chain_rule", "mln_init_batch", "mln_batch_tune", "mln_batch_configure",
@@ -106,6 +106,9 @@ def load():
         "mln_configure": ([P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
         "mln_tune": ([P, ctypes.c_int32, i32p, i32p, i32p], ctypes.c_int),
         "mln_get_fields": ([P, _dp, _dp], ctypes.c_int),
+        "mln_get_state": ([P, _dp, _dp, _dp], ctypes.c_int),
+        "mln_get_bloch": ([P, _dp], ctypes.c_int),
+        "mln_set_state": ([P, _dp, _dp, _dp], ctypes.c_int),
         "mln_state_bytes": ([P, i64p], ctypes.c_int),
         "mln_save_state": ([P, P], ctypes.c_int),
         "mln_load_state": ([P, P], ctypes.c_int),
@@ -312,6 +315,32 @@ class Solver:
         H = np.zeros(nx - 1)
         _check(self._L.mln_get_fields(self._h, _ptr(E), _ptr(H)))
         return E, H
+
+    def state(self):
+        """E (nx), H (nx - 1) and the populations (N x nmed) after the
+        completed steps (mln_get_state)."""
+        g, n = self.problem.grid, self.problem.medium.n_levels
+        E, H = np.zeros(g.nx), np.zeros(g.nx - 1)
+        pop = np.zeros((n, g.n_med))
+        _check(self._L.mln_get_state(self._h, _ptr(E), _ptr(H), _ptr(pop)))
+        return E, H, pop
+
+    def bloch(self):
+        """Bloch vectors (D x nmed) of every medium cell (mln_get_bloch)."""
+        n = self.problem.medium.n_levels
+        d = np.zeros((n * n - 1, self.problem.grid.n_med))
+        _check(self._L.mln_get_bloch(self._h, _ptr(d)))
+        return d
+
+    def set_state(self, E=None, H=None, d=None):
+        """Replace E (nx), H (nx - 1) and/or the Bloch vectors (D x nmed) at
+        the current step (mln_set_state)."""
+        arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in (E, H, d)]
+        g, n = self.problem.grid, self.problem.medium.n_levels
+        for a, shape in zip(arrs, ((g.nx,), (g.nx - 1,), (n * n - 1, g.n_med))):
+            if a is not None and a.shape != shape:
+                raise ValueError(f"expected shape {shape}, got {a.shape}")
+        _check(self._L.mln_set_state(self._h, *(_ptr(a) for a in arrs)))
 
     def save_state(self):
         nb = ctypes.c_int64()
