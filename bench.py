@@ -121,17 +121,24 @@ def rel_err(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-def cpu_baseline(p, nt):
+def cpu_baseline(p, nt, nt_single=500):
+    """The oracle on the host's cores (OpenMP over cells), and on one thread
+    as the paper times its solvers, each on a bounded sample of the run."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or (os.cpu_count() or 1)
     t0 = time.perf_counter()
     oracle.run(p, nt=nt, nthreads=threads)
     dt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.run(p, nt=nt_single, nthreads=1)
+    d1 = time.perf_counter() - t0
     return {"value": p.grid.n_med * nt / dt, "unit": "Liouville cell-updates/s", "cores": threads,
             "kind": "oracle",
             "sample": f"three-level ladder on the full 20000-cell grid, first {nt} of "
                       f"{p.grid.nt} steps, FP64 density-matrix oracle, OpenMP over cells "
-                      f"({dt:.1f} s)"}
+                      f"({dt:.1f} s)",
+            "single_thread": {"value": p.grid.n_med * nt_single / d1, "cores": 1,
+                              "sample": f"first {nt_single} steps of the same grid on one thread ({d1:.1f} s)"}}
 
 
 def variants(p3, ref64, pop64, headline):
