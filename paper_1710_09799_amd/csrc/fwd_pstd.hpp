@@ -26,8 +26,12 @@
 //     bit-reversed order out; the mode-wise step works in bit-reversed order;
 //     inverse FFT: decimation in time, bit-reversed order in, natural order
 //     out, so no permutation pass is needed;
-//   * one LDS table tab[k] = exp(-i pi k / nx), k < M, holds every twiddle,
-//     the unpacking factors exp(-2 pi i k / nx) and the half-cell shifts.
+//   * LDS holds the packed buffer, swizzled (element i at i ^ 5 ((i >> 4) & 3):
+//     the groups of the short-span passes and contiguous runs alike then fall
+//     on distinct 16-byte bank slots), and tables laid out in the order the
+//     lanes read them: per radix-4 pass its twiddles W_4h^j, j < h, and per
+//     mode pair its unpacking factor exp(-2 pi i k / nx) and half-cell shift
+//     exp(-i pi k / nx).
 #pragma once
 
 #include "fwd_impl.hpp"
@@ -48,7 +52,9 @@ struct PstdInst {
 
 struct PstdArgs {
   const PstdInst *inst;
-  const double2 *tab;  // M values exp(-i pi k / nx)
+  const double2 *tab;  // pass twiddles (pt_size), then per mode pair u < M/2 its
+                       // exp(-2 pi i k / nx), then its exp(-i pi k / nx)
+  int pt_size;
   int64_t nx, mb, me, ld;
   int log2m;           // M = nx / 2 = 2^log2m
   int nsteps;
@@ -74,13 +80,21 @@ __device__ __forceinline__ double2 c_scale(double2 a, double s) { return make_do
 // i * a
 __device__ __forceinline__ double2 c_i(double2 a) { return make_double2(-a.y, a.x); }
 
-// exp(-i pi idx / nx) for 0 <= idx < nx = 2 M from the table of the first M
-// values: exp(-i pi (idx - M) / nx) exp(-i pi / 2) for idx >= M.
-__device__ __forceinline__ double2 pstd_tw(const double2 *tab, int idx, int M) {
-  if (idx < M) return tab[idx];
-  const double2 t = tab[idx - M];
-  return make_double2(t.y, -t.x);
-}
+// Slot of packed element i in LDS: an XOR of bits 0-3 by 5 ((i >> 4) & 3), a
+// bijection inside every block of 16 elements.
+__device__ __forceinline__ int psw(int i) { return i ^ (((i >> 4) & 3) * 5); }
+
+// Slot (in reals) of cell i's value in the packed buffer: element i / 2,
+// real part for even i, imaginary part for odd i.
+__device__ __forceinline__ int pstd_real_slot(int64_t i) { return 2 * psw((int)(i >> 1)) + (int)(i & 1); }
+
+// Twiddles W_4h^j (j < h) of the radix-4 pass of span h start at
+// (h - h0) / 3 in the pass table (h0 = 1 or 2: the smallest span; the spans
+// of the passes grow by factors of 4).
+__device__ __forceinline__ int pstd_pt_off(int h, int lm) { return (h - ((lm & 1) ? 2 : 1)) / 3; }
+
+// Number of pass-table entries for a transform of length 2^lm.
+__host__ __device__ inline int pstd_pt_size(int lm) { return ((1 << lm) - ((lm & 1) ? 2 : 1)) / 3; }
 
 // Position of mode k in the bit-reversed output of the forward transform.
 __device__ __forceinline__ int pstd_pos(int k, int lm) { return (int)(__brev((unsigned)k) >> (32 - lm)); }
@@ -105,33 +119,35 @@ __device__ __forceinline__ double2 c_mi(double2 a) { return make_double2(a.y, -a
 // the stage of span h (twiddle W_2h^j = (W_4h^j)^2), W_L = exp(-2 pi i / L).
 // An odd stage count leaves the span-1 stage (twiddle 1) for last.  Ends
 // with a barrier.
-__device__ __forceinline__ void pstd_fft_dif(double2 *buf, const double2 *tab, int lm) {
+__device__ __forceinline__ void pstd_fft_dif(double2 *buf, const double2 *pt, int lm) {
   const int M = 1 << lm;
   int lh = lm - 1;
   for (; lh >= 1; lh -= 2) {
     const int lq = lh - 1, h = 1 << lq;
+    const double2 *tw = pt + pstd_pt_off(h, lm);
     for (int q = threadIdx.x; q < M / 4; q += blockDim.x) {
       const int j = q & (h - 1);
       const int i0 = ((q >> lq) << (lq + 2)) | j;
-      const double2 a0 = buf[i0], a1 = buf[i0 + h], a2 = buf[i0 + 2 * h], a3 = buf[i0 + 3 * h];
-      // W_4h^j = exp(-i pi (j 2^(lm - lq)) / nx), an index below M
-      const double2 w1 = tab[j << (lm - lq)];
+      const int s0 = psw(i0), s1 = psw(i0 + h), s2 = psw(i0 + 2 * h), s3 = psw(i0 + 3 * h);
+      const double2 a0 = buf[s0], a1 = buf[s1], a2 = buf[s2], a3 = buf[s3];
+      const double2 w1 = tw[j];
       const double2 w2 = c_mul(w1, w1);
       const double2 b0 = c_add(a0, a2), b1 = c_add(a1, a3);
       const double2 b2 = c_mul(c_sub(a0, a2), w1);
       const double2 b3 = c_mi(c_mul(c_sub(a1, a3), w1));
-      buf[i0] = c_add(b0, b1);
-      buf[i0 + h] = c_mul(c_sub(b0, b1), w2);
-      buf[i0 + 2 * h] = c_add(b2, b3);
-      buf[i0 + 3 * h] = c_mul(c_sub(b2, b3), w2);
+      buf[s0] = c_add(b0, b1);
+      buf[s1] = c_mul(c_sub(b0, b1), w2);
+      buf[s2] = c_add(b2, b3);
+      buf[s3] = c_mul(c_sub(b2, b3), w2);
     }
     __syncthreads();
   }
   if (lh == 0) {
     for (int b = threadIdx.x; b < M / 2; b += blockDim.x) {
-      const double2 u = buf[2 * b], v = buf[2 * b + 1];
-      buf[2 * b] = c_add(u, v);
-      buf[2 * b + 1] = c_sub(u, v);
+      const int s0 = psw(2 * b), s1 = psw(2 * b + 1);
+      const double2 u = buf[s0], v = buf[s1];
+      buf[s0] = c_add(u, v);
+      buf[s1] = c_sub(u, v);
     }
     __syncthreads();
   }
@@ -143,35 +159,38 @@ __device__ __forceinline__ void pstd_fft_dif(double2 *buf, const double2 *tab, i
 // then two stages per pass (span h with twiddle conj W_2h^j, then span 2h
 // with conj W_4h^j and conj W_4h^(j+h) = i conj W_4h^j).  Ends with a
 // barrier.
-__device__ __forceinline__ void pstd_fft_dit_inv(double2 *buf, const double2 *tab, int lm) {
+__device__ __forceinline__ void pstd_fft_dit_inv(double2 *buf, const double2 *pt, int lm) {
   const int M = 1 << lm;
   int lh = 0;
   if (lm & 1) {
     for (int b = threadIdx.x; b < M / 2; b += blockDim.x) {
-      const double2 u = buf[2 * b], v = buf[2 * b + 1];
-      buf[2 * b] = c_add(u, v);
-      buf[2 * b + 1] = c_sub(u, v);
+      const int s0 = psw(2 * b), s1 = psw(2 * b + 1);
+      const double2 u = buf[s0], v = buf[s1];
+      buf[s0] = c_add(u, v);
+      buf[s1] = c_sub(u, v);
     }
     __syncthreads();
     lh = 1;
   }
   for (; lh + 1 < lm; lh += 2) {
     const int h = 1 << lh;
+    const double2 *tw = pt + pstd_pt_off(h, lm);
     for (int q = threadIdx.x; q < M / 4; q += blockDim.x) {
       const int j = q & (h - 1);
       const int i0 = ((q >> lh) << (lh + 2)) | j;
-      const double2 a0 = buf[i0], a1 = buf[i0 + h], a2 = buf[i0 + 2 * h], a3 = buf[i0 + 3 * h];
-      const double2 u1 = c_conj(tab[j << (lm - lh)]);
+      const int s0 = psw(i0), s1 = psw(i0 + h), s2 = psw(i0 + 2 * h), s3 = psw(i0 + 3 * h);
+      const double2 a0 = buf[s0], a1 = buf[s1], a2 = buf[s2], a3 = buf[s3];
+      const double2 u1 = c_conj(tw[j]);
       const double2 v = c_mul(u1, u1);
       const double2 t1 = c_mul(a1, v), t3 = c_mul(a3, v);
       const double2 b0 = c_add(a0, t1), b1 = c_sub(a0, t1);
       const double2 b2 = c_add(a2, t3), b3 = c_sub(a2, t3);
-      const double2 s2 = c_mul(b2, u1);
-      const double2 s3 = c_i(c_mul(b3, u1));
-      buf[i0] = c_add(b0, s2);
-      buf[i0 + 2 * h] = c_sub(b0, s2);
-      buf[i0 + h] = c_add(b1, s3);
-      buf[i0 + 3 * h] = c_sub(b1, s3);
+      const double2 q2 = c_mul(b2, u1);
+      const double2 q3 = c_i(c_mul(b3, u1));
+      buf[s0] = c_add(b0, q2);
+      buf[s2] = c_sub(b0, q2);
+      buf[s1] = c_add(b1, q3);
+      buf[s3] = c_sub(b1, q3);
     }
     __syncthreads();
   }
@@ -210,16 +229,18 @@ __global__ void __launch_bounds__(TMAX) fwd_pstd_kernel(PstdArgs a) {
   __shared__ double sF[L::size];
   __shared__ double sP[N * D + N];
   const int lm = a.log2m, M = 1 << lm;
-  double2 *tab = pstd_lds;
-  double2 *buf = pstd_lds + M;
-  double *bufd = reinterpret_cast<double *>(buf);  // the packed buffer as nx reals
+  double2 *buf = pstd_lds;            // M packed elements, swizzled
+  double *bufd = reinterpret_cast<double *>(buf);
+  double2 *pt = pstd_lds + M;         // pass twiddles
+  double2 *mw = pt + a.pt_size;       // per mode pair: exp(-2 pi i k / nx)
+  double2 *me = mw + M / 2;           //                exp(-i pi k / nx)
   const PstdInst in = a.inst[blockIdx.x];
   const int T = blockDim.x, t = threadIdx.x;
   const int64_t nx = a.nx, nmed = a.me - a.mb;
 
   L::stage(in.fac, sF);
   L::stage_pop(in.fac, sP);
-  for (int i = t; i < M; i += T) tab[i] = a.tab[i];
+  for (int i = t; i < a.pt_size + M; i += T) pt[i] = a.tab[i];
 
   double E[C];
   double z[C][D];
@@ -231,14 +252,14 @@ __global__ void __launch_bounds__(TMAX) fwd_pstd_kernel(PstdArgs a) {
     const bool med = i >= a.mb && i < a.me;
 #pragma unroll
     for (int j = 0; j < D; ++j) z[c][j] = med ? in.z[j * a.ld + (i - a.mb)] : 0.0;
-    bufd[i] = in.H[i];
+    bufd[pstd_real_slot(i)] = in.H[i];
   }
   __syncthreads();
 
   // H into Fourier space: modes k and M - k of the pairs this thread owns;
   // the k = 0 slot (DC and Nyquist modes, which no update touches) is kept
   // as packed for the way back.
-  pstd_fft_dif(buf, tab, lm);
+  pstd_fft_dif(buf, pt, lm);
   double2 hk[R], hm[R];
   double2 h0 = make_double2(0.0, 0.0);
 #pragma unroll
@@ -247,7 +268,7 @@ __global__ void __launch_bounds__(TMAX) fwd_pstd_kernel(PstdArgs a) {
     hk[r] = hm[r] = make_double2(0.0, 0.0);
     if (u < M / 2) {
       const int k = pstd_pair_k(u, lm);
-      pstd_unpack(buf[pstd_pair_pos(u)], buf[pstd_pos(M - k, lm)], pstd_tw(tab, 2 * k, M), hk[r], hm[r]);
+      pstd_unpack(buf[psw(pstd_pair_pos(u))], buf[psw(pstd_pos(M - k, lm))], mw[u], hk[r], hm[r]);
     }
   }
   if (t == 0) h0 = buf[0];
@@ -260,21 +281,21 @@ __global__ void __launch_bounds__(TMAX) fwd_pstd_kernel(PstdArgs a) {
     int ts = t;  // per-step copy: addresses are recomputed, not held across steps
     asm volatile("" : "+v"(ts));
 #pragma unroll
-    for (int c = 0; c < C; ++c) bufd[ts + c * T] = E[c];
+    for (int c = 0; c < C; ++c) bufd[pstd_real_slot(ts + c * T)] = E[c];
     __syncthreads();
-    pstd_fft_dif(buf, tab, lm);
+    pstd_fft_dif(buf, pt, lm);
     // Mode-wise: H += (dt / mu) i kappa e^{+i kappa dx / 2} F(E^n); then the
     // packed spectrum of (cb / M) D- H for the inverse transform.  With
-    // e = tab[k] = exp(-i pi k / nx): e^{+i kappa_k dx / 2} = conj e and
+    // e = exp(-i pi k / nx): e^{+i kappa_k dx / 2} = conj e and
     // e^{+i kappa_{M-k} dx / 2} = i e.
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int u = t + r * T;
       if (u < M / 2) {
         const int k = pstd_pair_k(u, lm);
-        const int pk = pstd_pair_pos(u), pm = pstd_pos(M - k, lm);
-        const double2 w = pstd_tw(tab, 2 * k, M);
-        const double2 e = tab[k];
+        const int pk = psw(pstd_pair_pos(u)), pm = psw(pstd_pos(M - k, lm));
+        const double2 w = mw[u];
+        const double2 e = me[u];
         double2 Fk, Fm;
         pstd_unpack(buf[pk], buf[pm], w, Fk, Fm);
         const double kk = (double)k, km = (double)(M - k);
@@ -290,7 +311,7 @@ __global__ void __launch_bounds__(TMAX) fwd_pstd_kernel(PstdArgs a) {
     }
     if (t == 0) buf[0] = make_double2(0.0, 0.0);
     __syncthreads();
-    pstd_fft_dit_inv(buf, tab, lm);
+    pstd_fft_dit_inv(buf, pt, lm);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int64_t i = ts + (int64_t)c * T;
@@ -300,7 +321,7 @@ __global__ void __launch_bounds__(TMAX) fwd_pstd_kernel(PstdArgs a) {
         double *pp = (snap && in.pop_out) ? in.pop_out + si * N * nmed + cm : nullptr;
         P = cell_step<N, double, ROUTE_ROT, false>(in.fac, sF, sP, E[c], z[c], zl, pp, nmed, a.opaque0 * s);
       }
-      E[c] = a.ca * E[c] - a.cb * P + bufd[i];
+      E[c] = a.ca * E[c] - a.cb * P + bufd[pstd_real_slot(i)];
       if (i == nx - 1 && in.probe) in.probe[n + 1] = E[c];
       if (snap && in.e_out) in.e_out[si * nx + i] = E[c];
     }
@@ -318,14 +339,14 @@ __global__ void __launch_bounds__(TMAX) fwd_pstd_kernel(PstdArgs a) {
     if (u < M / 2) {
       const int k = pstd_pair_k(u, lm);
       double2 Zk, Zm;
-      pstd_pack(hk[r], hm[r], pstd_tw(tab, 2 * k, M), Zk, Zm);
-      buf[pstd_pair_pos(u)] = Zk;
-      buf[pstd_pos(M - k, lm)] = Zm;
+      pstd_pack(hk[r], hm[r], mw[u], Zk, Zm);
+      buf[psw(pstd_pair_pos(u))] = Zk;
+      buf[psw(pstd_pos(M - k, lm))] = Zm;
     }
   }
   if (t == 0) buf[0] = h0;
   __syncthreads();
-  pstd_fft_dit_inv(buf, tab, lm);
+  pstd_fft_dit_inv(buf, pt, lm);
   const double inv_m = 1.0 / (double)M;
   // a fresh copy of the thread index, so that the write-back addresses are
   // computed here rather than kept live from the loads at entry
@@ -334,7 +355,7 @@ __global__ void __launch_bounds__(TMAX) fwd_pstd_kernel(PstdArgs a) {
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const int64_t i = tb + (int64_t)c * T;
-    in.H[i] = bufd[i] * inv_m;
+    in.H[i] = bufd[pstd_real_slot(i)] * inv_m;
     in.E[i] = E[c];
     if (i >= a.mb && i < a.me) {
 #pragma unroll

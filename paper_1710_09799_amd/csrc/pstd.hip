@@ -133,6 +133,7 @@ int pstd_steps(mln_pstd *p, int64_t n) {
   a.me = p->grid.med_end;
   a.ld = p->ld;
   a.log2m = p->log2m;
+  a.pt_size = pstd_pt_size(p->log2m);
   a.snap_every = p->snap_every;
   a.ca = p->ca;
   a.cb = p->cb;
@@ -238,7 +239,7 @@ int mln_pstd_init(int32_t n_inst, const mln_medium *media, const mln_grid *grid,
   if (rc0) return rc0;
   p->log2m = 0;
   while ((int64_t(1) << p->log2m) < M) ++p->log2m;
-  p->lds = (size_t)2 * M * sizeof(double2);
+  p->lds = (size_t)(2 * M + pstd_pt_size(p->log2m)) * sizeof(double2);
   p->stream = (hipStream_t)stream;
   p->nmed = g.med_end - g.med_begin;
   p->ld = std::max<int64_t>(1, (p->nmed + 63) / 64 * 64);
@@ -306,11 +307,28 @@ int mln_pstd_init(int32_t n_inst, const mln_medium *media, const mln_grid *grid,
   }
   HIP_TRY(p->dinst.alloc(hi.size() * sizeof(PstdInst)));
   HIP_TRY(hipMemcpy(p->dinst.p, hi.data(), hi.size() * sizeof(PstdInst), hipMemcpyHostToDevice));
-  // exp(-i pi k / nx), k < M
-  std::vector<double2> tab(M);
-  for (int64_t k = 0; k < M; ++k) {
-    const double ph = kPi * (double)k / (double)nx;
-    tab[k] = make_double2(std::cos(ph), -std::sin(ph));
+  // pass twiddles W_4h^j = exp(-2 pi i j / (4h)), j < h, for every radix-4
+  // span h (at (h - h0) / 3); then per mode pair u (k = M/2 for u = 0, else
+  // the bit reversal of 2u) exp(-2 pi i k / nx) and exp(-i pi k / nx)
+  const int lm = p->log2m;
+  const int pts = pstd_pt_size(lm);
+  std::vector<double2> tab((size_t)pts + M);
+  const int h0 = (lm & 1) ? 2 : 1;
+  for (int h = h0; 4 * h <= M; h *= 4)
+    for (int j = 0; j < h; ++j) {
+      const double ph = 2.0 * kPi * (double)j / (4.0 * h);
+      tab[(h - h0) / 3 + j] = make_double2(std::cos(ph), -std::sin(ph));
+    }
+  auto rev = [lm](int64_t v) {
+    int64_t r = 0;
+    for (int b = 0; b < lm; ++b) r |= ((v >> b) & 1) << (lm - 1 - b);
+    return r;
+  };
+  for (int64_t u = 0; u < M / 2; ++u) {
+    const int64_t k = u ? rev(2 * u) : M / 2;
+    const double pw = 2.0 * kPi * (double)k / (double)nx, pe = kPi * (double)k / (double)nx;
+    tab[pts + u] = make_double2(std::cos(pw), -std::sin(pw));
+    tab[pts + M / 2 + u] = make_double2(std::cos(pe), -std::sin(pe));
   }
   HIP_TRY(p->tab.alloc(tab.size() * sizeof(double2)));
   HIP_TRY(hipMemcpy(p->tab.p, tab.data(), tab.size() * sizeof(double2), hipMemcpyHostToDevice));
