@@ -329,10 +329,13 @@ __global__ void __launch_bounds__(TMAX) fwd_pstd_kernel(PstdArgs a) {
       snap_next += a.snap_every;
       ++si;
     }
-    __syncthreads();  // the packed buffer is read before the next step writes it
+    // No barrier here: the next step writes E^{n+1} into exactly the slots
+    // of the buffer this thread has just read, which no other thread touches
+    // before the barrier that follows those writes.
   }
 
-  // H back to real space
+  // H back to real space (after every thread has read its last D- H)
+  __syncthreads();
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int u = t + r * T;
