@@ -168,16 +168,20 @@ def variants(p3, ref64, pop64, headline):
     # the paper's comparison of the exponential routes (Sec. 5.3): the per-step
     # Pade route against diagonalisation and Rodrigues, and the rotation form,
     # all FP64 on the one-cell-per-thread kernel (tile 256, 32 steps per launch)
+    # The paper's own two-level case on its printed grid (Sec. 5.1: 32768
+    # cells, 24559 steps to 187.5 fs; stand-in density, medium and pulse) is
+    # timed too, with the paper's metric P = Nx Nt / t beside the Liouville rate.
     p2 = W.two_level()
     comp = {}
-    for lbl, prob in (("n2_two_level", p2), ("n3_three_level", p3)):
+    for lbl, prob in (("n2_two_level", p2), ("n2_sit_paper_grid", W.sit_paper()), ("n3_three_level", p3)):
         nu = prob.grid.n_med * prob.grid.nt
-        rates = {}
+        rates, paper_p = {}, {}
         for route in ("pade", "diag", "rodrigues", "rotation"):
             t, _, _, _ = time_solver(prob, 1, 1, 0, precision="fp64", variant="block", route=route, tile=256,
                                      steps_per_launch=32, record_pop=False, record_e=False)
             rates[route] = nu / t
-        comp[lbl] = {"cell_updates_per_s": rates,
+            paper_p[route] = prob.grid.nx * prob.grid.nt / t
+        comp[lbl] = {"cell_updates_per_s": rates, "paper_P": paper_p,
                      "speedup_vs_pade": {r: rates[r] / rates["pade"] for r in ("diag", "rodrigues", "rotation")}}
     # N = 6 (the paper leaves many-level behaviour open): the six-level grid,
     # a 512-step sample of its run; the Pade route on its one-wavefront-per-

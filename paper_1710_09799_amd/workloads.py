@@ -190,6 +190,39 @@ def two_level(nx=2000, nt=10000, name="two_level_2pi_sech"):
     return Problem(name, med, grid, src)
 
 
+def sit_paper(nt=None, nx=32768, medium_from=1024, tau=10e-15, name="sit_paper_grid"):
+    """The paper's two-level self-induced-transparency test case (Sec. 5.1)
+    on the grid it prints: 32768 cells over 150 um (4.578 nm), Courant 0.5
+    (7.635e-18 s), run to 187.5 fs (24559 steps; nt overrides);
+    H0 = hbar w12 diag(-1/2, 1/2) with w12 = 4 pi 1e14 /s, mu12 = 1e-29 C m,
+    the printed relaxation superoperator with T1 = T2 = 1e-10 s (the garbled
+    unit read as seconds), ground-state start.  The paper leaves the density,
+    the medium's extent and the pulse to its reference; stand-ins: N_a = 1e24
+    /m^3, the medium from cell medium_from to the last cell, a 2-pi sech pulse
+    of tau = 10 fs (area (mu/hbar) E0 pi tau = 2 pi) at w12, centred at 6 tau,
+    injected at cell 0."""
+    w12 = 4.0 * math.pi * 1e14
+    mu12 = 1e-29
+    t1 = t2 = 1e-10
+    med = ladder_medium([-0.5 * HBAR * w12, 0.5 * HBAR * w12], [mu12], density=1e24)
+    # printed superoperator on row-major vec(rho), index 2a + b:
+    # G11 = rho22/T1, G12 = -rho12/T2, G21 = -rho21/T2, G22 = -rho22/T1
+    g = np.zeros((4, 4), dtype=np.complex128)
+    g[0, 3] = 1.0 / t1
+    g[1, 1] = -1.0 / t2
+    g[2, 2] = -1.0 / t2
+    g[3, 3] = -1.0 / t1
+    med.relax_superop = g
+    dx = 150e-6 / 32768
+    dt = 0.5 * dx / C0
+    if nt is None:
+        nt = int(round(187.5e-15 / dt))
+    grid = Grid(nx=nx, nt=nt, dx=dx, dt=dt, med_begin=medium_from, med_end=nx - 1)
+    e0 = 2.0 * HBAR / (mu12 * tau)
+    src = Source(samples=sech_pulse(nt, dt, w12, tau, 6.0 * tau), amplitude=e0)
+    return Problem(name, med, grid, src)
+
+
 def three_level(nx=20000, nt=100000, name="three_level_ladder_pi_gauss"):
     """N=3 ladder: energies hbar*omega0*{0, 1.0, 2.1}, mu01=1e-29,
     mu12=0.8e-29, Lindblad decay 1e12/s, pure dephasing 5e12/s, medium fills
