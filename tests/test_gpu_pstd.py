@@ -165,3 +165,31 @@ def test_pstd_single_mode_exact_at_the_largest_grid(orc, m):
     assert err_e < 1e-9 and err_h < 1e-9
     n = np.arange(nt + 1)
     assert np.max(np.abs(out["probe"] - A * np.cos(kap * x[-1] - w * n * dt))) < 1e-9 * A
+
+
+def test_pstd_bench_workload_full_size(orc):
+    """The bench's ring (three-level ladder, 2048 cells, 8192 steps, default
+    launch shape): its first 40 steps element by element against the oracle
+    on the full ring, and over the whole run the properties that hold at any
+    size (populations in [0, 1] summing to 1, finite fields and probe)."""
+    p, e0, h0 = W.pstd_three_level()
+    g = p.grid
+    short = W.Problem(p.name, p.medium, W.Grid(nx=g.nx, nt=40, dx=g.dx, dt=g.dt, med_begin=g.med_begin,
+                                              med_end=g.med_end), p.source)
+    ref = orc.pstd_run(short, snap_every=10, e_init=e0, h_init=h0)
+    s = mln.Pstd([short], e_init=e0, h_init=h0, snap_every=10)
+    out = {k: (v.cpu().numpy() if v is not None else None) for k, v in s.run()[0].items()}
+    s.close()
+    print("[case] bench ring, first 40 steps", flush=True)
+    _check(out, ref)
+    print("[case] bench ring, full run", flush=True)
+    full = mln.pstd_run(p, e_init=e0, h_init=h0, snap_every=g.nt // 4)
+    pop = full["pop"]
+    assert np.all(np.isfinite(full["probe"])) and np.all(np.isfinite(full["e"])) and np.all(np.isfinite(full["h"]))
+    assert pop.min() > -1e-12 and pop.max() < 1 + 1e-12
+    assert np.max(np.abs(pop.sum(axis=1) - 1.0)) < 1e-12
+    # the pi pulse inverts the medium where it passes; the upper levels decay
+    # (1 ps) over the 2.6 ps run, so the inversion shows in the early snapshots
+    mins = pop[:, 0].min(axis=1)
+    print("  lowest ground-state population per snapshot:", np.round(mins, 3), flush=True)
+    assert mins.min() < 0.5
