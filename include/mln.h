@@ -389,8 +389,9 @@ int mln_pstd_init(int32_t n_inst, const mln_medium *media, const mln_grid *grid,
  * cells then runs min(nx, max_threads) threads of nx / threads cells each).
  * 256 threads hold every built grid size in registers; 512 build up to half
  * as many cells per thread (MLN_ENOTSUPPORTED beyond).  Automatic: 512
- * where built, which steps one problem fastest; 256 lets two workgroups
- * share a compute unit, which can serve batches of small grids better. */
+ * where built for N <= 4 (it steps one problem fastest), else 256; and 256
+ * for batches of more problems than the device has compute units on grids
+ * of at most 1024 cells, where two workgroups then share a compute unit. */
 int mln_pstd_configure(mln_pstd *p, int32_t steps_per_launch, int32_t max_threads);
 
 /* Launch shape: threads per workgroup (nx / cells_per_thread), cells per

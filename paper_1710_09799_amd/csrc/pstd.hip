@@ -94,6 +94,7 @@ struct mln_pstd {
   int N = 0, n_inst = 0;
   mln_grid grid{};
   int C = 1, threads = 0, tmax = 256, log2m = 0;
+  int n_cu = 256;  // compute units of the device the handle was created on
   size_t lds = 0;
   hipStream_t stream = nullptr;
   int64_t nmed = 0, ld = 0, step = 0;
@@ -160,13 +161,17 @@ int pstd_steps(mln_pstd *p, int64_t n) {
 }
 
 // Threads per workgroup: at most tmax (256 or 512), fewer on grids below
-// that; C = nx / threads cells per thread.  Automatic (0): 512 where that
-// shape is built (one problem steps fastest with the medium spread over more
-// threads), except N = 6, whose 35-component state fits one thread's
-// registers only at 256.  For batches of small grids 256 can be faster: two
-// workgroups then share a compute unit.
+// that; C = nx / threads cells per thread.  Automatic (0), from measured
+// step times: 512 where that shape is built (one problem steps fastest with
+// the medium spread over more threads), except N = 6, whose 35-component
+// state fits one thread's registers only at 256, and except batches of more
+// problems than compute units on grids of at most 1024 cells, where two
+// 256-thread workgroups share a compute unit (about 1.3x the throughput).
 int set_shape(mln_pstd *p, int tmax) {
-  if (tmax == 0) tmax = (p->N < 6 && p->grid.nx <= 512 * pstd_max_cells(p->N, 512)) ? 512 : 256;
+  if (tmax == 0) {
+    const bool shared_cu = p->grid.nx <= 1024 && p->n_inst > p->n_cu;
+    tmax = (p->N < 6 && !shared_cu && p->grid.nx <= 512 * pstd_max_cells(p->N, 512)) ? 512 : 256;
+  }
   if (tmax != 256 && tmax != 512) return set_err(MLN_EINVAL, "PSTD threads per workgroup: 0, 256 or 512");
   const int64_t nx = p->grid.nx;
   const int threads = (int)std::min<int64_t>(nx, tmax);
@@ -235,6 +240,12 @@ int mln_pstd_init(int32_t n_inst, const mln_medium *media, const mln_grid *grid,
   p->N = N;
   p->n_inst = n_inst;
   p->grid = g;
+  {
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (cus > 0) p->n_cu = cus;
+  }
   rc0 = set_shape(p.get(), 0);
   if (rc0) return rc0;
   p->log2m = 0;

@@ -193,3 +193,19 @@ def test_pstd_bench_workload_full_size(orc):
     mins = pop[:, 0].min(axis=1)
     print("  lowest ground-state population per snapshot:", np.round(mins, 3), flush=True)
     assert mins.min() < 0.5
+
+
+def test_pstd_automatic_launch_shape():
+    """One problem runs 512-thread workgroups where built (N <= 4); N = 6 runs
+    256; a batch of more problems than compute units on a grid of at most
+    1024 cells runs 256 (two workgroups share a compute unit)."""
+    import torch
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    for n, nx, ninst, want in ((3, 1024, 1, 512), (2, 4096, 1, 512), (6, 512, 1, 256),
+                               (3, 1024, n_cu + 1, 256), (3, 2048, n_cu + 1, 512)):
+        items = [W.pstd_random(n, 1, nx=nx, nt=4) for _ in range(1)]
+        p, e0, h0 = items[0]
+        s = mln.Pstd([p] * ninst, e_init=e0, h_init=h0, record_pop=False, record_e=False, record_probe=False)
+        got = s.config()["threads"]
+        s.close()
+        assert got == min(nx, want), (n, nx, ninst, got)
