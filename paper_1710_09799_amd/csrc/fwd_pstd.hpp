@@ -119,9 +119,9 @@ __device__ __forceinline__ double2 c_mi(double2 a) { return make_double2(a.y, -a
 // the stage of span h (twiddle W_2h^j = (W_4h^j)^2), W_L = exp(-2 pi i / L).
 // An odd stage count leaves the span-1 stage (twiddle 1) for last.  Ends
 // with a barrier.
-__device__ __forceinline__ void pstd_fft_dif(double2 *buf, const double2 *pt, int lm) {
+__device__ __forceinline__ void pstd_fft_dif(double2 *buf, const double2 *pt, int lm, int lh_first = -1) {
   const int M = 1 << lm;
-  int lh = lm - 1;
+  int lh = lh_first < 0 ? lm - 1 : lh_first;
   for (; lh >= 1; lh -= 2) {
     const int lq = lh - 1, h = 1 << lq;
     const double2 *tw = pt + pstd_pt_off(h, lm);
@@ -159,8 +159,9 @@ __device__ __forceinline__ void pstd_fft_dif(double2 *buf, const double2 *pt, in
 // then two stages per pass (span h with twiddle conj W_2h^j, then span 2h
 // with conj W_4h^j and conj W_4h^(j+h) = i conj W_4h^j).  Ends with a
 // barrier.
-__device__ __forceinline__ void pstd_fft_dit_inv(double2 *buf, const double2 *pt, int lm) {
+__device__ __forceinline__ void pstd_fft_dit_inv(double2 *buf, const double2 *pt, int lm, bool skip_last = false) {
   const int M = 1 << lm;
+  const int lh_end = skip_last ? lm - 2 : lm;  // passes with lh + 1 < lh_end
   int lh = 0;
   if (lm & 1) {
     for (int b = threadIdx.x; b < M / 2; b += blockDim.x) {
@@ -172,7 +173,7 @@ __device__ __forceinline__ void pstd_fft_dit_inv(double2 *buf, const double2 *pt
     __syncthreads();
     lh = 1;
   }
-  for (; lh + 1 < lm; lh += 2) {
+  for (; lh + 1 < lh_end; lh += 2) {
     const int h = 1 << lh;
     const double2 *tw = pt + pstd_pt_off(h, lm);
     for (int q = threadIdx.x; q < M / 4; q += blockDim.x) {
@@ -193,6 +194,82 @@ __device__ __forceinline__ void pstd_fft_dit_inv(double2 *buf, const double2 *pt
       buf[s3] = c_sub(b1, q3);
     }
     __syncthreads();
+  }
+}
+
+// Exchange a double with the other lane of the pair (2e, 2e + 1) (DPP
+// quad_perm [1, 0, 3, 2] on both halves).
+__device__ __forceinline__ double pstd_pair_swap(double x) {
+  constexpr int ctrl = 1 | (0 << 2) | (3 << 4) | (2 << 6);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), ctrl, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), ctrl, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// With C >= 4 cells per thread (thread t owns cells t + c T, M = C T / 2),
+// the lanes 2e and 2e + 1 hold the real and the imaginary parts of the
+// packed elements e + c T / 2, which are C / 4 whole groups of the first
+// forward pass and of the last inverse pass (span-M/4 radix 4: elements
+// q + r M / 4, q = e + g T / 2, r < 4, from cells c = g + r C / 4).  Those
+// passes then run on the cells' own values: a complex product needs the
+// other lane's component, one pair exchange, and with sg = -1 on the real
+// and +1 on the imaginary lane it reads own * w.x + sg * other * w.y.
+
+// First forward pass from the values x of the thread's cells; writes the
+// pass's outputs (this lane's components).  No barrier.
+template <int C>
+__device__ __forceinline__ void pstd_dif_first_regs(double *bufd, const double2 *pt, int lm, int T, int t,
+                                                    const double (&x)[C]) {
+  static_assert(C % 4 == 0, "whole groups per thread");
+  const int h = 1 << (lm - 2);
+  const double2 *tw = pt + pstd_pt_off(h, lm);
+  const int p = t & 1, e0 = t >> 1;
+  const double sg = p ? 1.0 : -1.0;
+#pragma unroll
+  for (int g = 0; g < C / 4; ++g) {
+    const int q = e0 + g * (T / 2);
+    const double a0 = x[g], a1 = x[g + C / 4], a2 = x[g + C / 2], a3 = x[g + 3 * C / 4];
+    const double2 w1 = tw[q];
+    const double2 w2 = c_mul(w1, w1);
+    const double b0 = a0 + a2, b1 = a1 + a3;
+    const double d02 = a0 - a2, d13 = a1 - a3;
+    const double o02 = pstd_pair_swap(d02), o13 = pstd_pair_swap(d13);
+    const double b2 = d02 * w1.x + sg * o02 * w1.y;         // (a0 - a2) w1
+    const double b3 = d13 * w1.y - sg * o13 * w1.x;         // (a1 - a3) (-i w1)
+    const double d01 = b0 - b1, d23 = b2 - b3;
+    const double o01 = pstd_pair_swap(d01), o23 = pstd_pair_swap(d23);
+    bufd[2 * psw(q) + p] = b0 + b1;
+    bufd[2 * psw(q + h) + p] = d01 * w2.x + sg * o01 * w2.y;
+    bufd[2 * psw(q + 2 * h) + p] = b2 + b3;
+    bufd[2 * psw(q + 3 * h) + p] = d23 * w2.x + sg * o23 * w2.y;
+  }
+}
+
+// Last inverse pass: reads the pass's inputs and returns this lane's
+// component of the outputs for the thread's cells in y.
+template <int C>
+__device__ __forceinline__ void pstd_dit_last_regs(const double2 *buf, const double2 *pt, int lm, int T, int t,
+                                                   double (&y)[C]) {
+  static_assert(C % 4 == 0, "whole groups per thread");
+  const int h = 1 << (lm - 2);
+  const double2 *tw = pt + pstd_pt_off(h, lm);
+  const int p = t & 1, e0 = t >> 1;
+#pragma unroll
+  for (int g = 0; g < C / 4; ++g) {
+    const int q = e0 + g * (T / 2);
+    const double2 a0 = buf[psw(q)], a1 = buf[psw(q + h)], a2 = buf[psw(q + 2 * h)], a3 = buf[psw(q + 3 * h)];
+    const double2 u1 = c_conj(tw[q]);
+    const double2 v = c_mul(u1, u1);
+    const double2 t1 = c_mul(a1, v), t3 = c_mul(a3, v);
+    const double2 b0 = c_add(a0, t1), b1 = c_sub(a0, t1);
+    const double2 b2 = c_add(a2, t3), b3 = c_sub(a2, t3);
+    const double2 q2 = c_mul(b2, u1);
+    const double2 q3 = c_i(c_mul(b3, u1));
+    const double2 c0 = c_add(b0, q2), c1 = c_add(b1, q3), c2 = c_sub(b0, q2), c3 = c_sub(b1, q3);
+    y[g] = p ? c0.y : c0.x;
+    y[g + C / 4] = p ? c1.y : c1.x;
+    y[g + C / 2] = p ? c2.y : c2.x;
+    y[g + 3 * C / 4] = p ? c3.y : c3.x;
   }
 }
 
@@ -245,6 +322,12 @@ __global__ void __launch_bounds__(TMAX) fwd_pstd_kernel(PstdArgs a) {
   double E[C];
   double z[C][D];
   double zl[1] = {0.0};
+  // first and last passes on the cells' own values, where the registers
+  // leave room for them (whole groups per thread, at most 32 state
+  // components per thread: N = 2 with 4 or 8 cells, N = 3 with 4)
+  constexpr bool REG = C % 4 == 0 && D * C <= 32;
+  constexpr int CR = REG ? C : 1;
+  double Hc[CR];  // with REG: H of the thread's cells (at entry and at exit)
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const int64_t i = t + (int64_t)c * T;
@@ -252,14 +335,21 @@ __global__ void __launch_bounds__(TMAX) fwd_pstd_kernel(PstdArgs a) {
     const bool med = i >= a.mb && i < a.me;
 #pragma unroll
     for (int j = 0; j < D; ++j) z[c][j] = med ? in.z[j * a.ld + (i - a.mb)] : 0.0;
-    bufd[pstd_real_slot(i)] = in.H[i];
+    if constexpr (REG)
+      Hc[c] = in.H[i];
+    else
+      bufd[pstd_real_slot(i)] = in.H[i];
   }
-  __syncthreads();
+  __syncthreads();  // also orders the tables
+  if constexpr (REG) {
+    pstd_dif_first_regs<C>(bufd, pt, lm, T, t, Hc);
+    __syncthreads();
+  }
 
   // H into Fourier space: modes k and M - k of the pairs this thread owns;
   // the k = 0 slot (DC and Nyquist modes, which no update touches) is kept
   // as packed for the way back.
-  pstd_fft_dif(buf, pt, lm);
+  pstd_fft_dif(buf, pt, lm, REG ? lm - 3 : -1);
   double2 hk[R], hm[R];
   double2 h0 = make_double2(0.0, 0.0);
 #pragma unroll
@@ -280,10 +370,14 @@ __global__ void __launch_bounds__(TMAX) fwd_pstd_kernel(PstdArgs a) {
     const bool snap = n == snap_next;
     int ts = t;  // per-step copy: addresses are recomputed, not held across steps
     asm volatile("" : "+v"(ts));
+    if constexpr (REG) {
+      pstd_dif_first_regs<C>(bufd, pt, lm, T, ts, E);
+    } else {
 #pragma unroll
-    for (int c = 0; c < C; ++c) bufd[pstd_real_slot(ts + c * T)] = E[c];
+      for (int c = 0; c < C; ++c) bufd[pstd_real_slot(ts + c * T)] = E[c];
+    }
     __syncthreads();
-    pstd_fft_dif(buf, pt, lm);
+    pstd_fft_dif(buf, pt, lm, REG ? lm - 3 : -1);
     // Mode-wise: H += (dt / mu) i kappa e^{+i kappa dx / 2} F(E^n); then the
     // packed spectrum of (cb / M) D- H for the inverse transform.  With
     // e = exp(-i pi k / nx): e^{+i kappa_k dx / 2} = conj e and
@@ -311,7 +405,9 @@ __global__ void __launch_bounds__(TMAX) fwd_pstd_kernel(PstdArgs a) {
     }
     if (t == 0) buf[0] = make_double2(0.0, 0.0);
     __syncthreads();
-    pstd_fft_dit_inv(buf, pt, lm);
+    pstd_fft_dit_inv(buf, pt, lm, REG);
+    double Dh[CR];  // with REG: (cb / M) D- H of the thread's cells
+    if constexpr (REG) pstd_dit_last_regs<C>(buf, pt, lm, T, ts, Dh);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const int64_t i = ts + (int64_t)c * T;
@@ -321,7 +417,12 @@ __global__ void __launch_bounds__(TMAX) fwd_pstd_kernel(PstdArgs a) {
         double *pp = (snap && in.pop_out) ? in.pop_out + si * N * nmed + cm : nullptr;
         P = cell_step<N, double, ROUTE_ROT, false>(in.fac, sF, sP, E[c], z[c], zl, pp, nmed, a.opaque0 * s);
       }
-      E[c] = a.ca * E[c] - a.cb * P + bufd[pstd_real_slot(i)];
+      double dh;
+      if constexpr (REG)
+        dh = Dh[c];
+      else
+        dh = bufd[pstd_real_slot(i)];
+      E[c] = a.ca * E[c] - a.cb * P + dh;
       if (i == nx - 1 && in.probe) in.probe[n + 1] = E[c];
       if (snap && in.e_out) in.e_out[si * nx + i] = E[c];
     }
@@ -330,8 +431,9 @@ __global__ void __launch_bounds__(TMAX) fwd_pstd_kernel(PstdArgs a) {
       ++si;
     }
     // No barrier here: the next step writes E^{n+1} into exactly the slots
-    // of the buffer this thread has just read, which no other thread touches
-    // before the barrier that follows those writes.
+    // of the buffer that this thread (or, with REG, the other lane of its
+    // pair, in the same wavefront and so in order) has just read, which no
+    // other thread touches before the barrier that follows those writes.
   }
 
   // H back to real space (after every thread has read its last D- H)
@@ -349,7 +451,8 @@ __global__ void __launch_bounds__(TMAX) fwd_pstd_kernel(PstdArgs a) {
   }
   if (t == 0) buf[0] = h0;
   __syncthreads();
-  pstd_fft_dit_inv(buf, pt, lm);
+  pstd_fft_dit_inv(buf, pt, lm, REG);
+  if constexpr (REG) pstd_dit_last_regs<C>(buf, pt, lm, T, t, Hc);
   const double inv_m = 1.0 / (double)M;
   // a fresh copy of the thread index, so that the write-back addresses are
   // computed here rather than kept live from the loads at entry
@@ -358,7 +461,10 @@ __global__ void __launch_bounds__(TMAX) fwd_pstd_kernel(PstdArgs a) {
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const int64_t i = tb + (int64_t)c * T;
-    in.H[i] = bufd[pstd_real_slot(i)] * inv_m;
+    if constexpr (REG)
+      in.H[i] = Hc[c] * inv_m;
+    else
+      in.H[i] = bufd[pstd_real_slot(i)] * inv_m;
     in.E[i] = E[c];
     if (i >= a.mb && i < a.me) {
 #pragma unroll
