@@ -387,10 +387,37 @@ PROFILE_CASES = {
     "n2_large_fp32_k16": ("n2_large", {}, dict(precision="fp32", variant="block", tile=256, steps_per_launch=16)),
     # pseudo-spectral ring (2048 cells, 2048 of its 8192 steps): the problem
     # alone, its field part alone (one medium cell), and 256 problems at once
+    # the 64-problem sweep at the shape the autotuner picks (one cell per
+    # thread, tile 256, 16 steps per launch), 2048 of its 20000 steps
+    "batch64_fp64": ("batch", dict(nt=2048), dict(precision="fp64", variant="block", tile=256, steps_per_launch=16)),
+    "batch64_fp32c": ("batch", dict(nt=2048), dict(precision="fp32c", variant="block", tile=256, steps_per_launch=16)),
     "pstd_n3_ring": ("pstd", dict(batch=1, med=True), dict(steps_per_launch=256)),
     "pstd_n3_ring_fields": ("pstd", dict(batch=1, med=False), dict(steps_per_launch=256)),
     "pstd_n3_ring_batch256": ("pstd", dict(batch=256, med=True), dict(steps_per_launch=256)),
 }
+
+
+def profile_batch(name, nt, kw, steps, warmup):
+    import torch
+    from paper_1710_09799_amd import mln
+    from paper_1710_09799_amd import workloads as W
+    probs = W.batched_sweep(nt=nt)
+    b = mln.Batch(probs, snap_every=0, record_pop=False, record_e=False, graph=False, **kw)
+    ts = []
+    for r in range(warmup + steps):
+        b.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run()
+        torch.cuda.synchronize()
+        if r >= warmup:
+            ts.append(time.perf_counter() - t0)
+    cfg = b.config()
+    b.close()
+    t = min(ts)
+    nu = sum(p.grid.n_med for p in probs) * nt
+    print(json.dumps({"profile_case": name, "problems": len(probs), "nt": nt, "cell_updates": nu,
+                      "ms_per_run": t * 1e3, "cell_updates_per_s": nu / t, **cfg}))
 
 
 def profile_pstd(name, batch, med, steps_per_launch, steps, warmup):
@@ -427,6 +454,9 @@ def profile_case(name, steps, warmup, calib):
     wl, pkw, kw = PROFILE_CASES[name]
     if wl == "pstd":
         profile_pstd(name, pkw["batch"], pkw["med"], kw["steps_per_launch"], steps, warmup)
+        return
+    if wl == "batch":
+        profile_batch(name, pkw["nt"], kw, steps, warmup)
         return
     p = n2_large_problem() if wl == "n2_large" else getattr(W, wl)(**pkw)
     t, g, nl, _ = time_solver(p, steps, warmup, 0, record_pop=False, record_e=False, **kw)
