@@ -209,3 +209,14 @@ def test_pstd_automatic_launch_shape():
         got = s.config()["threads"]
         s.close()
         assert got == min(nx, want), (n, nx, ninst, got)
+
+
+def test_pstd_empty_medium_matches_oracle(orc):
+    """A ring with an empty medium range (med_begin == med_end) propagates the
+    initial pulse as the oracle does."""
+    p, e0, h0 = W.pstd_random(3, 4, nx=256, nt=120, med=(100, 100))
+    ref = orc.pstd_run(p, snap_every=40, e_init=e0, h_init=h0)
+    out = mln.pstd_run(p, e_init=e0, h_init=h0, snap_every=40)
+    assert out["pop"] is None or out["pop"].size == 0
+    ref["pop"] = None
+    _check(out, ref, h_final=out["h"])

@@ -85,3 +85,27 @@ def test_set_state_rejects_non_finite():
     with pytest.raises(mln.MLNError):
         s.set_state(E=E)
     s.close()
+
+
+def test_state_of_a_batch_instance(orc):
+    """mln_get_state on the handle of one problem of a batch (mln_batch_instance)
+    after the batch has stepped: populations and E against the oracle."""
+    import ctypes
+    probs = [W.random_problem(2, 5, nx=150, nt=200), W.random_problem(3, 6, nx=230, nt=200)]
+    k = 120
+    b = mln.Batch(probs, precision="fp64", variant="block", tile=128, steps_per_launch=8, graph=False)
+    b.step(k)
+    L = mln.load()
+    for i, p in enumerate(probs):
+        h = ctypes.c_void_p()
+        assert L.mln_batch_instance(b._h, i, ctypes.byref(h)) == 0
+        g, n = p.grid, p.medium.n_levels
+        E, H = np.zeros(g.nx), np.zeros(g.nx - 1)
+        pop = np.zeros((n, g.n_med))
+        assert L.mln_get_state(h, mln._ptr(E), mln._ptr(H), mln._ptr(pop)) == 0
+        ref = orc.run(p, snap_every=k)
+        err_e = np.max(np.abs(E - ref["e_snap"][0])) / np.max(np.abs(ref["e_snap"]))
+        err_p = np.max(np.abs(pop - ref["pop"][0]))
+        print(f"[case] batch instance {i}: err_E={err_e:.2e} err_pop={err_p:.2e}", flush=True)
+        assert err_e < 1e-10 and err_p < 1e-10
+    b.close()
