@@ -106,20 +106,29 @@ def test_three_level_reduced_fp64(orc):
     assert np.max(ref["pop"][:, 1]) > 1e-2  # the pulse moved population
 
 
+_FULL_REF = {}
+
+
 @pytest.mark.slow
-def test_three_level_full_grid_through_pulse(orc):
-    """Full 20000-cell grid in the benchmark's launch configuration, followed
-    by the oracle for 12000 steps: the pi pulse (peak at step 9600) has
-    entered the medium, so the comparison is not dominated by the ~1e-9 V/m
-    fields ahead of it, where both solvers sit at their round-off floor."""
+@pytest.mark.parametrize("precision,kw,tol", [("fp64", {}, TOL64),
+                                              ("fp32c", dict(variant="quad", tile=128, steps_per_launch=20), 1e-5)])
+def test_three_level_full_grid_through_pulse(orc, precision, kw, tol):
+    """Full 20000-cell grid (FP64 in the automatic configuration, compensated
+    FP32 in the benchmark's: four lanes per cell, 128 cells, 20 steps per
+    launch), followed by the oracle for 12000 steps: the pi pulse (peak at
+    step 9600) has entered the medium, so the comparison is not dominated by
+    the ~1e-9 V/m fields ahead of it, where both solvers sit at their
+    round-off floor."""
     p = W.three_level()
     p.grid.nt = 12000
-    _print_case("three_level_full_grid")
-    ref = orc.run(p, snap_every=3000)
-    got = mln.run(p, precision="fp64", snap_every=3000)
+    _print_case("three_level_full_grid", precision=precision)
+    if "ref" not in _FULL_REF:
+        _FULL_REF["ref"] = orc.run(p, snap_every=3000)
+    ref = _FULL_REF["ref"]
+    got = mln.run(p, precision=precision, snap_every=3000, **kw)
     ee, ep = _errs(got, ref)
     print("three_level_full_grid err_E", ee, "err_pop", ep)
-    assert ee < TOL64 and ep < TOL64
+    assert ee < tol and ep < tol
     assert np.max(np.abs(ref["e_snap"])) > 1e-2 * p.source.amplitude
 
 
