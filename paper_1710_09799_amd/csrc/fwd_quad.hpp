@@ -149,10 +149,17 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
     if constexpr (CF) sEl[b][i] = Real(0);
   }
   __syncthreads();
-  int64_t snap_next = a.snap_next, si = a.snap_i0;
+  // the step loop keeps its bookkeeping in 32-bit scalars and its field
+  // updates free of divergent branches (the step's time is the length of
+  // one wavefront's instruction stream): the next snapshot as a step index
+  // within this launch (-1: none), the cell's role as loop-invariant masks
+  int s_snap = (a.snap_next >= a.step0 && a.snap_next < a.step0 + a.nsteps) ? (int)(a.snap_next - a.step0) : -1;
+  const int snap_gap = (int)(a.snap_every < kMaxStepsPerLaunch ? a.snap_every : kMaxStepsPerLaunch);
+  const bool interior = g >= 1 && g <= a.nx - 2;
+  const bool is_src = g == 0;
+  int64_t si = a.snap_i0;
   for (int s = 0; s < a.nsteps; ++s) {
-    const int64_t n = a.step0 + s;
-    const bool snap = n == snap_next;
+    const bool snap = s == s_snap;
     const int b = s & 1;
     if (r == 0) {
       sE[b][cl + 1] = E;
@@ -160,29 +167,35 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
     }
     lds_barrier();
     const Real El = sE[b][cl], Er = sE[b][cl + 2];
-    Real Ell = 0, Erl = 0;
+    const Real src = sSrc[s];
+    Real Ell = 0, Erl = 0, srcl = 0;
     if constexpr (CF) {
       Ell = sEl[b][cl];
       Erl = sEl[b][cl + 2];
+      srcl = sSrcl[s];
     }
-    if (in_dom) {
-      // the private copy is updated with the operands and operations the
-      // left neighbour uses for its own face, so the two stay bitwise equal
-      if constexpr (CF) {
-        if (g >= 1) add_comp(Hl, Hll, a.ch * ((E - El) + (Elo - Ell)));
-        if (g <= a.nx - 2) add_comp(H, Hlo, a.ch * ((Er - E) + (Erl - Elo)));
-      } else {
-        if (g >= 1) Hl += a.ch * (E - El);
-        if (g <= a.nx - 2) H += a.ch * (Er - E);
-      }
+    // H at both faces of the cell; the private copy Hl is updated with the
+    // operands and operations the left neighbour uses for its own face, so
+    // the two stay bitwise equal.  Faces outside the grid (left of cell 0,
+    // right of cell nx-1, and those of cells beyond the grid in edge tiles)
+    // are updated too, without a branch: nothing reads them.
+    if constexpr (CF) {
+      add_comp(Hl, Hll, a.ch * ((E - El) + (Elo - Ell)));
+      add_comp(H, Hlo, a.ch * ((Er - E) + (Erl - Elo)));
+    } else {
+      Hl += a.ch * (E - El);
+      H += a.ch * (Er - E);
     }
     Real P = 0;
     if (tile_med && is_med) {
-      if (a.tape && owned && n >= a.tape_step0) {
-        Real *tp = a.tape + (n - a.tape_step0) * (D + 1) * a.ld + c;
-        if (v0) tp[i0 * a.ld] = y0;
-        if (v1) tp[i1 * a.ld] = y1;
-        if (r == 0) tp[D * a.ld] = E;
+      if (a.tape) {
+        const int64_t n = a.step0 + s;
+        if (owned && n >= a.tape_step0) {
+          Real *tp = a.tape + (n - a.tape_step0) * (D + 1) * a.ld + c;
+          if (v0) tp[i0 * a.ld] = y0;
+          if (v1) tp[i1 * a.ld] = y1;
+          if (r == 0) tp[D * a.ld] = E;
+        }
       }
       // y'' = Rot(y) + (Rot - I) zr on this lane's pair; a lane without a
       // pair has th = 0, so its increment is exactly zero (no divergence)
@@ -254,14 +267,16 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
       }
     }
     const Real Eold = E, Eoldl = Elo;
-    if (g >= 1 && g <= a.nx - 2) {
+    {
+      // interior cells: the Yee update; cell 0: the source sample; other
+      // cells (nx-1, set below, and cells beyond the grid) keep E
+      Real En = E, Enl = Elo;
       if constexpr (CF)
-        add_comp(E, Elo, a.cam1 * E + a.cb * (-P + ((H - Hl) + (Hlo - Hll)) * a.inv_dx));
+        add_comp(En, Enl, a.cam1 * E + a.cb * (-P + ((H - Hl) + (Hlo - Hll)) * a.inv_dx));
       else
-        E = a.ca * E + a.cb * (-P + (H - Hl) * a.inv_dx);
-    } else if (g == 0) {
-      E = sSrc[s];
-      if constexpr (CF) Elo = sSrcl[s];
+        En = a.ca * E + a.cb * (-P + (H - Hl) * a.inv_dx);
+      E = interior ? En : (is_src ? src : E);
+      if constexpr (CF) Elo = interior ? Enl : (is_src ? srcl : Elo);
     }
     if (has_right) {  // first-order Mur boundary at cell nx-1
       if (g == a.nx - 2 && r == 0) {
@@ -280,13 +295,13 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
         if constexpr (kProbeLds) {
           if (owned && r == 0) sPr[s] = E;
         } else {
-          if (a.probe_out && owned && r == 0) a.probe_out[n + 1] = (double)E + (double)Elo;
+          if (a.probe_out && owned && r == 0) a.probe_out[a.step0 + s + 1] = (double)E + (double)Elo;
         }
       }
     }
     if (snap) {
       if (owned && r == 0 && a.e_out) a.e_out[si * a.nx + g] = (double)E + (double)Elo;
-      snap_next += a.snap_every;
+      s_snap += snap_gap;
       ++si;
     }
   }
