@@ -54,7 +54,7 @@ __device__ __forceinline__ void lds_barrier() { __asm__ volatile("s_waitcnt lgkm
 __device__ __forceinline__ bool wave_any(bool p) { return __any(p); }
 
 __device__ __forceinline__ void sincm1(double x, double &s, double &cm1) {
-  if (!wave_any(fabs(x) > 0.0625)) {
+  if (__builtin_expect(!wave_any(fabs(x) > 0.0625), 1)) {
     // |x| <= 1/16: terms through x^9 (sine) and x^10 (cos - 1) leave a
     // truncation below 1e-19 relative
     const double x2 = x * x, x4 = x2 * x2;
@@ -90,7 +90,7 @@ __device__ __forceinline__ void sincm1(double x, double &s, double &cm1) {
 }
 
 __device__ __forceinline__ void sincm1(float x, float &s, float &cm1) {
-  if (!wave_any(fabsf(x) > 0.0625f)) {
+  if (__builtin_expect(!wave_any(fabsf(x) > 0.0625f), 1)) {
     // |x| <= 1/16: sin x = x + x^3 (-1/3! + x^2/5!), cos x - 1 =
     // x^2 (-1/2 + x^2 (1/4! - x^2/6!)); truncation below 1e-11 relative
     const float x2 = x * x;

@@ -161,10 +161,10 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
   for (int s = 0; s < a.nsteps; ++s) {
     const bool snap = s == s_snap;
     const int b = s & 1;
-    if (r == 0) {
-      sE[b][cl + 1] = E;
-      if constexpr (CF) sEl[b][cl + 1] = Elo;
-    }
+    // every lane of the quad writes the cell's E (the four values are
+    // bitwise equal), so the exchange write needs no branch
+    sE[b][cl + 1] = E;
+    if constexpr (CF) sEl[b][cl + 1] = Elo;
     lds_barrier();
     const Real El = sE[b][cl], Er = sE[b][cl + 2];
     const Real src = sSrc[s];
