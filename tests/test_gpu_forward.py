@@ -407,3 +407,25 @@ def test_pade_wavefront_kernel_fp32(ref_cache, n, seed, tile, k):
     ee, ep = _errs(got, ref)
     print(f"pade fp32 n={n} err_E={ee:.3e} err_pop={ep:.3e}")
     assert ee < 1e-3 and ep < 1e-3
+
+
+_SNAP_REF = {}
+
+
+@pytest.mark.parametrize("snap", [1, 3, 7, 20, 33, 128, 150, 300])
+@pytest.mark.parametrize("n", [2, 3])
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("fp32c", 1e-5)])
+def test_snapshot_schedule_across_launches(orc, snap, n, precision, tol):
+    """Snapshots every `snap` steps on the four-lane kernel with 20 steps per
+    launch (the kernel keeps the schedule as a step index within the launch):
+    intervals of one step, intervals that do not divide the launch, longer
+    than a launch and than the longest launch allowed, against the oracle."""
+    p = W.random_problem(n, 12 + n, nx=150, nt=320)
+    _print_case("snapshot_schedule", n=n, snap=snap, precision=precision)
+    if (n, snap) not in _SNAP_REF:
+        _SNAP_REF[(n, snap)] = orc.run(p, snap_every=snap)
+    ref = _SNAP_REF[(n, snap)]
+    got = mln.run(p, precision=precision, snap_every=snap, variant="quad", tile=64, steps_per_launch=20)
+    assert got["e_snap"].shape == ref["e_snap"].shape and got["pop"].shape == ref["pop"].shape
+    ee, ep = _errs(got, ref)
+    assert ee < tol and ep < tol, (ee, ep)
