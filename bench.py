@@ -168,12 +168,14 @@ def variants(p3, ref64, pop64, headline):
     # the paper's comparison of the exponential routes (Sec. 5.3): the per-step
     # Pade route against diagonalisation and Rodrigues, and the rotation form,
     # all FP64 on the one-cell-per-thread kernel (tile 256, 32 steps per launch)
-    # The paper's own two-level case on its printed grid (Sec. 5.1: 32768
-    # cells, 24559 steps to 187.5 fs; stand-in density, medium and pulse) is
-    # timed too, with the paper's metric P = Nx Nt / t beside the Liouville rate.
+    # The paper's own two-level and three-level cases on their printed grid
+    # (Sec. 5.1, 5.2: 32768 cells, 24559 steps to 187.5 fs; stand-in density,
+    # medium and pulse) are timed too, with the paper's metric P = Nx Nt / t
+    # beside the Liouville rate.
     p2 = W.two_level()
     comp = {}
-    for lbl, prob in (("n2_two_level", p2), ("n2_sit_paper_grid", W.sit_paper()), ("n3_three_level", p3)):
+    for lbl, prob in (("n2_two_level", p2), ("n2_sit_paper_grid", W.sit_paper()),
+                      ("n3_song_paper_grid", W.song_paper()), ("n3_three_level", p3)):
         nu = prob.grid.n_med * prob.grid.nt
         rates, paper_p = {}, {}
         for route in ("pade", "diag", "rodrigues", "rotation"):

@@ -223,6 +223,50 @@ def sit_paper(nt=None, nx=32768, medium_from=1024, tau=10e-15, name="sit_paper_g
     return Problem(name, med, grid, src)
 
 
+def song_paper(nt=None, nx=32768, medium_from=1024, tau=10e-15, area=0.5 * math.pi, name="song_paper_grid"):
+    """The paper's three-level test case (Sec. 5.2) on the grid of its
+    two-level case (32768 cells of 4.578 nm, Courant 0.5, 7.635e-18 s, run to
+    187.5 fs; nt overrides): H0 = hbar diag(0, w2, w3) with w2 = 2.372e15 and
+    w3 = 2.417e15 /s (the printed exponent is lost; 1e15 because the case runs
+    on the two-level grid, made for w ~ 1.3e15 /s, and it puts the two
+    transitions near 794 and 779 nm), a V system: dipole mu12 = 1.48e-29 C m
+    between levels 1 and 2 and gamma mu12 (gamma = sqrt 2) between 1 and 3,
+    the printed relaxation superoperator with T1 = 1e-10 s, ground-state
+    start.  The paper leaves density, medium extent and pulse to its
+    reference; stand-ins: N_a = 1e24 /m^3, the medium from cell medium_from to
+    the last cell, a sech pulse of tau = 10 fs at the mean transition
+    frequency (its spectrum covers both lines) with pulse area `area` on the
+    1-2 transition, centred at 6 tau, injected at cell 0."""
+    w2, w3 = 2.372e15, 2.417e15
+    mu12, gamma = 1.48e-29, math.sqrt(2.0)
+    t1 = 1e-10
+    h0 = np.diag(np.array([0.0, HBAR * w2, HBAR * w3], dtype=np.complex128))
+    mu = np.zeros((3, 3), dtype=np.complex128)
+    mu[0, 1] = mu[1, 0] = mu12
+    mu[0, 2] = mu[2, 0] = gamma * mu12
+    rho0 = np.zeros((3, 3), dtype=np.complex128)
+    rho0[0, 0] = 1.0
+    med = Medium(h0=h0, dipole=mu, rho0=rho0, density=1e24)
+    # printed superoperator (1/T1) x [[g/3, -r12, -r13], [-r21, g/3 - (r22 -
+    # r11), -r23], [-r31, -r32, g/3 - (r33 - r11)]], g = r33 + r22 - 2 r11, on
+    # the row-major vec(rho) (index 3a + b)
+    g = np.zeros((9, 9), dtype=np.complex128)
+    g[0, [0, 4, 8]] = [-2.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0]
+    g[4, [0, 4, 8]] = [1.0 / 3.0, -2.0 / 3.0, 1.0 / 3.0]
+    g[8, [0, 4, 8]] = [1.0 / 3.0, 1.0 / 3.0, -2.0 / 3.0]
+    for k in (1, 2, 3, 5, 6, 7):
+        g[k, k] = -1.0
+    med.relax_superop = g / t1
+    dx = 150e-6 / 32768
+    dt = 0.5 * dx / C0
+    if nt is None:
+        nt = int(round(187.5e-15 / dt))
+    grid = Grid(nx=nx, nt=nt, dx=dx, dt=dt, med_begin=medium_from, med_end=nx - 1)
+    e0 = area * HBAR / (mu12 * math.pi * tau)
+    src = Source(samples=sech_pulse(nt, dt, 0.5 * (w2 + w3), tau, 6.0 * tau), amplitude=e0)
+    return Problem(name, med, grid, src)
+
+
 def three_level(nx=20000, nt=100000, name="three_level_ladder_pi_gauss"):
     """N=3 ladder: energies hbar*omega0*{0, 1.0, 2.1}, mu01=1e-29,
     mu12=0.8e-29, Lindblad decay 1e12/s, pure dephasing 5e12/s, medium fills

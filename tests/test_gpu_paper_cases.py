@@ -1,10 +1,12 @@
-"""The paper's two-level self-induced-transparency test case (Sec. 5.1) on
-its printed grid, with the stand-ins for what the paper leaves to its
-reference (density, medium extent, pulse): the GPU path against the oracle
-on a truncated domain, the four exponential routes against each other on the
-full grid (the paper reports them indistinguishable), and the self-induced
-transparency itself (a 2-pi pulse leaves the absorber behind it in the
-ground state)."""
+"""The paper's test cases on their printed grid, with the stand-ins for what
+the paper leaves to its references (density, medium extent, pulse).
+Two-level self-induced transparency (Sec. 5.1): the GPU path against the
+oracle on a truncated domain, the four exponential routes against each other
+on the full grid (the paper reports them indistinguishable), and the
+self-induced transparency itself (a 2-pi pulse leaves the absorber behind it
+in the ground state).  Three-level V system (Sec. 5.2): the same parity and
+route agreement, and the two upper levels sharing the excitation by the
+squared dipole ratio."""
 import numpy as np
 import pytest
 
@@ -77,3 +79,63 @@ def test_sit_two_pi_pulse_leaves_ground_state_behind(full_runs):
     assert r22[behind].max() < 2e-2
     assert r22.max() > 0.5
     assert np.all(pop >= -1e-12) and np.max(np.abs(pop.sum(axis=0) - 1.0)) < 1e-12
+
+
+# The paper's three-level test case (Sec. 5.2): V system on the same grid
+
+
+@pytest.fixture(scope="module")
+def song_truncated(orc):
+    # 4096 cells, 12000 steps (92 fs): the pulse has entered the medium
+    p = W.song_paper(nt=12000, nx=4096)
+    return p, orc.run(p, snap_every=3000)
+
+
+@pytest.mark.parametrize("route", ROUTES)
+def test_song_truncated_domain_matches_oracle(song_truncated, route):
+    p, ref = song_truncated
+    print(f"[case] song truncated {route}", flush=True)
+    out = mln.run(p, precision="fp64", route=route, snap_every=3000)
+    scale = np.max(np.abs(ref["e_snap"]))
+    err_e = max(np.max(np.abs(out["e_snap"] - ref["e_snap"])), np.max(np.abs(out["probe"] - ref["probe"]))) / scale
+    err_p = np.max(np.abs(out["pop"] - ref["pop"]))
+    print(f"  err_E={err_e:.2e} err_pop={err_p:.2e} max rho22={ref['pop'][:, 1].max():.3f} "
+          f"max rho33={ref['pop'][:, 2].max():.3f}", flush=True)
+    assert err_e < 1e-10 and err_p < 1e-10
+
+
+@pytest.fixture(scope="module")
+def song_full():
+    p = W.song_paper()
+    outs = {}
+    for route in ROUTES:
+        print(f"[case] song full grid {route}", flush=True)
+        outs[route] = mln.run(p, precision="fp64", route=route, snap_every=p.grid.nt)
+    return p, outs
+
+
+def test_song_full_grid_routes_agree(song_full):
+    p, outs = song_full
+    ref = outs["rotation"]
+    scale = np.max(np.abs(ref["e_snap"]))
+    for route in ROUTES[1:]:
+        o = outs[route]
+        err_e = np.max(np.abs(o["e_snap"] - ref["e_snap"])) / scale
+        err_p = np.max(np.abs(o["pop"] - ref["pop"]))
+        print(f"  {route} vs rotation: err_E={err_e:.2e} err_pop={err_p:.2e}", flush=True)
+        assert err_e < 1e-9 and err_p < 1e-9
+
+
+def test_song_v_system_shares_excitation_by_dipole_ratio(song_full):
+    """The sech pulse sits midway between the two transitions, so the two
+    upper levels see the same detuning and take population in about the ratio
+    of the squared dipoles (gamma^2 = 2); populations stay a probability
+    distribution (the printed relaxation moves them towards 1/3 each at
+    (1/3)/T1, about 6e-4 over the run)."""
+    p, outs = song_full
+    pop = outs["rotation"]["pop"][0]  # (3, nmed) at 187.5 fs
+    r22, r33 = pop[1].max(), pop[2].max()
+    print(f"[case] song physics: max rho22 {r22:.3f}, max rho33 {r33:.3f}, ratio {r33 / r22:.2f}", flush=True)
+    assert r22 > 0.05 and 1.6 < r33 / r22 < 2.4
+    assert np.all(pop >= -1e-12) and np.max(np.abs(pop.sum(axis=0) - 1.0)) < 1e-10
+    assert pop[1].min() > 0.5 * (187.5e-15 / 3e-10)  # the relaxation's drift toward 1/3
