@@ -38,43 +38,50 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build()
-        L = ctypes.CDLL(_LIB)
-        dp = ctypes.POINTER(ctypes.c_double)
-        i64 = ctypes.c_int64
-        L.orc_run.restype = ctypes.c_int
-        L.orc_run.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, ctypes.c_double, dp, dp,
-                              ctypes.c_double, i64, i64, ctypes.c_double, ctypes.c_double, i64, i64,
-                              ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, ctypes.c_double,
-                              i64, dp, dp, dp, dp, ctypes.c_int]
-        L.orc_bloch.restype = ctypes.c_int
-        L.orc_bloch.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, ctypes.c_double, dp, dp,
-                                ctypes.c_double, i64, i64, ctypes.c_double, dp, dp, dp, dp, dp,
-                                ctypes.c_int]
-        L.orc_grad.restype = ctypes.c_int
-        L.orc_grad.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, ctypes.c_double, dp, dp,
+        _lib = bind(_LIB)
+    return _lib
+
+
+def bind(path):
+    """Load an oracle library from ``path`` and declare its entry points (the
+    tests also use it to load deliberately broken copies built on the CPU and
+    check that the pins reject them)."""
+    L = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    i64 = ctypes.c_int64
+    L.orc_run.restype = ctypes.c_int
+    L.orc_run.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, ctypes.c_double, dp, dp,
+                          ctypes.c_double, i64, i64, ctypes.c_double, ctypes.c_double, i64, i64,
+                          ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, ctypes.c_double,
+                          dp, dp, i64, dp, dp, dp, dp, dp, ctypes.c_int]
+    L.orc_bloch.restype = ctypes.c_int
+    L.orc_bloch.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, ctypes.c_double, dp, dp,
+                            ctypes.c_double, i64, i64, ctypes.c_double, dp, dp, dp, dp, dp,
+                            ctypes.c_int]
+    L.orc_grad.restype = ctypes.c_int
+    L.orc_grad.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, ctypes.c_double, dp, dp,
+                           ctypes.c_double, i64, i64, ctypes.c_double, ctypes.c_double, i64, i64,
+                           ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, ctypes.c_double,
+                           dp, dp, dp, dp, dp, dp, dp, ctypes.c_int]
+    L.orc_pstd_run.restype = ctypes.c_int
+    L.orc_pstd_run.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, ctypes.c_double, dp, dp,
                                ctypes.c_double, i64, i64, ctypes.c_double, ctypes.c_double, i64, i64,
                                ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, ctypes.c_double,
-                               dp, dp, dp, dp, dp, dp, dp, ctypes.c_int]
-        L.orc_pstd_run.restype = ctypes.c_int
-        L.orc_pstd_run.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, ctypes.c_double, dp, dp,
-                                   ctypes.c_double, i64, i64, ctypes.c_double, ctypes.c_double, i64, i64,
-                                   ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, ctypes.c_double,
-                                   dp, dp, i64, dp, dp, dp, dp, ctypes.c_int]
-        L.orc_spectral_derivative.restype = None
-        L.orc_spectral_derivative.argtypes = [i64, ctypes.c_double, dp, ctypes.c_double, dp]
-        L.orc_expm.restype = ctypes.c_int
-        L.orc_expm.argtypes = [ctypes.c_int, dp, dp]
-        L.orc_superop.restype = ctypes.c_int
-        L.orc_superop.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, ctypes.c_double, dp,
-                                  ctypes.c_double, dp, dp]
-        L.orc_pade_coef.restype = ctypes.c_double
-        L.orc_pade_coef.argtypes = [ctypes.c_int, ctypes.c_int]
-        L.orc_min_eig.restype = ctypes.c_double
-        L.orc_min_eig.argtypes = [ctypes.c_int, dp]
-        L.orc_constants.restype = None
-        L.orc_constants.argtypes = [dp]
-        _lib = L
-    return _lib
+                               dp, dp, i64, dp, dp, dp, dp, ctypes.c_int]
+    L.orc_spectral_derivative.restype = None
+    L.orc_spectral_derivative.argtypes = [i64, ctypes.c_double, dp, ctypes.c_double, dp]
+    L.orc_expm.restype = ctypes.c_int
+    L.orc_expm.argtypes = [ctypes.c_int, dp, dp]
+    L.orc_superop.restype = ctypes.c_int
+    L.orc_superop.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, ctypes.c_double, dp,
+                              ctypes.c_double, dp, dp]
+    L.orc_pade_coef.restype = ctypes.c_double
+    L.orc_pade_coef.argtypes = [ctypes.c_int, ctypes.c_int]
+    L.orc_min_eig.restype = ctypes.c_double
+    L.orc_min_eig.argtypes = [ctypes.c_int, dp]
+    L.orc_constants.restype = None
+    L.orc_constants.argtypes = [dp]
+    return L
 
 
 def _p(a):
@@ -134,9 +141,12 @@ def superop(med, dt):
     return S, E0
 
 
-def run(problem, snap_every=0, nthreads=0, nt=None):
-    """Coupled FDTD + density-matrix run.  Returns dict with 'probe' (nt+1),
-    'e_snap' (nsnap, nx), 'pop' (nsnap, N, n_med), 'diag'."""
+def run(problem, snap_every=0, nthreads=0, nt=None, e_init=None, h_init=None):
+    """Coupled FDTD + density-matrix run.  e_init (nx values, E^0 including
+    the source cell) and h_init (nx - 1 values, H^{-1/2} on the faces
+    (i + 1/2) dx) replace the zero initial fields.  Returns dict with 'probe'
+    (nt+1), 'e_snap' (nsnap, nx), 'pop' (nsnap, N, n_med), 'h' (H^{nt-1/2},
+    nx - 1 values) and 'diag'."""
     med, g, src = problem.medium, problem.grid, problem.source
     nt = g.nt if nt is None else nt
     n, h0, mu, nj, jumps, rates, deph, relax, rho0 = _medium_args(med)
@@ -144,15 +154,23 @@ def run(problem, snap_every=0, nthreads=0, nt=None):
     probe = np.zeros(nt + 1)
     e_snap = np.zeros((max(nsnap, 1), g.nx))
     pop = np.zeros((max(nsnap, 1), n, max(g.n_med, 1)))
+    hfin = np.zeros(g.nx - 1)
     diag = np.zeros(4)
     samples = np.ascontiguousarray(src.samples[: nt + 1], dtype=np.float64)
+    ei = None if e_init is None else np.ascontiguousarray(e_init, dtype=np.float64)
+    hi = None if h_init is None else np.ascontiguousarray(h_init, dtype=np.float64)
+    if ei is not None and ei.shape != (g.nx,):
+        raise ValueError("e_init must have nx values")
+    if hi is not None and hi.shape != (g.nx - 1,):
+        raise ValueError("h_init must have nx - 1 values")
     rc = lib().orc_run(n, _p(h0), _p(mu), nj, _p(jumps), _p(rates), deph, _p(relax), _p(rho0),
                        float(med.density), g.nx, nt, g.dx, g.dt, g.med_begin, g.med_end,
                        g.eps_r, g.mu_r, g.sigma, _p(samples), float(src.amplitude),
-                       snap_every, _p(e_snap), _p(pop), _p(probe), _p(diag), nthreads)
+                       _p(ei), _p(hi), snap_every, _p(e_snap), _p(pop), _p(probe), _p(hfin),
+                       _p(diag), nthreads)
     if rc:
         raise RuntimeError(f"oracle run failed ({rc})")
-    return dict(probe=probe, e_snap=e_snap[:nsnap], pop=pop[:nsnap, :, : g.n_med],
+    return dict(probe=probe, e_snap=e_snap[:nsnap], pop=pop[:nsnap, :, : g.n_med], h=hfin,
                 diag=dict(trace=diag[0], herm=diag[1], min_eig=diag[2], purity=diag[3]))
 
 

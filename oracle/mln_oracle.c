@@ -455,8 +455,9 @@ int orc_run(int n, const double *h0, const double *mu, int n_jump, const double 
             const double *rate, double deph, const double *relax, const double *rho0,
             double Na, int64_t nx, int64_t nt, double dx, double dt, int64_t mb, int64_t me,
             double eps_r, double mu_r, double sigma, const double *src, double amp,
+            const double *e_init, const double *h_init,
             int64_t snap_every, double *e_snap, double *pop_snap, double *probe,
-            double *diag, int nthreads)
+            double *h_out, double *diag, int nthreads)
 {
     if (n < 2 || nx < 3 || nt < 0 || mb < 1 || me < mb || me > nx - 1) return -1;
 #ifdef _OPENMP
@@ -480,6 +481,10 @@ int orc_run(int n, const double *h0, const double *mu, int n_jump, const double 
     double ca = (1.0 - sg) / (1.0 + sg), cb = (dt / eps) / (1.0 + sg);
     double ch = dt / (muu * dx);
     E[0] = amp * src[0];
+    /* optional initial fields: E^0 on every cell (including the source cell)
+     * and H^{-1/2} on the nx - 1 faces */
+    if (e_init) memcpy(E, e_init, sizeof(double) * nx);
+    if (h_init) memcpy(H, h_init, sizeof(double) * (nx - 1));
     if (probe) probe[0] = E[nx - 1];
     if (diag) { diag[0] = 0; diag[1] = 0; diag[2] = 1e300; diag[3] = 0; }
     for (int64_t t = 0; t < nt; ++t) {
@@ -513,6 +518,7 @@ int orc_run(int n, const double *h0, const double *mu, int n_jump, const double 
             }
         }
     }
+    if (h_out) memcpy(h_out, H, sizeof(double) * (nx - 1));   /* H^{nt-1/2} */
     free(rho); free(r0); free(E); free(H); free(P);
     medium_free(&m);
     return 0;

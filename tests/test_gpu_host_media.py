@@ -1,0 +1,117 @@
+"""GPU parity against the oracle for a host medium that is not vacuum: the
+conductivity sigma and the relative permittivity and permeability of the
+Yee update (Sec. 2, Eq. maxwell), in every precision and kernel variant that
+runs the rotation route; and runs started from given fields (mln_set_state
+at step 0), with the magnetic field read back (mln_get_state), which in the
+single-precision modes is carried rescaled on the device.
+
+The oracle's handling of these parameters is pinned on the CPU by the lossy
+Yee dispersion relation, the magic time step in a host medium and the
+energy balance of a coherent medium (test_oracle_media.py).
+"""
+import numpy as np
+import pytest
+
+from paper_1710_09799_amd import mln
+from paper_1710_09799_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+HOSTS = [(2.0e3, 1.0, 1.0), (0.0, 2.25, 1.0), (0.0, 1.0, 2.25), (1.0e3, 1.5, 1.8)]
+MODES = [("fp64", "auto", 1e-10), ("fp64", "block", 1e-10), ("fp32c", "quad", 1e-5),
+         ("fp32c", "block", 1e-5), ("fp32cf", "quad", 1e-5), ("fp32cf", "block", 1e-5),
+         ("fp32c", "wave", 1e-5), ("bf16x6", "auto", 1e-4)]
+
+
+def _supported(n, precision, variant):
+    if variant == "quad" and n > 3:
+        return False
+    if variant == "wave" and n == 6:
+        return False
+    if precision == "bf16x6" and n < 4:
+        return False
+    return True
+
+
+def _host_problem(n, seed, sigma, eps_r, mu_r, nx=203, nt=360):
+    p = W.random_problem(n, seed, nx=nx, nt=nt)
+    p.grid.sigma, p.grid.eps_r, p.grid.mu_r = sigma, eps_r, mu_r
+    return p
+
+
+def _errs(got, ref, h_got, h_ref):
+    e = np.concatenate([got["e_snap"].ravel(), got["probe"].ravel()])
+    er = np.concatenate([ref["e_snap"].ravel(), ref["probe"].ravel()])
+    err_e = np.max(np.abs(e - er)) / np.max(np.abs(er))
+    err_p = np.max(np.abs(got["pop"] - ref["pop"]))
+    err_h = np.max(np.abs(h_got - h_ref)) / np.max(np.abs(h_ref))
+    return err_e, err_p, err_h
+
+
+@pytest.fixture(scope="module")
+def host_refs(orc):
+    cache = {}
+
+    def get(n, seed, host):
+        key = (n, seed, host)
+        if key not in cache:
+            cache[key] = orc.run(_host_problem(n, seed, *host), snap_every=40)
+        return cache[key]
+    return get
+
+
+@pytest.mark.parametrize("host", HOSTS)
+@pytest.mark.parametrize("n,seed", [(2, 11), (3, 12), (6, 13)])
+@pytest.mark.parametrize("precision,variant,tol", MODES)
+def test_host_medium_parity(host_refs, host, n, seed, precision, variant, tol):
+    """Random medium with relaxation inside a conducting / dielectric /
+    magnetic host: every recorded E and population and the final H."""
+    if not _supported(n, precision, variant):
+        pytest.skip("kernel variant not built for this level count and precision")
+    sigma, eps_r, mu_r = host
+    print(f"[case] host n={n} sigma={sigma} eps_r={eps_r} mu_r={mu_r} {precision} {variant}",
+          flush=True)
+    p = _host_problem(n, seed, *host)
+    ref = host_refs(n, seed, host)
+    s = mln.Solver(p, precision=precision, snap_every=40, variant=variant)
+    got = {k: v.cpu().numpy() for k, v in s.run().items() if v is not None}
+    _, H, _ = s.state()
+    s.close()
+    ee, ep, eh = _errs(got, ref, H, ref["h"])
+    print(f"  err_E={ee:.2e} err_pop={ep:.2e} err_H={eh:.2e}", flush=True)
+    assert ee < tol and ep < tol and eh < tol
+
+
+@pytest.mark.parametrize("n,seed", [(2, 21), (3, 22), (6, 23)])
+@pytest.mark.parametrize("precision,variant,tol", [("fp64", "auto", 1e-10), ("fp32c", "auto", 1e-5),
+                                                   ("fp32cf", "block", 1e-5), ("bf16x6", "auto", 1e-4)])
+@pytest.mark.parametrize("host", [(0.0, 1.0, 1.0), (1.0e3, 1.5, 1.8)])
+def test_initial_fields_parity(orc, n, seed, precision, variant, tol, host):
+    """A pulse given as initial fields (E^0 and H^{-1/2} written at step 0
+    with mln_set_state, zero source) moves into the medium: every recorded E
+    and population, and the final H read back, against the oracle started
+    from the same fields."""
+    if not _supported(n, precision, variant):
+        pytest.skip("kernel variant not built for this level count and precision")
+    sigma, eps_r, mu_r = host
+    nx, nt = 400, 500
+    p = _host_problem(n, seed, sigma, eps_r, mu_r, nx=nx, nt=nt)
+    p.grid.med_begin, p.grid.med_end = 150, 330
+    p.source = W.Source(np.zeros(nt + 1), 0.0)
+    e0, h0 = W.moving_pulse(nx, p.grid.dx, p.grid.dt, 80 * p.grid.dx, 15 * p.grid.dx, W.OMEGA0,
+                            2e9, eps_r=eps_r, mu_r=mu_r)
+    e0[0] = 0.0
+    e0[-1] = 0.0
+    h0 = h0[: nx - 1]
+    print(f"[case] initial fields n={n} {precision} {variant} host={host}", flush=True)
+    ref = orc.run(p, snap_every=50, e_init=e0, h_init=h0)
+    s = mln.Solver(p, precision=precision, snap_every=50, variant=variant)
+    s.set_state(E=e0, H=h0)
+    got = {k: v.cpu().numpy() for k, v in s.run().items() if v is not None}
+    _, H, _ = s.state()
+    s.close()
+    ee, ep, eh = _errs(got, ref, H, ref["h"])
+    print(f"  err_E={ee:.2e} err_pop={ep:.2e} err_H={eh:.2e}", flush=True)
+    assert ee < tol and ep < tol and eh < tol
+    # the pulse reached the medium
+    assert np.max(np.abs(ref["e_snap"][:, 150:330])) > 0.1 * 2e9

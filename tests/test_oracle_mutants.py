@@ -1,0 +1,73 @@
+"""The oracle's pins reject plausible mistakes in its coupled Yee run.
+
+Each case copies the oracle's C source, plants one mistake in the coupled
+run (orc_run: the first occurrence of the line in the file), builds the copy
+with gcc into a temporary directory, loads it in place of the real oracle
+and runs the pin that covers that part.  The pin must fail.  The mistakes
+are those a reading of Sec. 2 (Eq. maxwell) and Eq. polarization2 could make
+the same way on both the oracle's and the GPU's side, so parity alone would
+not catch them:
+
+* the polarisation current fed back with the wrong sign, or twice;
+* the density N_a dropped by half in dP/dt;
+* the semi-implicit conductivity with half its weight;
+* eps_r and mu_r exchanged;
+* the Mur coefficient taken with the vacuum speed of light in a host medium.
+
+Everything here runs on the CPU.
+"""
+import os
+import subprocess
+
+import pytest
+
+import oracle
+import test_oracle_media as M
+
+MUTANTS = {
+    "feedback_sign": ("E[i] = ca * E[i] + cb * (-dp + (H[i] - H[i - 1]) / dx);",
+                      "E[i] = ca * E[i] + cb * (dp + (H[i] - H[i - 1]) / dx);",
+                      lambda: M.check_coherent_energy(oracle)),
+    "feedback_twice": ("E[i] = ca * E[i] + cb * (-dp + (H[i] - H[i - 1]) / dx);",
+                       "E[i] = ca * E[i] + cb * (-2.0 * dp + (H[i] - H[i - 1]) / dx);",
+                       lambda: M.check_coherent_energy(oracle)),
+    "density_half": ("P[c] = cell_step(&m, rho + c * n2, E[mb + c], dt, Na, &ws);",
+                     "P[c] = cell_step(&m, rho + c * n2, E[mb + c], dt, 0.5 * Na, &ws);",
+                     lambda: M.check_coherent_energy(oracle)),
+    "sigma_quarter": ("double sg = sigma * dt / (2.0 * eps);",
+                      "double sg = sigma * dt / (4.0 * eps);",
+                      lambda: M.check_cw_dispersion(oracle, 2.25, 1.0, 3.0e3)),
+    "eps_mu_exchanged": ("double eps = ORC_EPS0 * eps_r, muu = ORC_MU0 * mu_r;",
+                         "double eps = ORC_EPS0 * mu_r, muu = ORC_MU0 * eps_r;",
+                         lambda: M.check_magic_step_in_host(oracle, 2.25, 1.0)),
+    "mur_vacuum_speed": ("double cl = 1.0 / sqrt(eps * muu);",
+                         "double cl = 1.0 / sqrt(ORC_EPS0 * ORC_MU0);",
+                         lambda: M.check_magic_step_in_host(oracle, 2.25, 1.0)),
+}
+
+
+def _build_mutant(tmp_path, name, old, new):
+    src = open(oracle._SRC).read()
+    assert old in src, f"mutation site of {name} not found"
+    mutated = src.replace(old, new, 1)
+    c_file = tmp_path / f"orc_{name}.c"
+    so_file = tmp_path / f"liborc_{name}.so"
+    c_file.write_text(mutated)
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
+                           "-o", str(so_file), str(c_file), "-lm"])
+    return str(so_file)
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pin_rejects_planted_mistake(tmp_path, name):
+    old, new, pin = MUTANTS[name]
+    real = oracle.lib()
+    pin()  # the pin passes on the real oracle
+    path = _build_mutant(tmp_path, name, old, new)
+    oracle._lib = oracle.bind(path)
+    try:
+        with pytest.raises(AssertionError):
+            pin()
+    finally:
+        oracle._lib = real
+        os.remove(path)
