@@ -59,13 +59,22 @@ typedef enum {
                              1.5e-5 in the populations after 1e5 steps), the other
                              routes carry d itself (about 1e-4)                        */
   MLN_FP32_COMP = 2,      /* single precision with a compensated (two-float) Bloch-vector
-                             state and two-float factors; E and H in plain FP32        */
+                             state and two-float factors; E and H in plain FP32, whose
+                             rounding accumulates along long propagation paths (2.6e-5
+                             in the six-level probe after 2e5 steps, 4.9e-5 in the
+                             30000-cell problems of the 64-problem sweep): past ~1e5
+                             steps or ~2e4 cells use MLN_FP32_COMP_FIELDS for 1e-5   */
   MLN_FP32_BF16SPLIT = 3, /* compensated FP32 state and fields; the shared-factor
                              transform runs on MFMA with three-part BF16 splits of both
                              operands and six products (~2^-24 relative), FP32
                              accumulation; N = 4, 6                                     */
   MLN_FP32_BF16X3 = 4,    /* as MLN_FP32_BF16SPLIT with two-part splits and three
-                             products (~2^-16 relative)                                */
+                             products (~2^-16 relative).  Outside the split-BF16
+                             tolerance of 1e-4 on long runs: the six-level workload
+                             (50000 cells, 2e5 steps) ends 4.9e-4 away from the FP64
+                             path in the probe field (1e-5 after 2e4 steps; bound
+                             stated for such runs: 1e-3); use MLN_FP32_BF16SPLIT
+                             where 1e-4 must hold past ~5e4 steps                     */
   MLN_FP32_COMP_FIELDS = 5 /* as MLN_FP32_COMP, and E, H and the source samples are
                              two-float pairs as well (for runs of 1e5 steps and more,
                              where FP32 rounding of the fields accumulates); workgroup

@@ -607,7 +607,11 @@ static int frechet_adj(int n, const cx *A, const cx *G, cx *out)
         for (int i = 0; i < n * n; ++i) out[i] = 0.0;
         return 0;
     }
-    double sc = (an > 0.0 ? an : 1.0) / gn;
+    /* G enters as (G / |G|_1) * |A|_1 and the result is scaled back by
+     * |G|_1 / |A|_1: dividing first keeps a G near the bottom of the
+     * double range (an adjoint that has barely reached a cell) from
+     * overflowing the factor |A|_1 / |G|_1 */
+    double an1 = an > 0.0 ? an : 1.0;
     cx *B = (cx *)calloc((size_t)m * m, sizeof(cx));
     cx *F = (cx *)malloc(sizeof(cx) * m * m);
     cx *w = (cx *)malloc(sizeof(cx) * 5 * m * m);
@@ -616,11 +620,11 @@ static int frechet_adj(int n, const cx *A, const cx *G, cx *out)
             cx ah = conj(A[j * n + i]);
             B[i * m + j] = ah;
             B[(n + i) * m + n + j] = ah;
-            B[i * m + n + j] = sc * G[i * n + j];
+            B[i * m + n + j] = (G[i * n + j] / gn) * an1;
         }
     int rc = expm_work(m, B, F, w);
     for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) out[i * n + j] = F[i * m + n + j] / sc;
+        for (int j = 0; j < n; ++j) out[i * n + j] = (F[i * m + n + j] / an1) * gn;
     free(B); free(F); free(w);
     return rc;
 }

@@ -230,3 +230,37 @@ def test_adjoint_case_full_size():
     rel = np.abs(a - b) / np.max(np.abs(b))
     print("fp32c vs fp64 gradient, relative to the largest:", rel)
     assert np.max(rel) < 1e-3
+
+
+def _p5_problem():
+    """The adjoint workload cut to 1000 cells x 5000 steps (checkpoints every
+    500 steps).  Its Gaussian pi pulse (200 fs envelope FWHM) is centred at
+    step 2500 instead of 600 fs so that the transmitted pulse reaches the
+    probe inside the shorter run (it arrives about 2000 steps after it
+    leaves the source)."""
+    nx, nt = 1000, 5000
+    p = W.adjoint_case(nx=nx, nt=nt)
+    sig = 200e-15 / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+    p.source = W.Source(W.gauss_pulse(nt, W.DT0, W.OMEGA0, sig, 2500 * W.DT0), p.source.amplitude)
+    return p
+
+
+@pytest.mark.slow
+def test_p5_adjoint_matches_oracle_adjoint(orc):
+    """The reduced adjoint workload (1000 cells x 5000 steps, checkpoints
+    every 500): the GPU's FP64 gradient of the transmitted energy against the
+    oracle's FP64 adjoint on every gradient group (1e-10 of the group's
+    largest entry), and the compensated-FP32 gradient within 1e-3."""
+    prob = _p5_problem()
+    print("[case] P5 adjoint vs oracle adjoint (1000 x 5000)", flush=True)
+    ref_probe = orc.run(prob)["probe"]
+    assert np.max(np.abs(ref_probe)) > 0.3 * prob.source.amplitude  # the pulse arrived
+    ref = orc.grad(prob, 2.0 * prob.grid.dt * ref_probe)
+    for precision, tol in (("fp64", 1e-10), ("fp32c", 1e-3)):
+        s = mln.Solver(prob, precision=precision, ckpt_every=500)
+        probe = s.run()["probe"].cpu().numpy()
+        g = s.grad(2.0 * prob.grid.dt * probe)
+        s.close()
+        print(f"  {precision}", flush=True)
+        worst = _cmp_oracle_adjoint(g, ref, tol, 0.0 if precision != "fp64" else 1e-8)
+        print(f"  {precision} worst group error {worst:.2e}", flush=True)

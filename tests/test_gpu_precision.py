@@ -172,13 +172,15 @@ def test_six_level_full_size():
     benchmark's launch configurations.  The oracle cannot run it; the FP64 GPU
     path (matched to the oracle to 1e-10 on the reduced six-level shape) is
     the reference: split-BF16 (six products) within its 1e-4 bound and
-    compensated fields within 1e-5 on the probe; populations of every run in
-    [0, 1] and summing to one."""
+    compensated fields within 1e-5 on the probe; split-BF16 with three
+    products within the 1e-3 its header entry states for runs this long
+    (measured 4.9e-4, outside the 1e-4 split-BF16 tolerance); populations of
+    every run in [0, 1] and summing to one."""
     p = W.six_level()
     nt = p.grid.nt
     kw = dict(tile=256, steps_per_launch=16, snap_every=nt // 2, record_e=False)
     ref = mln.run(p, precision="fp64", variant="block", **kw)
-    for prec, tol in (("bf16x6", 1e-4), ("fp32cf", 1e-5)):
+    for prec, tol in (("bf16x6", 1e-4), ("fp32cf", 1e-5), ("bf16x3", 1e-3)):
         got = mln.run(p, precision=prec, **kw)
         err = np.max(np.abs(got["probe"] - ref["probe"])) / np.max(np.abs(ref["probe"]))
         print(f"six-level full size {prec}: probe deviation from FP64 {err:.2e}")
