@@ -607,11 +607,14 @@ static int frechet_adj(int n, const cx *A, const cx *G, cx *out)
         for (int i = 0; i < n * n; ++i) out[i] = 0.0;
         return 0;
     }
-    /* G enters as (G / |G|_1) * |A|_1 and the result is scaled back by
-     * |G|_1 / |A|_1: dividing first keeps a G near the bottom of the
-     * double range (an adjoint that has barely reached a cell) from
-     * overflowing the factor |A|_1 / |G|_1 */
-    double an1 = an > 0.0 ? an : 1.0;
+    /* G enters as (G / |G|_1) * s and the result is scaled back by
+     * |G|_1 / s, with s = max(|A|_1, 1/4): dividing first keeps a G near
+     * the bottom of the double range (an adjoint that has barely reached a
+     * cell) from overflowing the factor s / |G|_1, and the floor on s keeps
+     * G out of the subnormal range when A is tiny (a cell the field has
+     * barely reached, E ~ 1e-300), where it would lose its significant
+     * digits; the block's norm stays below 1/2 + |A|_1 either way */
+    double an1 = an > 0.25 ? an : 0.25;
     cx *B = (cx *)calloc((size_t)m * m, sizeof(cx));
     cx *F = (cx *)malloc(sizeof(cx) * m * m);
     cx *w = (cx *)malloc(sizeof(cx) * 5 * m * m);

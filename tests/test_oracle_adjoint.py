@@ -151,3 +151,26 @@ def test_adjoint_finite_where_it_barely_reaches(orc):
         pp.source = W.Source(pp.source.samples, pp.source.amplitude + d)
     fd = _fd(orc, p, set_amp, p.source.amplitude, 1e-4)
     assert abs(g["d_amplitude"] - fd) <= 1e-6 * abs(fd)
+
+
+def test_adjoint_accurate_where_the_field_is_subnormal(orc):
+    """Regression: on an 800-cell ladder the cells near the numerical light
+    cone of the Yee scheme see fields of 1e-300 V/m and below.  The adjoint
+    of their interaction exponential exp(i alpha E mu) was evaluated with the
+    Frechet direction scaled to the exponent's subnormal norm, which dropped
+    its significant digits and moved the off-diagonal H0 gradients by up to
+    6e-6 of the largest H0 gradient.  Against central differences (Richardson,
+    h = 1e-4 of the level spacing) the off-diagonal entry holds to 1e-9 of the
+    group's largest entry."""
+    import math
+    nx, nt = 800, 1700
+    p = W.adjoint_case(nx=nx, nt=nt)
+    sig = 200e-15 / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+    p.source = W.Source(W.gauss_pulse(nt, W.DT0, W.OMEGA0, sig, 600 * W.DT0), p.source.amplitude)
+    g = _grad(orc, p)
+    scale = W.HBAR * W.OMEGA0
+    big = np.max(np.abs(g["d_h0"]))
+    for imag in (False, True):
+        fd = _fd(orc, p, _set_herm("h0", 0, 1, imag), scale, 1e-4)
+        got = g["d_h0"][0, 1].imag if imag else g["d_h0"][0, 1].real
+        assert abs(got - fd) <= 1e-9 * big, (imag, got, fd, big)
