@@ -277,6 +277,25 @@ int mln_load_state(mln_handle *h, const void *host_buf);
 int mln_bloch_only(mln_handle *h, const double *efield, int64_t n_steps, double *pop_out,
                    double *dp_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as mln_bloch_only, with the same kernels, that allocates
+ * nothing.  mln_bloch_only stages the initial Bloch state in a device buffer
+ * it allocates per call; this variant stages it in a library-owned device
+ * array of MLN_NOALLOC_SCRATCH_BYTES per GPU (held until the process ends;
+ * its address is looked up once per device at mln_init).  efield, pop_out
+ * and dp_out must be DEVICE pointers whatever out_on_device says (no host
+ * staging); pop_out and dp_out may be NULL.  The scratch is shared by every
+ * call on one GPU and keeps the last call's contents (each call overwrites
+ * what it reads): calls that overlap in time on one GPU (other host threads,
+ * other streams) race and must be serialised by the caller.  Errors:
+ * MLN_EINVAL (null pointer, negative n_steps, or an initial state larger
+ * than the scratch), MLN_ESTATE, MLN_EHIP.  Synchronises the handle's
+ * stream. */
+#define MLN_NOALLOC_SCRATCH_BYTES 4096
+int mln_bloch_only_noalloc(mln_handle *h, const double *efield, int64_t n_steps, double *pop_out,
+                           double *dp_out);
+
 /* Vector-Jacobian product of the whole run (the adjoint, reverse-time pass):
  * given g[n] = dJ/dprobe[n] for n = 0..nt (host array), fill *out with
  * dJ/d(inputs).  Needs a handle created with ckpt_every > 0 on which mln_run

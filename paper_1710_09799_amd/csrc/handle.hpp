@@ -82,6 +82,7 @@ struct mln_handle {
   bool cf = false;    // compensated FP32 fields and source samples (two floats each)
   int mfma = 0;       // split-BF16 products of the MFMA shared-factor kernel (6, 3) or 0
   hipStream_t stream = nullptr;
+  int device = 0;  // the device current at mln_init
   int64_t nmed = 0, ld = 0, step = 0;
   int W = 256, halo = 0, owned = 0;  // cells per tile, halo = max steps per launch
   bool wave = false;                  // single-wavefront tile kernel (W = 64 * C cells)

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,6 +18,45 @@ using namespace mln;
 
 namespace {
 thread_local std::string g_last_error;
+}  // namespace
+
+// ---- device scratch of the no-allocation entry point --------------------
+// mln_bloch_only stages the initial Bloch state of the prescribed-field run in
+// a small device buffer it allocates per call; mln_bloch_only_noalloc stages
+// it here instead.  Each device holds its own copy of this array (its address
+// differs per device) until the process ends.  In host code the array's name
+// is not a device address: the address is looked up with hipGetSymbolAddress
+// once per device (in mln_init, with that device current) and only that
+// address is used (copies, kernel arguments).
+static __device__ __align__(256) unsigned char scratch[MLN_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// Address of `scratch` on the current device, resolved on first use.
+int scratch_setup(int *device) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return set_err(MLN_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return set_err(MLN_ENOTSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_err(MLN_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = p;
+  }
+  *device = dev;
+  return MLN_OK;
+}
+
+void *scratch_of(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return (device >= 0 && device < kMaxDevices) ? g_scratch_dev[device] : nullptr;
+}
 }  // namespace
 
 int mln::set_err(int code, const std::string &msg) {
@@ -451,6 +491,8 @@ int mln_init(const mln_medium *medium, const mln_grid *grid, const mln_source *s
   int rc = validate_grid(grid, source);
   if (rc) return rc;
   std::unique_ptr<mln_handle> h(new mln_handle());
+  rc = scratch_setup(&h->device);
+  if (rc) return rc;
   std::string err;
   rc = build_factors(medium, grid->dt, &h->f, &err);
   if (rc) return set_err(rc, err);
@@ -945,6 +987,42 @@ int mln_bloch_only(mln_handle *h, const double *efield, int64_t n_steps, double 
     if (pop_out) HIP_TRY(hipMemcpy(pop_out, pop_dev, sizeof(double) * nc * n_steps * N, hipMemcpyDeviceToHost));
     if (dp_out) HIP_TRY(hipMemcpy(dp_out, dp_dev, sizeof(double) * nc * n_steps, hipMemcpyDeviceToHost));
   }
+  return MLN_OK;
+}
+
+int mln_bloch_only_noalloc(mln_handle *h, const double *efield, int64_t n_steps, double *pop_out,
+                           double *dp_out) {
+  if (!h || !efield || n_steps < 0) return set_err(MLN_EINVAL, "bad argument");
+  const int64_t nc = h->nmed;
+  const int N = h->f.N, D = h->f.D;
+  if (nc == 0 || n_steps == 0) return MLN_OK;
+  const bool f64 = h->prec == MLN_FP64;
+  const size_t need = f64 ? sizeof(double) * D : sizeof(float) * 2 * D;
+  constexpr int kMaxD = 35;  // N <= 6
+  if (D > kMaxD || need > MLN_NOALLOC_SCRATCH_BYTES)
+    return set_err(MLN_EINVAL, "initial state of " + std::to_string(need) + " bytes exceeds the " +
+                                   std::to_string(MLN_NOALLOC_SCRATCH_BYTES) + "-byte scratch");
+  void *sp = scratch_of(h->device);
+  if (!sp) return set_err(MLN_ESTATE, "scratch address of the handle's device was not set up");
+  const std::vector<double> &s0 = (h->route == MLN_ROUTE_ROTATION) ? h->f.y0 : h->f.dprime0;
+  hipError_t e;
+  if (f64) {
+    HIP_TRY(hipMemcpyAsync(sp, s0.data(), need, hipMemcpyHostToDevice, h->stream));
+    BlochArgs<double> a{h->fd, 0, (const double *)sp, efield, nc, n_steps, pop_out, dp_out};
+    e = launch_bloch<double>(N, h->route, false, a, h->stream);
+  } else {
+    float z0f[2 * kMaxD];
+    for (int j = 0; j < D; ++j) {
+      z0f[j] = (float)s0[j];
+      z0f[D + j] = (float)(s0[j] - (double)z0f[j]);
+    }
+    HIP_TRY(hipMemcpyAsync(sp, z0f, need, hipMemcpyHostToDevice, h->stream));
+    BlochArgs<float> a{h->ff, 0, (const float *)sp, efield, nc, n_steps, pop_out, dp_out};
+    e = launch_bloch<float>(N, h->route, h->comp, a, h->stream);
+  }
+  if (e != hipSuccess) return set_err(MLN_EHIP, std::string("bloch launch: ") + hipGetErrorString(e));
+  // z0f lives on this stack frame: the copy and the kernel end before return
+  HIP_TRY(hipStreamSynchronize(h->stream));
   return MLN_OK;
 }
 

@@ -72,7 +72,7 @@ class _Factors(ctypes.Structure):
 # every symbol include/mln.h declares
 EXPORTS = ["mln_init", "mln_step", "mln_run", "mln_reset", "mln_current_step", "mln_get_config", "mln_configure", "mln_tune",
            "mln_get_fields", "mln_get_state", "mln_get_bloch", "mln_set_state",
-           "mln_state_bytes", "mln_save_state", "mln_load_state", "mln_bloch_only", "mln_free",
+           "mln_state_bytes", "mln_save_state", "mln_load_state", "mln_bloch_only", "mln_bloch_only_noalloc", "mln_free",
            "mln_strerror", "mln_last_error", "mln_setup_factors", "mln_version", "mln_grad",
            "mln_chain_rule", "mln_init_batch", "mln_batch_tune", "mln_batch_configure",
            "mln_batch_get_config", "mln_batch_use_graph", "mln_batch_step", "mln_batch_run",
@@ -113,6 +113,7 @@ def load():
         "mln_save_state": ([P, P], ctypes.c_int),
         "mln_load_state": ([P, P], ctypes.c_int),
         "mln_bloch_only": ([P, _dp, ctypes.c_int64, _dp, _dp], ctypes.c_int),
+        "mln_bloch_only_noalloc": ([P, _dp, ctypes.c_int64, _dp, _dp], ctypes.c_int),
         "mln_free": ([P], None),
         "mln_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "mln_last_error": ([], ctypes.c_char_p),
@@ -363,6 +364,23 @@ class Solver:
         dp = torch.zeros((nt, nc), dtype=torch.float64, device=efield.device)
         cast = lambda t: ctypes.cast(ctypes.c_void_p(t.data_ptr()), _dp)
         _check(self._L.mln_bloch_only(self._h, cast(efield), nt, cast(pop), cast(dp)))
+        return dict(pop=pop, dp=dp)
+
+    def bloch_only_noalloc(self, efield, pop=None, dp=None):
+        """mln_bloch_only_noalloc: as bloch_only, writing into caller-owned
+        device tensors pop (nt, N, n_med) and dp (nt, n_med) (float64; either
+        may be None) with no device allocation inside the library."""
+        import torch
+        efield = efield.contiguous()
+        nt = efield.shape[0]
+        n, nc = self.problem.medium.n_levels, self.problem.grid.n_med
+        for t, shape in ((efield, (nt, nc)), (pop, (nt, n, nc)), (dp, (nt, nc))):
+            if t is None:
+                continue
+            if tuple(t.shape) != shape or t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"expected a contiguous float64 device tensor of shape {shape}")
+        cast = lambda t: ctypes.cast(ctypes.c_void_p(t.data_ptr()), _dp) if t is not None else None
+        _check(self._L.mln_bloch_only_noalloc(self._h, cast(efield), nt, cast(pop), cast(dp)))
         return dict(pop=pop, dp=dp)
 
     def grad(self, dJ_dprobe):
