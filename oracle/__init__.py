@@ -68,6 +68,12 @@ def bind(path):
                                ctypes.c_double, i64, i64, ctypes.c_double, ctypes.c_double, i64, i64,
                                ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, ctypes.c_double,
                                dp, dp, i64, dp, dp, dp, dp, ctypes.c_int]
+    L.orc_run2d.restype = ctypes.c_int
+    L.orc_run2d.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, ctypes.c_double, dp, dp,
+                            ctypes.c_double, i64, i64, i64, ctypes.c_double, ctypes.c_double,
+                            ctypes.c_double, i64, i64, i64, i64, ctypes.c_double, ctypes.c_double,
+                            ctypes.c_double, dp, ctypes.c_double, dp, dp, dp, dp, i64, dp, dp, dp,
+                            dp, dp, dp, ctypes.c_int]
     L.orc_spectral_derivative.restype = None
     L.orc_spectral_derivative.argtypes = [i64, ctypes.c_double, dp, ctypes.c_double, dp]
     L.orc_expm.restype = ctypes.c_int
@@ -254,3 +260,39 @@ def spectral_derivative(f, dx, shift):
     out = np.zeros_like(f)
     lib().orc_spectral_derivative(len(f), float(dx), _p(f), float(shift), _p(out))
     return out
+
+
+def run2d(problem, snap_every=0, nthreads=0, nt=None, ez_init=None, hx_init=None, hy_init=None):
+    """Coupled run on the 2-D TMz Yee grid (see orc_run2d).  Initial fields
+    are (ny, nx) arrays.  Returns 'probe' (nt+1, ny), 'e_snap' (nsnap, ny,
+    nx), 'pop' (nsnap, N, n_med), 'hx' and 'hy' (ny, nx: H^{nt-1/2}), 'diag'."""
+    med, g, src = problem.medium, problem.grid, problem.source
+    nt = g.nt if nt is None else nt
+    n, h0, mu, nj, jumps, rates, deph, relax, rho0 = _medium_args(med)
+    nsnap = nt // snap_every if snap_every > 0 else 0
+    probe = np.zeros((nt + 1, g.ny))
+    e_snap = np.zeros((max(nsnap, 1), g.ny, g.nx))
+    pop = np.zeros((max(nsnap, 1), n, max(g.n_med, 1)))
+    hx = np.zeros((g.ny, g.nx))
+    hy = np.zeros((g.ny, g.nx))
+    diag = np.zeros(4)
+    samples = np.ascontiguousarray(src.samples[: nt + 1], dtype=np.float64)
+    prof = np.ascontiguousarray(src.profile, dtype=np.float64)
+    if prof.shape != (g.ny,):
+        raise ValueError("profile must have ny values")
+    inits = []
+    for a in (ez_init, hx_init, hy_init):
+        if a is not None:
+            a = np.ascontiguousarray(a, dtype=np.float64)
+            if a.shape != (g.ny, g.nx):
+                raise ValueError("initial fields must be (ny, nx) arrays")
+        inits.append(a)
+    rc = lib().orc_run2d(n, _p(h0), _p(mu), nj, _p(jumps), _p(rates), deph, _p(relax), _p(rho0),
+                         float(med.density), g.nx, g.ny, nt, g.dx, g.dy, g.dt, g.mx0, g.mx1, g.my0,
+                         g.my1, g.eps_r, g.mu_r, g.sigma, _p(samples), float(src.amplitude), _p(prof),
+                         _p(inits[0]), _p(inits[1]), _p(inits[2]), snap_every, _p(e_snap), _p(pop),
+                         _p(probe), _p(hx), _p(hy), _p(diag), nthreads)
+    if rc:
+        raise RuntimeError(f"oracle 2-D run failed ({rc})")
+    return dict(probe=probe, e_snap=e_snap[:nsnap], pop=pop[:nsnap, :, : g.n_med], hx=hx, hy=hy,
+                diag=dict(trace=diag[0], herm=diag[1], min_eig=diag[2], purity=diag[3]))

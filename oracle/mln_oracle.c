@@ -32,7 +32,10 @@
  *     matrix, the jump and dephasing rates, N_a and the source amplitude;
  *   * a pseudo-spectral (PSTD) field solver on a periodic grid
  *     (orc_pstd_run): the same leapfrog and medium step with the spatial
- *     derivatives taken from direct DFT sums.
+ *     derivatives taken from direct DFT sums;
+ *   * the same medium step on a two-dimensional TMz Yee grid (orc_run2d),
+ *     the extension past the one-dimensional models the paper restricts
+ *     itself to (Conclusion).
  *
  * Readings of points the paper leaves open (same on the GPU side, but written
  * independently there):
@@ -520,6 +523,126 @@ int orc_run(int n, const double *h0, const double *mu, int n_jump, const double 
     }
     if (h_out) memcpy(h_out, H, sizeof(double) * (nx - 1));   /* H^{nt-1/2} */
     free(rho); free(r0); free(E); free(H); free(P);
+    medium_free(&m);
+    return 0;
+}
+
+/* ----------------------------------------------------------------------- */
+/* two-dimensional TMz run: the same medium step on a 2-D Yee grid           */
+/*
+ * The paper restricts itself to one spatial dimension (Conclusion); this is
+ * the same scheme on the 2-D transverse-magnetic Yee grid (E_z at cell
+ * centres (i, j), H_x at (i, j + 1/2), H_y at (i + 1/2, j), all arrays row
+ * major with index j * nx + i) with the medium step of every cell unchanged:
+ *   H_x += -dt/(mu dy) (E_z(i, j+1) - E_z(i, j))      (every column, j + 1
+ *                                                        taken modulo ny)
+ *   H_y += dt/(mu dx) (E_z(i+1, j) - E_z(i, j))        (i = 0 .. nx-2)
+ *   medium cells: Strang step with E_z(i, j), dP/dt  (as in orc_run)
+ *   E_z = ca E_z + cb (-dP/dt + (H_y(i) - H_y(i-1))/dx
+ *                             - (H_x(j) - H_x(j-1))/dy)  (i = 1 .. nx-2)
+ * Boundaries: periodic in y; a hard source column E_z(0, j) =
+ * amp * src[n] * prof[j]; a first-order Mur boundary (normal incidence, the
+ * coefficient of orc_run) on column nx-1.  The medium fills the rectangle
+ * [mx0, mx1) x [my0, my1) with 1 <= mx0 <= mx1 <= nx-1, 0 <= my0 <= my1 <=
+ * ny; its cells are numbered row major within the rectangle.  Records:
+ * snapshot s holds E_z^{(s+1)k} (ny x nx) and the populations of
+ * rho^{(s+1)k-1/2} ([s][a][cell]); probe[n * ny + j] = E_z^n(nx-1, j).
+ * Optional initial fields replace the zero fields (ez_init including the
+ * source column); hx_out and hy_out receive H^{nt-1/2}.
+ */
+int orc_run2d(int n, const double *h0, const double *mu, int n_jump, const double *jump,
+              const double *rate, double deph, const double *relax, const double *rho0,
+              double Na, int64_t nx, int64_t ny, int64_t nt, double dx, double dy, double dt,
+              int64_t mx0, int64_t mx1, int64_t my0, int64_t my1,
+              double eps_r, double mu_r, double sigma, const double *src, double amp,
+              const double *prof, const double *ez_init, const double *hx_init,
+              const double *hy_init, int64_t snap_every, double *e_snap, double *pop_snap,
+              double *probe, double *hx_out, double *hy_out, double *diag, int nthreads)
+{
+    if (n < 2 || nx < 3 || ny < 1 || nt < 0 || mx0 < 1 || mx1 < mx0 || mx1 > nx - 1 ||
+        my0 < 0 || my1 < my0 || my1 > ny)
+        return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    medium_t m;
+    if (medium_init(&m, n, h0, mu, n_jump, jump, rate, deph, relax, dt)) return -2;
+    int n2 = n * n;
+    int64_t mw = mx1 - mx0, nmed = mw * (my1 - my0), ncell = nx * ny;
+    cx *rho = (cx *)malloc(sizeof(cx) * (size_t)(nmed ? nmed : 1) * n2);
+    cx *r0 = load_cx(rho0, n2);
+    for (int64_t c = 0; c < nmed; ++c) memcpy(rho + c * n2, r0, sizeof(cx) * n2);
+    double pur0 = purity_of(n, r0);
+    double *E = (double *)calloc(ncell, sizeof(double));
+    double *Hx = (double *)calloc(ncell, sizeof(double));
+    double *Hy = (double *)calloc(ncell, sizeof(double));
+    double *P = (double *)calloc(nmed ? nmed : 1, sizeof(double));
+    double *eo = (double *)malloc(sizeof(double) * 2 * ny);  /* E(nx-2), E(nx-1) before the step */
+    double eps = ORC_EPS0 * eps_r, muu = ORC_MU0 * mu_r;
+    double cl = 1.0 / sqrt(eps * muu);
+    double kmur = (cl * dt - dx) / (cl * dt + dx);
+    double sg = sigma * dt / (2.0 * eps);
+    double ca = (1.0 - sg) / (1.0 + sg), cb = (dt / eps) / (1.0 + sg);
+    double chx = dt / (muu * dx), chy = dt / (muu * dy);
+    for (int64_t j = 0; j < ny; ++j) E[j * nx] = amp * src[0] * prof[j];
+    if (ez_init) memcpy(E, ez_init, sizeof(double) * ncell);
+    if (hx_init) memcpy(Hx, hx_init, sizeof(double) * ncell);
+    if (hy_init) memcpy(Hy, hy_init, sizeof(double) * ncell);
+    if (probe)
+        for (int64_t j = 0; j < ny; ++j) probe[j] = E[j * nx + nx - 1];
+    if (diag) { diag[0] = 0; diag[1] = 0; diag[2] = 1e300; diag[3] = 0; }
+    for (int64_t t = 0; t < nt; ++t) {
+        for (int64_t j = 0; j < ny; ++j) {
+            int64_t jp = (j + 1) % ny;
+            for (int64_t i = 0; i < nx; ++i) Hx[j * nx + i] -= chy * (E[jp * nx + i] - E[j * nx + i]);
+            for (int64_t i = 0; i + 1 < nx; ++i) Hy[j * nx + i] += chx * (E[j * nx + i + 1] - E[j * nx + i]);
+        }
+#pragma omp parallel
+        {
+            cell_ws_t ws;
+            ws_alloc(&ws, n);
+#pragma omp for schedule(static)
+            for (int64_t c = 0; c < nmed; ++c) {
+                int64_t i = mx0 + c % mw, j = my0 + c / mw;
+                P[c] = cell_step(&m, rho + c * n2, E[j * nx + i], dt, Na, &ws);
+            }
+            ws_free(&ws);
+        }
+        for (int64_t j = 0; j < ny; ++j) {
+            eo[2 * j] = E[j * nx + nx - 2];
+            eo[2 * j + 1] = E[j * nx + nx - 1];
+        }
+        for (int64_t j = 0; j < ny; ++j) {
+            int64_t jm = (j + ny - 1) % ny;
+            for (int64_t i = 1; i + 1 < nx; ++i) {
+                double dp = 0.0;
+                if (i >= mx0 && i < mx1 && j >= my0 && j < my1) dp = P[(j - my0) * mw + (i - mx0)];
+                double curl = (Hy[j * nx + i] - Hy[j * nx + i - 1]) / dx -
+                              (Hx[j * nx + i] - Hx[jm * nx + i]) / dy;
+                E[j * nx + i] = ca * E[j * nx + i] + cb * (-dp + curl);
+            }
+        }
+        for (int64_t j = 0; j < ny; ++j) {
+            E[j * nx] = amp * src[t + 1] * prof[j];
+            E[j * nx + nx - 1] = eo[2 * j] + kmur * (E[j * nx + nx - 2] - eo[2 * j + 1]);
+        }
+        if (probe)
+            for (int64_t j = 0; j < ny; ++j) probe[(t + 1) * ny + j] = E[j * nx + nx - 1];
+        if (snap_every > 0 && (t + 1) % snap_every == 0) {
+            int64_t s = (t + 1) / snap_every - 1;
+            if (e_snap) memcpy(e_snap + s * ncell, E, sizeof(double) * ncell);
+            for (int64_t c = 0; c < nmed; ++c) {
+                const cx *r = rho + c * n2;
+                if (pop_snap)
+                    for (int a = 0; a < n; ++a)
+                        pop_snap[(s * n + a) * nmed + c] = creal(r[a * n + a]);
+                if (diag) check_rho(n, r, pur0, diag);
+            }
+        }
+    }
+    if (hx_out) memcpy(hx_out, Hx, sizeof(double) * ncell);
+    if (hy_out) memcpy(hy_out, Hy, sizeof(double) * ncell);
+    free(rho); free(r0); free(E); free(Hx); free(Hy); free(P); free(eo);
     medium_free(&m);
     return 0;
 }

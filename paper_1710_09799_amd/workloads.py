@@ -431,3 +431,96 @@ def random_problem(n, seed, nx=48, nt=300, relax=True, med=None):
     src = Source(samples=gauss_pulse(nt, DT0, OMEGA0, sig, 4.0 * sig),
                  amplitude=float(rng.uniform(1e9, 3e9)))
     return Problem(f"random_n{n}_s{seed}", medium, grid, src)
+
+
+# ---------------------------------------------------------------------------
+# two-dimensional (TMz) problems: the paper's scheme is one-dimensional
+# (Conclusion names the restriction); these extend the grid to x-y with the
+# same medium step in every cell
+
+
+@dataclasses.dataclass
+class Grid2D:
+    """2-D TMz Yee grid: E_z at cell centres (i, j), H_x at (i, j + 1/2),
+    H_y at (i + 1/2, j); arrays row major (index j * nx + i).  Periodic in y;
+    column 0 carries the hard source (amplitude * samples[n] * profile[j]),
+    column nx-1 a first-order Mur boundary and the probe.  The medium fills
+    the rectangle [mx0, mx1) x [my0, my1), 1 <= mx0 <= mx1 <= nx-1."""
+
+    nx: int
+    ny: int
+    nt: int
+    dx: float
+    dy: float
+    dt: float
+    mx0: int
+    mx1: int
+    my0: int
+    my1: int
+    eps_r: float = 1.0
+    mu_r: float = 1.0
+    sigma: float = 0.0
+
+    @property
+    def n_med(self) -> int:
+        return (self.mx1 - self.mx0) * (self.my1 - self.my0)
+
+
+@dataclasses.dataclass
+class Source2D:
+    """Hard source column: E_z(0, j, step n) = amplitude * samples[n] * profile[j]."""
+
+    samples: np.ndarray
+    amplitude: float
+    profile: np.ndarray
+
+
+@dataclasses.dataclass
+class Problem2D:
+    name: str
+    medium: Medium
+    grid: Grid2D
+    source: Source2D
+
+
+def gaussian_profile(ny, centre, width):
+    """Transverse beam profile exp(-((j - centre) / width)^2 / 2), periodic
+    distance in j."""
+    j = np.arange(ny, dtype=np.float64)
+    u = (j - centre + 0.5 * ny) % ny - 0.5 * ny
+    return np.exp(-0.5 * (u / width) ** 2)
+
+
+def three_level_2d(nx=2048, ny=512, nt=4096, name="three_level_2d_beam"):
+    """The three-level ladder medium of three_level() on a 2-D grid of
+    nx x ny square cells of lambda0/40 (Courant number c dt/dx = 0.5, 0.71 of
+    the 2-D stability limit), the medium on columns [nx/8, 7nx/8) over the
+    full height; a Gaussian beam (profile width ny/8 cells, centred) carrying
+    a Gaussian pulse of 50 fs envelope FWHM at omega0, centred at 3 FWHM,
+    with the pi-pulse amplitude of the 1-D case for that width."""
+    mu01 = 1e-29
+    med = ladder_medium([0.0, HBAR * OMEGA0, 2.1 * HBAR * OMEGA0], [mu01, 0.8e-29],
+                        density=1e24, decay=1e12, dephasing=5e12)
+    sig = 50e-15 / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+    e0 = math.pi * HBAR / (mu01 * sig * math.sqrt(2.0 * math.pi))
+    grid = Grid2D(nx=nx, ny=ny, nt=nt, dx=DX0, dy=DX0, dt=DT0, mx0=nx // 8, mx1=7 * nx // 8,
+                  my0=0, my1=ny)
+    src = Source2D(samples=gauss_pulse(nt, DT0, OMEGA0, sig, 150e-15), amplitude=e0,
+                   profile=gaussian_profile(ny, ny / 2, ny / 8))
+    return Problem2D(name, med, grid, src)
+
+
+def random_problem_2d(n, seed, nx=64, ny=24, nt=200, relax=True, rect=None):
+    """Short 2-D run: random medium (random_medium) on a rectangle (default
+    [nx/4, 3nx/4) x [ny/4, 3ny/4)), a random transverse profile and a strong
+    resonant pulse, so that the medium sees a field within the run."""
+    rng = np.random.default_rng(seed + 13)
+    medium = random_medium(n, seed, relax=relax)
+    x0, x1, y0, y1 = rect if rect is not None else (nx // 4, 3 * nx // 4, ny // 4, 3 * ny // 4)
+    grid = Grid2D(nx=nx, ny=ny, nt=nt, dx=DX0, dy=DX0 * float(rng.uniform(0.8, 1.25)), dt=DT0,
+                  mx0=x0, mx1=x1, my0=y0, my1=y1)
+    sig = 15 * DT0 * float(rng.uniform(1.0, 1.5))
+    prof = 0.5 + rng.uniform(0.0, 1.0, size=ny)
+    src = Source2D(samples=gauss_pulse(nt, DT0, OMEGA0, sig, 4.0 * sig),
+                   amplitude=float(rng.uniform(1e9, 3e9)), profile=prof)
+    return Problem2D(f"random2d_n{n}_s{seed}", medium, grid, src)

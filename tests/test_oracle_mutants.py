@@ -12,7 +12,10 @@ not catch them:
 * the density N_a dropped by half in dP/dt;
 * the semi-implicit conductivity with half its weight;
 * eps_r and mu_r exchanged;
-* the Mur coefficient taken with the vacuum speed of light in a host medium.
+* the Mur coefficient taken with the vacuum speed of light in a host medium;
+* in the two-dimensional run: H_x updated with the wrong sign, dx and dy
+  exchanged in the H coefficients, the y direction not wrapped, and the
+  polarisation current fed back with the wrong sign.
 
 Everything here runs on the CPU.
 """
@@ -22,6 +25,7 @@ import subprocess
 import pytest
 
 import oracle
+import test_oracle_2d as M2
 import test_oracle_media as M
 
 MUTANTS = {
@@ -43,6 +47,19 @@ MUTANTS = {
     "mur_vacuum_speed": ("double cl = 1.0 / sqrt(eps * muu);",
                          "double cl = 1.0 / sqrt(ORC_EPS0 * ORC_MU0);",
                          lambda: M.check_magic_step_in_host(oracle, 2.25, 1.0)),
+    # the two-dimensional run
+    "2d_hx_sign": ("Hx[j * nx + i] -= chy * (E[jp * nx + i] - E[j * nx + i]);",
+                   "Hx[j * nx + i] += chy * (E[jp * nx + i] - E[j * nx + i]);",
+                   lambda: M2.check_mode(oracle, 40, 1, 3.0)),
+    "2d_dx_dy_exchanged": ("double chx = dt / (muu * dx), chy = dt / (muu * dy);",
+                           "double chx = dt / (muu * dy), chy = dt / (muu * dx);",
+                           lambda: M2.check_mode(oracle, 40, 1, 3.0)),
+    "2d_no_wrap": ("int64_t jm = (j + ny - 1) % ny;",
+                   "int64_t jm = j > 0 ? j - 1 : 0;",
+                   lambda: M2.check_mode(oracle, 40, 1, 3.0)),
+    "2d_feedback_sign": ("E[j * nx + i] = ca * E[j * nx + i] + cb * (-dp + curl);",
+                         "E[j * nx + i] = ca * E[j * nx + i] + cb * (dp + curl);",
+                         lambda: M2.check_beam_energy(oracle)),
 }
 
 
