@@ -446,6 +446,74 @@ int mln_pstd_get_fields(mln_pstd *p, int32_t inst, double *E, double *H);
 
 void mln_pstd_free(mln_pstd *p);
 
+/* ---- two-dimensional TMz grid ------------------------------------------ */
+/* The paper's models are one-dimensional (Conclusion names the restriction).
+ * Here the same medium step (the rotation route of Sec. 4.1-4.2, every
+ * medium cell as in mln_init) sits on the 2-D transverse-magnetic Yee grid:
+ * E_z at cell centres (i, j), H_x at (i, j + 1/2), H_y at (i + 1/2, j),
+ * the 2-D form of Eq. maxwell
+ *   H_x -= dt/(mu dy) dE_z/dy,  H_y += dt/(mu dx) dE_z/dx,
+ *   E_z  = ca E_z + cb (-dP/dt + dH_y/dx - dH_x/dy)   (semi-implicit sigma),
+ * periodic in y, a hard source column E_z(0, j) = amplitude * samples[n] *
+ * profile[j], a first-order Mur boundary (normal incidence) on column nx-1.
+ * Every field array is ny x nx, row major (index j * nx + i); H_y on column
+ * nx-1 is unused.
+ *
+ *   medium   N in {2, 3, 4, 6}; the same medium in every medium cell
+ *   grid     nx >= 3, ny >= 1, nt >= 0, dx, dy, dt > 0; the medium fills the
+ *            rectangle [mx0, mx1) x [my0, my1) with 1 <= mx0 <= mx1 <= nx-1,
+ *            0 <= my0 <= my1 <= ny (its nmed cells numbered row major);
+ *            eps_r, mu_r > 0, sigma >= 0.  Stability needs
+ *            c dt sqrt(1/dx^2 + 1/dy^2) <= 1, c = 1/sqrt(eps mu): else
+ *            MLN_ECOURANT
+ *   source   samples[0..nt] (n >= nt + 1), amplitude, profile[0..ny-1]
+ *   record   DEVICE pointers (FP64), each may be NULL: probe_out
+ *            ((nt + 1) x ny: E_z(nx-1, j) at step n at [n * ny + j]),
+ *            e_out (nsnap x ny x nx), pop_out (nsnap x N x nmed: rho_aa of
+ *            d^{n+1/2} as in mln_init), nsnap = nt / snap_every (0: none)
+ *   precision MLN_FP64, MLN_FP32 or MLN_FP32_COMP (MLN_ENOTSUPPORTED else)
+ *   stream   hipStream_t for all device work, NULL = the default stream
+ * One kernel launch per time step (64 x 4 cells per workgroup, the Bloch
+ * state streamed from and to device memory each step).  Inputs are copied;
+ * records stay owned by the caller.  Errors: MLN_EINVAL, MLN_ECOURANT,
+ * MLN_ENOTSUPPORTED, the medium errors of mln_init, MLN_ENOMEM, MLN_EHIP;
+ * on error *out is set to NULL. */
+typedef struct {
+  int64_t nx, ny, nt;
+  double dx, dy, dt;
+  int64_t mx0, mx1, my0, my1;
+  double eps_r, mu_r, sigma;
+} mln_tmz_grid;
+typedef struct {
+  const double *samples;
+  int64_t n;
+  double amplitude;
+  const double *profile;
+} mln_tmz_source;
+typedef struct {
+  int64_t snap_every;
+  double *pop_out, *e_out, *probe_out;
+} mln_tmz_record;
+typedef struct mln_tmz mln_tmz;
+int mln_tmz_init(const mln_medium *medium, const mln_tmz_grid *grid, const mln_tmz_source *source,
+                 const mln_tmz_record *record, int32_t precision, void *stream, mln_tmz **out);
+/* Advance min(n_steps, nt - current step) steps; asynchronous on the stream. */
+int mln_tmz_step(mln_tmz *t, int64_t n_steps);
+/* The remaining steps, then synchronise. */
+int mln_tmz_run(mln_tmz *t);
+/* Back to step 0 (initial fields and state); synchronises. */
+int mln_tmz_reset(mln_tmz *t);
+int mln_tmz_current_step(const mln_tmz *t, int64_t *step);
+/* Replace E_z (at the current step n) and/or H_x, H_y (at n - 1/2): host
+ * arrays of ny x nx values, each may be NULL; non-finite values give
+ * MLN_EINVAL.  At step 0 the probe's first row is rewritten from the new
+ * E_z.  Synchronises. */
+int mln_tmz_set_fields(mln_tmz *t, const double *Ez, const double *Hx, const double *Hy);
+/* E_z at the current step and H_x, H_y half a step earlier, into host arrays
+ * of ny x nx values (each may be NULL).  Synchronises. */
+int mln_tmz_get_fields(mln_tmz *t, double *Ez, double *Hx, double *Hy);
+void mln_tmz_free(mln_tmz *t);
+
 /* ---- one-time factors (host only, no GPU needed) ---------------------- */
 
 /* The FP64 quantities built once per medium and time step.  D = N^2-1,

@@ -147,6 +147,11 @@ int upload_factors(const Factors &f, int route, double dt, DevBuf &fac, DevBuf &
 
 // Fill h->fc32 and h->h_scale32 from h->fd_coef.
 void tune_fp32_coefs(mln_handle *h);
+// Single-precision H coefficient ch32 and 1/dx (inv_dx32) within 256 ulps of
+// their rounded values whose product with the rounded cb is closest to the
+// FP64 product ch * cb * inv_dx (the Yee scheme's phase velocity); H is then
+// carried scaled by ch32 / ch.
+void courant_pair32(double ch, double cb, double inv_dx, float &ch32, float &inv_dx32);
 
 template <typename Real>
 inline FwdArgs<Real> make_args(mln_handle *h, const FacDev<Real> &fd, int64_t step0, int nsteps,

@@ -76,31 +76,35 @@ int mln::set_err(int code, const std::string &msg) {
 // product with cb is closest to the FP64 value (typically within 1e-10).
 // inv_dx appears nowhere else; a different ch rescales the carried H, which
 // mln_get_fields undoes.
-void mln::tune_fp32_coefs(mln_handle *h) {
-  const double *c = h->fd_coef;
-  for (int i = 0; i < 6; ++i) h->fc32[i] = (float)c[i];
-  const long double target = (long double)c[0] * c[2] * c[3];
-  const float cb = h->fc32[2];
-  float best_ch = h->fc32[0], best_idx = h->fc32[3];
-  long double best = std::fabs((long double)best_ch * best_idx * cb - target);
+void mln::courant_pair32(double ch, double cb, double inv_dx, float &ch32, float &inv_dx32) {
+  const long double target = (long double)ch * cb * inv_dx;
+  const float cbf = (float)cb;
+  float best_ch = (float)ch, best_idx = (float)inv_dx;
+  long double best = std::fabs((long double)best_ch * best_idx * cbf - target);
   constexpr int K = 256;
-  float ch = h->fc32[0];
-  for (int i = 0; i < K; ++i) ch = std::nextafter(ch, 0.0f);
-  for (int i = -K; i <= K; ++i, ch = std::nextafter(ch, 2.0f * ch)) {
-    float idx = h->fc32[3];
+  float c = (float)ch;
+  for (int i = 0; i < K; ++i) c = std::nextafter(c, 0.0f);
+  for (int i = -K; i <= K; ++i, c = std::nextafter(c, 2.0f * c)) {
+    float idx = (float)inv_dx;
     for (int j = 0; j < K; ++j) idx = std::nextafter(idx, 0.0f);
     for (int j = -K; j <= K; ++j, idx = std::nextafter(idx, 2.0f * idx)) {
-      const long double e = std::fabs((long double)ch * idx * cb - target);
+      const long double e = std::fabs((long double)c * idx * cbf - target);
       if (e < best) {
         best = e;
-        best_ch = ch;
+        best_ch = c;
         best_idx = idx;
       }
     }
   }
-  h->fc32[0] = best_ch;
-  h->fc32[3] = best_idx;
-  h->h_scale32 = c[0] / (double)best_ch;
+  ch32 = best_ch;
+  inv_dx32 = best_idx;
+}
+
+void mln::tune_fp32_coefs(mln_handle *h) {
+  const double *c = h->fd_coef;
+  for (int i = 0; i < 6; ++i) h->fc32[i] = (float)c[i];
+  courant_pair32(c[0], c[2], c[3], h->fc32[0], h->fc32[3]);
+  h->h_scale32 = c[0] / (double)h->fc32[0];
 }
 
 // Upload the factors of the chosen route in precision Real.  The layout of

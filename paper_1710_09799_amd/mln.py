@@ -59,6 +59,23 @@ class _Options(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("ckpt_every", ctypes.c_int32), ("variant", ctypes.c_int32)]
 
 
+class _TmzGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nt", ctypes.c_int64),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dt", ctypes.c_double),
+                ("mx0", ctypes.c_int64), ("mx1", ctypes.c_int64), ("my0", ctypes.c_int64),
+                ("my1", ctypes.c_int64), ("eps_r", ctypes.c_double), ("mu_r", ctypes.c_double),
+                ("sigma", ctypes.c_double)]
+
+
+class _TmzSource(ctypes.Structure):
+    _fields_ = [("samples", _dp), ("n_samples", ctypes.c_int64), ("amplitude", ctypes.c_double),
+                ("profile", _dp)]
+
+
+class _TmzRecord(ctypes.Structure):
+    _fields_ = [("snap_every", ctypes.c_int64), ("pop_out", _dp), ("e_out", _dp), ("probe_out", _dp)]
+
+
 class _Grads(ctypes.Structure):
     _fields_ = [(n, _dp) for n in ("d_h0", "d_dipole", "d_jump_rate", "d_dephasing", "d_amplitude",
                                    "d_density")]
@@ -79,7 +96,8 @@ EXPORTS = ["mln_init", "mln_step", "mln_run", "mln_reset", "mln_current_step", "
            "mln_batch_reset", "mln_batch_instance", "mln_batch_free", "mln_measure_step_floor",
            "mln_measure_fma_rate", "mln_pstd_init", "mln_pstd_configure", "mln_pstd_get_config",
            "mln_pstd_step", "mln_pstd_run", "mln_pstd_reset", "mln_pstd_current_step", "mln_pstd_get_fields",
-           "mln_pstd_free"]
+           "mln_pstd_free", "mln_tmz_init", "mln_tmz_step", "mln_tmz_run", "mln_tmz_reset",
+           "mln_tmz_current_step", "mln_tmz_set_fields", "mln_tmz_get_fields", "mln_tmz_free"]
 
 _lib = None
 
@@ -148,6 +166,15 @@ def load():
         "mln_pstd_current_step": ([P, i64p], ctypes.c_int),
         "mln_pstd_get_fields": ([P, ctypes.c_int32, _dp, _dp], ctypes.c_int),
         "mln_pstd_free": ([P], None),
+        "mln_tmz_init": ([ctypes.POINTER(_Medium), ctypes.POINTER(_TmzGrid), ctypes.POINTER(_TmzSource),
+                          ctypes.POINTER(_TmzRecord), ctypes.c_int32, P, ctypes.POINTER(P)], ctypes.c_int),
+        "mln_tmz_step": ([P, ctypes.c_int64], ctypes.c_int),
+        "mln_tmz_run": ([P], ctypes.c_int),
+        "mln_tmz_reset": ([P], ctypes.c_int),
+        "mln_tmz_current_step": ([P, i64p], ctypes.c_int),
+        "mln_tmz_set_fields": ([P, _dp, _dp, _dp], ctypes.c_int),
+        "mln_tmz_get_fields": ([P, _dp, _dp, _dp], ctypes.c_int),
+        "mln_tmz_free": ([P], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -602,6 +629,104 @@ class Pstd:
             self.close()
         except Exception:
             pass
+
+
+class Tmz:
+    """One problem on the two-dimensional TMz grid (mln_tmz_init): a
+    workloads.Problem2D.  Outputs (torch float64 device tensors) after run():
+    probe (nt+1, ny), e_snap (nsnap, ny, nx), pop (nsnap, N, n_med)."""
+
+    def __init__(self, problem, precision="fp64", snap_every=0, record_probe=True, record_pop=True,
+                 record_e=True):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("Tmz needs a HIP device")
+        L = load()
+        self._L = L
+        self.problem = problem
+        med, g, src = problem.medium, problem.grid, problem.source
+        n = med.n_levels
+        nsnap = g.nt // snap_every if snap_every > 0 else 0
+        dev = torch.device("cuda")
+        self.probe = torch.zeros((g.nt + 1, g.ny), dtype=torch.float64, device=dev) if record_probe else None
+        self.e_snap = (torch.zeros((nsnap, g.ny, g.nx), dtype=torch.float64, device=dev)
+                       if (record_e and nsnap) else None)
+        self.pop = (torch.zeros((nsnap, n, g.n_med), dtype=torch.float64, device=dev)
+                    if (record_pop and nsnap) else None)
+        self._ma = _MediumArgs(med)
+        self._samples = np.ascontiguousarray(src.samples, dtype=np.float64)
+        self._prof = np.ascontiguousarray(src.profile, dtype=np.float64)
+        if self._prof.shape != (g.ny,):
+            raise ValueError("the source profile needs ny values")
+        gs = _TmzGrid(g.nx, g.ny, g.nt, g.dx, g.dy, g.dt, g.mx0, g.mx1, g.my0, g.my1, g.eps_r, g.mu_r,
+                      g.sigma)
+        ss = _TmzSource(_ptr(self._samples), len(self._samples), float(src.amplitude), _ptr(self._prof))
+        rs = _TmzRecord(snap_every, _dptr(self.pop), _dptr(self.e_snap), _dptr(self.probe))
+        self.stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(L.mln_tmz_init(ctypes.byref(self._ma.s), ctypes.byref(gs), ctypes.byref(ss), ctypes.byref(rs),
+                              PRECISIONS[precision], ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+
+    def step(self, n):
+        _check(self._L.mln_tmz_step(self._h, int(n)))
+
+    def run(self):
+        _check(self._L.mln_tmz_run(self._h))
+        return self.outputs()
+
+    def reset(self):
+        _check(self._L.mln_tmz_reset(self._h))
+
+    def current_step(self):
+        s = ctypes.c_int64()
+        _check(self._L.mln_tmz_current_step(self._h, ctypes.byref(s)))
+        return s.value
+
+    def outputs(self):
+        return dict(probe=self.probe, e_snap=self.e_snap, pop=self.pop)
+
+    def set_fields(self, Ez=None, Hx=None, Hy=None):
+        g = self.problem.grid
+        arrs = []
+        for a in (Ez, Hx, Hy):
+            if a is not None:
+                a = np.ascontiguousarray(a, dtype=np.float64)
+                if a.shape != (g.ny, g.nx):
+                    raise ValueError(f"fields need shape ({g.ny}, {g.nx})")
+            arrs.append(a)
+        _check(self._L.mln_tmz_set_fields(self._h, *(_ptr(a) for a in arrs)))
+
+    def fields(self):
+        """E_z (current step), H_x and H_y (half a step earlier), (ny, nx) each."""
+        g = self.problem.grid
+        out = [np.zeros((g.ny, g.nx)) for _ in range(3)]
+        _check(self._L.mln_tmz_get_fields(self._h, *(_ptr(a) for a in out)))
+        return tuple(out)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.mln_tmz_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tmz_run(problem, precision="fp64", snap_every=0, ez_init=None, hx_init=None, hy_init=None, **kw):
+    """Convenience: one 2-D problem run to the end (optionally from given
+    initial fields); outputs as numpy arrays plus the final 'ez', 'hx', 'hy'."""
+    s = Tmz(problem, precision=precision, snap_every=snap_every, **kw)
+    if ez_init is not None or hx_init is not None or hy_init is not None:
+        s.set_fields(ez_init, hx_init, hy_init)
+    out = s.run()
+    res = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+    res["ez"], res["hx"], res["hy"] = s.fields()
+    s.close()
+    return res
 
 
 def pstd_run(problem, e_init=None, h_init=None, snap_every=0, **kw):
