@@ -162,7 +162,12 @@ typedef struct {
                                   (one cell per thread, LDS exchange), 2 wavefront
                                   tile (rotation route; tile/64 cells per lane),
                                   3 quad tile (rotation route, N <= 3; four lanes
-                                  per cell, tile = cells per workgroup).
+                                  per cell, tile = cells per workgroup), 4
+                                  streamed (rotation route, FP64 / FP32 /
+                                  compensated FP32: one time step per launch,
+                                  one thread per cell, tile 0 or 256, steps per
+                                  launch 0 or 1; state, E and H read from and
+                                  written to device memory every step).
                                   Automatic: quad for N <= 3 on grids below 1e5
                                   cells (latency-bound sizes), workgroup tile on
                                   larger ones; N = 4: wavefront tile; N = 6:
@@ -213,7 +218,8 @@ int mln_reset(mln_handle *h);
 int mln_current_step(const mln_handle *h, int64_t *step);
 
 /* The kernel configuration the handle runs: variant (1 workgroup tile, 2
- * wavefront tile, 3 four lanes per cell; the automatic choice resolved),
+ * wavefront tile, 3 four lanes per cell, 4 streamed; the automatic choice
+ * resolved),
  * cells per tile and time steps per launch.  Any pointer may be NULL. */
 int mln_get_config(const mln_handle *h, int32_t *variant, int32_t *tile, int32_t *steps_per_launch);
 
@@ -224,7 +230,7 @@ int mln_get_config(const mln_handle *h, int32_t *variant, int32_t *tile, int32_t
 int mln_configure(mln_handle *h, int32_t variant, int32_t tile, int32_t steps_per_launch);
 
 /* Autotuner for one problem: time every kernel configuration the handle's
- * level count, precision and route allow (variants 1-3, several tile shapes)
+ * level count, precision and route allow (variants 1-4, several tile shapes)
  * on the problem itself, about trial_steps steps each from step 0 with
  * nothing recorded (HIP events on the handle's stream), keep the fastest per
  * time step and return the handle to step 0 with it.  The choice is returned

@@ -13,6 +13,8 @@ constexpr int kMaxTile = 256;      // threads (= cells) per tile workgroup
 constexpr int kMaxQuadTile = 256;  // cells per tile of the four-lanes-per-cell kernel
 constexpr int64_t kQuadMaxAutoCells = 100000;  // automatic variant: quad kernel below this grid size
 constexpr int kMaxStepsPerLaunch = 128;  // time steps fused into one launch (halo <= tile/2 < 128)
+constexpr int kStreamThreads = 256;       // threads per workgroup of the streamed kernel
+constexpr int kStreamCells = 1;           // consecutive cells per thread of the streamed kernel
 constexpr int kPadeMax = 7;              // highest Pade degree of the per-step Pade route
 constexpr size_t kPadeMaxLds = 160 * 1024;  // LDS of one compute unit
 
@@ -139,6 +141,12 @@ hipError_t launch_fwd_pade(int N, const FwdArgs<Real> &a, int64_t nblocks, hipSt
 template <typename Real>
 hipError_t launch_bloch_pade(int N, const BlochArgs<Real> &a, hipStream_t st);
 size_t pade_lds_bytes(int N, int real_bytes, int W);
+
+// Streamed one-step kernel of the rotation route (fwd_stream.hpp): one launch
+// per time step (a.nsteps must be 1), one thread per cell; N = 2, 3, 4, 6;
+// FP64, FP32 or the compensated FP32 state (plain fields).
+template <typename Real>
+hipError_t launch_fwd_stream(int N, bool comp, const FwdArgs<Real> &a, hipStream_t st);
 
 // Four-lanes-per-cell tile kernel of the rotation route (fwd_quad.hpp), N <= 3;
 // W cells per tile (W in 64..256, multiple of 16), 4 W threads.

@@ -74,17 +74,12 @@ hipError_t launch_fwd_quad_n3(bool comp, bool cf, int W, const FwdArgs<Real> &a,
   if (cf && !comp) return hipErrorInvalidValue;
   if (comp) {
     if constexpr (std::is_same<Real, float>::value) {
-      if (cf)
-        hipLaunchKernelGGL((fwd_quad_kernel<3, float, true, true>), dim3((unsigned)nblocks), dim3(4 * W), 0, st, a);
-      else
-        hipLaunchKernelGGL((fwd_quad_kernel<3, float, true>), dim3((unsigned)nblocks), dim3(4 * W), 0, st, a);
-    } else {
-      return hipErrorInvalidValue;
+      if (cf) return launch_quad<3, float, true, true>(W, a, nblocks, st);
+      return launch_quad<3, float, true, false>(W, a, nblocks, st);
     }
-  } else {
-    hipLaunchKernelGGL((fwd_quad_kernel<3, Real, false>), dim3((unsigned)nblocks), dim3(4 * W), 0, st, a);
+    return hipErrorInvalidValue;
   }
-  return hipGetLastError();
+  return launch_quad<3, Real, false, false>(W, a, nblocks, st);
 }
 
 template <typename Real>

@@ -330,9 +330,41 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
 }
 
 // COMP: compensated (float-float) state; CF: E and H as float-float pairs too.
-template <int N, typename Real, bool COMP, bool CF = false>
-__global__ void __launch_bounds__(1024) fwd_quad_kernel(FwdArgs<Real> a) {
+// LB: the launch bound the instance is compiled for (lanes per workgroup).
+// The LB = 512 instance may use up to 256 VGPRs per lane, which keeps the
+// FP64 and two-float-field step loops free of spills but leaves room for
+// one such workgroup per compute unit; LB = 1024 (at most 128 VGPRs) lets
+// two 512-lane workgroups share a compute unit.
+template <int N, typename Real, bool COMP, bool CF = false, int LB = 1024>
+__global__ void __launch_bounds__(LB) fwd_quad_kernel(FwdArgs<Real> a) {
   quad_tile<N, Real, COMP, CF>(a, blockIdx.x);
+}
+
+// Compute units of the current device (cached per device).
+inline int quad_device_cus() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cache[dev]) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    cache[dev] = cus;
+  }
+  return cache[dev];
+}
+
+// The LB = 512 instance for tiles of at most 128 cells when every tile has a
+// compute unit of its own, for the instances whose LB = 1024 build spills
+// (FP64 and two-float fields at N = 3: 36 and 20 bytes per lane; the
+// compensated-FP32 state fits 128 VGPRs and runs faster there); else LB = 1024.
+template <int N, typename Real, bool COMP, bool CF>
+hipError_t launch_quad(int W, const FwdArgs<Real> &a, int64_t nblocks, hipStream_t st) {
+  constexpr bool wide = std::is_same<Real, double>::value || CF;
+  if (wide && 4 * W <= 512 && nblocks <= quad_device_cus())
+    hipLaunchKernelGGL((fwd_quad_kernel<N, Real, COMP, CF, 512>), dim3((unsigned)nblocks), dim3(4 * W), 0, st, a);
+  else
+    hipLaunchKernelGGL((fwd_quad_kernel<N, Real, COMP, CF, 1024>), dim3((unsigned)nblocks), dim3(4 * W), 0, st, a);
+  return hipGetLastError();
 }
 
 }  // namespace mln

@@ -87,6 +87,7 @@ struct mln_handle {
   int W = 256, halo = 0, owned = 0;  // cells per tile, halo = max steps per launch
   bool wave = false;                  // single-wavefront tile kernel (W = 64 * C cells)
   bool quad = false;                  // four-lanes-per-cell tile kernel (W cells, 4 W threads)
+  bool streamed = false;              // one step per launch, state streamed through HBM
   int64_t ntiles = 0;
   int rs = 8;  // bytes per real of the state
   // device state (ping-pong)

@@ -263,7 +263,15 @@ int forward_steps(mln_handle *h, int64_t n, bool record, void *tape, int64_t tap
       k = std::min<int64_t>(k, h->ckpt_every - r);
     }
     hipError_t e;
-    if (h->prec == MLN_FP64) {
+    if (h->streamed) {
+      if (h->prec == MLN_FP64) {
+        auto args = make_args<double>(h, h->fd, h->step, 1, record, (double *)tape, tape_step0);
+        e = launch_fwd_stream<double>(h->f.N, false, args, h->stream);
+      } else {
+        auto args = make_args<float>(h, h->ff, h->step, 1, record, (float *)tape, tape_step0);
+        e = launch_fwd_stream<float>(h->f.N, h->comp, args, h->stream);
+      }
+    } else if (h->prec == MLN_FP64) {
       auto args = make_args<double>(h, h->fd, h->step, (int)k, record, (double *)tape, tape_step0);
       e = h->quad   ? launch_fwd_quad<double>(h->f.N, false, false, h->W, args, h->ntiles, h->stream)
           : h->wave ? launch_fwd_wave<double>(h->f.N, false, h->W / 64, args, h->ntiles, h->stream)
@@ -287,9 +295,25 @@ int forward_steps(mln_handle *h, int64_t n, bool record, void *tape, int64_t tap
 // Choose and validate the forward kernel (variant 0: automatic) and its
 // tiling (0: defaults); sets the tile bookkeeping of the handle.
 int set_kernel(mln_handle *h, int variant_req, int tile, int steps_per_launch) {
-  if (variant_req < 0 || variant_req > 3) return set_err(MLN_EINVAL, "unknown kernel variant");
+  if (variant_req < 0 || variant_req > 4) return set_err(MLN_EINVAL, "unknown kernel variant");
   const bool rot = h->route == MLN_ROUTE_ROTATION;
   int variant = variant_req;
+  if (variant == 4) {
+    // streamed: one step per launch, one thread per cell
+    if (!rot || h->cf || h->mfma)
+      return set_err(MLN_ENOTSUPPORTED,
+                     "the streamed kernel runs the rotation route in FP64, FP32 or compensated FP32");
+    if ((tile != 0 && tile != kStreamThreads) || steps_per_launch > 1)
+      return set_err(MLN_EINVAL, "the streamed kernel takes tile 0 or 256 and one step per launch");
+    h->streamed = true;
+    h->quad = h->wave = false;
+    h->W = kStreamThreads;
+    h->halo = 1;
+    h->owned = kStreamThreads;
+    h->ntiles = (h->grid.nx + kStreamThreads - 1) / kStreamThreads;
+    return MLN_OK;
+  }
+  h->streamed = false;
   // automatic choice: four lanes per cell while the grid is too small to
   // fill the chip with one cell per thread (the step is latency-bound there,
   // and four lanes give four times the wavefronts); one cell per thread on
@@ -604,14 +628,17 @@ int mln_current_step(const mln_handle *h, int64_t *step) {
 
 namespace {
 struct KernelChoice {
-  bool quad, wave;
+  bool quad, wave, streamed;
   int W, halo, owned;
   int64_t ntiles;
 };
-KernelChoice save_kernel(const mln_handle *h) { return {h->quad, h->wave, h->W, h->halo, h->owned, h->ntiles}; }
+KernelChoice save_kernel(const mln_handle *h) {
+  return {h->quad, h->wave, h->streamed, h->W, h->halo, h->owned, h->ntiles};
+}
 void restore_kernel(mln_handle *h, const KernelChoice &k) {
   h->quad = k.quad;
   h->wave = k.wave;
+  h->streamed = k.streamed;
   h->W = k.W;
   h->halo = k.halo;
   h->owned = k.owned;
@@ -637,7 +664,7 @@ int mln_tune(mln_handle *h, int32_t trial_steps, int32_t *variant, int32_t *tile
   static const int cand[][3] = {{3, 64, 8},   {3, 128, 16}, {3, 128, 20}, {3, 128, 32}, {3, 256, 16},
                                 {3, 256, 32}, {1, 64, 8},   {1, 128, 8},  {1, 128, 16}, {1, 128, 32},
                                 {1, 256, 8},  {1, 256, 16}, {1, 256, 32}, {2, 64, 8},   {2, 128, 16},
-                                {2, 256, 32}};
+                                {2, 256, 32}, {4, 256, 1}};
   const KernelChoice start = save_kernel(h);
   KernelChoice best_k = start;
   double best = INFINITY;
@@ -670,7 +697,7 @@ int mln_tune(mln_handle *h, int32_t trial_steps, int32_t *variant, int32_t *tile
   const int rc2 = reset_state(h);
   if (rc) return rc;
   if (rc2) return rc2;
-  if (variant) *variant = h->quad ? 3 : (h->wave ? 2 : 1);
+  if (variant) *variant = h->streamed ? 4 : (h->quad ? 3 : (h->wave ? 2 : 1));
   if (tile) *tile = h->W;
   if (steps_per_launch) *steps_per_launch = h->halo;
   return MLN_OK;
@@ -678,7 +705,7 @@ int mln_tune(mln_handle *h, int32_t trial_steps, int32_t *variant, int32_t *tile
 
 int mln_get_config(const mln_handle *h, int32_t *variant, int32_t *tile, int32_t *steps_per_launch) {
   if (!h) return set_err(MLN_EINVAL, "null handle");
-  if (variant) *variant = h->quad ? 3 : (h->wave ? 2 : 1);
+  if (variant) *variant = h->streamed ? 4 : (h->quad ? 3 : (h->wave ? 2 : 1));
   if (tile) *tile = h->W;
   if (steps_per_launch) *steps_per_launch = h->halo;
   return MLN_OK;
@@ -1043,18 +1070,33 @@ int mln_grad(mln_handle *h, const double *dJ_dprobe, mln_grads *out) {
   const int nacc = N == 2 ? adj_nacc(2, f64) : adj_nacc(3, f64);
   const int nm = adj_moments(f64);
   const size_t rs = h->rs;
-  if (!h->partial.p) {
+  // reverse-kernel tiling: the forward kernel's, except after the streamed
+  // forward kernel (one step per launch), whose segments are reversed by the
+  // one-cell-per-thread tile kernel, 256 cells and 16 steps per launch
+  bool rquad = h->quad;
+  int rW = h->W, rhalo = h->halo, rowned = h->owned;
+  int64_t rtiles = h->ntiles;
+  if (h->streamed) {
+    rquad = false;
+    rW = kMaxTile;
+    rhalo = 16;
+    rowned = rW - 2 * rhalo;
+    rtiles = (h->grid.nx + rowned - 1) / rowned;
+  }
+  if (!h->gprobe.p) {
     for (int b = 0; b < 2; ++b) {
       HIP_TRY(h->lE[b].alloc(rs * h->grid.nx));
       HIP_TRY(h->lH[b].alloc(rs * h->grid.nx));
       HIP_TRY(h->lz[b].alloc(rs * D * h->ld));
     }
     HIP_TRY(h->tape.alloc(rs * (size_t)h->ckpt_every * (D + 1) * h->ld));
-    HIP_TRY(h->partial.alloc(sizeof(double) * h->ntiles * nacc));
     HIP_TRY(h->gprobe.alloc(sizeof(double) * (nt + 1)));
     HIP_TRY(h->samples_dev.alloc(sizeof(double) * (nt + 1)));
     HIP_TRY(hipMemcpy(h->samples_dev.p, h->samples.data(), sizeof(double) * (nt + 1), hipMemcpyHostToDevice));
   }
+  // per-tile partial sums: the tiling may have changed since an earlier call
+  // (mln_configure at step 0)
+  if (h->partial.bytes < sizeof(double) * rtiles * nacc) HIP_TRY(h->partial.alloc(sizeof(double) * rtiles * nacc));
   HIP_TRY(hipMemcpyAsync(h->gprobe.p, dJ_dprobe, sizeof(double) * (nt + 1), hipMemcpyHostToDevice, h->stream));
   for (int b = 0; b < 2; ++b) {
     HIP_TRY(hipMemsetAsync(h->lE[b].p, 0, h->lE[b].bytes, h->stream));
@@ -1072,7 +1114,7 @@ int mln_grad(mln_handle *h, const double *dJ_dprobe, mln_grads *out) {
     rc = forward_steps(h, s1 - s0, false, h->tape.p, s0, false);
     if (rc) return rc;
     for (int64_t n_hi = s1; n_hi > s0;) {
-      const int k = (int)std::min<int64_t>(h->halo, n_hi - s0);
+      const int k = (int)std::min<int64_t>(rhalo, n_hi - s0);
       hipError_t e;
       if (f64) {
         AdjArgs<double> a{};
@@ -1088,12 +1130,12 @@ int mln_grad(mln_handle *h, const double *dJ_dprobe, mln_grads *out) {
         a.gprobe = (const double *)h->gprobe.p;
         a.samples = (const double *)h->samples_dev.p;
         a.nx = h->grid.nx; a.mb = h->grid.med_begin; a.me = h->grid.med_end; a.ld = h->ld;
-        a.n_hi = n_hi; a.nsteps = k; a.halo = h->halo; a.owned = h->owned;
+        a.n_hi = n_hi; a.nsteps = k; a.halo = rhalo; a.owned = rowned;
         double cam1;
         fdtd_coefs(h, a.ch, a.ca, a.cb, a.inv_dx, a.kmur, cam1);
         a.partial = (double *)h->partial.p;
-        e = (h->quad && h->W <= 128) ? launch_adj_quad<double>(N, a, h->ntiles, h->W, h->stream)
-                    : launch_adj<double>(N, a, h->ntiles, h->W, h->stream);
+        e = (rquad && rW <= 128) ? launch_adj_quad<double>(N, a, rtiles, rW, h->stream)
+                    : launch_adj<double>(N, a, rtiles, rW, h->stream);
       } else {
         AdjArgs<float> a{};
         a.fac = h->ff;
@@ -1108,12 +1150,12 @@ int mln_grad(mln_handle *h, const double *dJ_dprobe, mln_grads *out) {
         a.gprobe = (const double *)h->gprobe.p;
         a.samples = (const double *)h->samples_dev.p;
         a.nx = h->grid.nx; a.mb = h->grid.med_begin; a.me = h->grid.med_end; a.ld = h->ld;
-        a.n_hi = n_hi; a.nsteps = k; a.halo = h->halo; a.owned = h->owned;
+        a.n_hi = n_hi; a.nsteps = k; a.halo = rhalo; a.owned = rowned;
         float cam1;
         fdtd_coefs(h, a.ch, a.ca, a.cb, a.inv_dx, a.kmur, cam1);
         a.partial = (double *)h->partial.p;
-        e = (h->quad && h->W <= 128) ? launch_adj_quad<float>(N, a, h->ntiles, h->W, h->stream)
-                    : launch_adj<float>(N, a, h->ntiles, h->W, h->stream);
+        e = (rquad && rW <= 128) ? launch_adj_quad<float>(N, a, rtiles, rW, h->stream)
+                    : launch_adj<float>(N, a, rtiles, rW, h->stream);
       }
       if (e != hipSuccess) return set_err(MLN_EHIP, std::string("adjoint launch: ") + hipGetErrorString(e));
       lc = 1 - lc;
@@ -1124,9 +1166,9 @@ int mln_grad(mln_handle *h, const double *dJ_dprobe, mln_grads *out) {
   h->step = nt;  // the forward buffers now hold an intermediate state; mln_reset before stepping again
   h->ckpt_ok = false;
   // gather: per-tile partial sums, lz'_0 summed over the medium, lE^0 at cell 0
-  std::vector<double> part(h->ntiles * nacc), acc(nacc, 0.0);
+  std::vector<double> part(rtiles * nacc), acc(nacc, 0.0);
   HIP_TRY(hipMemcpy(part.data(), h->partial.p, sizeof(double) * part.size(), hipMemcpyDeviceToHost));
-  for (int64_t t = 0; t < h->ntiles; ++t)
+  for (int64_t t = 0; t < rtiles; ++t)
     for (int i = 0; i < nacc; ++i) acc[i] += part[t * nacc + i];
   std::vector<unsigned char> zb(rs * D * h->ld), eb(rs);
   HIP_TRY(hipMemcpy(zb.data(), h->lz[lc].p, zb.size(), hipMemcpyDeviceToHost));

@@ -19,8 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libmln.so")
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32c": 2, "bf16x6": 3, "bf16x3": 4, "fp32cf": 5}
 ROUTES = {"rotation": 0, "diag": 1, "rodrigues": 2, "pade": 3}
-VARIANTS = {"auto": 0, "block": 1, "wave": 2, "quad": 3}
-_VARIANT_NAMES = {1: "block", 2: "wave", 3: "quad"}
+VARIANTS = {"auto": 0, "block": 1, "wave": 2, "quad": 3, "stream": 4}
+_VARIANT_NAMES = {1: "block", 2: "wave", 3: "quad", 4: "stream"}
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
