@@ -39,6 +39,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12}
+REPS = 5  # repetitions of every variant (the median is reported), as the paper times its runs
 CSRC = os.path.join(ROOT, "paper_1710_09799_amd", "csrc")
 # sources of the dominant kernel; the committed counter summary records their hash
 QUAD_SOURCES = ["fwd_quad.hpp", "fwd_impl.hpp", "fwd_kernels.hpp", "fwd_n3.hip"]
@@ -64,30 +65,51 @@ def source_hash(files):
     return h.hexdigest()
 
 
-def measured_traffic(precision):
-    """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 counter summary, or None when it is missing or was taken on
-    other kernel sources."""
+TMZ_SOURCES = ["fwd_tmz.hpp", "fwd_impl.hpp", "fwd_kernels.hpp", "tmz.hip"]
+STREAM_SOURCES = ["fwd_stream.hpp", "fwd_impl.hpp", "fwd_kernels.hpp", "stream.hip"]
+
+
+def measured_traffic(precision, path=None, sources=QUAD_SOURCES):
+    """HBM bytes per launch of a kernel from its committed rocprofv3 counter
+    summary (the headline kernel's by default), or None when it is missing or
+    was taken on other kernel sources."""
     try:
         kv = {}
-        with open(traffic_file(precision)) as fh:
+        with open(path or traffic_file(precision)) as fh:
             for line in fh:
                 if ":" in line:
                     k, v = line.split(":", 1)
                     kv[k.strip()] = v.strip()
-        if kv.get("kernel_source_sha256") != source_hash(QUAD_SOURCES):
+        if kv.get("kernel_source_sha256") != source_hash(sources):
             return None
         return float(kv["hbm_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
 
 
+def copy_rate(reps=REPS):
+    """Device-to-device copy of 1 GiB (torch copy_): GB/s of bytes read plus
+    written, the median of `reps` copies, as a practical reference beside the
+    8 TB/s HBM peak."""
+    import torch
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    e0, e1 = _events()
+    ts = []
+    for _ in range(reps):
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    del x, y
+    return 2 * (1 << 30) / _median(ts) / 1e9
+
+
 def _events():
     import torch
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-
-
-REPS = 5  # repetitions of every variant (the median is reported), as the paper times its runs
 
 
 def _median(v):
@@ -385,6 +407,9 @@ def tmz_beam(reps=REPS):
         out[prec] = {"value": g.n_med * g.nt / t, "paper_P": cells * g.nt / t, "us_per_step": us,
                      "alg_bytes_per_step": byts, "alg_GBps": byts / (us * 1e-6) / 1e9,
                      "hbm_frac": byts / (us * 1e-6) / 8e12}
+        tf = os.path.join(ROOT, "profiles", f"fwd_tmz_n3_{prec}_2d_beam_traffic.txt")
+        if os.path.exists(tf):
+            out[prec]["traffic_bytes_per_step"] = measured_traffic(prec, tf, TMZ_SOURCES)
         if prec != "fp64":
             out[prec]["err_probe_vs_fp64"] = rel_err(rec[prec]["probe"], rec["fp64"]["probe"])
             out[prec]["err_pop_vs_fp64"] = float(np.max(np.abs(rec[prec]["pop"] - rec["fp64"]["pop"])))
@@ -467,6 +492,8 @@ def n2_large():
             out[f"{prec}_{name}"] = {"value": p.grid.n_med * p.grid.nt / t, "launch_us": launch * 1e6,
                                      "alg_GBps": byts / launch / 1e9, "hbm_frac": byts / launch / 8e12,
                                      "alg_bytes_per_launch": byts}
+    out["fp64_stream"]["traffic_bytes_per_launch"] = measured_traffic(
+        "fp64", os.path.join(ROOT, "profiles", "fwd_stream_n2_two_level_2p24_traffic.txt"), STREAM_SOURCES)
     return out
 
 
@@ -690,6 +717,7 @@ def main():
                            "launch_shape": f"{wg} workgroups x {4 * kw['tile']} lanes"}
     # the vector FMA rate the kernels can reach (plain instructions, measured)
     res["measured_fma_tflops"] = {"fp32": mln.fma_rate(False), "fp64": mln.fma_rate(True)}
+    res["measured_copy_GBps"] = copy_rate()
     if not args.no_variants:
         # FP64 on the headline's launch shape and on the shape mln_tune picks
         # for FP64; the headline precision's own tuned shape beside it
