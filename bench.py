@@ -360,6 +360,31 @@ def variants(p3, ref64, pop64, headline):
                             "total_over_forward": (tf + tg) / t_plain,
                             "workload": "three-level ladder, 10000 cells, 50000 steps, checkpoint every 500",
                             **akw}
+    # the same with the whole forward tape kept in HBM (z' and E of every
+    # step, 18 GB): mln_grad reverses without recomputation; median of REPS
+    s = mln.Solver(pa, ckpt_every="tape", **akw)
+    s.run()
+    s.grad(2 * pa.grid.dt * s.probe.cpu().numpy())  # warm-up
+    tfs, tgs = [], []
+    for _ in range(REPS):
+        s.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = s.run()
+        torch.cuda.synchronize()
+        tfs.append(time.perf_counter() - t0)
+        gp = 2 * pa.grid.dt * out["probe"].cpu().numpy()
+        t0 = time.perf_counter()
+        s.grad(gp)
+        tgs.append(time.perf_counter() - t0)
+    s.close()
+    tf, tg = _median(tfs), _median(tgs)
+    var["adjoint_fp32c_whole_tape"] = {"forward_ms": t_plain * 1e3, "forward_with_tape_ms": tf * 1e3,
+                                       "grad_ms": tg * 1e3, "grad_over_forward": tg / t_plain,
+                                       "total_over_forward": (tf + tg) / t_plain,
+                                       "tape_GB": 9 * 10048 * pa.grid.nt * 4 / 1e9,
+                                       "workload": "three-level ladder, 10000 cells, 50000 steps, whole tape "
+                                                   "in device memory", **akw}
     return var
 
 

@@ -51,6 +51,9 @@ extern "C" {
 #define MLN_ESTATE (-10)             /* call not valid in the handle's state        */
 #define MLN_ENUMERIC (-11)           /* a one-time factorisation failed to converge */
 
+/* mln_options.ckpt_every: keep the whole forward tape instead of checkpoints */
+#define MLN_TAPE_ALL (-1)
+
 /* ---- enumerations ------------------------------------------------------ */
 typedef enum {
   MLN_FP64 = 0,           /* state, factors and arithmetic in double precision          */
@@ -157,7 +160,13 @@ typedef struct {
   int32_t tile;                /* cells per workgroup tile (0 = automatic)         */
   void *stream;                /* hipStream_t, NULL = default stream               */
   int32_t ckpt_every;          /* > 0: mln_run keeps a full-state checkpoint every
-                                  ckpt_every steps so that mln_grad can run; 0: off */
+                                  ckpt_every steps so that mln_grad can run; 0: off;
+                                  MLN_TAPE_ALL: mln_run keeps the whole forward
+                                  tape (the state z' and E of every medium cell
+                                  and step, (N^2) x cells x nt reals, e.g. 18 GB
+                                  for 10000 cells x 50000 steps in FP32) in device
+                                  memory, so that mln_grad needs no recomputation
+                                  (MLN_ENOMEM if it does not fit)                 */
   int32_t variant;             /* forward kernel: 0 automatic, 1 workgroup tile
                                   (one cell per thread, LDS exchange), 2 wavefront
                                   tile (rotation route; tile/64 cells per lane),
@@ -304,10 +313,13 @@ int mln_bloch_only_noalloc(mln_handle *h, const double *efield, int64_t n_steps,
 
 /* Vector-Jacobian product of the whole run (the adjoint, reverse-time pass):
  * given g[n] = dJ/dprobe[n] for n = 0..nt (host array), fill *out with
- * dJ/d(inputs).  Needs a handle created with ckpt_every > 0 on which mln_run
- * has completed; the forward state is rebuilt segment by segment from the
- * checkpoints (recomputation), and each segment is then swept backwards by the
- * reverse kernel, which accumulates the parameter gradients on the GPU.  The
+ * dJ/d(inputs).  Needs a handle created with ckpt_every > 0 or MLN_TAPE_ALL
+ * on which mln_run has completed from step 0; with checkpoints the forward
+ * state is rebuilt segment by segment from them (recomputation, which leaves
+ * the forward buffers in an intermediate state: mln_reset before stepping
+ * again), with the whole tape in memory nothing is recomputed (and mln_grad
+ * may be called again for another dJ_dprobe); each segment is swept backwards
+ * by the reverse kernel, which accumulates the parameter gradients on the GPU.  The
  * final chain rule through exp(M dt/2) runs on the host in FP64.  Supported
  * for the rotation route, FP64 and FP32 (plain or compensated), N <= 3.
  * Errors: MLN_ESTATE (no completed checkpointed run), MLN_ENOTSUPPORTED.

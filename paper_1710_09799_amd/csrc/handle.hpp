@@ -106,6 +106,10 @@ struct mln_handle {
   // checkpoints of the forward run (for the adjoint)
   int64_t ckpt_every = 0, nckpt = 0, ckpt_count = 0;
   bool ckpt_ok = false;
+  // the whole forward tape kept in device memory (ckpt_every = MLN_TAPE_ALL):
+  // mln_run writes z' and E of every step, mln_grad reverses without
+  // recomputation; tape_ok while the run so far started at step 0 untouched
+  bool tape_all = false, tape_ok = false;
   DevBuf ckpt;
   // adjoint buffers (allocated by the first mln_grad)
   DevBuf lE[2], lH[2], lz[2], tape, partial, gprobe, samples_dev;

@@ -417,6 +417,7 @@ int mln::reset_state(mln_handle *h) {
   h->step = 0;
   h->ckpt_count = 0;
   h->ckpt_ok = h->ckpt_every > 0;
+  h->tape_ok = h->tape_all;
   if (h->d_probe) {
     double p0 = (h->grid.nx - 1 == 0) ? h->amp * h->samples[0] : 0.0;
     HIP_TRY(hipMemcpyAsync(h->d_probe, &p0, sizeof(double), hipMemcpyHostToDevice, h->stream));
@@ -589,8 +590,16 @@ int mln_init(const mln_medium *medium, const mln_grid *grid, const mln_source *s
   }
   rc = (h->prec == MLN_FP64) ? init_typed<double>(h.get(), h->fd) : init_typed<float>(h.get(), h->ff);
   if (rc) return rc;
-  if (opt.ckpt_every < 0) return set_err(MLN_EINVAL, "ckpt_every must be >= 0");
-  h->ckpt_every = opt.ckpt_every;
+  if (opt.ckpt_every < 0 && opt.ckpt_every != MLN_TAPE_ALL)
+    return set_err(MLN_EINVAL, "ckpt_every must be >= 0 or MLN_TAPE_ALL");
+  if (opt.ckpt_every == MLN_TAPE_ALL) {
+    if (h->route != MLN_ROUTE_ROTATION || h->f.N > 3)
+      return set_err(MLN_ENOTSUPPORTED, "the adjoint is built for the rotation route and N <= 3");
+    h->tape_all = true;
+    const size_t bytes = (size_t)h->rs * (h->f.D + 1) * (size_t)h->ld * (size_t)std::max<int64_t>(grid->nt, 1);
+    HIP_TRY(h->tape.alloc(bytes));
+  }
+  h->ckpt_every = std::max<int32_t>(opt.ckpt_every, 0);
   if (h->ckpt_every > 0) {
     h->nckpt = (grid->nt + h->ckpt_every - 1) / h->ckpt_every;
     HIP_TRY(h->ckpt.alloc(std::max<int64_t>(h->nckpt, 1) * state_slot_bytes(h.get())));
@@ -605,6 +614,7 @@ int mln_step(mln_handle *h, int64_t n_steps) {
   if (!h) return set_err(MLN_EINVAL, "null handle");
   if (n_steps < 0) return set_err(MLN_EINVAL, "n_steps must be >= 0");
   int64_t left = std::min<int64_t>(n_steps, h->grid.nt - h->step);
+  if (h->tape_all && h->tape_ok) return forward_steps(h, left, true, h->tape.p, 0, true);
   return forward_steps(h, left, true, nullptr, 0, true);
 }
 
@@ -928,6 +938,7 @@ int mln_set_state(mln_handle *h, const double *E, const double *H, const double 
     HIP_TRY(hipMemcpy(h->z[h->cur].p, buf.data(), buf.size(), hipMemcpyHostToDevice));
   }
   h->ckpt_ok = false;  // checkpoints of the run so far no longer lead here
+  h->tape_ok = false;
   return MLN_OK;
 }
 
@@ -970,6 +981,7 @@ int mln_load_state(mln_handle *h, const void *host_buf) {
   h->step = step;
   h->cur = 0;
   h->ckpt_ok = false;
+  h->tape_ok = false;
   return MLN_OK;
 }
 
@@ -1059,12 +1071,14 @@ int mln_bloch_only_noalloc(mln_handle *h, const double *efield, int64_t n_steps,
 
 int mln_grad(mln_handle *h, const double *dJ_dprobe, mln_grads *out) {
   if (!h || !dJ_dprobe || !out) return set_err(MLN_EINVAL, "null argument");
-  if (h->ckpt_every <= 0) return set_err(MLN_ESTATE, "handle was created without checkpoints (ckpt_every = 0)");
+  if (h->ckpt_every <= 0 && !h->tape_all)
+    return set_err(MLN_ESTATE, "handle was created without checkpoints or tape (ckpt_every = 0)");
   if (h->route != MLN_ROUTE_ROTATION || h->f.N > 3)
     return set_err(MLN_ENOTSUPPORTED, "the adjoint is built for the rotation route and N <= 3");
   const int64_t nt = h->grid.nt;
-  if (!h->ckpt_ok || h->step != nt || h->ckpt_count != h->nckpt)
-    return set_err(MLN_ESTATE, "mln_grad needs a completed checkpointed run (mln_reset + mln_run)");
+  if (h->tape_all ? (!h->tape_ok || h->step != nt)
+                  : (!h->ckpt_ok || h->step != nt || h->ckpt_count != h->nckpt))
+    return set_err(MLN_ESTATE, "mln_grad needs a completed run from step 0 (mln_reset + mln_run)");
   const int N = h->f.N, D = h->f.D, q = h->f.q;
   const bool f64 = h->prec == MLN_FP64;
   const int nacc = N == 2 ? adj_nacc(2, f64) : adj_nacc(3, f64);
@@ -1089,7 +1103,7 @@ int mln_grad(mln_handle *h, const double *dJ_dprobe, mln_grads *out) {
       HIP_TRY(h->lH[b].alloc(rs * h->grid.nx));
       HIP_TRY(h->lz[b].alloc(rs * D * h->ld));
     }
-    HIP_TRY(h->tape.alloc(rs * (size_t)h->ckpt_every * (D + 1) * h->ld));
+    if (!h->tape_all) HIP_TRY(h->tape.alloc(rs * (size_t)h->ckpt_every * (D + 1) * h->ld));
     HIP_TRY(h->gprobe.alloc(sizeof(double) * (nt + 1)));
     HIP_TRY(h->samples_dev.alloc(sizeof(double) * (nt + 1)));
     HIP_TRY(hipMemcpy(h->samples_dev.p, h->samples.data(), sizeof(double) * (nt + 1), hipMemcpyHostToDevice));
@@ -1105,14 +1119,21 @@ int mln_grad(mln_handle *h, const double *dJ_dprobe, mln_grads *out) {
   }
   HIP_TRY(hipMemsetAsync(h->partial.p, 0, h->partial.bytes, h->stream));
   int lc = 0;
-  for (int64_t seg = h->nckpt - 1; seg >= 0; --seg) {
-    const int64_t s0 = seg * h->ckpt_every, s1 = std::min<int64_t>(s0 + h->ckpt_every, nt);
-    h->cur = 0;
-    int rc = ckpt_copy(h, seg, false);
-    if (rc) return rc;
-    h->step = s0;
-    rc = forward_steps(h, s1 - s0, false, h->tape.p, s0, false);
-    if (rc) return rc;
+  // segments: the checkpoint intervals (each rebuilt from its checkpoint,
+  // writing the tape), or with the whole tape in memory one segment and no
+  // recomputation
+  const int64_t nseg = h->tape_all ? 1 : h->nckpt;
+  for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+    const int64_t s0 = h->tape_all ? 0 : seg * h->ckpt_every;
+    const int64_t s1 = h->tape_all ? nt : std::min<int64_t>(s0 + h->ckpt_every, nt);
+    if (!h->tape_all) {
+      h->cur = 0;
+      int rc = ckpt_copy(h, seg, false);
+      if (rc) return rc;
+      h->step = s0;
+      rc = forward_steps(h, s1 - s0, false, h->tape.p, s0, false);
+      if (rc) return rc;
+    }
     for (int64_t n_hi = s1; n_hi > s0;) {
       const int k = (int)std::min<int64_t>(rhalo, n_hi - s0);
       hipError_t e;
@@ -1163,8 +1184,10 @@ int mln_grad(mln_handle *h, const double *dJ_dprobe, mln_grads *out) {
     }
   }
   HIP_TRY(hipStreamSynchronize(h->stream));
-  h->step = nt;  // the forward buffers now hold an intermediate state; mln_reset before stepping again
-  h->ckpt_ok = false;
+  if (!h->tape_all) {
+    h->step = nt;  // the forward buffers now hold an intermediate state; mln_reset before stepping again
+    h->ckpt_ok = false;
+  }
   // gather: per-tile partial sums, lz'_0 summed over the medium, lE^0 at cell 0
   std::vector<double> part(rtiles * nacc), acc(nacc, 0.0);
   HIP_TRY(hipMemcpy(part.data(), h->partial.p, sizeof(double) * part.size(), hipMemcpyDeviceToHost));

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libmln.so")
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32c": 2, "bf16x6": 3, "bf16x3": 4, "fp32cf": 5}
 ROUTES = {"rotation": 0, "diag": 1, "rodrigues": 2, "pade": 3}
 VARIANTS = {"auto": 0, "block": 1, "wave": 2, "quad": 3, "stream": 4}
+TAPE_ALL = -1  # ckpt_every: keep the whole forward tape in device memory (Solver(ckpt_every="tape"))
 _VARIANT_NAMES = {1: "block", 2: "wave", 3: "quad", 4: "stream"}
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -293,6 +294,8 @@ class Solver:
 
         rs = _Record(snap_every, dptr(self.pop), dptr(self.e_snap), dptr(self.probe), 1)
         self.stream = torch.cuda.current_stream()
+        if ckpt_every == "tape":
+            ckpt_every = TAPE_ALL
         os_ = _Options(PRECISIONS[precision], ROUTES[route], steps_per_launch, tile,
                        ctypes.c_void_p(self.stream.cuda_stream), ckpt_every, VARIANTS[variant])
         h = ctypes.c_void_p()

@@ -264,3 +264,38 @@ def test_p5_adjoint_matches_oracle_adjoint(orc):
         print(f"  {precision}", flush=True)
         worst = _cmp_oracle_adjoint(g, ref, tol, 0.0 if precision != "fp64" else 1e-8)
         print(f"  {precision} worst group error {worst:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_whole_tape_equals_checkpoints(precision):
+    """ckpt_every = MLN_TAPE_ALL keeps the forward tape of every step in device
+    memory: the gradient equals the checkpointed one (same values recorded,
+    without recomputation), a second mln_grad for another objective works
+    without rerunning, and mln_set_state invalidates the tape."""
+    prob = _small_ladder(3, nx=160, nt=700)
+    print(f"[case] whole tape {precision}", flush=True)
+    _, gc = _grad(prob, precision, ckpt=64)
+    s = mln.Solver(prob, precision=precision, ckpt_every="tape")
+    probe = s.run()["probe"].cpu().numpy()
+    gt = s.grad(2.0 * prob.grid.dt * probe)
+    a, b = grads_to_ladder(gt, 3), grads_to_ladder(gc, 3)
+    # the tapes are the same; the reverse launches group the steps
+    # differently (one segment against 64-step segments), which changes the
+    # rounding of the single-precision per-launch sums
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    assert np.max(np.abs(a - b) / (np.abs(b) + 1e-300 + 1e-9 * np.abs(b).max())) < tol
+    # another objective on the same run: J' = dt sum probe (linear), twice
+    g1 = grads_to_ladder(s.grad(np.full(prob.grid.nt + 1, prob.grid.dt)), 3)
+    g2 = grads_to_ladder(s.grad(np.full(prob.grid.nt + 1, prob.grid.dt)), 3)
+    assert np.array_equal(g1, g2)
+    assert not np.allclose(g1, a)
+    E, H, _ = s.state()
+    s.set_state(E=E)
+    with pytest.raises(mln.MLNError) as e:
+        s.grad(2.0 * prob.grid.dt * probe)
+    assert e.value.code == -10
+    s.reset()
+    s.run()
+    g3 = grads_to_ladder(s.grad(2.0 * prob.grid.dt * probe), 3)
+    assert np.array_equal(g3, a)
+    s.close()
