@@ -43,6 +43,12 @@ REPS = 5  # repetitions of every variant (the median is reported), as the paper 
 CSRC = os.path.join(ROOT, "paper_1710_09799_amd", "csrc")
 # sources of the dominant kernel; the committed counter summary records their hash
 QUAD_SOURCES = ["fwd_quad.hpp", "fwd_impl.hpp", "fwd_kernels.hpp", "fwd_n3.hip"]
+# the four-lanes-per-cell kernel each precision runs fastest on at N = 3
+# (measured: the matrix-core product wins with the compensated state)
+HEAD_VARIANT = {"fp32": "quad", "fp32c": "quad_mfma", "fp32cf": "quad_mfma"}
+KERNEL_DESC = {"quad": "four lanes per cell, shared-factor product by DPP gathers and FMAs",
+               "quad_mfma": "four lanes per cell, shared-factor product on the matrix cores "
+                            "(two MFMA 16x16x4 f32 per wavefront and step)"}
 
 
 def traffic_file(precision):
@@ -137,7 +143,7 @@ def time_solver(problem, steps, warmup, snap, keep=False, mean=False, **kw):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         e0.record()
-        s.step(problem.grid.nt)
+        s.run()  # from step 0: one HIP graph of the run's launches
         e1.record()
         torch.cuda.synchronize()
         walls.append(time.perf_counter() - t0)
@@ -215,7 +221,8 @@ def variants(p3, ref64, pop64, headline):
     # N = 3: precisions on the four-lanes-per-cell kernel, and the paper's
     # two routes (and the rotation form) on the one-cell-per-thread kernel
     others = [pr for pr in ("fp32", "fp32c", "fp32cf") if pr != headline]
-    for name, kw in tuple((f"n3_{pr}_quad", dict(precision=pr, variant="quad", tile=128, steps_per_launch=20))
+    for name, kw in tuple((f"n3_{pr}_{HEAD_VARIANT[pr]}", dict(precision=pr, variant=HEAD_VARIANT[pr], tile=128,
+                                                                steps_per_launch=20))
                           for pr in others) + (
                      ("n3_fp64_block_rotation", dict(precision="fp64", variant="block", route="rotation",
                                                      tile=256, steps_per_launch=32)),
@@ -539,7 +546,8 @@ def calib_copy():
 PROFILE_CASES = {
     "n2_fp64": ("two_level", {}, dict(precision="fp64", variant="quad", tile=128, steps_per_launch=16)),
     "n3_fp64": ("three_level", {}, dict(precision="fp64", variant="quad", tile=128, steps_per_launch=20)),
-    "n3_fp32c": ("three_level", {}, dict(precision="fp32c", variant="quad", tile=128, steps_per_launch=20)),
+    "n3_fp32c": ("three_level", {}, dict(precision="fp32c", variant="quad_mfma", tile=128, steps_per_launch=20)),
+    "n3_fp32c_dpp": ("three_level", {}, dict(precision="fp32c", variant="quad", tile=128, steps_per_launch=20)),
     "n6_fp64": ("six_level", dict(nt=1600), dict(precision="fp64", variant="block", tile=256, steps_per_launch=16)),
     "n6_bf16x6": ("six_level", dict(nt=1600), dict(precision="bf16x6", tile=256, steps_per_launch=16)),
     "n6_bf16x3": ("six_level", dict(nt=1600), dict(precision="bf16x3", tile=256, steps_per_launch=16)),
@@ -691,7 +699,7 @@ def main():
     p = W.three_level()
     n_upd = p.grid.n_med * p.grid.nt
     K = 20
-    kw = dict(precision=args.precision, variant="quad", tile=128, steps_per_launch=K)
+    kw = dict(precision=args.precision, variant=HEAD_VARIANT[args.precision], tile=128, steps_per_launch=K)
     t, gpu_t, launches, out = time_solver(p, args.steps, args.warmup, 10000, keep=True, mean=True, **kw)
     value = n_upd / t
     fl = flops_per_update(p.medium.n_levels)
@@ -720,7 +728,8 @@ def main():
                    "precision": {"fp32": "fp32 (single precision, deviation form)",
                                  "fp32c": "fp32c (FP32 with compensated float-float state)",
                                  "fp32cf": "fp32cf (compensated state and fields)"}[args.precision],
-                   "kernel": "four lanes per cell", "tile": kw["tile"], "steps_per_launch": K},
+                   "kernel": KERNEL_DESC[kw["variant"]], "tile": kw["tile"], "steps_per_launch": K,
+                   "launches": "one HIP graph per run"},
         "paper_P": p.grid.nx * p.grid.nt / t,
         # the step is a dependency chain (exchange, rotation, gather, shared
         # factor, E update) that a few hundred tiles cannot hide: the kernel
@@ -728,7 +737,8 @@ def main():
         # the step time against its measured floor is in step_latency
         "roofline": {"bound": "latency", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                      "peak_of": "FP32 vector", "frac": achieved / peak, "traffic": traffic,
-                     "kernel": f"fwd_quad_kernel<3,float,{args.precision}>", "launch_us": launch_s * 1e6,
+                     "kernel": f"fwd_quad_kernel<3,float,{args.precision}"
+                               + (",mfma>" if kw["variant"] == "quad_mfma" else ">"), "launch_us": launch_s * 1e6,
                      "flop_per_update": fl, "updates_per_launch": p.grid.n_med * K},
     }
     # the latency floor of a step at the headline's launch shape: one LDS
@@ -757,6 +767,13 @@ def main():
                                       "oracle to 1e-10 on every parity shape"}
         var = {"n3_fp64_quad": {"value": n_upd / t64, "ms": t64 * 1e3, "launch_ms": g64 * 1e3 / nl64,
                                 "tile": kw["tile"], "steps_per_launch": K}}
+        # the headline precision on the other four-lanes-per-cell product
+        # (DPP gathers and FMAs against the matrix cores)
+        alt = "quad" if kw["variant"] == "quad_mfma" else "quad_mfma"
+        ta, ga, nla, _ = time_solver(p, REPS, 1, 10000, precision=args.precision, variant=alt,
+                                     tile=kw["tile"], steps_per_launch=K)
+        var[f"n3_{args.precision}_{alt}"] = {"value": n_upd / ta, "ms": ta * 1e3, "launch_ms": ga * 1e3 / nla,
+                                            "variant": alt, "tile": kw["tile"], "steps_per_launch": K}
         cfg64 = tuned_config(W.three_level(nt=4000), "fp64")
         tt, gt, nlt, _ = time_solver(p, REPS, 1, 10000, precision="fp64", **cfg64)
         var["n3_fp64_tuned"] = {"value": n_upd / tt, "ms": tt * 1e3, "launch_ms": gt * 1e3 / nlt, **cfg64}

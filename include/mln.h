@@ -176,7 +176,13 @@ typedef struct {
                                   compensated FP32: one time step per launch,
                                   one thread per cell, tile 0 or 256, steps per
                                   launch 0 or 1; state, E and H read from and
-                                  written to device memory every step).
+                                  written to device memory every step), 5 quad
+                                  tile with the shared-factor product on the
+                                  matrix cores (rotation route, N <= 3, FP64 /
+                                  FP32 / compensated modes; the 16 cells of a
+                                  wavefront as one 16 x 8 by 8 x 16 product per
+                                  step, Sec. 4.1 fused half steps; tile as for
+                                  3, a multiple of 16).
                                   Automatic: quad for N <= 3 on grids below 1e5
                                   cells (latency-bound sizes), workgroup tile on
                                   larger ones; N = 4: wavefront tile; N = 6:
@@ -217,8 +223,16 @@ int mln_init(const mln_medium *medium, const mln_grid *grid, const mln_source *s
 int mln_step(mln_handle *h, int64_t n_steps);
 
 /* Advance to step nt, wait for the stream, copy host-side records and check
- * the recorded output for NaN/Inf (MLN_ENONFINITE). */
+ * the recorded output for NaN/Inf (MLN_ENONFINITE).  From step 0 without
+ * checkpoints or tape (and unless mln_use_graph(h, 0)), the launches of the
+ * whole run are replayed as one HIP graph, captured on the first such call
+ * (on a private stream; kernel nodes only) and rebuilt after mln_configure /
+ * mln_tune. */
 int mln_run(mln_handle *h);
+
+/* on = 1 (default): mln_run from step 0 replays the graph described above;
+ * on = 0: its launches are enqueued one by one. */
+int mln_use_graph(mln_handle *h, int32_t on);
 
 /* Return to the initial state (step 0) without rebuilding factors. */
 int mln_reset(mln_handle *h);
@@ -227,8 +241,8 @@ int mln_reset(mln_handle *h);
 int mln_current_step(const mln_handle *h, int64_t *step);
 
 /* The kernel configuration the handle runs: variant (1 workgroup tile, 2
- * wavefront tile, 3 four lanes per cell, 4 streamed; the automatic choice
- * resolved),
+ * wavefront tile, 3 four lanes per cell, 4 streamed, 5 four lanes per cell
+ * with the matrix-core product; the automatic choice resolved),
  * cells per tile and time steps per launch.  Any pointer may be NULL. */
 int mln_get_config(const mln_handle *h, int32_t *variant, int32_t *tile, int32_t *steps_per_launch);
 
@@ -239,7 +253,7 @@ int mln_get_config(const mln_handle *h, int32_t *variant, int32_t *tile, int32_t
 int mln_configure(mln_handle *h, int32_t variant, int32_t tile, int32_t steps_per_launch);
 
 /* Autotuner for one problem: time every kernel configuration the handle's
- * level count, precision and route allow (variants 1-4, several tile shapes)
+ * level count, precision and route allow (variants 1-5, several tile shapes)
  * on the problem itself, about trial_steps steps each from step 0 with
  * nothing recorded (HIP events on the handle's stream), keep the fastest per
  * time step and return the handle to step 0 with it.  The choice is returned

@@ -11,9 +11,11 @@ namespace mln {
   template <typename Real>                                                                        \
   hipError_t launch_bloch_n##NN(int route, bool comp, const BlochArgs<Real> &a, hipStream_t st);
 template <typename Real>
-hipError_t launch_fwd_quad_n2(bool comp, bool cf, int W, const FwdArgs<Real> &a, int64_t nblocks, hipStream_t st);
+hipError_t launch_fwd_quad_n2(bool comp, bool cf, bool mf, int W, const FwdArgs<Real> &a, int64_t nblocks,
+                              hipStream_t st);
 template <typename Real>
-hipError_t launch_fwd_quad_n3(bool comp, bool cf, int W, const FwdArgs<Real> &a, int64_t nblocks, hipStream_t st);
+hipError_t launch_fwd_quad_n3(bool comp, bool cf, bool mf, int W, const FwdArgs<Real> &a, int64_t nblocks,
+                              hipStream_t st);
 hipError_t launch_fwd_mfma_n4(int nprod, const FwdArgs<float> &a, int64_t nblocks, int W, hipStream_t st);
 hipError_t launch_fwd_mfma_n6(int nprod, const FwdArgs<float> &a, int64_t nblocks, int W, hipStream_t st);
 
@@ -75,16 +77,17 @@ template hipError_t launch_fwd_wave<double>(int, bool, int, const FwdArgs<double
 template hipError_t launch_fwd_wave<float>(int, bool, int, const FwdArgs<float> &, int64_t, hipStream_t);
 
 template <typename Real>
-hipError_t launch_fwd_quad(int N, bool comp, bool cf, int W, const FwdArgs<Real> &a, int64_t nblocks, hipStream_t st) {
+hipError_t launch_fwd_quad(int N, bool comp, bool cf, bool mf, int W, const FwdArgs<Real> &a, int64_t nblocks,
+                           hipStream_t st) {
   switch (N) {
-    case 2: return launch_fwd_quad_n2<Real>(comp, cf, W, a, nblocks, st);
-    case 3: return launch_fwd_quad_n3<Real>(comp, cf, W, a, nblocks, st);
+    case 2: return launch_fwd_quad_n2<Real>(comp, cf, mf, W, a, nblocks, st);
+    case 3: return launch_fwd_quad_n3<Real>(comp, cf, mf, W, a, nblocks, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template hipError_t launch_fwd_quad<double>(int, bool, bool, int, const FwdArgs<double> &, int64_t, hipStream_t);
-template hipError_t launch_fwd_quad<float>(int, bool, bool, int, const FwdArgs<float> &, int64_t, hipStream_t);
+template hipError_t launch_fwd_quad<double>(int, bool, bool, bool, int, const FwdArgs<double> &, int64_t, hipStream_t);
+template hipError_t launch_fwd_quad<float>(int, bool, bool, bool, int, const FwdArgs<float> &, int64_t, hipStream_t);
 
 template <typename Real>
 hipError_t launch_adj(int N, const AdjArgs<Real> &a, int64_t nblocks, int W, hipStream_t st) {

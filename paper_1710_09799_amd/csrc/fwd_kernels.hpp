@@ -149,9 +149,10 @@ template <typename Real>
 hipError_t launch_fwd_stream(int N, bool comp, const FwdArgs<Real> &a, hipStream_t st);
 
 // Four-lanes-per-cell tile kernel of the rotation route (fwd_quad.hpp), N <= 3;
-// W cells per tile (W in 64..256, multiple of 16), 4 W threads.
+// W cells per tile (W in 32..256, multiple of 16), 4 W threads; mf: the
+// shared-factor product on the matrix cores.
 template <typename Real>
-hipError_t launch_fwd_quad(int N, bool comp, bool cf, int W, const FwdArgs<Real> &a, int64_t nblocks,
+hipError_t launch_fwd_quad(int N, bool comp, bool cf, bool mf, int W, const FwdArgs<Real> &a, int64_t nblocks,
                            hipStream_t st);
 
 // Batched launch (fwd_batch.hpp): per-problem arguments for reading from

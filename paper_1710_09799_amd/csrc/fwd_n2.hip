@@ -70,16 +70,17 @@ hipError_t launch_fwd_wave_n2(bool comp, int C, const FwdArgs<Real> &a, int64_t 
 }
 
 template <typename Real>
-hipError_t launch_fwd_quad_n2(bool comp, bool cf, int W, const FwdArgs<Real> &a, int64_t nblocks, hipStream_t st) {
+hipError_t launch_fwd_quad_n2(bool comp, bool cf, bool mf, int W, const FwdArgs<Real> &a, int64_t nblocks,
+                              hipStream_t st) {
   if (cf && !comp) return hipErrorInvalidValue;
   if (comp) {
     if constexpr (std::is_same<Real, float>::value) {
-      if (cf) return launch_quad<2, float, true, true>(W, a, nblocks, st);
-      return launch_quad<2, float, true, false>(W, a, nblocks, st);
+      if (cf) return launch_quad<2, float, true, true>(W, a, nblocks, st, mf);
+      return launch_quad<2, float, true, false>(W, a, nblocks, st, mf);
     }
     return hipErrorInvalidValue;
   }
-  return launch_quad<2, Real, false, false>(W, a, nblocks, st);
+  return launch_quad<2, Real, false, false>(W, a, nblocks, st, mf);
 }
 
 template <typename Real>
@@ -115,8 +116,8 @@ template hipError_t launch_fwd_n2<double>(int, bool, bool, const FwdArgs<double>
 template hipError_t launch_fwd_n2<float>(int, bool, bool, const FwdArgs<float> &, int64_t, int, hipStream_t);
 template hipError_t launch_fwd_wave_n2<double>(bool, int, const FwdArgs<double> &, int64_t, hipStream_t);
 template hipError_t launch_fwd_wave_n2<float>(bool, int, const FwdArgs<float> &, int64_t, hipStream_t);
-template hipError_t launch_fwd_quad_n2<double>(bool, bool, int, const FwdArgs<double> &, int64_t, hipStream_t);
-template hipError_t launch_fwd_quad_n2<float>(bool, bool, int, const FwdArgs<float> &, int64_t, hipStream_t);
+template hipError_t launch_fwd_quad_n2<double>(bool, bool, bool, int, const FwdArgs<double> &, int64_t, hipStream_t);
+template hipError_t launch_fwd_quad_n2<float>(bool, bool, bool, int, const FwdArgs<float> &, int64_t, hipStream_t);
 template hipError_t launch_bloch_n2<double>(int, bool, const BlochArgs<double> &, hipStream_t);
 template hipError_t launch_bloch_n2<float>(int, bool, const BlochArgs<float> &, hipStream_t);
 

@@ -20,6 +20,18 @@
 //   * a workgroup holds up to 256 cells (1024 lanes, 4 wavefronts per SIMD).
 // Temporal blocking as in the other tile kernels: a launch advances
 // nsteps <= halo steps and writes back the owned central cells.
+//
+// Matrix-core form (MF): the shared-factor product of the 16 cells of a
+// wavefront is one 16 x 8 by 8 x 16 product, done by two 16x16x4 MFMA
+// instructions.  Lanes are then laid out 16 r + (cell mod 16), so that the
+// B operand (component 2r resp. 2r+1 of cell j at lane 16r + j) is the
+// rotated state each lane already holds, and four result rows of cell j
+// land on lane 16r + j (rows 4r .. 4r+3 in FP32, rows r, r+4, r+8, r+12 in
+// FP64); the A operand stacks the factor rows so that these are rows 2r,
+// 2r+1 of (K - I) and, with the compensated state, of its low part.  The constant c enters as the accumulator.  The four lanes
+// of a cell sit in the four 16-lane rows of the wavefront, so dP/dt is
+// summed with the gfx950 row swaps (v_permlane32_swap, v_permlane16_swap)
+// instead of DPP, in an order that again gives bitwise-equal sums.
 #pragma once
 
 #include <type_traits>
@@ -63,9 +75,50 @@ __device__ __forceinline__ Real quad_sum(Real x) {
   return a + quad_perm<kQuadSwap2>(a);
 }
 
+// (x_r0 + x_r2) + (x_r1 + x_r3) over the four 16-lane rows of a wavefront,
+// bitwise equal on all four rows.  permlane32_swap(x, x) returns x with rows
+// 2, 3 replaced by rows 0, 1 (first) and x with rows 0, 1 replaced by rows
+// 2, 3 (second), so first + second adds the lower row's value first on both
+// sides; permlane16_swap does the same for rows 0 <-> 1 and 2 <-> 3.
+__device__ __forceinline__ float row_sum(float x) {
+  const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  const float s = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+  const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(s), __float_as_uint(s), false, false);
+  return __uint_as_float(q[0]) + __uint_as_float(q[1]);
+}
+__device__ __forceinline__ double row_sum(double x) {
+  const unsigned lo = (unsigned)__double2loint(x), hi = (unsigned)__double2hiint(x);
+  const auto pl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto ph = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  const double s = __hiloint2double((int)ph[0], (int)pl[0]) + __hiloint2double((int)ph[1], (int)pl[1]);
+  const unsigned slo = (unsigned)__double2loint(s), shi = (unsigned)__double2hiint(s);
+  const auto ql = __builtin_amdgcn_permlane16_swap(slo, slo, false, false);
+  const auto qh = __builtin_amdgcn_permlane16_swap(shi, shi, false, false);
+  return __hiloint2double((int)qh[0], (int)ql[0]) + __hiloint2double((int)qh[1], (int)ql[1]);
+}
+
+typedef float mf_f32x4 __attribute__((ext_vector_type(4)));
+typedef double mf_f64x4 __attribute__((ext_vector_type(4)));
+template <typename Real>
+struct MfAcc;
+template <>
+struct MfAcc<float> {
+  typedef mf_f32x4 type;
+  static __device__ __forceinline__ type mac(float a, float b, type c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct MfAcc<double> {
+  typedef mf_f64x4 type;
+  static __device__ __forceinline__ type mac(double a, double b, type c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
 // One tile (index `tile` of the problem described by `a`) on one workgroup of
 // 4 W lanes.
-template <int N, typename Real, bool COMP, bool CF>
+template <int N, typename Real, bool COMP, bool CF, bool MF = false>
 __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) {
   static_assert(COMP || !CF, "compensated fields come with the compensated state");
   constexpr int D = N * N - 1, Q = N * (N - 1) / 2;
@@ -82,8 +135,10 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
   constexpr bool kProbeLds = N == 3 && std::is_same<Real, float>::value && !CF;
   __shared__ Real sPr[kProbeLds ? kMaxStepsPerLaunch : 1];
   const int t = threadIdx.x;
-  const int r = t & 3;      // lane within the quad: state components 2r, 2r+1
-  const int cl = t >> 2;    // cell within the tile
+  // state components 2r, 2r+1 of cell cl; DPP form: lane 4 cl + r; matrix-
+  // core form: wavefront cl / 16, lane 16 r + (cl mod 16)
+  const int r = MF ? ((t >> 4) & 3) : (t & 3);
+  const int cl = MF ? (((t >> 6) << 4) | (t & 15)) : (t >> 2);
   const int W = blockDim.x >> 2;
   const int64_t base = tile * a.owned - a.halo;
   const int64_t g = base + cl;
@@ -99,21 +154,44 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
 
   // this lane's rows of the factors, in registers for the whole launch
   Real K0[8], K1[8], K0l[8], K1l[8];
+  // MF: the A operands, columns 2r and 2r+1 of row (t mod 16) of the stacked
+  // factor.  Result item v of lane 16 q + j is row 4q + v of the product in
+  // the FP32 instruction and row 4v + q in the FP64 one; the stacked row that
+  // lands there is row 2q + (v & 1) of (K - I) for v < 2 and of its low part
+  // for v >= 2 (zero without the compensated state).
+  Real Am0 = 0, Am1 = 0;
+  if constexpr (MF) {
+    constexpr bool f64 = std::is_same<Real, double>::value;
+    const int row = t & 15;
+    const int q = f64 ? (row & 3) : (row >> 2), v = f64 ? (row >> 2) : (row & 3);
+    const bool lo = v >= 2;
+    const int ki = 2 * q + (v & 1);
+    const bool okr = ki < D && (COMP || !lo);
+    if (okr && i0 < D) Am0 = cld(lo ? a.fac.Km_lo : a.fac.Km, ki * D + i0);
+    if (okr && i1 < D) Am1 = cld(lo ? a.fac.Km_lo : a.fac.Km, ki * D + i1);
+  } else {
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    K0[j] = (v0 && j < D) ? cld(a.fac.Km, i0 * D + j) : Real(0);
-    K1[j] = (v1 && j < D) ? cld(a.fac.Km, i1 * D + j) : Real(0);
-    K0l[j] = (COMP && v0 && j < D) ? cld(a.fac.Km_lo, i0 * D + j) : Real(0);
-    K1l[j] = (COMP && v1 && j < D) ? cld(a.fac.Km_lo, i1 * D + j) : Real(0);
+    for (int j = 0; j < 8; ++j) {
+      K0[j] = (v0 && j < D) ? cld(a.fac.Km, i0 * D + j) : Real(0);
+      K1[j] = (v1 && j < D) ? cld(a.fac.Km, i1 * D + j) : Real(0);
+      K0l[j] = (COMP && v0 && j < D) ? cld(a.fac.Km_lo, i0 * D + j) : Real(0);
+      K1l[j] = (COMP && v1 && j < D) ? cld(a.fac.Km_lo, i1 * D + j) : Real(0);
+    }
   }
-  const Real c0 = v0 ? cld(a.fac.cz, i0) : Real(0), c1 = v1 ? cld(a.fac.cz, i1) : Real(0);
-  const Real c0l = (COMP && v0) ? cld(a.fac.cz_lo, i0) : Real(0);
-  const Real c1l = (COMP && v1) ? cld(a.fac.cz_lo, i1) : Real(0);
-  const Real w0 = v0 ? cld(a.fac.wz, i0) : Real(0), w1 = v1 ? cld(a.fac.wz, i1) : Real(0);
+  // Cells outside the medium in a tile that holds medium cells run the
+  // matrix-core kernel's medium step with zero angle, constants, weights and
+  // p0: their state and their dP/dt stay exactly zero, so that step has no
+  // per-cell branch.
+  const bool m0 = v0 && is_med, m1 = v1 && is_med;
+  const Real c0 = m0 ? cld(a.fac.cz, i0) : Real(0), c1 = m1 ? cld(a.fac.cz, i1) : Real(0);
+  const Real c0l = (COMP && m0) ? cld(a.fac.cz_lo, i0) : Real(0);
+  const Real c1l = (COMP && m1) ? cld(a.fac.cz_lo, i1) : Real(0);
+  const Real w0 = m0 ? cld(a.fac.wz, i0) : Real(0), w1 = m1 ? cld(a.fac.wz, i1) : Real(0);
   const Real zr0 = v0 ? cld(a.fac.zr, i0) : Real(0), zr1 = v1 ? cld(a.fac.zr, i1) : Real(0);
-  const bool rot = r < Q;
+  const bool rot = r < Q && is_med;
   const Real th = rot ? cld(a.fac.thdt, r) : Real(0);
   const Real thl = (COMP && rot) ? cld(a.fac.th_lo, r) : Real(0);
+  const Real p0 = is_med ? a.fac.p0 : Real(0);
 
   // E, H and the private copy Hl of the face left of the cell; with CF each
   // has a low part (Elo, Hlo, Hll)
@@ -158,6 +236,20 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
   const bool interior = g >= 1 && g <= a.nx - 2;
   const bool is_src = g == 0;
   int64_t si = a.snap_i0;
+  // MF: the product of step n is consumed at the start of step n + 1, after
+  // the exchange and its barrier, so the matrix-core latency overlaps them
+  // (pd: the rotation increments with the compensated state, else y'')
+  typename MfAcc<Real>::type pacc = {0, 0, 0, 0};
+  Real pd0 = COMP ? Real(0) : y0, pd1 = COMP ? Real(0) : y1;  // applying these leaves y as loaded
+  auto mf_apply = [&]() {
+    if constexpr (COMP) {
+      add_comp(y0, l0, pd0 + (pacc[0] + pacc[2]));
+      add_comp(y1, l1, pd1 + (pacc[1] + pacc[3]));
+    } else {
+      y0 = pd0 + pacc[0];
+      y1 = pd1 + pacc[1];
+    }
+  };
   for (int s = 0; s < a.nsteps; ++s) {
     const bool snap = s == s_snap;
     const int b = s & 1;
@@ -187,7 +279,60 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
       H += a.ch * (Er - E);
     }
     Real P = 0;
-    if (tile_med && is_med) {
+    if constexpr (MF) {
+      // the matrix-core product and the row sums take every lane of the
+      // wavefront: the branch is uniform (tile_med, snap, pop_out), the
+      // cell's own role (is_med, owned) only selects what is kept
+      if (tile_med) {
+        mf_apply();
+        if (a.tape) {
+          const int64_t n = a.step0 + s;
+          if (owned && is_med && n >= a.tape_step0) {
+            Real *tp = a.tape + (n - a.tape_step0) * (D + 1) * a.ld + c;
+            if (v0) tp[i0 * a.ld] = y0;
+            if (v1) tp[i1 * a.ld] = y1;
+            if (r == 0) tp[D * a.ld] = E;
+          }
+        }
+        Real sn, cm;
+        if constexpr (COMP)
+          sincm1(fmaf(th, E, thl * E), sn, cm);
+        else
+          sincm1(th * E, sn, cm);
+        const Real d0 = (cm * y0 + sn * y1) + (cm * zr0 + sn * zr1);
+        const Real d1 = (cm * y1 - sn * y0) + (cm * zr1 - sn * zr0);
+        const Real u0 = y0 + d0, u1 = y1 + d1;
+        if (snap && a.pop_out) {
+          // population of level lv = popc + pop row lv . y'' (FP64): each
+          // lane's two terms, summed over the cell's four lanes
+          Real e0 = 0, e1 = 0;
+          if constexpr (COMP) {
+            const Real bb0 = u0 - y0, bb1 = u1 - y1;
+            e0 = l0 + ((y0 - (u0 - bb0)) + (d0 - bb0));
+            e1 = l1 + ((y1 - (u1 - bb1)) + (d1 - bb1));
+          }
+          const double z0 = (double)u0 + (double)e0, z1 = (double)u1 + (double)e1;
+          double mine = 0.0;
+#pragma unroll
+          for (int lv = 0; lv < N; ++lv) {
+            const double pr0 = v0 ? cld(a.fac.pop, lv * D + i0) : 0.0;
+            const double pr1 = v1 ? cld(a.fac.pop, lv * D + i1) : 0.0;
+            const double sum = row_sum(pr0 * z0 + pr1 * z1);
+            if (lv == r) mine = cld(a.fac.popc, lv) + sum;
+          }
+          if (owned && is_med && r < N) a.pop_out[si * N * nmed + (int64_t)r * nmed + c] = mine;
+        }
+        const Real ps = row_sum(w0 * u0 + w1 * u1);
+        pacc = {c0, c1, c0l, c1l};
+        pacc = MfAcc<Real>::mac(Am0, u0, pacc);
+        pacc = MfAcc<Real>::mac(Am1, u1, pacc);
+        pd0 = COMP ? d0 : u0;
+        pd1 = COMP ? d1 : u1;
+        P = p0 + ps;
+      }
+    } else if (tile_med && is_med) {
+      // (the DPP kernel keeps the per-cell branch: measured faster here
+      // than the branch-free form the matrix-core kernel uses)
       if (a.tape) {
         const int64_t n = a.step0 + s;
         if (owned && n >= a.tape_step0) {
@@ -219,7 +364,7 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
       zz[5] = quad_bcast<2>(u1);
       zz[6] = quad_bcast<3>(u0);
       zz[7] = quad_bcast<3>(u1);
-      if (snap && owned && a.pop_out) {
+      if (snap && owned && is_med && a.pop_out) {
         // all four lanes take part in the broadcasts; lanes 0..N-1 each
         // form the population of one level.  With COMP the low parts of
         // y'' are l + the rounding error of y + d (two-sum).
@@ -246,7 +391,7 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
           a.pop_out[si * N * nmed + (int64_t)r * nmed + c] = acc;
         }
       }
-      P = a.fac.p0 + quad_sum(w0 * u0 + w1 * u1);
+      P = p0 + quad_sum(w0 * u0 + w1 * u1);
       // y_next = y'' + (K - I) y'' + constant, rows 2r and 2r+1
       Real a0 = c0, a1 = c1, b0 = c0l, b1 = c1l;
 #pragma unroll
@@ -305,6 +450,9 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
       ++si;
     }
   }
+  if constexpr (MF) {
+    if (tile_med) mf_apply();
+  }
   if constexpr (kProbeLds) {
     if (a.probe_out && has_right && owned && r == 0 && g == a.nx - 1)
       for (int s = 0; s < a.nsteps; ++s) a.probe_out[a.step0 + 1 + s] = (double)sPr[s];
@@ -335,9 +483,9 @@ __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) 
 // FP64 and two-float-field step loops free of spills but leaves room for
 // one such workgroup per compute unit; LB = 1024 (at most 128 VGPRs) lets
 // two 512-lane workgroups share a compute unit.
-template <int N, typename Real, bool COMP, bool CF = false, int LB = 1024>
+template <int N, typename Real, bool COMP, bool CF = false, int LB = 1024, bool MF = false>
 __global__ void __launch_bounds__(LB) fwd_quad_kernel(FwdArgs<Real> a) {
-  quad_tile<N, Real, COMP, CF>(a, blockIdx.x);
+  quad_tile<N, Real, COMP, CF, MF>(a, blockIdx.x);
 }
 
 // Compute units of the current device (cached per device).
@@ -357,10 +505,14 @@ inline int quad_device_cus() {
 // compute unit of its own, for the instances whose LB = 1024 build spills
 // (FP64 and two-float fields at N = 3: 36 and 20 bytes per lane; the
 // compensated-FP32 state fits 128 VGPRs and runs faster there); else LB = 1024.
+// MF (the matrix-core product): one build, LB = 1024 (the factor rows are
+// two registers instead of 32).
 template <int N, typename Real, bool COMP, bool CF>
-hipError_t launch_quad(int W, const FwdArgs<Real> &a, int64_t nblocks, hipStream_t st) {
+hipError_t launch_quad(int W, const FwdArgs<Real> &a, int64_t nblocks, hipStream_t st, bool mf = false) {
   constexpr bool wide = std::is_same<Real, double>::value || CF;
-  if (wide && 4 * W <= 512 && nblocks <= quad_device_cus())
+  if (mf)
+    hipLaunchKernelGGL((fwd_quad_kernel<N, Real, COMP, CF, 1024, true>), dim3((unsigned)nblocks), dim3(4 * W), 0, st, a);
+  else if (wide && 4 * W <= 512 && nblocks <= quad_device_cus())
     hipLaunchKernelGGL((fwd_quad_kernel<N, Real, COMP, CF, 512>), dim3((unsigned)nblocks), dim3(4 * W), 0, st, a);
   else
     hipLaunchKernelGGL((fwd_quad_kernel<N, Real, COMP, CF, 1024>), dim3((unsigned)nblocks), dim3(4 * W), 0, st, a);

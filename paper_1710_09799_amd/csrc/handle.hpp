@@ -87,6 +87,7 @@ struct mln_handle {
   int W = 256, halo = 0, owned = 0;  // cells per tile, halo = max steps per launch
   bool wave = false;                  // single-wavefront tile kernel (W = 64 * C cells)
   bool quad = false;                  // four-lanes-per-cell tile kernel (W cells, 4 W threads)
+  bool qmf = false;                   // ... with the shared-factor product on the matrix cores
   bool streamed = false;              // one step per launch, state streamed through HBM
   int64_t ntiles = 0;
   int rs = 8;  // bytes per real of the state
@@ -121,6 +122,23 @@ struct mln_handle {
   // h_scale32 = ch / ch32 where H leaves the library
   float fc32[6] = {0, 0, 0, 0, 0, 0};
   double h_scale32 = 1.0;
+  // mln_run from step 0 (no checkpoints, no tape) replays one HIP graph of
+  // the run's launches, captured on a private stream on first use and
+  // dropped when the kernel configuration changes
+  bool use_graph = true;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t run_graph = nullptr;
+  hipGraphExec_t run_exec = nullptr;
+  void drop_graph() {
+    if (run_exec) (void)hipGraphExecDestroy(run_exec);
+    if (run_graph) (void)hipGraphDestroy(run_graph);
+    run_exec = nullptr;
+    run_graph = nullptr;
+  }
+  ~mln_handle() {
+    drop_graph();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
 };
 
 namespace mln {

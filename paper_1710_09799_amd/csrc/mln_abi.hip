@@ -273,14 +273,14 @@ int forward_steps(mln_handle *h, int64_t n, bool record, void *tape, int64_t tap
       }
     } else if (h->prec == MLN_FP64) {
       auto args = make_args<double>(h, h->fd, h->step, (int)k, record, (double *)tape, tape_step0);
-      e = h->quad   ? launch_fwd_quad<double>(h->f.N, false, false, h->W, args, h->ntiles, h->stream)
+      e = h->quad   ? launch_fwd_quad<double>(h->f.N, false, false, h->qmf, h->W, args, h->ntiles, h->stream)
           : h->wave ? launch_fwd_wave<double>(h->f.N, false, h->W / 64, args, h->ntiles, h->stream)
                     : launch_fwd<double>(h->f.N, h->route, false, false, args, h->ntiles, h->W, h->stream);
     } else {
       auto args = make_args<float>(h, h->ff, h->step, (int)k, record, (float *)tape, tape_step0);
       e = (h->mfma && h->quad) ? launch_fwd_mfmaq(h->f.N, h->mfma, args, h->ntiles, h->W, h->stream)
           : h->mfma ? launch_fwd_mfma(h->f.N, h->mfma, args, h->ntiles, h->W, h->stream)
-          : h->quad ? launch_fwd_quad<float>(h->f.N, h->comp, h->cf, h->W, args, h->ntiles, h->stream)
+          : h->quad ? launch_fwd_quad<float>(h->f.N, h->comp, h->cf, h->qmf, h->W, args, h->ntiles, h->stream)
           : h->wave ? launch_fwd_wave<float>(h->f.N, h->comp, h->W / 64, args, h->ntiles, h->stream)
                     : launch_fwd<float>(h->f.N, h->route, h->comp, h->cf, args, h->ntiles, h->W, h->stream);
     }
@@ -295,7 +295,8 @@ int forward_steps(mln_handle *h, int64_t n, bool record, void *tape, int64_t tap
 // Choose and validate the forward kernel (variant 0: automatic) and its
 // tiling (0: defaults); sets the tile bookkeeping of the handle.
 int set_kernel(mln_handle *h, int variant_req, int tile, int steps_per_launch) {
-  if (variant_req < 0 || variant_req > 4) return set_err(MLN_EINVAL, "unknown kernel variant");
+  if (variant_req < 0 || variant_req > 5) return set_err(MLN_EINVAL, "unknown kernel variant");
+  h->drop_graph();
   const bool rot = h->route == MLN_ROUTE_ROTATION;
   int variant = variant_req;
   if (variant == 4) {
@@ -306,7 +307,7 @@ int set_kernel(mln_handle *h, int variant_req, int tile, int steps_per_launch) {
     if ((tile != 0 && tile != kStreamThreads) || steps_per_launch > 1)
       return set_err(MLN_EINVAL, "the streamed kernel takes tile 0 or 256 and one step per launch");
     h->streamed = true;
-    h->quad = h->wave = false;
+    h->quad = h->wave = h->qmf = false;
     h->W = kStreamThreads;
     h->halo = 1;
     h->owned = kStreamThreads;
@@ -319,14 +320,25 @@ int set_kernel(mln_handle *h, int variant_req, int tile, int steps_per_launch) {
   // and four lanes give four times the wavefronts); one cell per thread on
   // large grids, where the quad's replicated field work costs issue slots
   // (measured crossover near 1e5 cells at N = 2, 3)
-  if (variant == 0)
+  if (variant == 0) {
     variant = !rot ? 1 : (h->f.N <= 3 ? (h->grid.nx < kQuadMaxAutoCells ? 3 : 1) : (h->f.N == 4 && !h->cf ? 2 : 1));
+    // the matrix-core product pays off with the compensated state at N = 3
+    // and with compensated fields (measured; FP64 and plain FP32 run faster
+    // on the DPP product, whose FMA chain is shorter than the MFMA latency)
+    if (variant == 3 && !h->mfma && h->comp && (h->f.N == 3 || h->cf)) variant = 5;
+  }
   if (h->mfma) {
     // one cell per thread (1) or four lanes per cell (3, the default)
     if (variant_req == 0) variant = 3;
     if (variant != 1 && variant != 3)
       return set_err(MLN_ENOTSUPPORTED, "the split-BF16 MFMA kernels are workgroup-tile or four-lanes-per-cell kernels");
   }
+  // variant 5: the four-lanes-per-cell kernel with its shared-factor
+  // product on the matrix cores (N <= 3, FP64 / FP32 / compensated modes)
+  h->qmf = variant == 5;
+  if (h->qmf && (h->mfma || h->f.N > 3))
+    return set_err(MLN_ENOTSUPPORTED, "the matrix-core quad kernel is built for N <= 3 in FP64 and FP32 modes");
+  if (h->qmf) variant = 3;
   h->wave = variant == 2;
   if (h->wave && h->cf)
     return set_err(MLN_ENOTSUPPORTED, "the wavefront kernel keeps E and H in plain precision");
@@ -357,6 +369,38 @@ int set_kernel(mln_handle *h, int variant_req, int tile, int steps_per_launch) {
   h->halo = K;
   h->owned = h->W - 2 * K;
   h->ntiles = (h->grid.nx + h->owned - 1) / h->owned;
+  return MLN_OK;
+}
+
+// Capture the launches of a whole run from step 0 (forward_steps enqueues
+// kernels only when there are no checkpoints or tape) on the private capture
+// stream; nothing runs during the capture, so step and ping-pong slot are
+// restored afterwards.
+int capture_run(mln_handle *h) {
+  if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  hipStream_t user = h->stream;
+  h->stream = h->cap_stream;
+  hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    h->stream = user;
+    return set_err(MLN_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+  }
+  int rc = forward_steps(h, h->grid.nt, true, nullptr, 0, false);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(h->cap_stream, &g);
+  h->stream = user;
+  h->step = 0;
+  h->cur = 0;
+  if (rc || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc ? rc : set_err(MLN_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+  }
+  h->run_graph = g;
+  e = hipGraphInstantiate(&h->run_exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    h->drop_graph();
+    return set_err(MLN_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+  }
   return MLN_OK;
 }
 
@@ -620,9 +664,24 @@ int mln_step(mln_handle *h, int64_t n_steps) {
 
 int mln_run(mln_handle *h) {
   if (!h) return set_err(MLN_EINVAL, "null handle");
-  int rc = mln_step(h, h->grid.nt - h->step);
-  if (rc) return rc;
+  int rc;
+  if (h->use_graph && h->step == 0 && h->cur == 0 && h->grid.nt > 0 && h->ckpt_every == 0 && !h->tape_all) {
+    if (!h->run_exec && (rc = capture_run(h))) return rc;
+    HIP_TRY(hipGraphLaunch(h->run_exec, h->stream));
+    const int64_t launches = h->streamed ? h->grid.nt : (h->grid.nt + h->halo - 1) / h->halo;
+    h->step = h->grid.nt;
+    h->cur = (int)(launches & 1);
+  } else {
+    rc = mln_step(h, h->grid.nt - h->step);
+    if (rc) return rc;
+  }
   return finish_run(h);
+}
+
+int mln_use_graph(mln_handle *h, int32_t on) {
+  if (!h) return set_err(MLN_EINVAL, "null handle");
+  h->use_graph = on != 0;
+  return MLN_OK;
 }
 
 int mln_reset(mln_handle *h) {
@@ -638,15 +697,16 @@ int mln_current_step(const mln_handle *h, int64_t *step) {
 
 namespace {
 struct KernelChoice {
-  bool quad, wave, streamed;
+  bool quad, qmf, wave, streamed;
   int W, halo, owned;
   int64_t ntiles;
 };
 KernelChoice save_kernel(const mln_handle *h) {
-  return {h->quad, h->wave, h->streamed, h->W, h->halo, h->owned, h->ntiles};
+  return {h->quad, h->qmf, h->wave, h->streamed, h->W, h->halo, h->owned, h->ntiles};
 }
 void restore_kernel(mln_handle *h, const KernelChoice &k) {
   h->quad = k.quad;
+  h->qmf = k.qmf;
   h->wave = k.wave;
   h->streamed = k.streamed;
   h->W = k.W;
@@ -674,7 +734,8 @@ int mln_tune(mln_handle *h, int32_t trial_steps, int32_t *variant, int32_t *tile
   static const int cand[][3] = {{3, 64, 8},   {3, 128, 16}, {3, 128, 20}, {3, 128, 32}, {3, 256, 16},
                                 {3, 256, 32}, {1, 64, 8},   {1, 128, 8},  {1, 128, 16}, {1, 128, 32},
                                 {1, 256, 8},  {1, 256, 16}, {1, 256, 32}, {2, 64, 8},   {2, 128, 16},
-                                {2, 256, 32}, {4, 256, 1}};
+                                {2, 256, 32}, {4, 256, 1},  {5, 64, 8},   {5, 128, 16}, {5, 128, 20},
+                                {5, 128, 32}, {5, 256, 16}, {5, 256, 32}};
   const KernelChoice start = save_kernel(h);
   KernelChoice best_k = start;
   double best = INFINITY;
@@ -707,7 +768,7 @@ int mln_tune(mln_handle *h, int32_t trial_steps, int32_t *variant, int32_t *tile
   const int rc2 = reset_state(h);
   if (rc) return rc;
   if (rc2) return rc2;
-  if (variant) *variant = h->streamed ? 4 : (h->quad ? 3 : (h->wave ? 2 : 1));
+  if (variant) *variant = h->streamed ? 4 : (h->qmf ? 5 : (h->quad ? 3 : (h->wave ? 2 : 1)));
   if (tile) *tile = h->W;
   if (steps_per_launch) *steps_per_launch = h->halo;
   return MLN_OK;
@@ -715,7 +776,7 @@ int mln_tune(mln_handle *h, int32_t trial_steps, int32_t *variant, int32_t *tile
 
 int mln_get_config(const mln_handle *h, int32_t *variant, int32_t *tile, int32_t *steps_per_launch) {
   if (!h) return set_err(MLN_EINVAL, "null handle");
-  if (variant) *variant = h->streamed ? 4 : (h->quad ? 3 : (h->wave ? 2 : 1));
+  if (variant) *variant = h->streamed ? 4 : (h->qmf ? 5 : (h->quad ? 3 : (h->wave ? 2 : 1)));
   if (tile) *tile = h->W;
   if (steps_per_launch) *steps_per_launch = h->halo;
   return MLN_OK;

@@ -19,9 +19,9 @@ LIB_PATH = os.path.join(_HERE, "libmln.so")
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32c": 2, "bf16x6": 3, "bf16x3": 4, "fp32cf": 5}
 ROUTES = {"rotation": 0, "diag": 1, "rodrigues": 2, "pade": 3}
-VARIANTS = {"auto": 0, "block": 1, "wave": 2, "quad": 3, "stream": 4}
+VARIANTS = {"auto": 0, "block": 1, "wave": 2, "quad": 3, "stream": 4, "quad_mfma": 5}
 TAPE_ALL = -1  # ckpt_every: keep the whole forward tape in device memory (Solver(ckpt_every="tape"))
-_VARIANT_NAMES = {1: "block", 2: "wave", 3: "quad", 4: "stream"}
+_VARIANT_NAMES = {1: "block", 2: "wave", 3: "quad", 4: "stream", 5: "quad_mfma"}
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -88,7 +88,7 @@ class _Factors(ctypes.Structure):
 
 
 # every symbol include/mln.h declares
-EXPORTS = ["mln_init", "mln_step", "mln_run", "mln_reset", "mln_current_step", "mln_get_config", "mln_configure", "mln_tune",
+EXPORTS = ["mln_init", "mln_step", "mln_run", "mln_use_graph", "mln_reset", "mln_current_step", "mln_get_config", "mln_configure", "mln_tune",
            "mln_get_fields", "mln_get_state", "mln_get_bloch", "mln_set_state",
            "mln_state_bytes", "mln_save_state", "mln_load_state", "mln_bloch_only", "mln_bloch_only_noalloc", "mln_free",
            "mln_strerror", "mln_last_error", "mln_setup_factors", "mln_version", "mln_grad",
@@ -119,6 +119,7 @@ def load():
                       ctypes.POINTER(_Record), ctypes.POINTER(_Options), ctypes.POINTER(P)], ctypes.c_int),
         "mln_step": ([P, ctypes.c_int64], ctypes.c_int),
         "mln_run": ([P], ctypes.c_int),
+        "mln_use_graph": ([P, ctypes.c_int32], ctypes.c_int),
         "mln_reset": ([P], ctypes.c_int),
         "mln_current_step": ([P, i64p], ctypes.c_int),
         "mln_get_config": ([P, i32p, i32p, i32p], ctypes.c_int),
@@ -313,6 +314,11 @@ class Solver:
 
     def reset(self):
         _check(self._L.mln_reset(self._h))
+
+    def use_graph(self, on=True):
+        """run() from step 0 replays one HIP graph of the run's launches (on,
+        the default) or enqueues them one by one."""
+        _check(self._L.mln_use_graph(self._h, 1 if on else 0))
 
     def current_step(self):
         v = ctypes.c_int64()
