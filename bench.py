@@ -545,9 +545,11 @@ def calib_copy():
 # 50000-cell grid (every launch is alike).
 PROFILE_CASES = {
     "n2_fp64": ("two_level", {}, dict(precision="fp64", variant="quad", tile=128, steps_per_launch=16)),
-    "n3_fp64": ("three_level", {}, dict(precision="fp64", variant="quad", tile=128, steps_per_launch=20)),
-    "n3_fp32c": ("three_level", {}, dict(precision="fp32c", variant="quad_mfma", tile=128, steps_per_launch=20)),
-    "n3_fp32c_dpp": ("three_level", {}, dict(precision="fp32c", variant="quad", tile=128, steps_per_launch=20)),
+    "n3_fp64": ("three_level", dict(nt=20000), dict(precision="fp64", variant="quad", tile=128, steps_per_launch=20)),
+    "n3_fp32c": ("three_level", dict(nt=20000), dict(precision="fp32c", variant="quad_mfma", tile=128,
+                                                   steps_per_launch=20)),
+    "n3_fp32c_dpp": ("three_level", dict(nt=20000), dict(precision="fp32c", variant="quad", tile=128,
+                                                       steps_per_launch=20)),
     "n6_fp64": ("six_level", dict(nt=1600), dict(precision="fp64", variant="block", tile=256, steps_per_launch=16)),
     "n6_bf16x6": ("six_level", dict(nt=1600), dict(precision="bf16x6", tile=256, steps_per_launch=16)),
     "n6_bf16x3": ("six_level", dict(nt=1600), dict(precision="bf16x3", tile=256, steps_per_launch=16)),

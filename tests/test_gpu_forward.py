@@ -332,10 +332,15 @@ def test_bloch_only_fp32_pade(orc, n, seed, fmax):
 
 
 def test_automatic_kernel_choice():
-    """Variant 0 resolves to the quad kernel on latency-bound grids and to one
-    cell per thread on large ones; the large-grid choice matches the quad
-    kernel's FP64 result to rounding."""
-    cases = [(W.three_level(nx=20000, nt=10), "fp32c", "quad"),
+    """Variant 0 resolves to a four-lanes-per-cell kernel on latency-bound
+    grids (its matrix-core form with the compensated state at N = 3 and with
+    compensated fields) and to one cell per thread on large ones; the
+    large-grid choice matches the quad kernel's FP64 result to rounding."""
+    cases = [(W.three_level(nx=20000, nt=10), "fp32c", "quad_mfma"),
+             (W.three_level(nx=20000, nt=10), "fp64", "quad"),
+             (W.three_level(nx=20000, nt=10), "fp32", "quad"),
+             (W.two_level(), "fp32c", "quad"),
+             (W.two_level(), "fp32cf", "quad_mfma"),
              (W.two_level(), "fp64", "quad"),
              (W.three_level(nx=150000, nt=10), "fp64", "block"),
              (W.six_level(nx=2000, nt=10), "fp64", "block"),
@@ -359,14 +364,14 @@ def test_single_problem_autotuner_and_configure():
     mln_configure rejects invalid shapes and leaves the configuration
     unchanged, and works only at step 0."""
     for p, prec, bad in ((W.three_level(nx=20000, nt=1200), "fp32c", None),
-                         (W.two_level(nx=1 << 20, nt=300), "fp64", "quad"),
+                         (W.two_level(nx=1 << 20, nt=300), "fp64", ("quad", "quad_mfma")),
                          (W.six_level(nx=3000, nt=400), "bf16x6", "wave")):
         s = mln.Solver(p, precision=prec, snap_every=p.grid.nt // 2)
         cfg = s.tune(trial_steps=64)
         print("tuned", p.name, prec, cfg, flush=True)
         assert s.current_step() == 0
         if bad:
-            assert cfg["variant"] != bad
+            assert cfg["variant"] not in ((bad,) if isinstance(bad, str) else bad)
         tuned = {k: v.cpu().numpy().copy() for k, v in s.run().items() if v is not None}
         s.reset()
         s.configure("auto")
