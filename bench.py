@@ -46,6 +46,11 @@ QUAD_SOURCES = ["fwd_quad.hpp", "fwd_impl.hpp", "fwd_kernels.hpp", "fwd_n3.hip"]
 # the four-lanes-per-cell kernel each precision runs fastest on at N = 3
 # (measured: the matrix-core product wins with the compensated state)
 HEAD_VARIANT = {"fp32": "quad", "fp32c": "quad_mfma", "fp32cf": "quad_mfma"}
+# steps per launch with 128-cell tiles (measured best: the matrix-core form
+# amortises its launch cost over the most steps that keep one tile per compute
+# unit, 250 tiles of 80 owned cells; the DPP form, FP64 included, runs best
+# at 20)
+HEAD_K = {"quad": 20, "quad_mfma": 24}
 KERNEL_DESC = {"quad": "four lanes per cell, shared-factor product by DPP gathers and FMAs",
                "quad_mfma": "four lanes per cell, shared-factor product on the matrix cores "
                             "(two MFMA 16x16x4 f32 per wavefront and step)"}
@@ -222,7 +227,7 @@ def variants(p3, ref64, pop64, headline):
     # two routes (and the rotation form) on the one-cell-per-thread kernel
     others = [pr for pr in ("fp32", "fp32c", "fp32cf") if pr != headline]
     for name, kw in tuple((f"n3_{pr}_{HEAD_VARIANT[pr]}", dict(precision=pr, variant=HEAD_VARIANT[pr], tile=128,
-                                                                steps_per_launch=20))
+                                                                steps_per_launch=HEAD_K[HEAD_VARIANT[pr]]))
                           for pr in others) + (
                      ("n3_fp64_block_rotation", dict(precision="fp64", variant="block", route="rotation",
                                                      tile=256, steps_per_launch=32)),
@@ -288,8 +293,8 @@ def variants(p3, ref64, pop64, headline):
                      ("n6_fp32", dict(precision="fp32", **blk)),
                      ("n6_fp32c", dict(precision="fp32c", **blk)),
                      ("n6_fp32cf", dict(precision="fp32cf", **blk)),
-                     ("n6_bf16x6_mfma", dict(precision="bf16x6", tile=256, steps_per_launch=16)),
-                     ("n6_bf16x3_mfma", dict(precision="bf16x3", tile=256, steps_per_launch=16))):
+                     ("n6_bf16x6_mfma", dict(precision="bf16x6", tile=256)),
+                     ("n6_bf16x3_mfma", dict(precision="bf16x3", tile=256))):
         t, g, nl, _ = time_solver(p6t, REPS, 1, 0, record_pop=False, record_e=False, **kw)
         rec = {"value": n6 / t, "ms_40000_steps": t * 1e3, "launch_ms": g * 1e3 / nl,
                "tflops": n6 * flops_per_update(6) / g / 1e12, **kw}
@@ -547,12 +552,12 @@ PROFILE_CASES = {
     "n2_fp64": ("two_level", {}, dict(precision="fp64", variant="quad", tile=128, steps_per_launch=16)),
     "n3_fp64": ("three_level", dict(nt=20000), dict(precision="fp64", variant="quad", tile=128, steps_per_launch=20)),
     "n3_fp32c": ("three_level", dict(nt=20000), dict(precision="fp32c", variant="quad_mfma", tile=128,
-                                                   steps_per_launch=20)),
+                                                   steps_per_launch=24)),
     "n3_fp32c_dpp": ("three_level", dict(nt=20000), dict(precision="fp32c", variant="quad", tile=128,
                                                        steps_per_launch=20)),
     "n6_fp64": ("six_level", dict(nt=1600), dict(precision="fp64", variant="block", tile=256, steps_per_launch=16)),
-    "n6_bf16x6": ("six_level", dict(nt=1600), dict(precision="bf16x6", tile=256, steps_per_launch=16)),
-    "n6_bf16x3": ("six_level", dict(nt=1600), dict(precision="bf16x3", tile=256, steps_per_launch=16)),
+    "n6_bf16x6": ("six_level", dict(nt=1800), dict(precision="bf16x6", tile=256, steps_per_launch=30)),
+    "n6_bf16x3": ("six_level", dict(nt=1800), dict(precision="bf16x3", tile=256, steps_per_launch=30)),
     "n2_large_fp64_stream": ("n2_large", {}, dict(precision="fp64", variant="stream")),
     "n2_large_fp32_stream": ("n2_large", {}, dict(precision="fp32", variant="stream")),
     "n2_large_fp64_k1": ("n2_large", {}, dict(precision="fp64", variant="block", tile=256, steps_per_launch=1)),
@@ -700,7 +705,7 @@ def main():
         return
     p = W.three_level()
     n_upd = p.grid.n_med * p.grid.nt
-    K = 20
+    K = HEAD_K[HEAD_VARIANT[args.precision]]
     kw = dict(precision=args.precision, variant=HEAD_VARIANT[args.precision], tile=128, steps_per_launch=K)
     t, gpu_t, launches, out = time_solver(p, args.steps, args.warmup, 10000, keep=True, mean=True, **kw)
     value = n_upd / t
@@ -759,7 +764,7 @@ def main():
         # FP64 on the headline's launch shape and on the shape mln_tune picks
         # for FP64; the headline precision's own tuned shape beside it
         t64, g64, nl64, out64 = time_solver(p, REPS, 1, 10000, keep=True, precision="fp64", variant="quad",
-                                            tile=kw["tile"], steps_per_launch=K)
+                                            tile=kw["tile"], steps_per_launch=HEAD_K["quad"])
         import numpy as np
         e32 = np.concatenate([out["probe"], out["e_snap"].ravel()])
         e64 = np.concatenate([out64["probe"], out64["e_snap"].ravel()])
@@ -768,14 +773,14 @@ def main():
                               "note": "full-length deviation from the FP64 GPU path, which matches the "
                                       "oracle to 1e-10 on every parity shape"}
         var = {"n3_fp64_quad": {"value": n_upd / t64, "ms": t64 * 1e3, "launch_ms": g64 * 1e3 / nl64,
-                                "tile": kw["tile"], "steps_per_launch": K}}
+                                "tile": kw["tile"], "steps_per_launch": HEAD_K["quad"]}}
         # the headline precision on the other four-lanes-per-cell product
         # (DPP gathers and FMAs against the matrix cores)
         alt = "quad" if kw["variant"] == "quad_mfma" else "quad_mfma"
         ta, ga, nla, _ = time_solver(p, REPS, 1, 10000, precision=args.precision, variant=alt,
-                                     tile=kw["tile"], steps_per_launch=K)
+                                     tile=kw["tile"], steps_per_launch=HEAD_K[alt])
         var[f"n3_{args.precision}_{alt}"] = {"value": n_upd / ta, "ms": ta * 1e3, "launch_ms": ga * 1e3 / nla,
-                                            "variant": alt, "tile": kw["tile"], "steps_per_launch": K}
+                                            "variant": alt, "tile": kw["tile"], "steps_per_launch": HEAD_K[alt]}
         cfg64 = tuned_config(W.three_level(nt=4000), "fp64")
         tt, gt, nlt, _ = time_solver(p, REPS, 1, 10000, precision="fp64", **cfg64)
         var["n3_fp64_tuned"] = {"value": n_upd / tt, "ms": tt * 1e3, "launch_ms": gt * 1e3 / nlt, **cfg64}

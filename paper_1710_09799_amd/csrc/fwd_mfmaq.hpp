@@ -13,9 +13,14 @@
 //     2q + r, 2q + r + 4, ..; S slots per lane (padded to a multiple of 4);
 //   * the shared factor K - I is used in this slot order (rows and columns
 //     permuted: slot k = S r + i), split once per launch into three (or two)
-//     BF16 parts in the A-operand layout of v_mfma_f32_16x16x16_bf16, with
-//     K = 4 S a multiple of 16; the high part lives in registers, the others
-//     in LDS in lane order (conflict-free reads);
+//     BF16 parts in the A-operand layouts of v_mfma_f32_16x16x32_bf16 (the
+//     first K - K mod 32 columns) and v_mfma_f32_16x16x16_bf16 (a remaining
+//     16), with K = 4 S a multiple of 16; the high part lives in registers,
+//     the others in LDS in lane order (conflict-free reads);
+//   * the products of each 16-row block go to two accumulators, the main
+//     terms and (six-product form) the small cross terms, which halves the
+//     dependency chain of accumulating MFMAs; E is updated while the matrix
+//     cores work, before the results are read back;
 //   * every lane splits the high parts of its slots of y'' into BF16 parts and
 //     writes them, contiguous, into its cell's LDS record; a wavefront holds
 //     16 cells, multiplies exactly its own 16 records (one 16-column block),
@@ -38,6 +43,7 @@
 namespace mln {
 
 typedef short shortx4_t __attribute__((ext_vector_type(4)));
+typedef short shortx8_t __attribute__((ext_vector_type(8)));
 
 // slot layout of the four-lanes-per-cell split-BF16 kernel
 template <int N>
@@ -48,7 +54,9 @@ struct QuadSlots {
   static constexpr int USED = 2 * NP + NPOP;       // slots that can hold a row
   static constexpr int S = (USED + 3) / 4 * 4;     // slots per lane
   static constexpr int K = 4 * S;                  // GEMM size (rows = columns)
-  static constexpr int NB = K / 16;                // 16-blocks in M and in K
+  static constexpr int NB = K / 16;                // 16-row blocks of the output
+  static constexpr int KB32 = K / 32;              // 32-wide blocks of the contraction
+  static constexpr int R16 = (K % 32) / 16;        // and a remaining 16-wide block (0 or 1)
   // state row held in slot i of lane r, or -1 (padding)
   __host__ __device__ static constexpr int row(int r, int i) {
     if (i < 2 * NP) {
@@ -63,10 +71,11 @@ struct QuadSlots {
   }
   __host__ __device__ static constexpr int row_of_slot(int k) { return row(k / S, k % S); }
   // LDS record per cell (in bf16 units): NPART parts of K values, each part
-  // padded by 4; the FP32 result row (K floats = 2 K bf16) overlays the start.
-  // Records start 16-byte aligned, and their stride in dwords is 4 mod 8 so
-  // that the 16 cells of a B-operand read spread over the banks.
-  static constexpr int KP = K + 4;
+  // padded by 8 (16-byte aligned parts for the 8-value B-operand reads); the
+  // FP32 result row (K floats = 2 K bf16) overlays the start.  Records start
+  // 16-byte aligned, and their stride in dwords is 4 mod 8 so that the 16
+  // cells of a B-operand read spread over the banks.
+  static constexpr int KP = K + 8;
   template <int NPART>
   static constexpr int rec() {
     constexpr int need = NPART * KP > 2 * K ? NPART * KP : 2 * K;
@@ -82,7 +91,7 @@ template <int N, int NPROD>
 constexpr size_t mfmaq_lds_bytes(int W) {
   using SL = QuadSlots<N>;
   return (size_t)W * SL::template rec<NPROD == 6 ? 3 : 2>() * 2 + (size_t)4 * W * ((SL::USED + 1) / 2 * 2) * 4 +
-         (size_t)(NPROD == 6 ? 2 : 1) * SL::NB * SL::NB * 64 * 8;
+         (size_t)(NPROD == 6 ? 2 : 1) * SL::NB * (SL::KB32 * 64 * 16 + SL::R16 * 64 * 8);
 }
 
 constexpr int kMaxMfmaqTile = 256;  // cells per tile (1024 lanes)
@@ -91,6 +100,7 @@ template <int N, int NPROD>
 __global__ void __launch_bounds__(4 * kMaxMfmaqTile) fwd_mfmaq_kernel(FwdArgs<float> a) {
   using SL = QuadSlots<N>;
   constexpr int D = SL::D, S = SL::S, K = SL::K, NB = SL::NB, NP = SL::NP, USED = SL::USED, KP = SL::KP;
+  constexpr int KB32 = SL::KB32, R16 = SL::R16;
   constexpr int NPART = NPROD == 6 ? 3 : 2;
   constexpr int REC = SL::template rec<NPART>();
   extern __shared__ __align__(16) unsigned char smem[];
@@ -113,9 +123,11 @@ __global__ void __launch_bounds__(4 * kMaxMfmaqTile) fwd_mfmaq_kernel(FwdArgs<fl
   const int lane = t & 63, wave = t >> 6;
   const int W = blockDim.x >> 2;
   float2 *sPark = (float2 *)(smem + (size_t)W * REC * 2);
-  // middle (and low) factor parts: fragment f = NB mb + kb of lane at
-  // sA[(part NB^2 + f) 64 + lane]
-  shortx4_t *sA = (shortx4_t *)(smem + (size_t)W * REC * 2 + (size_t)4 * W * NH * 8);
+  // middle (and low) factor parts, per part: the 32-wide fragments
+  // (mb, kb) of lane at byte ((KB32 mb + kb) 64 + lane) 16, then the 16-wide
+  // fragment of block mb at byte NB KB32 1024 + (64 mb + lane) 8
+  constexpr int APART = NB * (KB32 * 64 * 16 + R16 * 64 * 8);
+  unsigned char *sA = smem + (size_t)W * REC * 2 + (size_t)4 * W * NH * 8;
   for (int k = t; k < K; k += blockDim.x) {
     const int j = SL::row_of_slot(k);
     sCst[k] = j >= 0 ? make_float4(cld(a.fac.zr, j), cld(a.fac.wz, j), cld(a.fac.cz, j), cld(a.fac.cz_lo, j))
@@ -144,36 +156,59 @@ __global__ void __launch_bounds__(4 * kMaxMfmaqTile) fwd_mfmaq_kernel(FwdArgs<fl
   const int64_t c = g - a.mb;
   const int64_t nmed = a.me - a.mb;
 
-  // K - I in slot order, split into BF16 parts, A-operand layout of the
-  // 16x16x16 MFMA: lane holds A[16 mb + lane%16][16 kb + 4 (lane/16) + i].
-  // The high part stays in registers; the middle and low parts go to LDS (one
-  // copy per wavefront position: every wavefront writes the same values).
-  shortx4_t Ah[NB][NB];
+  // K - I in slot order, split into BF16 parts, A-operand layouts: lane
+  // holds A[16 mb + lane%16][32 kb + 8 (lane/16) + i] (i < 8) of a 32-wide
+  // block and A[16 mb + lane%16][32 KB32 + 4 (lane/16) + i] (i < 4) of the
+  // 16-wide one.  The high part stays in registers; the middle and low parts
+  // go to LDS (written once, by the first wavefront).
+  shortx8_t Ah[NB][KB32 > 0 ? KB32 : 1];
+  shortx4_t Ah16[NB];
+  auto split3 = [&](int jm, int jk, short &h, short &md, short &lo) {
+    const bool v = jm >= 0 && jk >= 0;
+    const float x = v ? cld(a.fac.Km, jm * D + jk) : 0.0f;
+    const float xl = v ? cld(a.fac.Km_lo, jm * D + jk) : 0.0f;
+    const unsigned short hh = f2bf(x);
+    const float r1 = (x - bf2f(hh)) + xl;
+    const unsigned short mm = f2bf(r1);
+    h = (short)hh;
+    md = (short)mm;
+    lo = (short)f2bf(r1 - bf2f(mm));
+  };
 #pragma unroll
-  for (int mb = 0; mb < NB; ++mb)
+  for (int mb = 0; mb < NB; ++mb) {
+    const int jm = SL::row_of_slot(16 * mb + (lane & 15));
 #pragma unroll
-    for (int kb = 0; kb < NB; ++kb) {
+    for (int kb = 0; kb < KB32; ++kb) {
+      shortx8_t am, al;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        short h, md, lo;
+        split3(jm, SL::row_of_slot(32 * kb + 8 * (lane >> 4) + i), h, md, lo);
+        Ah[mb][kb][i] = h;
+        am[i] = md;
+        al[i] = lo;
+      }
+      if (wave == 0) {
+        *(shortx8_t *)(sA + ((KB32 * mb + kb) * 64 + lane) * 16) = am;
+        if constexpr (NPROD == 6) *(shortx8_t *)(sA + APART + ((KB32 * mb + kb) * 64 + lane) * 16) = al;
+      }
+    }
+    if constexpr (R16 > 0) {
       shortx4_t am, al;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int jm = SL::row_of_slot(16 * mb + (lane & 15));
-        const int jk = SL::row_of_slot(16 * kb + 4 * (lane >> 4) + i);
-        const bool v = jm >= 0 && jk >= 0;
-        const float x = v ? cld(a.fac.Km, jm * D + jk) : 0.0f;
-        const float xl = v ? cld(a.fac.Km_lo, jm * D + jk) : 0.0f;
-        const unsigned short h = f2bf(x);
-        const float r1 = (x - bf2f(h)) + xl;
-        const unsigned short md = f2bf(r1);
-        const unsigned short lo = f2bf(r1 - bf2f(md));
-        Ah[mb][kb][i] = (short)h;
-        am[i] = (short)md;
-        al[i] = (short)lo;
+        short h, md, lo;
+        split3(jm, SL::row_of_slot(32 * KB32 + 4 * (lane >> 4) + i), h, md, lo);
+        Ah16[mb][i] = h;
+        am[i] = md;
+        al[i] = lo;
       }
       if (wave == 0) {
-        sA[(NB * mb + kb) * 64 + lane] = am;
-        if constexpr (NPROD == 6) sA[(NB * NB + NB * mb + kb) * 64 + lane] = al;
+        *(shortx4_t *)(sA + NB * KB32 * 1024 + (64 * mb + lane) * 8) = am;
+        if constexpr (NPROD == 6) *(shortx4_t *)(sA + APART + NB * KB32 * 1024 + (64 * mb + lane) * 8) = al;
       }
     }
+  }
 
   // fields (float-float), private copy of the left H face, state slots
   float E = 0, H = 0, Hl = 0, Elo = 0, Hlo = 0, Hll = 0;
@@ -212,6 +247,8 @@ __global__ void __launch_bounds__(4 * kMaxMfmaqTile) fwd_mfmaq_kernel(FwdArgs<fl
       if (g <= a.nx - 2) add_comp(H, Hlo, a.ch * ((Er - E) + (Erl - Elo)));
     }
     float P = 0.0f;
+    floatx4_t acc[NB], acs[NB];
+    const unsigned short *brec = sY + (size_t)(16 * wave + (lane & 15)) * REC;
     if (tile_med) {
       // per-slot constants are read from LDS inside the step loop: the offset
       // zo is always 0, but opaque to the compiler, so the loads are not
@@ -288,65 +325,93 @@ __global__ void __launch_bounds__(4 * kMaxMfmaqTile) fwd_mfmaq_kernel(FwdArgs<fl
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       // (K - I) y'' for the 16 cells of this wavefront: column n = lane%16 is
-      // cell 16 wave + n
-      {
-        const unsigned short *brec = sY + (size_t)(16 * wave + (lane & 15)) * REC;
-        const shortx4_t *aml = sA + lane + 64 * zo;
-        floatx4_t acc[NB];
+      // cell 16 wave + n; main terms in acc, the small cross terms in acs
 #pragma unroll
-        for (int mb = 0; mb < NB; ++mb) acc[mb] = floatx4_t{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int kb = 0; kb < NB; ++kb) {
-          const int k0 = 16 * kb + 4 * (lane >> 4);
-          const shortx4_t Bh = *(const shortx4_t *)&brec[k0];
-          const shortx4_t Bm = *(const shortx4_t *)&brec[KP + k0];
-          shortx4_t Bl;
-          if constexpr (NPART == 3) Bl = *(const shortx4_t *)&brec[2 * KP + k0];
-#pragma unroll
-          for (int mb = 0; mb < NB; ++mb) {
-            const shortx4_t Am = aml[(NB * mb + kb) * 64];
-            if constexpr (NPROD == 6) {
-              const shortx4_t Al = aml[(NB * NB + NB * mb + kb) * 64];
-              acc[mb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Al, Bh, acc[mb], 0, 0, 0);
-              acc[mb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Am, Bm, acc[mb], 0, 0, 0);
-              acc[mb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Ah[mb][kb], Bl, acc[mb], 0, 0, 0);
-            }
-            acc[mb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Am, Bh, acc[mb], 0, 0, 0);
-            acc[mb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Ah[mb][kb], Bm, acc[mb], 0, 0, 0);
-            acc[mb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Ah[mb][kb], Bh, acc[mb], 0, 0, 0);
-          }
-        }
-        // C layout: lane holds rows 16 mb + 4 (lane/16) + j of its column;
-        // every read of these records has fed acc already
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        float *res = (float *)brec;
-#pragma unroll
-        for (int mb = 0; mb < NB; ++mb) *(floatx4_t *)&res[16 * mb + 4 * (lane >> 4)] = acc[mb];
+      for (int mb = 0; mb < NB; ++mb) {
+        acc[mb] = floatx4_t{0.0f, 0.0f, 0.0f, 0.0f};
+        acs[mb] = floatx4_t{0.0f, 0.0f, 0.0f, 0.0f};
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      if (is_med) {
-        const float *res = (const float *)(sY + (size_t)cl * REC) + S * r;
+      const unsigned char *ab = sA + zo;
 #pragma unroll
-        for (int h = 0; h < NH; ++h) {
-          const float2 dd = sPark[h * 4 * W + t];
-          const float4 c0 = cst[2 * h];
-          add_comp(y[2 * h], l[2 * h], dd.x + (res[2 * h] + (c0.z + c0.w)));
-          if (2 * h + 1 < USED) {
-            const float4 c1 = cst[2 * h + 1];
-            add_comp(y[2 * h + 1], l[2 * h + 1], dd.y + (res[2 * h + 1] + (c1.z + c1.w)));
+      for (int kb = 0; kb < KB32; ++kb) {
+        const int k0 = 32 * kb + 8 * (lane >> 4);
+        const bf16x8_t Bh = __builtin_bit_cast(bf16x8_t, *(const shortx8_t *)&brec[k0]);
+        const bf16x8_t Bm = __builtin_bit_cast(bf16x8_t, *(const shortx8_t *)&brec[KP + k0]);
+        bf16x8_t Bl;
+        if constexpr (NPART == 3) Bl = __builtin_bit_cast(bf16x8_t, *(const shortx8_t *)&brec[2 * KP + k0]);
+#pragma unroll
+        for (int mb = 0; mb < NB; ++mb) {
+          const int off = ((KB32 * mb + kb) * 64 + lane) * 16;
+          const bf16x8_t Am = __builtin_bit_cast(bf16x8_t, *(const shortx8_t *)(ab + off));
+          const bf16x8_t Ahi = __builtin_bit_cast(bf16x8_t, Ah[mb][kb]);
+          if constexpr (NPROD == 6) {
+            const bf16x8_t Al = __builtin_bit_cast(bf16x8_t, *(const shortx8_t *)(ab + APART + off));
+            acs[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Bh, acs[mb], 0, 0, 0);
+            acs[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Am, Bm, acs[mb], 0, 0, 0);
+            acs[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ahi, Bl, acs[mb], 0, 0, 0);
           }
+          acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Am, Bh, acc[mb], 0, 0, 0);
+          acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ahi, Bm, acc[mb], 0, 0, 0);
+          acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ahi, Bh, acc[mb], 0, 0, 0);
+        }
+      }
+      if constexpr (R16 > 0) {
+        const int k0 = 32 * KB32 + 4 * (lane >> 4);
+        const shortx4_t Bh = *(const shortx4_t *)&brec[k0];
+        const shortx4_t Bm = *(const shortx4_t *)&brec[KP + k0];
+        shortx4_t Bl;
+        if constexpr (NPART == 3) Bl = *(const shortx4_t *)&brec[2 * KP + k0];
+#pragma unroll
+        for (int mb = 0; mb < NB; ++mb) {
+          const int off = NB * KB32 * 1024 + (64 * mb + lane) * 8;
+          const shortx4_t Am = *(const shortx4_t *)(ab + off);
+          if constexpr (NPROD == 6) {
+            const shortx4_t Al = *(const shortx4_t *)(ab + APART + off);
+            acs[mb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Al, Bh, acs[mb], 0, 0, 0);
+            acs[mb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Am, Bm, acs[mb], 0, 0, 0);
+            acs[mb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Ah16[mb], Bl, acs[mb], 0, 0, 0);
+          }
+          acc[mb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Am, Bh, acc[mb], 0, 0, 0);
+          acc[mb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Ah16[mb], Bm, acc[mb], 0, 0, 0);
+          acc[mb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Ah16[mb], Bh, acc[mb], 0, 0, 0);
         }
       }
     }
+    // E is updated while the matrix cores work (it needs P, not the product)
     const float Eold = E, Eoldl = Elo;
     if (g >= 1 && g <= a.nx - 2) {
       add_comp(E, Elo, a.cam1 * E + a.cb * (-P + ((H - Hl) + (Hlo - Hll)) * a.inv_dx));
     } else if (g == 0) {
       E = sSrc[s];
       Elo = sSrcl[s];
+    }
+    if (tile_med) {
+      // C layout: lane holds rows 16 mb + 4 (lane/16) + j of its column;
+      // every read of these records has fed the accumulators already
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      float *res = (float *)brec;
+#pragma unroll
+      for (int mb = 0; mb < NB; ++mb)
+        *(floatx4_t *)&res[16 * mb + 4 * (lane >> 4)] = NPROD == 6 ? acc[mb] + acs[mb] : acc[mb];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (is_med) {
+        const int zo = (int)(a.opaque0 * s);
+        const float4 *cst = sCst + S * r + zo;
+        const float *rs = (const float *)(sY + (size_t)cl * REC) + S * r;
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+          const float2 dd = sPark[h * 4 * W + t];
+          const float4 c0 = cst[2 * h];
+          add_comp(y[2 * h], l[2 * h], dd.x + (rs[2 * h] + (c0.z + c0.w)));
+          if (2 * h + 1 < USED) {
+            const float4 c1 = cst[2 * h + 1];
+            add_comp(y[2 * h + 1], l[2 * h + 1], dd.y + (rs[2 * h + 1] + (c1.z + c1.w)));
+          }
+        }
+      }
     }
     if (has_right) {  // first-order Mur boundary at cell nx-1
       if (g == a.nx - 2 && r == 0) {

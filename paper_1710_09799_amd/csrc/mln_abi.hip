@@ -362,6 +362,22 @@ int set_kernel(mln_handle *h, int variant_req, int tile, int steps_per_launch) {
   int K = steps_per_launch > 0
               ? steps_per_launch
               : (pade_wave ? 8 : (h->wave ? h->W / 8 : (h->mfma ? 16 : (h->quad ? h->W / 4 : 32))));
+  if (steps_per_launch <= 0 && (h->qmf || (h->mfma && h->quad))) {
+    // the matrix-core quad kernels: a step costs about the same with any
+    // number of tiles up to one per compute unit, and every launch has a
+    // fixed cost (prologue, epilogue, kernel boundary), so take the largest
+    // even step count (up to 24 at N = 3, 30 at N = 4, 6; measured optimum)
+    // that keeps the tiles within the compute units
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus <= 0)
+      cus = 256;
+    const int kmax = std::min(h->qmf ? 24 : 30, (h->W - 1) / 2);
+    for (int k = kmax & ~1; k >= 8; k -= 2)
+      if ((h->grid.nx + (h->W - 2 * k) - 1) / (h->W - 2 * k) <= cus) {
+        K = k;
+        break;
+      }
+  }
   if (2 * K >= h->W || K > kMaxStepsPerLaunch)
     return set_err(MLN_EINVAL, "steps_per_launch must be below tile/2 (and at most 128)");
   if (pade_wave && pade_lds_bytes(h->f.N, h->rs, h->W) > kPadeMaxLds)
