@@ -114,10 +114,10 @@ __device__ __forceinline__ void sincm1(float x, float &s, float &cm1) {
 // The same with the device-library path (|x| > 1/2 somewhere in the
 // wavefront) kept out of line: kernels whose register budget is tight do not
 // carry that path's registers through their step loop.
-__device__ __noinline__ void sincm1_library(float x, float &s, float &cm1) {
+// (returns (sin x, cos x - 1) by value: results in registers, no stack frame)
+__device__ __noinline__ float2 sincm1_library(float x) {
   const float h = sinf(0.5f * x);
-  s = sinf(x);
-  cm1 = -2.0f * h * h;
+  return make_float2(sinf(x), -2.0f * h * h);
 }
 
 __device__ __forceinline__ void sincm1_lean(float x, float &s, float &cm1) {
@@ -132,7 +132,9 @@ __device__ __forceinline__ void sincm1_lean(float x, float &s, float &cm1) {
     const float ca = fmaf(x2, 1.0f / 24.0f, -0.5f), cb = fmaf(x2, 1.0f / 40320.0f, -1.0f / 720.0f);
     cm1 = x2 * fmaf(x4, fmaf(x4, -1.0f / 3628800.0f, cb), ca);
   } else {
-    sincm1_library(x, s, cm1);
+    const float2 r = sincm1_library(x);
+    s = r.x;
+    cm1 = r.y;
   }
 }
 
