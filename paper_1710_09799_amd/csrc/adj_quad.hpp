@@ -30,8 +30,12 @@ namespace mln {
 
 constexpr int kMaxAdjQuadTile = 128;  // cells per tile (512 lanes: room for the accumulators)
 
-template <int N, typename Real>
-__global__ void __launch_bounds__(4 * kMaxAdjQuadTile) adj_quad_kernel(AdjArgs<Real> a) {
+// LB: the launch bound the instance is built for; the 256-lane instance
+// (tiles of at most 64 cells) has the whole register file of a SIMD for one
+// wavefront, which the FP64 three-level reverse step needs to run without
+// spilling (its 512-lane build spills 216 bytes per lane).
+template <int N, typename Real, int LB = 4 * kMaxAdjQuadTile>
+__global__ void __launch_bounds__(LB) adj_quad_kernel(AdjArgs<Real> a) {
   constexpr int D = N * N - 1, Q = N * (N - 1) / 2;
   static_assert(D <= 8, "four lanes of two components each");
   constexpr bool F64 = sizeof(Real) == 8;

@@ -1173,6 +1173,14 @@ int mln_grad(mln_handle *h, const double *dJ_dprobe, mln_grads *out) {
     rhalo = 16;
     rowned = rW - 2 * rhalo;
     rtiles = (h->grid.nx + rowned - 1) / rowned;
+  } else if (rquad && f64 && N == 3 && rW > 64) {
+    // the FP64 three-level reverse step runs spill-free only on the
+    // 256-lane build: 64-cell tiles, 16 steps per launch (the tape is read
+    // by cell, so the reverse tiling need not be the forward one)
+    rW = 64;
+    rhalo = 16;
+    rowned = rW - 2 * rhalo;
+    rtiles = (h->grid.nx + rowned - 1) / rowned;
   }
   if (!h->gprobe.p) {
     for (int b = 0; b < 2; ++b) {
