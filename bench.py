@@ -215,6 +215,51 @@ def cpu_baseline(reps=REPS):
             "single_thread": head["single_thread"], "per_config": per}
 
 
+ADJ_KW = dict(precision="fp32c", variant="quad", tile=128, steps_per_launch=32)
+
+
+def adjoint_legs(reps):
+    """The adjoint workload (three-level ladder, 10000 cells x 50000 steps,
+    compensated FP32) with checkpoints every 500 steps (the gradient pass
+    recomputes each segment) and with the whole forward tape in device
+    memory; medians of `reps` forward runs and gradient passes, against the
+    plain forward run."""
+    import torch
+    from paper_1710_09799_amd import mln
+    from paper_1710_09799_amd import workloads as W
+    pa = W.adjoint_case()
+    akw = ADJ_KW
+    t_plain, _, _, _ = time_solver(pa, reps, 1, 0, record_pop=False, record_e=False, **akw)
+    res = {}
+    for name, ck in (("adjoint_fp32c", 500), ("adjoint_fp32c_whole_tape", "tape")):
+        s = mln.Solver(pa, ckpt_every=ck, **akw)
+        s.run()
+        s.grad(2 * pa.grid.dt * s.probe.cpu().numpy())  # warm-up (allocates the adjoint buffers)
+        tfs, tgs = [], []
+        for _ in range(reps):
+            s.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = s.run()
+            torch.cuda.synchronize()
+            tfs.append(time.perf_counter() - t0)
+            gp = 2 * pa.grid.dt * out["probe"].cpu().numpy()
+            t0 = time.perf_counter()
+            s.grad(gp)
+            tgs.append(time.perf_counter() - t0)
+        s.close()
+        tf, tg = _median(tfs), _median(tgs)
+        r = {"forward_ms": t_plain * 1e3, ("forward_with_checkpoints_ms" if ck == 500 else "forward_with_tape_ms"):
+             tf * 1e3, "grad_ms": tg * 1e3, "grad_over_forward": tg / t_plain, "total_over_forward": (tf + tg) / t_plain}
+        if ck == 500:
+            r["workload"] = "three-level ladder, 10000 cells, 50000 steps, checkpoint every 500"
+        else:
+            r["tape_GB"] = 9 * 10048 * pa.grid.nt * 4 / 1e9
+            r["workload"] = "three-level ladder, 10000 cells, 50000 steps, whole tape in device memory"
+        res[name] = {**r, **akw}
+    return res
+
+
 def variants(p3, ref64, pop64, headline):
     """The other configurations of the metric, one warm-up and one timed run
     each."""
@@ -350,53 +395,7 @@ def variants(p3, ref64, pop64, headline):
             bat[prec]["max_err_E_vs_fp64"] = max(eE)
             bat[prec]["max_err_pop_vs_fp64"] = max(eP)
     var["batched_64"] = bat
-    # adjoint: three-level ladder, 10000 cells x 50000 steps, checkpoints every 500
-    pa = W.adjoint_case()
-    akw = dict(precision="fp32c", variant="quad", tile=128, steps_per_launch=32)
-    s = mln.Solver(pa, ckpt_every=500, **akw)
-    s.run()
-    s.grad(2 * pa.grid.dt * s.probe.cpu().numpy())  # warm-up (allocates the adjoint buffers)
-    s.reset()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    out = s.run()
-    torch.cuda.synchronize()
-    tf = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    s.grad(2 * pa.grid.dt * out["probe"].cpu().numpy())
-    tg = time.perf_counter() - t0
-    s.close()
-    t_plain, _, _, _ = time_solver(pa, REPS, 1, 0, record_pop=False, record_e=False, **akw)
-    var["adjoint_fp32c"] = {"forward_ms": t_plain * 1e3, "forward_with_checkpoints_ms": tf * 1e3,
-                            "grad_ms": tg * 1e3, "grad_over_forward": tg / t_plain,
-                            "total_over_forward": (tf + tg) / t_plain,
-                            "workload": "three-level ladder, 10000 cells, 50000 steps, checkpoint every 500",
-                            **akw}
-    # the same with the whole forward tape kept in HBM (z' and E of every
-    # step, 18 GB): mln_grad reverses without recomputation; median of REPS
-    s = mln.Solver(pa, ckpt_every="tape", **akw)
-    s.run()
-    s.grad(2 * pa.grid.dt * s.probe.cpu().numpy())  # warm-up
-    tfs, tgs = [], []
-    for _ in range(REPS):
-        s.reset()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        out = s.run()
-        torch.cuda.synchronize()
-        tfs.append(time.perf_counter() - t0)
-        gp = 2 * pa.grid.dt * out["probe"].cpu().numpy()
-        t0 = time.perf_counter()
-        s.grad(gp)
-        tgs.append(time.perf_counter() - t0)
-    s.close()
-    tf, tg = _median(tfs), _median(tgs)
-    var["adjoint_fp32c_whole_tape"] = {"forward_ms": t_plain * 1e3, "forward_with_tape_ms": tf * 1e3,
-                                       "grad_ms": tg * 1e3, "grad_over_forward": tg / t_plain,
-                                       "total_over_forward": (tf + tg) / t_plain,
-                                       "tape_GB": 9 * 10048 * pa.grid.nt * 4 / 1e9,
-                                       "workload": "three-level ladder, 10000 cells, 50000 steps, whole tape "
-                                                   "in device memory", **akw}
+    var.update(adjoint_legs(REPS))
     return var
 
 
@@ -657,6 +656,9 @@ def profile_tmz(name, nt, precision, steps, warmup):
 
 def profile_case(name, steps, warmup, calib):
     from paper_1710_09799_amd import workloads as W
+    if name == "adjoint":
+        print(json.dumps({"profile_case": name, **adjoint_legs(max(steps, 1))}))
+        return
     wl, pkw, kw = PROFILE_CASES[name]
     if wl == "tmz":
         profile_tmz(name, pkw["nt"], kw["precision"], steps, warmup)
@@ -689,7 +691,7 @@ def main():
                     help="precision of the headline run (the others are reported as variants)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM counters)")
-    ap.add_argument("--profile-case", choices=sorted(PROFILE_CASES),
+    ap.add_argument("--profile-case", choices=sorted(PROFILE_CASES) + ["adjoint"],
                     help="run only this workload (for hardware counters) and print its timing")
     args = ap.parse_args()
     if args.gpus != 1:
