@@ -215,7 +215,7 @@ def cpu_baseline(reps=REPS):
             "single_thread": head["single_thread"], "per_config": per}
 
 
-ADJ_KW = dict(precision="fp32c", variant="quad", tile=128, steps_per_launch=32)
+ADJ_KW = dict(precision="fp32c", variant="quad_mfma", tile=128, steps_per_launch=24)
 
 
 def adjoint_legs(reps):

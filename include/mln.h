@@ -340,6 +340,20 @@ int mln_bloch_only_noalloc(mln_handle *h, const double *efield, int64_t n_steps,
  * Synchronises. */
 int mln_grad(mln_handle *h, const double *dJ_dprobe, mln_grads *out);
 
+/* Tiling of mln_grad's reverse kernel.  variant 0 (default): automatic
+ * (after a four-lanes-per-cell forward kernel: 128-cell tiles and the
+ * largest even step count up to 48 that keeps the tiles within the compute
+ * units, 16 where none does; 64-cell tiles and 16 steps for the FP64
+ * three-level reverse step; 256 cells and 16 steps after the streamed
+ * forward kernel; otherwise the forward kernel's tiling); 1: one thread per cell, tile a multiple of 64 in [64,
+ * 256]; 3: four lanes per cell, tile a multiple of 16 in [16, 128].  tile 0:
+ * 256 (variant 1) or 128; steps_per_launch 0: tile/4; the halo is
+ * steps_per_launch cells on each side, so 2 steps_per_launch < tile.  The
+ * tape is read by cell, so the reverse tiling is independent of the forward
+ * one; every tiling gives the same gradient to rounding.  Errors:
+ * MLN_EINVAL, MLN_ENOTSUPPORTED (route or N the adjoint does not cover). */
+int mln_configure_adjoint(mln_handle *h, int32_t variant, int32_t tile, int32_t steps_per_launch);
+
 void mln_free(mln_handle *h);
 
 const char *mln_strerror(int code);

@@ -28,7 +28,6 @@
 
 namespace mln {
 
-constexpr int kMaxAdjQuadTile = 128;  // cells per tile (512 lanes: room for the accumulators)
 
 // LB: the launch bound the instance is built for; the 256-lane instance
 // (tiles of at most 64 cells) has the whole register file of a SIMD for one
@@ -104,18 +103,20 @@ __global__ void __launch_bounds__(LB) adj_quad_kernel(AdjArgs<Real> a) {
     sS[i] = a.samples[a.n_hi - i];
   }
   if (t < 6) sE[t & 1][t < 2 ? 0 : (t < 4 ? W + 1 : W + 2)] = Real(0);
-  // tape values (y' of this lane's rows and E) of the step being reversed,
-  // loaded one step ahead so that their memory latency overlaps the work
-  Real ty0 = 0, ty1 = 0, tE = 0;
-  auto tape_load = [&](int64_t nn) {
-    if (is_med && a.nsteps > 0 && nn >= a.tape_step0) {
+  // tape values (y' of this lane's rows and E) of the step being reversed
+  // (t*) and of the step after it (u*): loaded two steps ahead, since one
+  // step takes about as long as a load from HBM
+  Real ty0 = 0, ty1 = 0, tE = 0, uy0 = 0, uy1 = 0, uE = 0;
+  auto tape_load = [&](int64_t nn, Real &y0, Real &y1, Real &e) {
+    if (is_med && nn >= a.tape_step0) {
       const Real *tp = a.tape + (nn - a.tape_step0) * (D + 1) * a.ld + c;
-      ty0 = v0 ? tp[i0 * a.ld] : Real(0);
-      ty1 = v1 ? tp[i1 * a.ld] : Real(0);
-      tE = tp[D * a.ld];
+      y0 = v0 ? tp[i0 * a.ld] : Real(0);
+      y1 = v1 ? tp[i1 * a.ld] : Real(0);
+      e = tp[D * a.ld];
     }
   };
-  tape_load(a.n_hi - 1);
+  if (a.nsteps > 0) tape_load(a.n_hi - 1, ty0, ty1, tE);
+  if (a.nsteps > 1) tape_load(a.n_hi - 2, uy0, uy1, uE);
   __syncthreads();
   for (int s = 0; s < a.nsteps; ++s) {
     const int64_t n = a.n_hi - 1 - s;
@@ -156,7 +157,10 @@ __global__ void __launch_bounds__(LB) adj_quad_kernel(AdjArgs<Real> a) {
       const Real x0 = v0 ? ty0 + zr0 : Real(0);  // z' of this lane's rows
       const Real x1 = v1 ? ty1 + zr1 : Real(0);
       const Real E = tE;
-      if (s + 1 < a.nsteps) tape_load(n - 1);
+      ty0 = uy0;
+      ty1 = uy1;
+      tE = uE;
+      if (s + 2 < a.nsteps) tape_load(n - 2, uy0, uy1, uE);
       Real sn = 0, cm = 0, z0 = x0, z1 = x1;  // z'' = Rot(x) z'
       if (rot) {
         sincm1(th * E, sn, cm);
@@ -259,13 +263,14 @@ __global__ void __launch_bounds__(LB) adj_quad_kernel(AdjArgs<Real> a) {
       if (v1) a.lzout[i1 * a.ld + c] = lz1;
     }
   }
-  // per-tile sums: over the 16 cells of a wavefront (lanes of equal r), then
-  // over the wavefronts through LDS
+  // per-tile sums: over the 16 cells of a wavefront (lanes of equal r: the
+  // lanes 4 and 8 apart within each 16-lane row by DPP row rotations, then
+  // the four rows by the permlane swaps), then over the wavefronts through LDS
   const int wid = t >> 6;
   auto wsum = [&](Real x) {
-#pragma unroll
-    for (int off = 4; off < 64; off <<= 1) x += __shfl_xor(x, off, 64);
-    return x;
+    x += row_ror<4>(x);
+    x += row_ror<8>(x);
+    return row_sum(x);
   };
   const bool lead = (t & 63) < 4;  // lanes 0..3 of the wavefront hold the sums
 #pragma unroll
@@ -307,7 +312,10 @@ __global__ void __launch_bounds__(LB) adj_quad_kernel(AdjArgs<Real> a) {
   for (int i = t; i < NACC; i += blockDim.x) {
     double acc = 0.0;
     for (int w = 0; w < nw; ++w) acc += sRed[w][i];
-    a.partial[(int64_t)blockIdx.x * NACC + i] += acc;
+    // the tile's own slot (no other tile adds to it; launches are ordered on
+    // the stream, so the sums are deterministic): a no-return atomic add
+    // lets the wavefront finish without waiting for the old value
+    atomicAdd(&a.partial[(int64_t)blockIdx.x * NACC + i], acc);
   }
 }
 

@@ -13,6 +13,7 @@ constexpr int kMaxTile = 256;      // threads (= cells) per tile workgroup
 constexpr int kMaxQuadTile = 256;  // cells per tile of the four-lanes-per-cell kernel
 constexpr int64_t kQuadMaxAutoCells = 100000;  // automatic variant: quad kernel below this grid size
 constexpr int kMaxStepsPerLaunch = 128;  // time steps fused into one launch (halo <= tile/2 < 128)
+constexpr int kMaxAdjQuadTile = 128;    // cells per four-lanes-per-cell reverse tile (512 lanes)
 constexpr int kStreamThreads = 256;       // threads per workgroup of the streamed kernel
 constexpr int kStreamCells = 1;           // consecutive cells per thread of the streamed kernel
 constexpr int kPadeMax = 7;              // highest Pade degree of the per-step Pade route
@@ -187,8 +188,7 @@ constexpr int adj_nacc(int N, bool fp64) {
 template <typename Real>
 hipError_t launch_adj(int N, const AdjArgs<Real> &a, int64_t nblocks, int W, hipStream_t st);
 // Four-lanes-per-cell adjoint kernel (adj_quad.hpp), N = 2 or 3, W <= 128
-// cells per tile (4 W lanes), the tiling of the forward four-lanes-per-cell
-// kernel.
+// cells per tile (4 W lanes, W a multiple of 16).
 template <typename Real>
 hipError_t launch_adj_quad(int N, const AdjArgs<Real> &a, int64_t nblocks, int W, hipStream_t st);
 

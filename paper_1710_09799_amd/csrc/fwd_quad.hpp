@@ -97,6 +97,19 @@ __device__ __forceinline__ double row_sum(double x) {
   return __hiloint2double((int)qh[0], (int)ql[0]) + __hiloint2double((int)qh[1], (int)ql[1]);
 }
 
+// DPP row rotation: lane i of each 16-lane row receives lane (i - N) mod 16
+// of that row
+template <int N>
+__device__ __forceinline__ float row_ror(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x120 + N, 0xf, 0xf, false));
+}
+template <int N>
+__device__ __forceinline__ double row_ror(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0x120 + N, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0x120 + N, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
 typedef float mf_f32x4 __attribute__((ext_vector_type(4)));
 typedef double mf_f64x4 __attribute__((ext_vector_type(4)));
 template <typename Real>

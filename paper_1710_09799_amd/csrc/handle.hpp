@@ -114,6 +114,12 @@ struct mln_handle {
   DevBuf ckpt;
   // adjoint buffers (allocated by the first mln_grad)
   DevBuf lE[2], lH[2], lz[2], tape, partial, gprobe, samples_dev;
+  // with checkpoints, mln_grad rebuilds the next segment on aux_stream into
+  // the other tape buffer (tape2) while the current one is reversed;
+  // ev_rec[b] / ev_rev[b]: tape buffer b written / read
+  DevBuf tape2;
+  hipStream_t aux_stream = nullptr;
+  hipEvent_t ev_start = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
   double fd_coef[6] = {0, 0, 0, 0, 0, 0};  // ch, ca, cb, inv_dx, kmur, ca - 1
   // the same coefficients for the single-precision kernels: ch and inv_dx
   // chosen so that ch * cb * inv_dx (the squared Courant number that sets the
@@ -126,6 +132,8 @@ struct mln_handle {
   // the run's launches, captured on a private stream on first use and
   // dropped when the kernel configuration changes
   bool use_graph = true;
+  // reverse-kernel tiling (mln_configure_adjoint): variant 0 = automatic
+  int adj_variant = 0, adj_W = 0, adj_K = 0;
   hipStream_t cap_stream = nullptr;
   hipGraph_t run_graph = nullptr;
   hipGraphExec_t run_exec = nullptr;
@@ -138,6 +146,12 @@ struct mln_handle {
   ~mln_handle() {
     drop_graph();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (aux_stream) {
+      (void)hipStreamSynchronize(aux_stream);
+      (void)hipStreamDestroy(aux_stream);
+    }
+    for (hipEvent_t e : {ev_start, ev_rec[0], ev_rec[1], ev_rev[0], ev_rev[1]})
+      if (e) (void)hipEventDestroy(e);
   }
 };
 

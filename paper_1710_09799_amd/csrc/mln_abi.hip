@@ -790,6 +790,30 @@ int mln_tune(mln_handle *h, int32_t trial_steps, int32_t *variant, int32_t *tile
   return MLN_OK;
 }
 
+int mln_configure_adjoint(mln_handle *h, int32_t variant, int32_t tile, int32_t steps_per_launch) {
+  if (!h) return set_err(MLN_EINVAL, "null handle");
+  if (variant == 0) {
+    if (tile || steps_per_launch) return set_err(MLN_EINVAL, "the automatic reverse tiling takes tile 0 and steps 0");
+    h->adj_variant = h->adj_W = h->adj_K = 0;
+    return MLN_OK;
+  }
+  if (variant != 1 && variant != 3)
+    return set_err(MLN_EINVAL, "reverse-kernel variant must be 0 (automatic), 1 or 3");
+  if (h->route != MLN_ROUTE_ROTATION || h->f.N > 3)
+    return set_err(MLN_ENOTSUPPORTED, "the adjoint is built for the rotation route and N <= 3");
+  const int W = tile > 0 ? tile : (variant == 1 ? kMaxTile : kMaxAdjQuadTile);
+  if (variant == 1 ? (W < 64 || W > kMaxTile || W % 64) : (W < 16 || W > kMaxAdjQuadTile || W % 16))
+    return set_err(MLN_EINVAL, variant == 1 ? "reverse tile must be a multiple of 64 in [64, 256]"
+                                            : "reverse quad tile must be a multiple of 16 in [16, 128]");
+  const int K = steps_per_launch > 0 ? steps_per_launch : W / 4;
+  if (steps_per_launch < 0 || 2 * K >= W || K > kMaxStepsPerLaunch)
+    return set_err(MLN_EINVAL, "reverse steps per launch must be in [1, tile/2)");
+  h->adj_variant = variant;
+  h->adj_W = W;
+  h->adj_K = K;
+  return MLN_OK;
+}
+
 int mln_get_config(const mln_handle *h, int32_t *variant, int32_t *tile, int32_t *steps_per_launch) {
   if (!h) return set_err(MLN_EINVAL, "null handle");
   if (variant) *variant = h->streamed ? 4 : (h->qmf ? 5 : (h->quad ? 3 : (h->wave ? 2 : 1)));
@@ -1161,16 +1185,42 @@ int mln_grad(mln_handle *h, const double *dJ_dprobe, mln_grads *out) {
   const int nacc = N == 2 ? adj_nacc(2, f64) : adj_nacc(3, f64);
   const int nm = adj_moments(f64);
   const size_t rs = h->rs;
-  // reverse-kernel tiling: the forward kernel's, except after the streamed
-  // forward kernel (one step per launch), whose segments are reversed by the
-  // one-cell-per-thread tile kernel, 256 cells and 16 steps per launch
+  // reverse-kernel tiling (the tape is read by cell, so it need not be the
+  // forward one): mln_configure_adjoint's if set; else after the streamed
+  // forward kernel (one step per launch) the one-cell-per-thread tile kernel,
+  // 256 cells and 16 steps per launch; after a four-lanes-per-cell forward
+  // kernel the four-lanes-per-cell reverse kernel on 128-cell tiles with the
+  // largest even step count up to 48 that keeps the tiles within the compute
+  // units (a reverse launch has a fixed cost of about eight steps: prologue,
+  // per-tile sums, kernel boundary), 16 where none does; otherwise the
+  // forward kernel's tiling
   bool rquad = h->quad;
   int rW = h->W, rhalo = h->halo, rowned = h->owned;
   int64_t rtiles = h->ntiles;
-  if (h->streamed) {
+  if (h->adj_variant) {
+    // set by mln_configure_adjoint
+    rquad = h->adj_variant == 3;
+    rW = h->adj_W;
+    rhalo = h->adj_K;
+    rowned = rW - 2 * rhalo;
+    rtiles = (h->grid.nx + rowned - 1) / rowned;
+  } else if (h->streamed) {
     rquad = false;
     rW = kMaxTile;
     rhalo = 16;
+    rowned = rW - 2 * rhalo;
+    rtiles = (h->grid.nx + rowned - 1) / rowned;
+  } else if (rquad && !(f64 && N == 3)) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus <= 0)
+      cus = 256;
+    rW = kMaxAdjQuadTile;
+    rhalo = 16;
+    for (int k = 48; k > 16; k -= 2)
+      if ((h->grid.nx + (rW - 2 * k) - 1) / (rW - 2 * k) <= cus) {
+        rhalo = k;
+        break;
+      }
     rowned = rW - 2 * rhalo;
     rtiles = (h->grid.nx + rowned - 1) / rowned;
   } else if (rquad && f64 && N == 3 && rW > 64) {
@@ -1189,6 +1239,7 @@ int mln_grad(mln_handle *h, const double *dJ_dprobe, mln_grads *out) {
       HIP_TRY(h->lz[b].alloc(rs * D * h->ld));
     }
     if (!h->tape_all) HIP_TRY(h->tape.alloc(rs * (size_t)h->ckpt_every * (D + 1) * h->ld));
+    if (!h->tape_all && h->nckpt > 1) HIP_TRY(h->tape2.alloc(rs * (size_t)h->ckpt_every * (D + 1) * h->ld));
     HIP_TRY(h->gprobe.alloc(sizeof(double) * (nt + 1)));
     HIP_TRY(h->samples_dev.alloc(sizeof(double) * (nt + 1)));
     HIP_TRY(hipMemcpy(h->samples_dev.p, h->samples.data(), sizeof(double) * (nt + 1), hipMemcpyHostToDevice));
@@ -1206,18 +1257,59 @@ int mln_grad(mln_handle *h, const double *dJ_dprobe, mln_grads *out) {
   int lc = 0;
   // segments: the checkpoint intervals (each rebuilt from its checkpoint,
   // writing the tape), or with the whole tape in memory one segment and no
-  // recomputation
+  // recomputation.  With two or more checkpoint intervals the rebuild of
+  // segment k-1 runs on a second stream into the other of two tape buffers
+  // while segment k is reversed on the handle's stream (the two kernels are
+  // latency-bound and fit on one compute unit together); events order each
+  // reverse sweep after its rebuild and each rebuild after the sweep that
+  // last read its buffer.
   const int64_t nseg = h->tape_all ? 1 : h->nckpt;
-  for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+  const bool overlap = !h->tape_all && nseg > 1;
+  if (overlap && !h->aux_stream) {
+    HIP_TRY(hipStreamCreateWithFlags(&h->aux_stream, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&h->ev_start, hipEventDisableTiming));
+    for (int b = 0; b < 2; ++b) {
+      HIP_TRY(hipEventCreateWithFlags(&h->ev_rec[b], hipEventDisableTiming));
+      HIP_TRY(hipEventCreateWithFlags(&h->ev_rev[b], hipEventDisableTiming));
+    }
+  }
+  if (overlap) {
+    HIP_TRY(hipEventRecord(h->ev_start, h->stream));
+    HIP_TRY(hipStreamWaitEvent(h->aux_stream, h->ev_start, 0));
+  }
+  // the rebuilds enqueue on h->stream: point it at the second stream for
+  // them, and restore it (and let the second stream drain) on every exit
+  struct Restore {
+    mln_handle *h;
+    hipStream_t main;
+    bool overlap;
+    ~Restore() {
+      h->stream = main;
+      if (overlap) (void)hipStreamSynchronize(h->aux_stream);
+    }
+  } restore{h, h->stream, overlap};
+  DevBuf *tapes[2] = {&h->tape, &h->tape2};
+  for (int64_t seg = nseg - 1, it = 0; seg >= 0; --seg, ++it) {
     const int64_t s0 = h->tape_all ? 0 : seg * h->ckpt_every;
     const int64_t s1 = h->tape_all ? nt : std::min<int64_t>(s0 + h->ckpt_every, nt);
+    const int tb = overlap ? (int)(it & 1) : 0;
+    void *tape_p = tapes[tb]->p;
     if (!h->tape_all) {
+      if (overlap) {
+        h->stream = h->aux_stream;
+        if (it >= 2) HIP_TRY(hipStreamWaitEvent(h->aux_stream, h->ev_rev[tb], 0));
+      }
       h->cur = 0;
       int rc = ckpt_copy(h, seg, false);
       if (rc) return rc;
       h->step = s0;
-      rc = forward_steps(h, s1 - s0, false, h->tape.p, s0, false);
+      rc = forward_steps(h, s1 - s0, false, tape_p, s0, false);
       if (rc) return rc;
+      if (overlap) {
+        HIP_TRY(hipEventRecord(h->ev_rec[tb], h->aux_stream));
+        h->stream = restore.main;
+        HIP_TRY(hipStreamWaitEvent(h->stream, h->ev_rec[tb], 0));
+      }
     }
     for (int64_t n_hi = s1; n_hi > s0;) {
       const int k = (int)std::min<int64_t>(rhalo, n_hi - s0);
@@ -1231,7 +1323,7 @@ int mln_grad(mln_handle *h, const double *dJ_dprobe, mln_grads *out) {
         a.lHout = (double *)h->lH[1 - lc].p;
         a.lzin = (const double *)h->lz[lc].p;
         a.lzout = (double *)h->lz[1 - lc].p;
-        a.tape = (const double *)h->tape.p;
+        a.tape = (const double *)tape_p;
         a.tape_step0 = s0;
         a.gprobe = (const double *)h->gprobe.p;
         a.samples = (const double *)h->samples_dev.p;
@@ -1251,7 +1343,7 @@ int mln_grad(mln_handle *h, const double *dJ_dprobe, mln_grads *out) {
         a.lHout = (float *)h->lH[1 - lc].p;
         a.lzin = (const float *)h->lz[lc].p;
         a.lzout = (float *)h->lz[1 - lc].p;
-        a.tape = (const float *)h->tape.p;
+        a.tape = (const float *)tape_p;
         a.tape_step0 = s0;
         a.gprobe = (const double *)h->gprobe.p;
         a.samples = (const double *)h->samples_dev.p;
@@ -1267,6 +1359,7 @@ int mln_grad(mln_handle *h, const double *dJ_dprobe, mln_grads *out) {
       lc = 1 - lc;
       n_hi -= k;
     }
+    if (overlap) HIP_TRY(hipEventRecord(h->ev_rev[tb], h->stream));
   }
   HIP_TRY(hipStreamSynchronize(h->stream));
   if (!h->tape_all) {

@@ -89,7 +89,7 @@ class _Factors(ctypes.Structure):
 
 # every symbol include/mln.h declares
 EXPORTS = ["mln_init", "mln_step", "mln_run", "mln_use_graph", "mln_reset", "mln_current_step", "mln_get_config", "mln_configure", "mln_tune",
-           "mln_get_fields", "mln_get_state", "mln_get_bloch", "mln_set_state",
+           "mln_configure_adjoint", "mln_get_fields", "mln_get_state", "mln_get_bloch", "mln_set_state",
            "mln_state_bytes", "mln_save_state", "mln_load_state", "mln_bloch_only", "mln_bloch_only_noalloc", "mln_free",
            "mln_strerror", "mln_last_error", "mln_setup_factors", "mln_version", "mln_grad",
            "mln_chain_rule", "mln_init_batch", "mln_batch_tune", "mln_batch_configure",
@@ -125,6 +125,7 @@ def load():
         "mln_get_config": ([P, i32p, i32p, i32p], ctypes.c_int),
         "mln_configure": ([P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
         "mln_tune": ([P, ctypes.c_int32, i32p, i32p, i32p], ctypes.c_int),
+        "mln_configure_adjoint": ([P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
         "mln_get_fields": ([P, _dp, _dp], ctypes.c_int),
         "mln_get_state": ([P, _dp, _dp, _dp], ctypes.c_int),
         "mln_get_bloch": ([P, _dp], ctypes.c_int),
@@ -335,6 +336,11 @@ class Solver:
     def configure(self, variant="auto", tile=0, steps_per_launch=0):
         """Change the kernel configuration (at step 0)."""
         _check(self._L.mln_configure(self._h, VARIANTS[variant], int(tile), int(steps_per_launch)))
+
+    def configure_adjoint(self, variant="auto", tile=0, steps_per_launch=0):
+        """Tiling of grad()'s reverse kernel: "auto", "block" or "quad", cells
+        per tile, steps per launch."""
+        _check(self._L.mln_configure_adjoint(self._h, VARIANTS[variant], int(tile), int(steps_per_launch)))
 
     def tune(self, trial_steps=256):
         """Autotune the kernel configuration on this problem (at step 0); the
