@@ -45,7 +45,7 @@ CSRC = os.path.join(ROOT, "paper_1710_09799_amd", "csrc")
 QUAD_SOURCES = ["fwd_quad.hpp", "fwd_impl.hpp", "fwd_kernels.hpp", "fwd_n3.hip"]
 # the four-lanes-per-cell kernel each precision runs fastest on at N = 3
 # (measured: the matrix-core product wins with the compensated state)
-HEAD_VARIANT = {"fp32": "quad", "fp32c": "quad_mfma", "fp32cf": "quad_mfma"}
+HEAD_VARIANT = {"fp32": "quad", "fp32c": "quad_mfma", "fp32cf": "quad_mfma", "fp32f": "quad"}
 # steps per launch with 128-cell tiles (measured best: the matrix-core form
 # amortises its launch cost over the most steps that keep one tile per compute
 # unit, 250 tiles of 80 owned cells; the DPP form, FP64 included, runs best
@@ -270,7 +270,7 @@ def variants(p3, ref64, pop64, headline):
     n3 = p3.grid.n_med * p3.grid.nt
     # N = 3: precisions on the four-lanes-per-cell kernel, and the paper's
     # two routes (and the rotation form) on the one-cell-per-thread kernel
-    others = [pr for pr in ("fp32", "fp32c", "fp32cf") if pr != headline]
+    others = [pr for pr in ("fp32", "fp32c", "fp32cf", "fp32f") if pr != headline]
     for name, kw in tuple((f"n3_{pr}_{HEAD_VARIANT[pr]}", dict(precision=pr, variant=HEAD_VARIANT[pr], tile=128,
                                                                 steps_per_launch=HEAD_K[HEAD_VARIANT[pr]]))
                           for pr in others) + (
@@ -373,15 +373,18 @@ def variants(p3, ref64, pop64, headline):
     b.close()
     bat = {"tuned": {"variant": variant, "tile": tile, "steps_per_launch": k}}
     outs = {}
-    for prec in ("fp64", "fp32", "fp32c", "fp32cf"):
+    for prec in ("fp64", "fp32", "fp32c", "fp32cf", "fp32f"):
         b = mln.Batch(probs, precision=prec, snap_every=nts, variant=variant, tile=tile, steps_per_launch=k)
         b.run()
-        b.reset()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        o = b.run()
-        torch.cuda.synchronize()
-        tb = time.perf_counter() - t0
+        tbs = []
+        for _ in range(REPS):
+            b.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            o = b.run()
+            torch.cuda.synchronize()
+            tbs.append(time.perf_counter() - t0)
+        tb = _median(tbs)
         outs[prec] = [{kk: (v.cpu().numpy() if v is not None else None) for kk, v in oi.items()} for oi in o]
         bat[prec] = {"value": nb / tb, "ms": tb * 1e3, "workgroups": b.config()["workgroups"]}
         b.close()

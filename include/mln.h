@@ -78,10 +78,21 @@ typedef enum {
                              path in the probe field (1e-5 after 2e4 steps; bound
                              stated for such runs: 1e-3); use MLN_FP32_BF16SPLIT
                              where 1e-4 must hold past ~5e4 steps                     */
-  MLN_FP32_COMP_FIELDS = 5 /* as MLN_FP32_COMP, and E, H and the source samples are
+  MLN_FP32_COMP_FIELDS = 5, /* as MLN_FP32_COMP, and E, H and the source samples are
                              two-float pairs as well (for runs of 1e5 steps and more,
                              where FP32 rounding of the fields accumulates); workgroup
                              and four-lanes-per-cell kernels                            */
+  MLN_FP32_FIELDS = 6     /* plain single-precision state (the deviation from the rest
+                             state, as MLN_FP32) with E, H and the source samples as
+                             two-float pairs: the fields' rounding, which dominates
+                             plain FP32's field error on long propagation paths, is
+                             removed at a fraction of the compensated state's cost.
+                             The state's rounding remains: worst deviation from FP64
+                             1.4e-5 (E and populations) over the 64-problem sweep of
+                             20000 steps at 1.47x the FP64 batch rate; 1.6e-5 in the
+                             populations after 1e5 steps (use MLN_FP32_COMP_FIELDS
+                             where 1e-5 must hold).  Rotation route, N <= 3,
+                             workgroup and four-lanes-per-cell kernels and the batch */
 } mln_precision;
 
 typedef enum {
@@ -372,8 +383,8 @@ const char *mln_last_error(void);
  *   media, grids, sources  arrays of n_inst descriptors (as for mln_init);
  *                          every grid has the same dt and nt; N = 2 or 3
  *   records                array of n_inst recordings, or NULL (none)
- *   options                precision MLN_FP64, MLN_FP32, MLN_FP32_COMP or
- *                          MLN_FP32_COMP_FIELDS;
+ *   options                precision MLN_FP64, MLN_FP32, MLN_FP32_COMP,
+ *                          MLN_FP32_COMP_FIELDS or MLN_FP32_FIELDS;
  *                          route MLN_ROUTE_ROTATION; variant 0 (= 1), 1 or
  *                          3; ckpt_every 0; tile / steps_per_launch as for
  *                          mln_init (0: 256 cells for variant 1, 128 for

@@ -23,8 +23,20 @@ hipError_t launch_fwd_batch(bool quad, bool comp, bool cf, int W, const BatchIns
                             const BatchTile *tiles, int64_t nblocks, int64_t step0, int nsteps, int slot,
                             hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
-  if (cf && !comp) return hipErrorInvalidValue;
   const dim3 grid((unsigned)nblocks), block(quad ? 4 * W : W);
+  if (cf && !comp) {
+    // plain single-precision state, float-float fields
+    if constexpr (std::is_same<Real, float>::value) {
+      if (quad)
+        hipLaunchKernelGGL((fwd_quad_batch_kernel<float, false, true>), grid, block, 0, st, inst, tiles, step0, nsteps,
+                           slot);
+      else
+        hipLaunchKernelGGL((fwd_block_batch_kernel<float, false, true>), grid, block, 0, st, inst, tiles, step0,
+                           nsteps, slot);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
   if (comp) {
     if constexpr (std::is_same<Real, float>::value) {
       if (quad && cf)
@@ -226,7 +238,7 @@ int mln_init_batch(int32_t n_inst, const mln_medium *media, const mln_grid *grid
   mln_options opt{};
   if (options) opt = *options;
   if (opt.precision != MLN_FP64 && opt.precision != MLN_FP32 && opt.precision != MLN_FP32_COMP &&
-      opt.precision != MLN_FP32_COMP_FIELDS)
+      opt.precision != MLN_FP32_COMP_FIELDS && opt.precision != MLN_FP32_FIELDS)
     return set_err(MLN_ENOTSUPPORTED, "batched launch: FP64, FP32 or compensated FP32");
   if (opt.route != MLN_ROUTE_ROTATION) return set_err(MLN_ENOTSUPPORTED, "batched launch: rotation route only");
   if (opt.variant != 0 && opt.variant != 1 && opt.variant != 3)
@@ -247,7 +259,7 @@ int mln_init_batch(int32_t n_inst, const mln_medium *media, const mln_grid *grid
   std::unique_ptr<mln_batch> b(new mln_batch());
   b->prec = opt.precision;
   b->comp = opt.precision == MLN_FP32_COMP || opt.precision == MLN_FP32_COMP_FIELDS;
-  b->cf = opt.precision == MLN_FP32_COMP_FIELDS;
+  b->cf = opt.precision == MLN_FP32_COMP_FIELDS || opt.precision == MLN_FP32_FIELDS;
   b->stream = (hipStream_t)opt.stream;
   b->nt = grids[0].nt;
   mln_options o = opt;

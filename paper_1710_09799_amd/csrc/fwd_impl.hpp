@@ -524,7 +524,6 @@ __device__ __forceinline__ Real cell_step(const FacDev<Real> &f, const Real *sF,
 // COMP: compensated (float-float) state; CF: E and H as float-float pairs too.
 template <int N, typename Real, int ROUTE, bool COMP, bool CF>
 __device__ __forceinline__ void block_tile(const FwdArgs<Real> &a, int64_t tile) {
-  static_assert(COMP || !CF, "compensated fields come with the compensated state");
   constexpr int D = N * N - 1;
   constexpr int DL = COMP ? D : 1;
   constexpr int FL = CF ? kMaxTile : 1;  // low parts of the exchanged fields

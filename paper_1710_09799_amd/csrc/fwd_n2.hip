@@ -8,7 +8,15 @@ namespace mln {
 
 template <typename Real>
 hipError_t launch_fwd_n2(int route, bool comp, bool cf, const FwdArgs<Real> &a, int64_t nblocks, int W, hipStream_t st) {
-  if (cf && !comp) return hipErrorInvalidValue;
+  if (cf && !comp) {
+    // plain single-precision state, float-float fields
+    if constexpr (std::is_same<Real, float>::value) {
+      if (route != ROUTE_ROT) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((fwd_tile_kernel<2, float, ROUTE_ROT, false, true>), dim3((unsigned)nblocks), dim3(W), 0, st, a);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
   if (comp) {
     if constexpr (std::is_same<Real, float>::value) {
       if (route != ROUTE_ROT) return hipErrorInvalidValue;
@@ -72,7 +80,10 @@ hipError_t launch_fwd_wave_n2(bool comp, int C, const FwdArgs<Real> &a, int64_t 
 template <typename Real>
 hipError_t launch_fwd_quad_n2(bool comp, bool cf, bool mf, int W, const FwdArgs<Real> &a, int64_t nblocks,
                               hipStream_t st) {
-  if (cf && !comp) return hipErrorInvalidValue;
+  if (cf && !comp) {
+    if constexpr (std::is_same<Real, float>::value) return launch_quad<2, float, false, true>(W, a, nblocks, st, mf);
+    return hipErrorInvalidValue;
+  }
   if (comp) {
     if constexpr (std::is_same<Real, float>::value) {
       if (cf) return launch_quad<2, float, true, true>(W, a, nblocks, st, mf);

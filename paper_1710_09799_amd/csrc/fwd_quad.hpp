@@ -133,7 +133,6 @@ struct MfAcc<double> {
 // 4 W lanes.
 template <int N, typename Real, bool COMP, bool CF, bool MF = false>
 __device__ __forceinline__ void quad_tile(const FwdArgs<Real> &a, int64_t tile) {
-  static_assert(COMP || !CF, "compensated fields come with the compensated state");
   constexpr int D = N * N - 1, Q = N * (N - 1) / 2;
   static_assert(D <= 8, "four lanes of two components each");
   // exchanged E of cell c at index c + 1; indices 0 and W + 1 stay zero

@@ -596,13 +596,15 @@ int mln_init(const mln_medium *medium, const mln_grid *grid, const mln_source *s
   h->stream = (hipStream_t)opt.stream;
   if (h->route < 0 || h->route > 3) return set_err(MLN_EINVAL, "unknown route");
   if (h->f.N == 5) return set_err(MLN_ENOTSUPPORTED, "kernels are built for N = 2, 3, 4 and 6");
-  if (h->prec < MLN_FP64 || h->prec > MLN_FP32_COMP_FIELDS)
+  if (h->prec < MLN_FP64 || h->prec > MLN_FP32_FIELDS)
     return set_err(MLN_ENOTSUPPORTED, "unknown precision");
-  h->comp = h->prec >= MLN_FP32_COMP;
+  h->comp = h->prec >= MLN_FP32_COMP && h->prec <= MLN_FP32_COMP_FIELDS;
   h->mfma = h->prec == MLN_FP32_BF16SPLIT ? 6 : (h->prec == MLN_FP32_BF16X3 ? 3 : 0);
-  h->cf = h->prec == MLN_FP32_COMP_FIELDS || h->mfma;
-  if (h->comp && h->route != MLN_ROUTE_ROTATION)
-    return set_err(MLN_ENOTSUPPORTED, "the compensated FP32 state is built for the rotation route only");
+  h->cf = h->prec == MLN_FP32_COMP_FIELDS || h->prec == MLN_FP32_FIELDS || h->mfma;
+  if ((h->comp || h->cf) && h->route != MLN_ROUTE_ROTATION)
+    return set_err(MLN_ENOTSUPPORTED, "the compensated FP32 state and fields are built for the rotation route only");
+  if (h->prec == MLN_FP32_FIELDS && h->f.N > 3)
+    return set_err(MLN_ENOTSUPPORTED, "MLN_FP32_FIELDS is built for N <= 3");
   if (h->mfma && h->f.N != 4 && h->f.N != 6)
     return set_err(MLN_ENOTSUPPORTED, "the split-BF16 MFMA kernel is built for N = 4 and 6");
   h->rs = (h->prec == MLN_FP64) ? 8 : 4;

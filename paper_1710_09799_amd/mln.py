@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmln.so")
 
-PRECISIONS = {"fp64": 0, "fp32": 1, "fp32c": 2, "bf16x6": 3, "bf16x3": 4, "fp32cf": 5}
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp32c": 2, "bf16x6": 3, "bf16x3": 4, "fp32cf": 5, "fp32f": 6}
 ROUTES = {"rotation": 0, "diag": 1, "rodrigues": 2, "pade": 3}
 VARIANTS = {"auto": 0, "block": 1, "wave": 2, "quad": 3, "stream": 4, "quad_mfma": 5}
 TAPE_ALL = -1  # ckpt_every: keep the whole forward tape in device memory (Solver(ckpt_every="tape"))

@@ -177,7 +177,7 @@ def test_vacuum_magic_time_step_exact(orc):
     assert np.max(np.abs(got["probe"] - want)) < 1e-12 * 1.5 * np.abs(s).max()
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp32c", "fp32cf"])
+@pytest.mark.parametrize("precision", ["fp32", "fp32c", "fp32cf", "fp32f"])
 def test_vacuum_magic_time_step_single_precision(orc, precision):
     """Courant number 1 in single precision: the FP32 coefficients realise
     the product ch cb / dx = 1 to about 1e-10 (instead of the ~1e-7 of
@@ -199,7 +199,7 @@ def test_vacuum_magic_time_step_single_precision(orc, precision):
     assert err < 1e-5
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp32c", "fp32cf"])
+@pytest.mark.parametrize("precision", ["fp32", "fp32c", "fp32cf", "fp32f"])
 def test_single_precision_fields_match_fp64(precision):
     """E and H read back through mln_get_fields agree with the FP64 run (the
     single-precision kernels carry H in units rescaled by their tuned

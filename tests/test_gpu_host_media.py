@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 HOSTS = [(2.0e3, 1.0, 1.0), (0.0, 2.25, 1.0), (0.0, 1.0, 2.25), (1.0e3, 1.5, 1.8)]
 MODES = [("fp64", "auto", 1e-10), ("fp64", "block", 1e-10), ("fp32c", "quad", 1e-5),
          ("fp32c", "block", 1e-5), ("fp32cf", "quad", 1e-5), ("fp32cf", "block", 1e-5),
-         ("fp32c", "wave", 1e-5), ("bf16x6", "auto", 1e-4)]
+         ("fp32c", "wave", 1e-5), ("bf16x6", "auto", 1e-4), ("fp32f", "quad", 1e-5), ("fp32f", "block", 1e-5)]
 
 
 def _supported(n, precision, variant):
@@ -29,6 +29,8 @@ def _supported(n, precision, variant):
     if variant == "wave" and n == 6:
         return False
     if precision == "bf16x6" and n < 4:
+        return False
+    if precision == "fp32f" and n > 3:
         return False
     return True
 

@@ -1,7 +1,8 @@
 """Reduced-precision paths against the FP64 oracle.
 
 Tolerances: single precision ("fp32"; compensated "fp32c": two-float Bloch
-vectors and factors; "fp32cf": E and H as two-float pairs as well) must meet
+vectors and factors; "fp32cf": E and H as two-float pairs as well; "fp32f":
+plain single-precision state with two-float E and H) must meet
 1e-5 on err_E and err_pop (the FP32 target); plain single precision on the
 diagonalisation and Rodrigues routes, which carry d rather than its deviation
 from the rest state, is held to a looser bound that documents its drift
@@ -36,7 +37,8 @@ def two_level_ref(orc):
     return p, orc.run(p, snap_every=1000)
 
 
-@pytest.mark.parametrize("precision,variant", [("fp32c", "auto"), ("fp32cf", "quad"), ("fp32cf", "block")])
+@pytest.mark.parametrize("precision,variant", [("fp32c", "auto"), ("fp32cf", "quad"), ("fp32cf", "block"),
+                                               ("fp32f", "quad"), ("fp32f", "block")])
 def test_fp32c_three_level(three_level_ref, precision, variant):
     p, ref = three_level_ref
     got = mln.run(p, precision=precision, variant=variant, snap_every=500)
@@ -164,6 +166,27 @@ def test_wave_kernel_rejects_compensated_fields():
     with pytest.raises(mln.MLNError) as e:
         mln.Solver(p, precision="fp32cf", variant="wave", tile=64, steps_per_launch=8)
     assert e.value.code == -8
+
+
+def test_plain_state_compensated_fields_limits():
+    """MLN_FP32_FIELDS is built for the rotation route and N <= 3; it runs on
+    the workgroup and four-lanes-per-cell kernels (the automatic choice is
+    the DPP quad kernel) and not on the wavefront or streamed kernels."""
+    p6 = W.random_problem(6, 3, nx=100, nt=50)
+    with pytest.raises(mln.MLNError) as e:
+        mln.Solver(p6, precision="fp32f")
+    assert e.value.code == -8
+    p3 = W.random_problem(3, 3, nx=100, nt=50)
+    with pytest.raises(mln.MLNError) as e:
+        mln.Solver(p3, precision="fp32f", route="diag")
+    assert e.value.code == -8
+    for variant in ("wave", "stream"):
+        with pytest.raises(mln.MLNError) as e:
+            mln.Solver(p3, precision="fp32f", variant=variant)
+        assert e.value.code == -8
+    s = mln.Solver(p3, precision="fp32f")
+    assert s.config()["variant"] == "quad"
+    s.close()
 
 
 @pytest.mark.slow

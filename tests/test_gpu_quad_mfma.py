@@ -18,7 +18,7 @@ from paper_1710_09799_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-10, "fp32c": 1e-5, "fp32cf": 1e-5, "fp32": 1e-5}
+TOL = {"fp64": 1e-10, "fp32c": 1e-5, "fp32cf": 1e-5, "fp32": 1e-5, "fp32f": 1e-5}
 
 
 def _errs(got, ref):
@@ -46,7 +46,7 @@ def refs(orc):
 
 @pytest.mark.parametrize("n,seed", [(2, 1), (3, 2), (3, 7)])
 @pytest.mark.parametrize("tile,k", [(32, 8), (128, 20), (256, 63), (80, 20), (48, 11)])
-@pytest.mark.parametrize("precision", ["fp64", "fp32c", "fp32cf", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32c", "fp32cf", "fp32", "fp32f"])
 def test_quad_mfma_random_media(refs, n, seed, tile, k, precision):
     """Random media with complex dipoles and general Lindblad channels on 203
     cells (several tiles, ragged last tile), snapshots across launches."""
