@@ -747,13 +747,14 @@ int mln_tune(mln_handle *h, int32_t trial_steps, int32_t *variant, int32_t *tile
   if (!h) return set_err(MLN_EINVAL, "null handle");
   if (h->step != 0) return set_err(MLN_ESTATE, "tune a handle at step 0 (mln_reset)");
   if (trial_steps < 1) return set_err(MLN_EINVAL, "trial_steps must be >= 1");
-  // (variant, cells per tile, steps per launch); candidates the handle's
-  // precision, route or level count does not allow are skipped
+  // (variant, cells per tile, steps per launch; 0: the automatic step
+  // count, the largest that keeps one tile per compute unit); candidates the
+  // handle's precision, route or level count does not allow are skipped
   static const int cand[][3] = {{3, 64, 8},   {3, 128, 16}, {3, 128, 20}, {3, 128, 32}, {3, 256, 16},
                                 {3, 256, 32}, {1, 64, 8},   {1, 128, 8},  {1, 128, 16}, {1, 128, 32},
                                 {1, 256, 8},  {1, 256, 16}, {1, 256, 32}, {2, 64, 8},   {2, 128, 16},
                                 {2, 256, 32}, {4, 256, 1},  {5, 64, 8},   {5, 128, 16}, {5, 128, 20},
-                                {5, 128, 32}, {5, 256, 16}, {5, 256, 32}};
+                                {5, 128, 0},  {5, 128, 32}, {5, 256, 16}, {5, 256, 32}};
   const KernelChoice start = save_kernel(h);
   KernelChoice best_k = start;
   double best = INFINITY;
@@ -763,10 +764,11 @@ int mln_tune(mln_handle *h, int32_t trial_steps, int32_t *variant, int32_t *tile
   int rc = MLN_OK;
   for (const auto &c : cand) {
     if (set_kernel(h, c[0], c[1], c[2]) != MLN_OK) continue;
+    const int kk = h->halo;  // the resolved steps per launch
     // one warm-up launch, then whole launches, all within the run length
-    const int64_t steps = std::max<int64_t>(2 * c[2], (trial_steps + c[2] - 1) / c[2] * c[2]);
-    if (steps + c[2] > h->grid.nt) continue;
-    if ((rc = reset_state(h)) || (rc = forward_steps(h, c[2], false, nullptr, 0, false))) break;
+    const int64_t steps = std::max<int64_t>(2 * kk, (trial_steps + kk - 1) / kk * kk);
+    if (steps + kk > h->grid.nt) continue;
+    if ((rc = reset_state(h)) || (rc = forward_steps(h, kk, false, nullptr, 0, false))) break;
     if (hipEventRecord(e0, h->stream) != hipSuccess) { rc = set_err(MLN_EHIP, "event record"); break; }
     if ((rc = forward_steps(h, steps, false, nullptr, 0, false))) break;
     if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
