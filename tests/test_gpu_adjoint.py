@@ -172,10 +172,14 @@ def test_checkpoint_interval_does_not_change_gradient(ckpt):
     assert np.max(np.abs(a - b) / (np.abs(b) + 1e-300 + 1e-6 * np.abs(b).max())) < 1e-9
 
 
-def test_fp32_adjoint_close_to_fp64():
+@pytest.mark.parametrize("precision", ["fp32c", "fp32cf", "fp32f", "fp32"])
+def test_fp32_adjoint_close_to_fp64(precision):
+    """The single-precision modes' gradients (the reverse step runs in FP32
+    on the tape the forward kernel wrote; with float-float fields the tape
+    holds the high part of E) against FP64."""
     prob = _small_ladder(3, nt=2000)
     _, g64 = _grad(prob, "fp64", ckpt=200)
-    _, g32 = _grad(prob, "fp32c", ckpt=200)
+    _, g32 = _grad(prob, precision, ckpt=200)
     a, b = grads_to_ladder(g32, 3), grads_to_ladder(g64, 3)
     scale = ladder_params(prob)
     scale[:3] = np.max(np.abs(np.diff(scale[:3])))
@@ -266,7 +270,7 @@ def test_p5_adjoint_matches_oracle_adjoint(orc):
         print(f"  {precision} worst group error {worst:.2e}", flush=True)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32c", "fp32cf"])
 def test_whole_tape_equals_checkpoints(precision):
     """ckpt_every = MLN_TAPE_ALL keeps the forward tape of every step in device
     memory: the gradient equals the checkpointed one (same values recorded,
@@ -324,3 +328,51 @@ def test_overlapped_rebuild_is_deterministic(precision, variant):
     s1.close()
     tol = 1e-9 if precision == "fp64" else 1e-4
     assert np.max(np.abs(gs[0] - g1) / (np.abs(g1) + 1e-300 + 1e-6 * np.abs(g1).max())) < tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_reverse_tiling_does_not_change_gradient(precision):
+    """mln_configure_adjoint: the reverse kernel's tiling is independent of
+    the forward one (the tape is read by cell); every tiling, on both
+    reverse kernels, gives the automatic tiling's gradient to rounding, with
+    checkpoints and with the whole tape."""
+    prob = _small_ladder(3, nx=300, nt=900)
+    print(f"[case] reverse tiling {precision}", flush=True)
+    tol = 1e-11 if precision == "fp64" else 2e-5
+    for ck in (128, "tape"):
+        s = mln.Solver(prob, precision=precision, ckpt_every=ck)
+        probe = s.run()["probe"].cpu().numpy()
+        gp = 2.0 * prob.grid.dt * probe
+        ref = grads_to_ladder(s.grad(gp), 3)
+        for variant, tile, k in (("quad", 128, 44), ("quad", 64, 16), ("quad", 32, 7), ("quad", 128, 1),
+                                 ("block", 256, 16), ("block", 64, 31)):
+            if ck != "tape":
+                s.reset()
+                s.run()
+            s.configure_adjoint(variant, tile, k)
+            g = grads_to_ladder(s.grad(gp), 3)
+            dev = np.max(np.abs(g - ref) / (np.abs(ref) + 1e-300 + 1e-6 * np.abs(ref).max()))
+            print(f"  ckpt={ck} {variant} tile={tile} k={k}: {dev:.2e}", flush=True)
+            assert dev < tol
+        s.configure_adjoint("auto")
+        s.close()
+
+
+def test_configure_adjoint_errors():
+    prob = _small_ladder(3, nx=160, nt=300)
+    s = mln.Solver(prob, precision="fp64", ckpt_every=50)
+    for args in (("quad", 72, 8), ("quad", 256, 8), ("quad", 64, 32), ("block", 96, 8), ("block", 256, 200),
+                 ("wave", 64, 8), ("auto", 64, 0)):
+        with pytest.raises(mln.MLNError) as e:
+            s.configure_adjoint(*args)
+        assert e.value.code == -1, args
+    s.configure_adjoint("quad", 0, 0)  # tile 128, 32 steps
+    s.configure_adjoint("block")  # tile 256, 64 steps
+    s.configure_adjoint()
+    s.close()
+    p6 = W.random_problem(6, 3, nx=100, nt=50)
+    s6 = mln.Solver(p6, precision="fp64")
+    with pytest.raises(mln.MLNError) as e:
+        s6.configure_adjoint("quad", 64, 8)
+    assert e.value.code == -8
+    s6.close()
