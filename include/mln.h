@@ -344,7 +344,11 @@ int mln_bloch_only_noalloc(mln_handle *h, const double *efield, int64_t n_steps,
  * the forward buffers in an intermediate state: mln_reset before stepping
  * again), with the whole tape in memory nothing is recomputed (and mln_grad
  * may be called again for another dJ_dprobe); each segment is swept backwards
- * by the reverse kernel, which accumulates the parameter gradients on the GPU.  The
+ * by the reverse kernel, which accumulates the parameter gradients on the GPU.
+ * With two or more checkpoint intervals the rebuild of the next segment runs
+ * on a second stream the handle creates (non-blocking, default priority) into
+ * a second segment tape while the current one is reversed, ordered by events;
+ * the call waits for both streams before it returns.  The
  * final chain rule through exp(M dt/2) runs on the host in FP64.  Supported
  * for the rotation route, FP64 and FP32 (plain or compensated), N <= 3.
  * Errors: MLN_ESTATE (no completed checkpointed run), MLN_ENOTSUPPORTED.
