@@ -8,7 +8,10 @@
 namespace mln {
 
 namespace {
-// at most 8 workgroups per compute unit; each loops over its chunks of cells
+// at most 16 workgroups per compute unit; each loops over its chunks of cells
+// (measured on 2^24 two-level cells: 16 per CU moves 5.07 / 4.18 / 4.70 TB/s
+// in FP64 / FP32 / compensated FP32, 8 per CU 4.80 / 3.72 / 4.15, 4 and 32
+// per CU within 2 % of 16, one workgroup per chunk 4.17 / 2.60 / 3.35)
 int max_stream_blocks() {
   static int cache[64] = {0};
   int dev = 0;
@@ -16,7 +19,7 @@ int max_stream_blocks() {
   if (!cache[dev]) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-    cache[dev] = 8 * cus;
+    cache[dev] = 16 * cus;
   }
   return cache[dev];
 }
