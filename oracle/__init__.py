@@ -54,6 +54,11 @@ def bind(path):
                           ctypes.c_double, i64, i64, ctypes.c_double, ctypes.c_double, i64, i64,
                           ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, ctypes.c_double,
                           dp, dp, i64, dp, dp, dp, dp, dp, ctypes.c_int]
+    L.orc_run_pol2.restype = ctypes.c_int
+    L.orc_run_pol2.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_int, dp, dp, ctypes.c_double, dp, dp,
+                               ctypes.c_double, i64, i64, ctypes.c_double, ctypes.c_double, i64, i64,
+                               ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, ctypes.c_double,
+                               ctypes.c_double, dp, dp, dp, dp, i64, dp, dp, dp, dp, dp, dp, dp, ctypes.c_int]
     L.orc_bloch.restype = ctypes.c_int
     L.orc_bloch.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, ctypes.c_double, dp, dp,
                             ctypes.c_double, i64, i64, ctypes.c_double, dp, dp, dp, dp, dp,
@@ -178,6 +183,44 @@ def run(problem, snap_every=0, nthreads=0, nt=None, e_init=None, h_init=None):
         raise RuntimeError(f"oracle run failed ({rc})")
     return dict(probe=probe, e_snap=e_snap[:nsnap], pop=pop[:nsnap, :, : g.n_med], h=hfin,
                 diag=dict(trace=diag[0], herm=diag[1], min_eig=diag[2], purity=diag[3]))
+
+
+def run_pol2(problem, dipole_y, amplitude_y, snap_every=0, nthreads=0, nt=None, init=None):
+    """Both transverse field components (orc_run_pol2): the medium's dipole
+    couples to E_z, dipole_y (N x N Hermitian) to E_y; the source waveform
+    drives E_z with the problem's amplitude and E_y with amplitude_y.  init:
+    optional dict of initial fields 'ez', 'ey' (nx values) and 'hy', 'g'
+    (nx - 1 values, g = -H_z).  Returns 'probe_z', 'probe_y' (nt+1),
+    'ez_snap', 'ey_snap' (nsnap, nx), 'pop' (nsnap, N, n_med), 'hy', 'g'."""
+    med, g, src = problem.medium, problem.grid, problem.source
+    nt = g.nt if nt is None else nt
+    n, h0, mu, nj, jumps, rates, deph, relax, rho0 = _medium_args(med)
+    muy = _cx(np.asarray(dipole_y, dtype=np.complex128).reshape(n, n))
+    nsnap = nt // snap_every if snap_every > 0 else 0
+    probe_z, probe_y = np.zeros(nt + 1), np.zeros(nt + 1)
+    ez_snap, ey_snap = np.zeros((max(nsnap, 1), g.nx)), np.zeros((max(nsnap, 1), g.nx))
+    pop = np.zeros((max(nsnap, 1), n, max(g.n_med, 1)))
+    hy, gf = np.zeros(g.nx - 1), np.zeros(g.nx - 1)
+    samples = np.ascontiguousarray(src.samples[: nt + 1], dtype=np.float64)
+    init = init or {}
+    fields = {}
+    for key, size in (("ez", g.nx), ("hy", g.nx - 1), ("ey", g.nx), ("g", g.nx - 1)):
+        v = init.get(key)
+        if v is not None:
+            v = np.ascontiguousarray(v, dtype=np.float64)
+            if v.shape != (size,):
+                raise ValueError(f"initial field {key} must have {size} values")
+        fields[key] = v
+    rc = lib().orc_run_pol2(n, _p(h0), _p(mu), _p(muy), nj, _p(jumps), _p(rates), deph, _p(relax), _p(rho0),
+                            float(med.density), g.nx, nt, g.dx, g.dt, g.med_begin, g.med_end,
+                            g.eps_r, g.mu_r, g.sigma, _p(samples), float(src.amplitude), float(amplitude_y),
+                            _p(fields["ez"]), _p(fields["hy"]), _p(fields["ey"]), _p(fields["g"]),
+                            snap_every, _p(ez_snap), _p(ey_snap), _p(pop), _p(probe_z), _p(probe_y),
+                            _p(hy), _p(gf), nthreads)
+    if rc:
+        raise RuntimeError(f"oracle two-component run failed ({rc})")
+    return dict(probe_z=probe_z, probe_y=probe_y, ez_snap=ez_snap[:nsnap], ey_snap=ey_snap[:nsnap],
+                pop=pop[:nsnap, :, : g.n_med], hy=hy, g=gf)
 
 
 def bloch(med, efield, dt, nthreads=0):

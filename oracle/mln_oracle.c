@@ -35,7 +35,11 @@
  *     derivatives taken from direct DFT sums;
  *   * the same medium step on a two-dimensional TMz Yee grid (orc_run2d),
  *     the extension past the one-dimensional models the paper restricts
- *     itself to (Conclusion).
+ *     itself to (Conclusion);
+ *   * both transverse field components with an interaction Hamiltonian
+ *     -mu_z E_z - mu_y E_y (orc_run_pol2), the extension past the single
+ *     component and fixed interaction form the paper keeps (Sec. 2,
+ *     Conclusion).
  *
  * Readings of points the paper leaves open (same on the GPU side, but written
  * independently there):
@@ -523,6 +527,152 @@ int orc_run(int n, const double *h0, const double *mu, int n_jump, const double 
     }
     if (h_out) memcpy(h_out, H, sizeof(double) * (nx - 1));   /* H^{nt-1/2} */
     free(rho); free(r0); free(E); free(H); free(P);
+    medium_free(&m);
+    return 0;
+}
+
+/* ----------------------------------------------------------------------- */
+/* two transverse field components: H_I = -mu_z E_z - mu_y E_y              */
+/*
+ * The paper keeps one field component and the interaction -mu E_z (Sec. 2)
+ * and names the fixed interaction form as a limitation (Conclusion).  For a
+ * wave along x both transverse components take part: Maxwell's equations
+ * split into two independent Yee pairs, (E_z, H_y) as in orc_run and
+ * (E_y, G) with G = -H_z, which obeys the same update in the same form,
+ *   G_i += dt/(mu dx) (E_y(i+1) - E_y(i)),
+ *   E_y(i) = ca E_y(i) + cb (-dP_y/dt + (G_i - G_{i-1})/dx),
+ * and the medium couples them through H_I = -mu_z E_z - mu_y E_y.
+ * Reading of the Strang step of Sec. 4.1 for two components: the
+ * interaction factor is itself split symmetrically, so that each factor
+ * keeps a fixed generator (the property the paper's exponential routes
+ * rely on):  rho'' = W rho' W^+ with W = W_y W_z W_y,
+ * W_y = exp(+i mu_y E_y^n dt / (2 hbar)), W_z = exp(+i mu_z E_z^n dt / hbar)
+ * (second order in dt like the step around it; exact when mu_y and mu_z
+ * commute).  dP_k/dt = N_a Re Tr{mu_k (L0 + G)(rho^{n+1/2})}, k = z, y.
+ * Sources E_z(0) = amp_z src[n], E_y(0) = amp_y src[n]; the Mur boundary of
+ * orc_run on both components.  Records as orc_run for each component
+ * (ez_snap / ey_snap, probe_z / probe_y) and the populations once; optional
+ * initial fields (E^0 on every cell, H^{-1/2} and G^{-1/2} on the nx - 1
+ * faces); hy_out and g_out receive H^{nt-1/2} and G^{nt-1/2}.
+ */
+static double cell_step_pol2(const medium_t *m, const cx *muy, cx *rho, double Ez, double Ey, double dt,
+                             double Na, cell_ws_t *s, cx *Wy, cx *Wz, double *dpy)
+{
+    int n = m->n, n2 = n * n;
+    super_apply(n2, m->E0, rho, s->v);                        /* rho' */
+    for (int i = 0; i < n2; ++i) s->Wa[i] = (I * (0.5 * dt) * Ey / ORC_HBAR) * muy[i];
+    expm_work(n, s->Wa, Wy, s->ex);                            /* W_y */
+    for (int i = 0; i < n2; ++i) s->Wa[i] = (I * dt * Ez / ORC_HBAR) * m->mu[i];
+    expm_work(n, s->Wa, Wz, s->ex);                            /* W_z */
+    mat_mul(n, Wz, Wy, s->t);
+    mat_mul(n, Wy, s->t, s->W);                                /* W = W_y W_z W_y */
+    mat_mul(n, s->W, s->v, s->t);
+    for (int a = 0; a < n; ++a)                                /* rho'' = W rho' W^+ */
+        for (int b = 0; b < n; ++b) {
+            cx acc = 0;
+            for (int k = 0; k < n; ++k) acc += s->t[a * n + k] * conj(s->W[b * n + k]);
+            s->w[a * n + b] = acc;
+        }
+    super_apply(n2, m->E0, s->w, rho);                         /* rho^{n+1/2} */
+    super_apply(n2, m->S, rho, s->v);                          /* (L0 + G)(rho) */
+    cx trz = 0, tr_y = 0;
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+            trz += m->mu[a * n + b] * s->v[b * n + a];
+            tr_y += muy[a * n + b] * s->v[b * n + a];
+        }
+    *dpy = Na * creal(tr_y);
+    return Na * creal(trz);
+}
+
+/* one Yee pair: H on the faces, then E with the polarisation current */
+static void yee_pair_h(int64_t nx, double ch, const double *E, double *H)
+{
+    for (int64_t i = 0; i + 1 < nx; ++i) H[i] += ch * (E[i + 1] - E[i]);
+}
+
+static void yee_pair_e(int64_t nx, int64_t mb, int64_t me, double ca, double cb, double dx, double kmur,
+                       double e0_next, const double *P, const double *H, double *E)
+{
+    double e_nm2 = E[nx - 2], e_nm1 = E[nx - 1];
+    for (int64_t i = 1; i + 1 < nx; ++i) {
+        double dp = (i >= mb && i < me) ? P[i - mb] : 0.0;
+        E[i] = ca * E[i] + cb * (-dp + (H[i] - H[i - 1]) / dx);
+    }
+    E[0] = e0_next;
+    E[nx - 1] = e_nm2 + kmur * (E[nx - 2] - e_nm1);
+}
+
+int orc_run_pol2(int n, const double *h0, const double *mu_z, const double *mu_y, int n_jump,
+                 const double *jump, const double *rate, double deph, const double *relax,
+                 const double *rho0, double Na, int64_t nx, int64_t nt, double dx, double dt, int64_t mb,
+                 int64_t me, double eps_r, double mu_r, double sigma, const double *src, double amp_z,
+                 double amp_y, const double *ez_init, const double *hy_init, const double *ey_init,
+                 const double *g_init, int64_t snap_every, double *ez_snap, double *ey_snap, double *pop_snap,
+                 double *probe_z, double *probe_y, double *hy_out, double *g_out, int nthreads)
+{
+    if (n < 2 || nx < 3 || nt < 0 || mb < 1 || me < mb || me > nx - 1 || !mu_y) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    medium_t m;
+    if (medium_init(&m, n, h0, mu_z, n_jump, jump, rate, deph, relax, dt)) return -2;
+    int n2 = n * n;
+    int64_t nmed = me - mb;
+    cx *muy = load_cx(mu_y, n2);
+    cx *rho = (cx *)malloc(sizeof(cx) * (size_t)(nmed ? nmed : 1) * n2);
+    cx *r0 = load_cx(rho0, n2);
+    for (int64_t c = 0; c < nmed; ++c) memcpy(rho + c * n2, r0, sizeof(cx) * n2);
+    double *Ez = (double *)calloc(nx, sizeof(double)), *Hy = (double *)calloc(nx, sizeof(double));
+    double *Ey = (double *)calloc(nx, sizeof(double)), *G = (double *)calloc(nx, sizeof(double));
+    double *Pz = (double *)calloc(nmed ? nmed : 1, sizeof(double));
+    double *Py = (double *)calloc(nmed ? nmed : 1, sizeof(double));
+    double eps = ORC_EPS0 * eps_r, muu = ORC_MU0 * mu_r;
+    double cl = 1.0 / sqrt(eps * muu);
+    double kmur = (cl * dt - dx) / (cl * dt + dx);
+    double sg = sigma * dt / (2.0 * eps);
+    double ca = (1.0 - sg) / (1.0 + sg), cb = (dt / eps) / (1.0 + sg);
+    double ch = dt / (muu * dx);
+    Ez[0] = amp_z * src[0];
+    Ey[0] = amp_y * src[0];
+    if (ez_init) memcpy(Ez, ez_init, sizeof(double) * nx);
+    if (ey_init) memcpy(Ey, ey_init, sizeof(double) * nx);
+    if (hy_init) memcpy(Hy, hy_init, sizeof(double) * (nx - 1));
+    if (g_init) memcpy(G, g_init, sizeof(double) * (nx - 1));
+    if (probe_z) probe_z[0] = Ez[nx - 1];
+    if (probe_y) probe_y[0] = Ey[nx - 1];
+    for (int64_t t = 0; t < nt; ++t) {
+        yee_pair_h(nx, ch, Ez, Hy);
+        yee_pair_h(nx, ch, Ey, G);
+#pragma omp parallel
+        {
+            cell_ws_t ws;
+            ws_alloc(&ws, n);
+            cx *Wy = (cx *)malloc(sizeof(cx) * n2), *Wz = (cx *)malloc(sizeof(cx) * n2);
+#pragma omp for schedule(static)
+            for (int64_t c = 0; c < nmed; ++c)
+                Pz[c] = cell_step_pol2(&m, muy, rho + c * n2, Ez[mb + c], Ey[mb + c], dt, Na, &ws, Wy, Wz,
+                                       Py + c);
+            free(Wy); free(Wz);
+            ws_free(&ws);
+        }
+        yee_pair_e(nx, mb, me, ca, cb, dx, kmur, amp_z * src[t + 1], Pz, Hy, Ez);
+        yee_pair_e(nx, mb, me, ca, cb, dx, kmur, amp_y * src[t + 1], Py, G, Ey);
+        if (probe_z) probe_z[t + 1] = Ez[nx - 1];
+        if (probe_y) probe_y[t + 1] = Ey[nx - 1];
+        if (snap_every > 0 && (t + 1) % snap_every == 0) {
+            int64_t s = (t + 1) / snap_every - 1;
+            if (ez_snap) memcpy(ez_snap + s * nx, Ez, sizeof(double) * nx);
+            if (ey_snap) memcpy(ey_snap + s * nx, Ey, sizeof(double) * nx);
+            if (pop_snap)
+                for (int64_t c = 0; c < nmed; ++c)
+                    for (int a = 0; a < n; ++a)
+                        pop_snap[(s * n + a) * nmed + c] = creal(rho[c * n2 + a * n + a]);
+        }
+    }
+    if (hy_out) memcpy(hy_out, Hy, sizeof(double) * (nx - 1));
+    if (g_out) memcpy(g_out, G, sizeof(double) * (nx - 1));
+    free(muy); free(rho); free(r0); free(Ez); free(Hy); free(Ey); free(G); free(Pz); free(Py);
     medium_free(&m);
     return 0;
 }

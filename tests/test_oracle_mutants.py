@@ -15,7 +15,10 @@ not catch them:
 * the Mur coefficient taken with the vacuum speed of light in a host medium;
 * in the two-dimensional run: H_x updated with the wrong sign, dx and dy
   exchanged in the H coefficients, the y direction not wrapped, and the
-  polarisation current fed back with the wrong sign.
+  polarisation current fed back with the wrong sign;
+* in the two-component run: the E_y polarisation current with the wrong
+  sign, the y factors of the split interaction with the full angle, and the
+  y dipole driven by E_z.
 
 Everything here runs on the CPU.
 """
@@ -27,6 +30,7 @@ import pytest
 import oracle
 import test_oracle_2d as M2
 import test_oracle_media as M
+import test_oracle_pol2 as MP
 
 MUTANTS = {
     "feedback_sign": ("E[i] = ca * E[i] + cb * (-dp + (H[i] - H[i - 1]) / dx);",
@@ -60,6 +64,15 @@ MUTANTS = {
     "2d_feedback_sign": ("E[j * nx + i] = ca * E[j * nx + i] + cb * (-dp + curl);",
                          "E[j * nx + i] = ca * E[j * nx + i] + cb * (dp + curl);",
                          lambda: M2.check_beam_energy(oracle)),
+    # the two-component run
+    "pol2_y_feedback_sign": ("*dpy = Na * creal(tr_y);", "*dpy = -Na * creal(tr_y);",
+                             lambda: MP.check_equal_dipoles(oracle)),
+    "pol2_y_full_angle": ("s->Wa[i] = (I * (0.5 * dt) * Ey / ORC_HBAR) * muy[i];",
+                          "s->Wa[i] = (I * dt * Ey / ORC_HBAR) * muy[i];",
+                          lambda: MP.check_equal_dipoles(oracle)),
+    "pol2_y_driven_by_ez": ("Pz[c] = cell_step_pol2(&m, muy, rho + c * n2, Ez[mb + c], Ey[mb + c], dt, Na, &ws, Wy, Wz,",
+                            "Pz[c] = cell_step_pol2(&m, muy, rho + c * n2, Ez[mb + c], Ez[mb + c], dt, Na, &ws, Wy, Wz,",
+                            lambda: MP.check_noncommuting_energy(oracle)),
 }
 
 
