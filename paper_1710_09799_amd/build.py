@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmln.so")
 OBJDIR = os.path.join(PKG, "_build")
 
-HIP_SOURCES = ["mln_abi.hip", "batch.hip", "fwd_dispatch.hip", "adj_n23.hip", "mfmaq_n46.hip", "pade_n46.hip", "floor.hip", "pstd.hip", "tmz.hip", "stream.hip"] + ["fwd_n%d.hip" % n for n in (2, 3, 4, 6)]
+HIP_SOURCES = ["mln_abi.hip", "batch.hip", "fwd_dispatch.hip", "adj_n23.hip", "mfmaq_n46.hip", "pade_n46.hip", "floor.hip", "pstd.hip", "tmz.hip", "stream.hip", "pol2.hip"] + ["fwd_n%d.hip" % n for n in (2, 3, 4, 6)]
 CXX_SOURCES = ["setup.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

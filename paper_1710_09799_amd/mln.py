@@ -77,6 +77,11 @@ class _TmzRecord(ctypes.Structure):
     _fields_ = [("snap_every", ctypes.c_int64), ("pop_out", _dp), ("e_out", _dp), ("probe_out", _dp)]
 
 
+class _Pol2Record(ctypes.Structure):
+    _fields_ = [("snap_every", ctypes.c_int64), ("ez_out", _dp), ("ey_out", _dp), ("pop_out", _dp),
+                ("probe_z_out", _dp), ("probe_y_out", _dp)]
+
+
 class _Grads(ctypes.Structure):
     _fields_ = [(n, _dp) for n in ("d_h0", "d_dipole", "d_jump_rate", "d_dephasing", "d_amplitude",
                                    "d_density")]
@@ -98,7 +103,9 @@ EXPORTS = ["mln_init", "mln_step", "mln_run", "mln_use_graph", "mln_reset", "mln
            "mln_measure_fma_rate", "mln_pstd_init", "mln_pstd_configure", "mln_pstd_get_config",
            "mln_pstd_step", "mln_pstd_run", "mln_pstd_reset", "mln_pstd_current_step", "mln_pstd_get_fields",
            "mln_pstd_free", "mln_tmz_init", "mln_tmz_step", "mln_tmz_run", "mln_tmz_reset",
-           "mln_tmz_current_step", "mln_tmz_set_fields", "mln_tmz_get_fields", "mln_tmz_free"]
+           "mln_tmz_current_step", "mln_tmz_set_fields", "mln_tmz_get_fields", "mln_tmz_free",
+           "mln_pol2_init", "mln_pol2_step", "mln_pol2_run", "mln_pol2_reset", "mln_pol2_current_step",
+           "mln_pol2_get_fields", "mln_pol2_free"]
 
 _lib = None
 
@@ -178,6 +185,14 @@ def load():
         "mln_tmz_set_fields": ([P, _dp, _dp, _dp], ctypes.c_int),
         "mln_tmz_get_fields": ([P, _dp, _dp, _dp], ctypes.c_int),
         "mln_tmz_free": ([P], None),
+        "mln_pol2_init": ([ctypes.POINTER(_Medium), _dp, ctypes.POINTER(_Grid), ctypes.POINTER(_Source),
+                           ctypes.c_double, ctypes.POINTER(_Pol2Record), P, ctypes.POINTER(P)], ctypes.c_int),
+        "mln_pol2_step": ([P, ctypes.c_int64], ctypes.c_int),
+        "mln_pol2_run": ([P], ctypes.c_int),
+        "mln_pol2_reset": ([P], ctypes.c_int),
+        "mln_pol2_current_step": ([P, i64p], ctypes.c_int),
+        "mln_pol2_get_fields": ([P, _dp, _dp, _dp, _dp], ctypes.c_int),
+        "mln_pol2_free": ([P], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -637,6 +652,83 @@ class Pstd:
     def close(self):
         if getattr(self, "_h", None):
             self._L.mln_pstd_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Pol2:
+    """Both transverse field components (mln_pol2_init): the problem's dipole
+    couples to E_z, dipole_y (N x N Hermitian) to E_y; the source waveform
+    drives E_z with the problem's amplitude and E_y with amplitude_y.  FP64,
+    N = 2, 3.  Outputs (torch float64 device tensors) after run(): probe_z,
+    probe_y (nt+1), ez_snap, ey_snap (nsnap, nx), pop (nsnap, N, n_med)."""
+
+    def __init__(self, problem, dipole_y, amplitude_y, snap_every=0, record_probe=True, record_pop=True,
+                 record_e=True):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("Pol2 needs a HIP device")
+        L = load()
+        self._L = L
+        self.problem = problem
+        med, g, src = problem.medium, problem.grid, problem.source
+        n = med.n_levels
+        nsnap = g.nt // snap_every if snap_every > 0 else 0
+        dev = torch.device("cuda")
+        z = lambda shape, on: torch.zeros(shape, dtype=torch.float64, device=dev) if on else None
+        self.probe_z = z((g.nt + 1,), record_probe)
+        self.probe_y = z((g.nt + 1,), record_probe)
+        self.ez_snap = z((nsnap, g.nx), record_e and nsnap)
+        self.ey_snap = z((nsnap, g.nx), record_e and nsnap)
+        self.pop = z((nsnap, n, g.n_med), record_pop and nsnap)
+        self._ma = _MediumArgs(med)
+        self._muy = _cx(np.asarray(dipole_y, dtype=np.complex128).reshape(n, n))
+        self._samples = np.ascontiguousarray(src.samples, dtype=np.float64)
+        gs = _Grid(g.nx, g.nt, g.dx, g.dt, g.med_begin, g.med_end, g.eps_r, g.mu_r, g.sigma)
+        ss = _Source(_ptr(self._samples), len(self._samples), float(src.amplitude))
+        rs = _Pol2Record(snap_every, _dptr(self.ez_snap), _dptr(self.ey_snap), _dptr(self.pop),
+                         _dptr(self.probe_z), _dptr(self.probe_y))
+        self.stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(L.mln_pol2_init(ctypes.byref(self._ma.s), _ptr(self._muy), ctypes.byref(gs), ctypes.byref(ss),
+                               float(amplitude_y), ctypes.byref(rs), ctypes.c_void_p(self.stream.cuda_stream),
+                               ctypes.byref(h)))
+        self._h = h
+
+    def step(self, n):
+        _check(self._L.mln_pol2_step(self._h, int(n)))
+
+    def run(self):
+        _check(self._L.mln_pol2_run(self._h))
+        return self.outputs()
+
+    def reset(self):
+        _check(self._L.mln_pol2_reset(self._h))
+
+    def current_step(self):
+        s = ctypes.c_int64()
+        _check(self._L.mln_pol2_current_step(self._h, ctypes.byref(s)))
+        return s.value
+
+    def outputs(self):
+        return dict(probe_z=self.probe_z, probe_y=self.probe_y, ez_snap=self.ez_snap, ey_snap=self.ey_snap,
+                    pop=self.pop)
+
+    def fields(self):
+        """E_z, H_y, E_y, H_z (E at the current step, H half a step earlier)."""
+        g = self.problem.grid
+        out = [np.zeros(g.nx), np.zeros(g.nx - 1), np.zeros(g.nx), np.zeros(g.nx - 1)]
+        _check(self._L.mln_pol2_get_fields(self._h, *(_ptr(a) for a in out)))
+        return tuple(out)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.mln_pol2_free(self._h)
             self._h = None
 
     def __del__(self):

@@ -433,6 +433,16 @@ def random_problem(n, seed, nx=48, nt=300, relax=True, med=None):
     return Problem(f"random_n{n}_s{seed}", medium, grid, src)
 
 
+def random_dipole(n, seed, scale):
+    """A random N x N complex Hermitian dipole operator whose largest entry is
+    `scale` [C m] (the second dipole of the two-component runs: it does not
+    commute with a random first one)."""
+    rng = np.random.default_rng(seed + 29)
+    a = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    h = 0.5 * (a + a.conj().T)
+    return scale * h / np.max(np.abs(h))
+
+
 # ---------------------------------------------------------------------------
 # two-dimensional (TMz) problems: the paper's scheme is one-dimensional
 # (Conclusion names the restriction); these extend the grid to x-y with the

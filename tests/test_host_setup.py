@@ -27,7 +27,7 @@ def lib():
 
 def test_library_exports_every_header_symbol(lib):
     hdr = open(os.path.join(ROOT, "include", "mln.h")).read()
-    declared = set(re.findall(r"\b(mln_[a-z_]+)\s*\(", hdr))
+    declared = set(re.findall(r"\b(mln_[a-z0-9_]+)\s*\(", hdr))
     assert declared == set(mln.EXPORTS), declared ^ set(mln.EXPORTS)
     for name in declared:
         assert hasattr(lib, name)
