@@ -456,6 +456,43 @@ def tmz_beam(reps=REPS):
     return out
 
 
+def pol2_cross_ladder(reps=REPS):
+    """Both transverse field components (mln_pol2_*, FP64): the three-level
+    ladder with mu01 on E_z and mu12 on E_y (workloads.cross_ladder), 20000
+    cells x 20000 steps, one launch per step.  GB/s are algorithmic: every
+    cell's E_z, H_y, E_y, H_z and every medium cell's Bloch vector read and
+    written once per step; the median of `reps` runs."""
+    import torch
+    from paper_1710_09799_amd import mln
+    from paper_1710_09799_amd import workloads as W
+    p, muy, amp_y = W.cross_ladder()
+    g = p.grid
+    D = p.medium.n_levels ** 2 - 1
+    s = mln.Pol2(p, muy, amp_y, record_pop=False, record_e=False)
+    s.run()
+    e0, e1 = _events()
+    walls, gpus = [], []
+    for _ in range(reps):
+        s.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record()
+        s.step(g.nt)
+        e1.record()
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        gpus.append(e0.elapsed_time(e1) * 1e-3)
+    s.close()
+    t, gt = _median(walls), _median(gpus)
+    us = gt / g.nt * 1e6
+    byts = (g.nx * 4 * 2 + g.n_med * D * 2) * 8
+    return {"workload": f"three-level ladder, mu01 on E_z and mu12 on E_y, {g.nx} cells, {g.nt} steps",
+            "kernel": "fwd_pol2_kernel (one thread per cell, 256 per workgroup, one launch per step)",
+            "value": g.n_med * g.nt / t, "us_per_step": us, "alg_bytes_per_step": byts,
+            "alg_GBps": byts / (us * 1e-6) / 1e9, "hbm_frac": byts / (us * 1e-6) / 8e12,
+            "dtype": "f64"}
+
+
 def pstd_ring():
     """Pseudo-spectral field solver (one workgroup per problem): the
     three-level ladder on a periodic ring of 2048 cells of lambda0/8 (medium
@@ -576,6 +613,8 @@ PROFILE_CASES = {
     "tmz_fp64": ("tmz", dict(nt=512), dict(precision="fp64")),
     "tmz_fp32": ("tmz", dict(nt=512), dict(precision="fp32")),
     "tmz_fp32c": ("tmz", dict(nt=512), dict(precision="fp32c")),
+    # both transverse components (cross-polarised ladder, 20000 cells), 4000 steps
+    "pol2_fp64": ("pol2", dict(nt=4000), {}),
     "pstd_n3_ring": ("pstd", dict(batch=1, med=True), dict(steps_per_launch=256)),
     "pstd_n3_ring_fields": ("pstd", dict(batch=1, med=False), dict(steps_per_launch=256)),
     "pstd_n3_ring_batch256": ("pstd", dict(batch=256, med=True), dict(steps_per_launch=256)),
@@ -657,6 +696,28 @@ def profile_tmz(name, nt, precision, steps, warmup):
                       "cell_updates_per_s": g.n_med * nt / t, "precision": precision}))
 
 
+def profile_pol2(name, nt, steps, warmup):
+    import torch
+    from paper_1710_09799_amd import mln
+    from paper_1710_09799_amd import workloads as W
+    p, muy, amp_y = W.cross_ladder(nt=nt)
+    s = mln.Pol2(p, muy, amp_y, record_pop=False, record_e=False)
+    ts = []
+    for r in range(warmup + steps):
+        s.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(nt)
+        torch.cuda.synchronize()
+        if r >= warmup:
+            ts.append(time.perf_counter() - t0)
+    s.close()
+    t = _median(ts)
+    g = p.grid
+    print(json.dumps({"profile_case": name, "nx": g.nx, "nt": nt, "n_med": g.n_med, "launches_per_run": nt,
+                      "ms_per_run": t * 1e3, "us_per_step": t / nt * 1e6, "cell_updates_per_s": g.n_med * nt / t}))
+
+
 def profile_case(name, steps, warmup, calib):
     from paper_1710_09799_amd import workloads as W
     if name == "adjoint":
@@ -670,6 +731,9 @@ def profile_case(name, steps, warmup, calib):
         return
     if wl == "pstd":
         profile_pstd(name, pkw["batch"], pkw["med"], kw["steps_per_launch"], steps, warmup)
+        return
+    if wl == "pol2":
+        profile_pol2(name, pkw["nt"], steps, warmup)
         return
     if wl == "batch":
         profile_batch(name, pkw["nt"], kw, steps, warmup)
@@ -799,6 +863,7 @@ def main():
         var["n3_speedup_vs_best_fp64"] = {
             k: var[k]["value"] / best64 for k in var if k.startswith("n3_fp32") and "value" in var[k]}
         var["tmz_2d_beam"] = tmz_beam()
+        var["pol2_cross_ladder"] = pol2_cross_ladder()
         var["pstd_ring"] = pstd_ring()
         res["variants"] = var
     if not args.no_cpu:

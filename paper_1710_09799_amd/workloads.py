@@ -281,6 +281,20 @@ def three_level(nx=20000, nt=100000, name="three_level_ladder_pi_gauss"):
     return Problem(name, med, grid, src)
 
 
+def cross_ladder(nx=20000, nt=20000, name="three_level_cross_polarised_ladder"):
+    """The three-level ladder of three_level() with its two transitions
+    coupled to different field components: mu01 (1e-29) to E_z and mu12
+    (0.8e-29) to E_y (dipoles that do not commute); the pi pulse of
+    three_level() drives E_z, the same waveform at 0.6 of its amplitude E_y.
+    Returns (problem, dipole_y, amplitude_y) for the two-component solver."""
+    p = three_level(nx=nx, nt=nt, name=name)
+    h0 = np.real(np.diag(p.medium.h0))
+    p.medium = ladder_medium(list(h0), [1e-29, 0.0], density=1e24, decay=1e12, dephasing=5e12)
+    muy = np.zeros((3, 3), dtype=np.complex128)
+    muy[1, 2] = muy[2, 1] = 0.8e-29
+    return p, muy, 0.6 * p.source.amplitude
+
+
 # A spectral grid resolves a wave with far fewer cells than the Yee grid.
 DX_PSTD = LAMBDA0 / 8.0
 DT_PSTD = 0.5 * DX_PSTD / C0  # Courant number 0.5 (PSTD leapfrog limit ~2/pi)
