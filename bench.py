@@ -208,6 +208,24 @@ def cpu_baseline(reps=REPS):
                                f"median of {reps} ({t:.2f} s each)",
                      "single_thread": {"value": v1, "cores": 1,
                                        "sample": f"first {nt1} steps, median of {reps} ({t1:.2f} s each)"}}
+    # the rows beyond the one-component 1-D path (all cores; the oracle's PSTD
+    # derivative is a direct DFT, O(nx^2) per step)
+    p2d = W.three_level_2d()
+    pp, e0, h0 = W.pstd_three_level()
+    pc, muy, ay = W.cross_ladder()
+    extra = (("tmz_2d_beam", p2d, 2, lambda nt: oracle.run2d(p2d, nt=nt, nthreads=threads)),
+             ("pstd_ring", pp, 4, lambda nt: oracle.pstd_run(pp, nt=nt, e_init=e0, h_init=h0, nthreads=threads)),
+             ("pol2_cross_ladder", pc, 100, lambda nt: oracle.run_pol2(pc, muy, ay, nt=nt, nthreads=threads)))
+    for name, p, nt, fn in extra:
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn(nt)
+            ts.append(time.perf_counter() - t0)
+        t = _median(ts)
+        per[name] = {"value": p.grid.n_med * nt / t, "cores": threads,
+                     "sample": f"{p.grid.n_med} medium cells, first {nt} of {p.grid.nt} steps, median of {reps} "
+                               f"({t:.2f} s each)"}
     head = per["n3_three_level"]
     return {"value": head["value"], "unit": "Liouville cell-updates/s", "cores": threads, "kind": "oracle",
             "sample": "three-level ladder on the full 20000-cell grid, " + head["sample"] +
