@@ -477,38 +477,48 @@ def tmz_beam(reps=REPS):
 def pol2_cross_ladder(reps=REPS):
     """Both transverse field components (mln_pol2_*, FP64): the three-level
     ladder with mu01 on E_z and mu12 on E_y (workloads.cross_ladder), 20000
-    cells x 20000 steps, one launch per step.  GB/s are algorithmic: every
-    cell's E_z, H_y, E_y, H_z and every medium cell's Bloch vector read and
-    written once per step; the median of `reps` runs."""
+    cells x 20000 steps; the blocked kernel at its default 32 steps per
+    launch (the value) and the one-step kernel (one launch per step).  GB/s
+    are the one-step kernel's algorithmic traffic: every cell's E_z, H_y,
+    E_y, H_z and every medium cell's Bloch vector read and written once per
+    step; the median of `reps` runs."""
     import torch
     from paper_1710_09799_amd import mln
     from paper_1710_09799_amd import workloads as W
     p, muy, amp_y = W.cross_ladder()
     g = p.grid
     D = p.medium.n_levels ** 2 - 1
-    s = mln.Pol2(p, muy, amp_y, record_pop=False, record_e=False)
-    s.run()
-    e0, e1 = _events()
-    walls, gpus = [], []
-    for _ in range(reps):
-        s.reset()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        e0.record()
-        s.step(g.nt)
-        e1.record()
-        torch.cuda.synchronize()
-        walls.append(time.perf_counter() - t0)
-        gpus.append(e0.elapsed_time(e1) * 1e-3)
-    s.close()
-    t, gt = _median(walls), _median(gpus)
-    us = gt / g.nt * 1e6
+
+    def timed(k):
+        s = mln.Pol2(p, muy, amp_y, record_pop=False, record_e=False, steps_per_launch=k)
+        s.run()
+        e0, e1 = _events()
+        walls, gpus = [], []
+        for _ in range(reps):
+            s.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e0.record()
+            s.step(g.nt)
+            e1.record()
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t0)
+            gpus.append(e0.elapsed_time(e1) * 1e-3)
+        s.close()
+        return _median(walls), _median(gpus)
+
+    t, gt = timed(32)
+    t1, gt1 = timed(1)
+    us, us1 = gt / g.nt * 1e6, gt1 / g.nt * 1e6
     byts = (g.nx * 4 * 2 + g.n_med * D * 2) * 8
     return {"workload": f"three-level ladder, mu01 on E_z and mu12 on E_y, {g.nx} cells, {g.nt} steps",
-            "kernel": "fwd_pol2_kernel (one thread per cell, 256 per workgroup, one launch per step)",
-            "value": g.n_med * g.nt / t, "us_per_step": us, "alg_bytes_per_step": byts,
-            "alg_GBps": byts / (us * 1e-6) / 1e9, "hbm_frac": byts / (us * 1e-6) / 8e12,
-            "dtype": "f64"}
+            "kernel": "fwd_pol2_tile_kernel (one thread per cell, 256-cell windows, 191 owned, "
+                      "32 steps per launch)",
+            "value": g.n_med * g.nt / t, "us_per_step": us, "dtype": "f64",
+            "one_step_kernel": {"kernel": "fwd_pol2_kernel (one launch per step)",
+                                "value": g.n_med * g.nt / t1, "us_per_step": us1,
+                                "alg_bytes_per_step": byts, "alg_GBps": byts / (us1 * 1e-6) / 1e9,
+                                "hbm_frac": byts / (us1 * 1e-6) / 8e12}}
 
 
 def pstd_ring():
@@ -632,7 +642,8 @@ PROFILE_CASES = {
     "tmz_fp32": ("tmz", dict(nt=512), dict(precision="fp32")),
     "tmz_fp32c": ("tmz", dict(nt=512), dict(precision="fp32c")),
     # both transverse components (cross-polarised ladder, 20000 cells), 4000 steps
-    "pol2_fp64": ("pol2", dict(nt=4000), {}),
+    "pol2_fp64": ("pol2", dict(nt=4000, k=32), {}),
+    "pol2_fp64_one_step": ("pol2", dict(nt=4000, k=1), {}),
     "pstd_n3_ring": ("pstd", dict(batch=1, med=True), dict(steps_per_launch=256)),
     "pstd_n3_ring_fields": ("pstd", dict(batch=1, med=False), dict(steps_per_launch=256)),
     "pstd_n3_ring_batch256": ("pstd", dict(batch=256, med=True), dict(steps_per_launch=256)),
@@ -714,12 +725,12 @@ def profile_tmz(name, nt, precision, steps, warmup):
                       "cell_updates_per_s": g.n_med * nt / t, "precision": precision}))
 
 
-def profile_pol2(name, nt, steps, warmup):
+def profile_pol2(name, nt, steps, warmup, k):
     import torch
     from paper_1710_09799_amd import mln
     from paper_1710_09799_amd import workloads as W
     p, muy, amp_y = W.cross_ladder(nt=nt)
-    s = mln.Pol2(p, muy, amp_y, record_pop=False, record_e=False)
+    s = mln.Pol2(p, muy, amp_y, record_pop=False, record_e=False, steps_per_launch=k)
     ts = []
     for r in range(warmup + steps):
         s.reset()
@@ -732,7 +743,8 @@ def profile_pol2(name, nt, steps, warmup):
     s.close()
     t = _median(ts)
     g = p.grid
-    print(json.dumps({"profile_case": name, "nx": g.nx, "nt": nt, "n_med": g.n_med, "launches_per_run": nt,
+    print(json.dumps({"profile_case": name, "nx": g.nx, "nt": nt, "n_med": g.n_med, "steps_per_launch": k,
+                      "launches_per_run": (nt + k - 1) // k,
                       "ms_per_run": t * 1e3, "us_per_step": t / nt * 1e6, "cell_updates_per_s": g.n_med * nt / t}))
 
 
@@ -751,7 +763,7 @@ def profile_case(name, steps, warmup, calib):
         profile_pstd(name, pkw["batch"], pkw["med"], kw["steps_per_launch"], steps, warmup)
         return
     if wl == "pol2":
-        profile_pol2(name, pkw["nt"], steps, warmup)
+        profile_pol2(name, pkw["nt"], steps, warmup, pkw["k"])
         return
     if wl == "batch":
         profile_batch(name, pkw["nt"], kw, steps, warmup)

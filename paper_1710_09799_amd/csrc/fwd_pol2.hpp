@@ -20,16 +20,28 @@
 // consecutive steps merge into K_u = T_y^T A0^2 T_y, c_u = T_y^T (A0 + I) b0.
 // A step costs three D x D products (B^T, B, K_u) and three rotation sets.
 //
-// One launch advances one time step, one thread per cell (the form streamed
-// through HBM): E, H, E_y, G and the state are read once and written once.
-// The new H on the face left of a cell is formed from the old values with
-// the expression its owner uses (bitwise equal), so no thread waits for
-// another.  FP64.
+// Two kernels share the cell arithmetic:
+// * fwd_pol2_kernel: one launch per time step, one thread per cell, every
+//   field and Bloch vector read from and written to device memory once per
+//   step; the new H on the face left of a cell is formed from the old values
+//   with the expression its owner uses (bitwise equal), so no thread waits
+//   for another;
+// * fwd_pol2_tile_kernel: several steps per launch (temporal blocking), one
+//   thread per cell of a window of kPol2TileW cells; E_z, H_y, E_y and G of
+//   the window in LDS (two buffers, one barrier per step), the Bloch vector
+//   in registers; each workgroup owns kPol2TileW - 2 K - 1 cells and
+//   recomputes K cells on its right and K + 1 on its left (the stencil
+//   radius is one cell, two for the Mur cell), so neighbouring workgroups
+//   never wait for each other.
+// FP64.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
 namespace mln {
+
+constexpr int kPol2TileW = 256;      // threads (cells) per workgroup of the tile kernel
+constexpr int kPol2MaxSteps = 64;    // steps per launch of the tile kernel: W - 2 K - 1 >= 127 owned cells
 
 // factor block (doubles): B, K_u, c_u, w_z, w_y (in u-coordinates), the
 // rotation angles per unit field theta_y dt/2 and theta_z dt, population
@@ -46,12 +58,14 @@ struct Pol2Args {
   const double *fac;
   const double *Ezin, *Hyin, *Eyin, *Gin;
   double *Ezout, *Hyout, *Eyout, *Gout;
-  double *u;            // state [D][ld], updated in place (each thread owns its cell)
+  const double *uin;    // state [D][ld] before the launch
+  double *uout;         // state after the launch
   const double *src;    // source waveform, nt + 1 samples
-  int64_t nx, mb, me, ld, n;  // n: the step taken (fields n -> n + 1)
+  int64_t nx, mb, me, ld, n0;  // n0: the launch's first step (fields n0 -> n0 + 1)
+  int nsteps, halo;            // tile kernel: steps in this launch (<= halo), steps per launch of the handle
+  int64_t owned;               // tile kernel: cells owned by a workgroup, kPol2TileW - 2 halo - 1
   double amp_z, amp_y, ch, ca, cb, inv_dx, kmur;
-  int snap;
-  int64_t snap_i;
+  int64_t snap_every, snap_next, snap_i0;  // first snapshot step >= n0 (-1: none) and its index
   double *ez_out, *ey_out, *pop_out, *probe_z, *probe_y;  // device records (NULL: not recorded)
 };
 
@@ -83,106 +97,137 @@ __device__ __forceinline__ void pol2_sincm1(double x, double &s, double &cm1) {
   }
 }
 
-// the 2x2 rotations of the pairs (2p, 2p+1) by angle th[p] e
+// sin and cos - 1 of the angles th[p] e, and the 2x2 rotations of the pairs
+// (2p, 2p+1) by them
+template <int Q>
+__device__ __forceinline__ void pol2_angles(const double *th, double e, double (&s)[Q], double (&cm1)[Q]) {
+#pragma unroll
+  for (int p = 0; p < Q; ++p) pol2_sincm1(th[p] * e, s[p], cm1[p]);
+}
 template <int D, int Q>
-__device__ __forceinline__ void pol2_rotate(double (&x)[D], const double *th, double e) {
+__device__ __forceinline__ void pol2_rotate(double (&x)[D], const double (&s)[Q], const double (&cm1)[Q]) {
 #pragma unroll
   for (int p = 0; p < Q; ++p) {
-    double s, cm1;
-    pol2_sincm1(th[p] * e, s, cm1);
     const double a = x[2 * p], b = x[2 * p + 1];
-    x[2 * p] = a + (cm1 * a + s * b);
-    x[2 * p + 1] = b + (cm1 * b - s * a);
+    x[2 * p] = a + (cm1[p] * a + s[p] * b);
+    x[2 * p + 1] = b + (cm1[p] * b - s[p] * a);
   }
+}
+
+// The medium step of one cell: u (= T_y^T d') -> T_y^T d'' through the split
+// interaction factor, dP_z/dt and dP_y/dt from it, the populations of
+// d^{n+1/2} into pp[lv * pstride] (pp NULL: not recorded), and the two half
+// steps of this and the next step.
+template <int N>
+__device__ __forceinline__ void pol2_medium(const double *F, double (&u)[N * N - 1], double Ecz, double Ecy,
+                                            double &Pz, double &Py, double *pp, int64_t pstride) {
+  using L = Pol2Layout<N>;
+  constexpr int D = L::D, Q = L::Q;
+  double w[D], sy[Q], cy[Q], sz[Q], cz[Q];
+  pol2_angles<Q>(F + L::othy, Ecy, sy, cy);  // the same angles for both y half steps
+  pol2_rotate<D, Q>(u, sy, cy);              // exp(U_y E_y dt/2)
+#pragma unroll
+  for (int i = 0; i < D; ++i) {  // to z-rotation coordinates: w = B^T u
+    double t = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) t += F[L::oB + j * D + i] * u[j];
+    w[i] = t;
+  }
+  pol2_angles<Q>(F + L::othz, Ecz, sz, cz);
+  pol2_rotate<D, Q>(w, sz, cz);  // exp(U_z E_z dt)
+#pragma unroll
+  for (int i = 0; i < D; ++i) {  // back: u = B w
+    double t = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) t += F[L::oB + i * D + j] * w[j];
+    u[i] = t;
+  }
+  pol2_rotate<D, Q>(u, sy, cy);  // exp(U_y E_y dt/2): u = T_y^T d''
+  Pz = F[L::op0];
+  Py = F[L::op0 + 1];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    Pz += F[L::owz + j] * u[j];
+    Py += F[L::owy + j] * u[j];
+  }
+  if (pp) {
+#pragma unroll
+    for (int lv = 0; lv < N; ++lv) {
+      double p = F[L::opopc + lv];
+#pragma unroll
+      for (int j = 0; j < D; ++j) p += F[L::opop + lv * D + j] * u[j];
+      pp[lv * pstride] = p;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i) {  // the two half steps of this and the next step
+    double t = F[L::oc + i];
+#pragma unroll
+    for (int j = 0; j < D; ++j) t += F[L::oK + i * D + j] * u[j];
+    w[i] = t;
+  }
+#pragma unroll
+  for (int j = 0; j < D; ++j) u[j] = w[j];
+}
+
+// The field part of one cell g (0 <= g <= nx - 2) from the old E of the
+// cell and its neighbours and the old H on its two faces: the new H on both
+// faces (the left one as its owner forms it), then the new E (hard source
+// at cell 0) with the medium's dP/dt, for one component pair.
+struct Pol2Pair {
+  double Hr, Hl;
+};
+__device__ __forceinline__ Pol2Pair pol2_faces(const Pol2Args &a, int64_t g, double El, double Ec, double Er,
+                                               double Hl_old, double Hr_old) {
+  Pol2Pair h;
+  h.Hr = Hr_old + a.ch * (Er - Ec);
+  h.Hl = g >= 1 ? Hl_old + a.ch * (Ec - El) : 0.0;
+  return h;
+}
+__device__ __forceinline__ double pol2_e(const Pol2Args &a, int64_t g, double amp, int64_t n, double Ec,
+                                         const Pol2Pair &h, double P) {
+  return g == 0 ? amp * a.src[n + 1] : a.ca * Ec + a.cb * (-P + (h.Hr - h.Hl) * a.inv_dx);
 }
 
 template <int N>
 __device__ __forceinline__ void pol2_cell(const Pol2Args &a, const double *F, int64_t g) {
-  using L = Pol2Layout<N>;
-  constexpr int D = L::D, Q = L::Q;
-  const int64_t nx = a.nx;
-  // (E_z, H_y): old E of the cell and its neighbours, new H on both faces
+  constexpr int D = N * N - 1;
+  const int64_t nx = a.nx, n = a.n0;
+  const bool snap = n == a.snap_next;
   const double Ecz = a.Ezin[g], Erz = a.Ezin[g + 1], Elz = g >= 1 ? a.Ezin[g - 1] : 0.0;
-  const double Hrz = a.Hyin[g] + a.ch * (Erz - Ecz);
-  const double Hlz = g >= 1 ? a.Hyin[g - 1] + a.ch * (Ecz - Elz) : 0.0;
-  // (E_y, G)
   const double Ecy = a.Eyin[g], Ery = a.Eyin[g + 1], Ely = g >= 1 ? a.Eyin[g - 1] : 0.0;
-  const double Hry = a.Gin[g] + a.ch * (Ery - Ecy);
-  const double Hly = g >= 1 ? a.Gin[g - 1] + a.ch * (Ecy - Ely) : 0.0;
-  a.Hyout[g] = Hrz;
-  a.Gout[g] = Hry;
+  const Pol2Pair hz = pol2_faces(a, g, Elz, Ecz, Erz, g >= 1 ? a.Hyin[g - 1] : 0.0, a.Hyin[g]);
+  const Pol2Pair hy = pol2_faces(a, g, Ely, Ecy, Ery, g >= 1 ? a.Gin[g - 1] : 0.0, a.Gin[g]);
+  a.Hyout[g] = hz.Hr;
+  a.Gout[g] = hy.Hr;
   double Pz = 0.0, Py = 0.0;
   if (g >= a.mb && g < a.me) {
     const int64_t c = g - a.mb, nmed = a.me - a.mb;
-    double u[D], w[D];
+    double u[D];
 #pragma unroll
-    for (int j = 0; j < D; ++j) u[j] = a.u[j * a.ld + c];
-    pol2_rotate<D, Q>(u, F + L::othy, Ecy);  // exp(U_y E_y dt/2)
+    for (int j = 0; j < D; ++j) u[j] = a.uin[j * a.ld + c];
+    double *pp = (snap && a.pop_out) ? a.pop_out + a.snap_i0 * N * nmed + c : nullptr;
+    pol2_medium<N>(F, u, Ecz, Ecy, Pz, Py, pp, nmed);
 #pragma unroll
-    for (int i = 0; i < D; ++i) {  // to z-rotation coordinates: w = B^T u
-      double s = 0.0;
-#pragma unroll
-      for (int j = 0; j < D; ++j) s += F[L::oB + j * D + i] * u[j];
-      w[i] = s;
-    }
-    pol2_rotate<D, Q>(w, F + L::othz, Ecz);  // exp(U_z E_z dt)
-#pragma unroll
-    for (int i = 0; i < D; ++i) {  // back: u = B w
-      double s = 0.0;
-#pragma unroll
-      for (int j = 0; j < D; ++j) s += F[L::oB + i * D + j] * w[j];
-      u[i] = s;
-    }
-    pol2_rotate<D, Q>(u, F + L::othy, Ecy);  // exp(U_y E_y dt/2): u = T_y^T d''
-    Pz = F[L::op0];
-    Py = F[L::op0 + 1];
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-      Pz += F[L::owz + j] * u[j];
-      Py += F[L::owy + j] * u[j];
-    }
-    if (a.snap && a.pop_out) {
-#pragma unroll
-      for (int lv = 0; lv < N; ++lv) {
-        double p = F[L::opopc + lv];
-#pragma unroll
-        for (int j = 0; j < D; ++j) p += F[L::opop + lv * D + j] * u[j];
-        a.pop_out[(a.snap_i * N + lv) * nmed + c] = p;
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < D; ++i) {  // the two half steps of this and the next step
-      double s = F[L::oc + i];
-#pragma unroll
-      for (int j = 0; j < D; ++j) s += F[L::oK + i * D + j] * u[j];
-      w[i] = s;
-    }
-#pragma unroll
-    for (int j = 0; j < D; ++j) a.u[j * a.ld + c] = w[j];
+    for (int j = 0; j < D; ++j) a.uout[j * a.ld + c] = u[j];
   }
-  double Ezn, Eyn;
-  if (g == 0) {  // hard sources
-    Ezn = a.amp_z * a.src[a.n + 1];
-    Eyn = a.amp_y * a.src[a.n + 1];
-  } else {
-    Ezn = a.ca * Ecz + a.cb * (-Pz + (Hrz - Hlz) * a.inv_dx);
-    Eyn = a.ca * Ecy + a.cb * (-Py + (Hry - Hly) * a.inv_dx);
-  }
+  const double Ezn = pol2_e(a, g, a.amp_z, n, Ecz, hz, Pz);
+  const double Eyn = pol2_e(a, g, a.amp_y, n, Ecy, hy, Py);
   a.Ezout[g] = Ezn;
   a.Eyout[g] = Eyn;
-  if (a.snap) {
-    if (a.ez_out) a.ez_out[a.snap_i * nx + g] = Ezn;
-    if (a.ey_out) a.ey_out[a.snap_i * nx + g] = Eyn;
+  if (snap) {
+    if (a.ez_out) a.ez_out[a.snap_i0 * nx + g] = Ezn;
+    if (a.ey_out) a.ey_out[a.snap_i0 * nx + g] = Eyn;
   }
   if (g == nx - 2) {  // first-order Mur boundary at cell nx - 1, both components
     const double Ebz = Ecz + a.kmur * (Ezn - Erz), Eby = Ecy + a.kmur * (Eyn - Ery);
     a.Ezout[nx - 1] = Ebz;
     a.Eyout[nx - 1] = Eby;
-    if (a.probe_z) a.probe_z[a.n + 1] = Ebz;
-    if (a.probe_y) a.probe_y[a.n + 1] = Eby;
-    if (a.snap) {
-      if (a.ez_out) a.ez_out[a.snap_i * nx + nx - 1] = Ebz;
-      if (a.ey_out) a.ey_out[a.snap_i * nx + nx - 1] = Eby;
+    if (a.probe_z) a.probe_z[n + 1] = Ebz;
+    if (a.probe_y) a.probe_y[n + 1] = Eby;
+    if (snap) {
+      if (a.ez_out) a.ez_out[a.snap_i0 * nx + nx - 1] = Ebz;
+      if (a.ey_out) a.ey_out[a.snap_i0 * nx + nx - 1] = Eby;
     }
   }
 }
@@ -197,6 +242,109 @@ __global__ void __launch_bounds__(256) fwd_pol2_kernel(Pol2Args a) {
   __syncthreads();
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g < a.nx - 1) pol2_cell<N>(a, sF, g);  // cell nx - 1 (Mur) is written by the thread of nx - 2
+}
+
+// a.nsteps steps (at most a.halo) on the window of workgroup b: cells
+// o0 - halo - 1 .. o0 + owned + halo - 1 with o0 = b owned, thread i on cell
+// o0 - halo - 1 + i.  Cells outside 0 .. nx-1 hold zero, as the one-step
+// kernel's missing neighbours do.  After s steps the window's values are
+// exact from its left end + s to its right end - s (the Mur cell from
+// nx - 3 on), so after at most halo steps on the owned cells, which alone
+// are written back and recorded.
+template <int N>
+__global__ void __launch_bounds__(kPol2TileW) fwd_pol2_tile_kernel(Pol2Args a) {
+  using L = Pol2Layout<N>;
+  constexpr int D = L::D, S = kPol2TileW + 2;
+  __shared__ double sF[L::size];
+  __shared__ double sE[2][2][S];  // [buffer][E_z, E_y][slot]; slot i + 1 holds thread i's cell
+  __shared__ double sH[2][2][S];  // [buffer][H_y, G][slot]
+  const int i = threadIdx.x, q = i + 1;
+  const int64_t nx = a.nx;
+  const int64_t o0 = (int64_t)blockIdx.x * a.owned, o1 = o0 + a.owned < nx ? o0 + a.owned : nx;
+  const int64_t g = o0 - a.halo - 1 + i;
+  for (int k = i; k < L::size; k += kPol2TileW) sF[k] = a.fac[k];
+  for (int k = i; k < 2 * 2 * S; k += kPol2TileW) {
+    (&sE[0][0][0])[k] = 0.0;
+    (&sH[0][0][0])[k] = 0.0;
+  }
+  __syncthreads();
+  const bool act = g >= 0 && g < nx - 1;  // cells with a step of their own (nx - 1: Mur, from nx - 2)
+  const bool med = g >= a.mb && g < a.me;
+  const bool own = g >= o0 && g < o1;
+  const bool last = o1 == nx;  // this workgroup records the Mur cell
+  const int64_t c = g - a.mb, nmed = a.me - a.mb;
+  if (g >= 0 && g < nx) {
+    sE[0][0][q] = a.Ezin[g];
+    sE[0][1][q] = a.Eyin[g];
+  }
+  if (act) {
+    sH[0][0][q] = a.Hyin[g];
+    sH[0][1][q] = a.Gin[g];
+  }
+  double u[D];
+  if (med) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) u[j] = a.uin[j * a.ld + c];
+  }
+  __syncthreads();
+  int b = 0;
+  int64_t sn = a.snap_next, si = a.snap_i0;
+  for (int s = 0; s < a.nsteps; ++s) {
+    const int64_t n = a.n0 + s;
+    const bool snap = n == sn;
+    if (act) {
+      const double Ecz = sE[b][0][q], Erz = sE[b][0][q + 1], Elz = sE[b][0][q - 1];
+      const double Ecy = sE[b][1][q], Ery = sE[b][1][q + 1], Ely = sE[b][1][q - 1];
+      const Pol2Pair hz = pol2_faces(a, g, Elz, Ecz, Erz, sH[b][0][q - 1], sH[b][0][q]);
+      const Pol2Pair hy = pol2_faces(a, g, Ely, Ecy, Ery, sH[b][1][q - 1], sH[b][1][q]);
+      double Pz = 0.0, Py = 0.0;
+      if (med) {
+        double *pp = (snap && own && a.pop_out) ? a.pop_out + si * N * nmed + c : nullptr;
+        pol2_medium<N>(sF, u, Ecz, Ecy, Pz, Py, pp, nmed);
+      }
+      const double Ezn = pol2_e(a, g, a.amp_z, n, Ecz, hz, Pz);
+      const double Eyn = pol2_e(a, g, a.amp_y, n, Ecy, hy, Py);
+      sH[b ^ 1][0][q] = hz.Hr;
+      sH[b ^ 1][1][q] = hy.Hr;
+      sE[b ^ 1][0][q] = Ezn;
+      sE[b ^ 1][1][q] = Eyn;
+      if (snap && own) {
+        if (a.ez_out) a.ez_out[si * nx + g] = Ezn;
+        if (a.ey_out) a.ey_out[si * nx + g] = Eyn;
+      }
+      if (g == nx - 2) {  // first-order Mur boundary at cell nx - 1, both components
+        const double Ebz = Ecz + a.kmur * (Ezn - Erz), Eby = Ecy + a.kmur * (Eyn - Ery);
+        sE[b ^ 1][0][q + 1] = Ebz;
+        sE[b ^ 1][1][q + 1] = Eby;
+        if (last) {
+          if (a.probe_z) a.probe_z[n + 1] = Ebz;
+          if (a.probe_y) a.probe_y[n + 1] = Eby;
+          if (snap) {
+            if (a.ez_out) a.ez_out[si * nx + nx - 1] = Ebz;
+            if (a.ey_out) a.ey_out[si * nx + nx - 1] = Eby;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    b ^= 1;
+    if (snap) {
+      sn += a.snap_every;
+      ++si;
+    }
+  }
+  if (own) {
+    a.Ezout[g] = sE[b][0][q];
+    a.Eyout[g] = sE[b][1][q];
+    if (g < nx - 1) {
+      a.Hyout[g] = sH[b][0][q];
+      a.Gout[g] = sH[b][1][q];
+    }
+    if (med) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) a.uout[j * a.ld + c] = u[j];
+    }
+  }
 }
 
 }  // namespace mln

@@ -1,7 +1,7 @@
 // pol2.hip -- the two-component solver of include/mln.h (mln_pol2_*): both
 // transverse field components with H_I = -mu_z E_z - mu_y E_y.  Validation,
 // the factors of the split interaction step (host, FP64), device state, the
-// per-step launch loop and the kernel instantiations of fwd_pol2.hpp.
+// launch loop and the kernel instantiations of fwd_pol2.hpp.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,10 +21,11 @@ struct mln_pol2 {
   mln_pol2_record rec{};
   hipStream_t stream = nullptr;
   int64_t nmed = 0, ld = 0, step = 0, nsnap = 0;
+  int K = 32;  // steps per launch: 1 = the one-step kernel, more = the tile kernel
   double amp_z = 0.0, amp_y = 0.0;
   double coef[5] = {0, 0, 0, 0, 0};  // ch, ca, cb, 1/dx, kmur
   std::vector<double> u0, src_host;
-  DevBuf fac, src, u, Ez[2], Hy[2], Ey[2], G[2];
+  DevBuf fac, src, u[2], Ez[2], Hy[2], Ey[2], G[2];
   int cur = 0;
 };
 
@@ -37,10 +38,17 @@ hipError_t launch_n(const Pol2Args &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_pol2(int N, const Pol2Args &a, hipStream_t st) {
+template <int N>
+hipError_t launch_tile_n(const Pol2Args &a, hipStream_t st) {
+  const unsigned nb = (unsigned)((a.nx + a.owned - 1) / a.owned);
+  hipLaunchKernelGGL((fwd_pol2_tile_kernel<N>), dim3(nb), dim3(kPol2TileW), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pol2(int N, bool tile, const Pol2Args &a, hipStream_t st) {
   switch (N) {
-    case 2: return launch_n<2>(a, st);
-    case 3: return launch_n<3>(a, st);
+    case 2: return tile ? launch_tile_n<2>(a, st) : launch_n<2>(a, st);
+    case 3: return tile ? launch_tile_n<3>(a, st) : launch_n<3>(a, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -123,7 +131,7 @@ int pol2_reset(mln_pol2 *p) {
   std::vector<double> ub((size_t)p->D * p->ld, 0.0);
   for (int j = 0; j < p->D; ++j)
     for (int64_t c = 0; c < p->nmed; ++c) ub[(size_t)j * p->ld + c] = p->u0[j];
-  HIP_TRY(hipMemcpy(p->u.p, ub.data(), ub.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p->u[0].p, ub.data(), ub.size() * sizeof(double), hipMemcpyHostToDevice));
   const double zero = 0.0;  // E at cell nx - 1 before the first step
   if (p->rec.probe_z_out) HIP_TRY(hipMemcpy(p->rec.probe_z_out, &zero, sizeof(double), hipMemcpyHostToDevice));
   if (p->rec.probe_y_out) HIP_TRY(hipMemcpy(p->rec.probe_y_out, &zero, sizeof(double), hipMemcpyHostToDevice));
@@ -133,7 +141,9 @@ int pol2_reset(mln_pol2 *p) {
 }
 
 int pol2_steps(mln_pol2 *p, int64_t n) {
-  for (int64_t s = 0; s < n; ++s) {
+  const bool tile = p->K > 1;
+  for (int64_t s = 0; s < n;) {
+    const int k = (int)std::min<int64_t>(p->K, n - s);
     Pol2Args a{};
     const int in = p->cur, out = 1 - p->cur;
     a.fac = (const double *)p->fac.p;
@@ -145,13 +155,17 @@ int pol2_steps(mln_pol2 *p, int64_t n) {
     a.Hyout = (double *)p->Hy[out].p;
     a.Eyout = (double *)p->Ey[out].p;
     a.Gout = (double *)p->G[out].p;
-    a.u = (double *)p->u.p;
+    a.uin = (const double *)p->u[in].p;
+    a.uout = (double *)p->u[out].p;
     a.src = (const double *)p->src.p;
     a.nx = p->grid.nx;
     a.mb = p->grid.med_begin;
     a.me = p->grid.med_end;
     a.ld = p->ld;
-    a.n = p->step;
+    a.n0 = p->step;
+    a.nsteps = k;
+    a.halo = p->K;
+    a.owned = kPol2TileW - 2 * p->K - 1;
     a.amp_z = p->amp_z;
     a.amp_y = p->amp_y;
     a.ch = p->coef[0];
@@ -159,18 +173,22 @@ int pol2_steps(mln_pol2 *p, int64_t n) {
     a.cb = p->coef[2];
     a.inv_dx = p->coef[3];
     a.kmur = p->coef[4];
+    // snapshot s is taken when step (s+1) snap_every - 1 completes
     const int64_t se = p->rec.snap_every;
-    a.snap = (se > 0 && (p->step + 1) % se == 0) ? 1 : 0;
-    a.snap_i = se > 0 ? (p->step + 1) / se - 1 : 0;
+    const int64_t m = se > 0 ? (p->step + se) / se : 0;  // the first snapshot at or after this step, plus one
+    a.snap_every = se;
+    a.snap_next = se > 0 ? m * se - 1 : -1;
+    a.snap_i0 = se > 0 ? m - 1 : 0;
     a.ez_out = p->rec.ez_out;
     a.ey_out = p->rec.ey_out;
     a.pop_out = p->rec.pop_out;
     a.probe_z = p->rec.probe_z_out;
     a.probe_y = p->rec.probe_y_out;
-    const hipError_t e = launch_pol2(p->N, a, p->stream);
+    const hipError_t e = launch_pol2(p->N, tile, a, p->stream);
     if (e != hipSuccess) return set_err(MLN_EHIP, std::string("two-component launch: ") + hipGetErrorString(e));
     p->cur = 1 - p->cur;
-    ++p->step;
+    p->step += k;
+    s += k;
   }
   return MLN_OK;
 }
@@ -249,10 +267,18 @@ int mln_pol2_init(const mln_medium *medium, const double *dipole_y, const mln_gr
     HIP_TRY(p->Hy[b].alloc((g.nx - 1) * sizeof(double)));
     HIP_TRY(p->G[b].alloc((g.nx - 1) * sizeof(double)));
   }
-  HIP_TRY(p->u.alloc((size_t)p->D * p->ld * sizeof(double)));
+  for (int b = 0; b < 2; ++b) HIP_TRY(p->u[b].alloc((size_t)p->D * p->ld * sizeof(double)));
   rc = pol2_reset(p.get());
   if (rc) return rc;
   *out = p.release();
+  return MLN_OK;
+}
+
+int mln_pol2_configure(mln_pol2 *p, int steps_per_launch) {
+  if (!p) return set_err(MLN_EINVAL, "null handle");
+  if (steps_per_launch < 1 || steps_per_launch > kPol2MaxSteps)
+    return set_err(MLN_EINVAL, "steps_per_launch must be in 1.." + std::to_string(kPol2MaxSteps));
+  p->K = steps_per_launch;
   return MLN_OK;
 }
 

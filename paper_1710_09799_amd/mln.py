@@ -104,7 +104,7 @@ EXPORTS = ["mln_init", "mln_step", "mln_run", "mln_use_graph", "mln_reset", "mln
            "mln_pstd_step", "mln_pstd_run", "mln_pstd_reset", "mln_pstd_current_step", "mln_pstd_get_fields",
            "mln_pstd_free", "mln_tmz_init", "mln_tmz_step", "mln_tmz_run", "mln_tmz_reset",
            "mln_tmz_current_step", "mln_tmz_set_fields", "mln_tmz_get_fields", "mln_tmz_free",
-           "mln_pol2_init", "mln_pol2_step", "mln_pol2_run", "mln_pol2_reset", "mln_pol2_current_step",
+           "mln_pol2_init", "mln_pol2_configure", "mln_pol2_step", "mln_pol2_run", "mln_pol2_reset", "mln_pol2_current_step",
            "mln_pol2_get_fields", "mln_pol2_free"]
 
 _lib = None
@@ -187,6 +187,7 @@ def load():
         "mln_tmz_free": ([P], None),
         "mln_pol2_init": ([ctypes.POINTER(_Medium), _dp, ctypes.POINTER(_Grid), ctypes.POINTER(_Source),
                            ctypes.c_double, ctypes.POINTER(_Pol2Record), P, ctypes.POINTER(P)], ctypes.c_int),
+        "mln_pol2_configure": ([P, ctypes.c_int], ctypes.c_int),
         "mln_pol2_step": ([P, ctypes.c_int64], ctypes.c_int),
         "mln_pol2_run": ([P], ctypes.c_int),
         "mln_pol2_reset": ([P], ctypes.c_int),
@@ -666,10 +667,11 @@ class Pol2:
     couples to E_z, dipole_y (N x N Hermitian) to E_y; the source waveform
     drives E_z with the problem's amplitude and E_y with amplitude_y.  FP64,
     N = 2, 3.  Outputs (torch float64 device tensors) after run(): probe_z,
-    probe_y (nt+1), ez_snap, ey_snap (nsnap, nx), pop (nsnap, N, n_med)."""
+    probe_y (nt+1), ez_snap, ey_snap (nsnap, nx), pop (nsnap, N, n_med).
+    steps_per_launch: mln_pol2_configure (None: the library's default)."""
 
     def __init__(self, problem, dipole_y, amplitude_y, snap_every=0, record_probe=True, record_pop=True,
-                 record_e=True):
+                 record_e=True, steps_per_launch=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("Pol2 needs a HIP device")
@@ -699,6 +701,11 @@ class Pol2:
                                float(amplitude_y), ctypes.byref(rs), ctypes.c_void_p(self.stream.cuda_stream),
                                ctypes.byref(h)))
         self._h = h
+        if steps_per_launch is not None:
+            self.configure(steps_per_launch)
+
+    def configure(self, steps_per_launch):
+        _check(self._L.mln_pol2_configure(self._h, int(steps_per_launch)))
 
     def step(self, n):
         _check(self._L.mln_pol2_step(self._h, int(n)))

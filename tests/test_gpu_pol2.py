@@ -8,7 +8,11 @@ that does not commute with the first, several workgroups with a ragged last
 one; edge geometries; a lossy / dielectric host; the exact reductions (no
 second component: the one-component GPU run; equal dipoles and sources: the
 one-component run with sqrt(2) mu and sqrt(2) s, rotated by 45 degrees);
-reset and stepping in pieces; field read-back; errors.
+reset and stepping in pieces; field read-back; errors.  Kernels: the
+blocked kernel at the default 32 steps per launch in every case, and each
+steps-per-launch setting against the oracle and against the one-step kernel
+(ragged last workgroups down to a single owned cell, run lengths and
+snapshot intervals that are not multiples of it).
 """
 import dataclasses
 import math
@@ -48,8 +52,8 @@ def _problem(n, seed, nx=600, nt=420, med=None, host=None):
     return p, muy
 
 
-def _run(p, muy, amp_y, snap):
-    s = mln.Pol2(p, muy, amp_y, snap_every=snap)
+def _run(p, muy, amp_y, snap, steps_per_launch=None):
+    s = mln.Pol2(p, muy, amp_y, snap_every=snap, steps_per_launch=steps_per_launch)
     out = _np(s.run())
     s.close()
     return out
@@ -90,6 +94,49 @@ def test_pol2_host_media(orc, host):
     got = _run(p, muy, 1.2 * p.source.amplitude, 50)
     e = _errs(got, ref)
     print(f"  err_Ez={e['z']:.2e} err_Ey={e['y']:.2e} err_pop={e['pop']:.2e}", flush=True)
+    assert e["z"] < 1e-10 and e["y"] < 1e-10 and e["pop"] < 1e-10
+
+
+# nx against the 256 - 2 K - 1 cells a workgroup owns: 447 = 2 x 223 + 1 and
+# 448 leave one and two cells to the last workgroup at K = 16; 600 with K =
+# 64 gives four workgroups of 127 and a fifth of 92, 130 one of 127 and one of 3
+@pytest.mark.parametrize("k,nx,nt", [(1, 600, 420), (2, 600, 420), (7, 509, 333), (16, 447, 420),
+                                     (16, 448, 421), (64, 600, 420), (64, 130, 300)])
+def test_pol2_steps_per_launch(orc, k, nx, nt):
+    p, muy = _problem(3, 9, nx=nx, nt=nt, med=(3, nx - 2))
+    amp_y = 0.7 * p.source.amplitude
+    _case("pol2_steps_per_launch", k=k, nx=nx, nt=nt)
+    ref = orc.run_pol2(p, muy, amp_y, snap_every=37)
+    got = _run(p, muy, amp_y, 37, steps_per_launch=k)
+    e = _errs(got, ref)
+    print(f"  err_Ez={e['z']:.2e} err_Ey={e['y']:.2e} err_pop={e['pop']:.2e}", flush=True)
+    assert e["z"] < 1e-10 and e["y"] < 1e-10 and e["pop"] < 1e-10
+    if k > 1:  # the one-step kernel does the same arithmetic per cell
+        one = _run(p, muy, amp_y, 37, steps_per_launch=1)
+        d = _errs(got, one)
+        print(f"  vs one-step kernel: {d['z']:.2e} {d['y']:.2e} {d['pop']:.2e}", flush=True)
+        assert d["z"] < 1e-13 and d["y"] < 1e-13 and d["pop"] < 1e-13
+
+
+def test_pol2_configure_between_steps(orc):
+    """Changing the steps per launch mid-run (and stepping in odd pieces)
+    leaves the run as it was."""
+    p, muy = _problem(2, 10, nx=700, nt=310)
+    amp_y = 0.9 * p.source.amplitude
+    _case("pol2_configure_between_steps")
+    s = mln.Pol2(p, muy, amp_y, snap_every=31)
+    for k, n in ((16, 5), (1, 3), (64, 70), (3, 11), (16, 1000)):
+        s.configure(k)
+        s.step(n)
+    assert s.current_step() == p.grid.nt
+    got = _np(s.outputs())
+    for bad in (0, 65, -3):
+        with pytest.raises(mln.MLNError) as e:
+            s.configure(bad)
+        assert e.value.code == -1
+    s.close()
+    ref = orc.run_pol2(p, muy, amp_y, snap_every=31)
+    e = _errs(got, ref)
     assert e["z"] < 1e-10 and e["y"] < 1e-10 and e["pop"] < 1e-10
 
 
