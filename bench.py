@@ -477,11 +477,12 @@ def tmz_beam(reps=REPS):
 def pol2_cross_ladder(reps=REPS):
     """Both transverse field components (mln_pol2_*, FP64): the three-level
     ladder with mu01 on E_z and mu12 on E_y (workloads.cross_ladder), 20000
-    cells x 20000 steps; the blocked kernel at its default 32 steps per
-    launch (the value) and the one-step kernel (one launch per step).  GB/s
-    are the one-step kernel's algorithmic traffic: every cell's E_z, H_y,
-    E_y, H_z and every medium cell's Bloch vector read and written once per
-    step; the median of `reps` runs."""
+    cells x 20000 steps; the library's default shape (four lanes per cell,
+    automatic steps per launch: 24 here) is the value, beside the blocked
+    one-lane kernel and the one-step kernel (one launch per step).  GB/s are
+    the one-step kernel's algorithmic traffic: every cell's E_z, H_y, E_y,
+    H_z and every medium cell's Bloch vector read and written once per step;
+    the median of `reps` runs."""
     import torch
     from paper_1710_09799_amd import mln
     from paper_1710_09799_amd import workloads as W
@@ -489,8 +490,8 @@ def pol2_cross_ladder(reps=REPS):
     g = p.grid
     D = p.medium.n_levels ** 2 - 1
 
-    def timed(k):
-        s = mln.Pol2(p, muy, amp_y, record_pop=False, record_e=False, steps_per_launch=k)
+    def timed(k, lanes):
+        s = mln.Pol2(p, muy, amp_y, record_pop=False, record_e=False, steps_per_launch=k, lanes_per_cell=lanes)
         s.run()
         e0, e1 = _events()
         walls, gpus = [], []
@@ -507,14 +508,18 @@ def pol2_cross_ladder(reps=REPS):
         s.close()
         return _median(walls), _median(gpus)
 
-    t, gt = timed(32)
-    t1, gt1 = timed(1)
-    us, us1 = gt / g.nt * 1e6, gt1 / g.nt * 1e6
+    t, gt = timed(0, 4)
+    tl, gtl = timed(0, 1)
+    t1, gt1 = timed(1, 1)
+    us, usl, us1 = gt / g.nt * 1e6, gtl / g.nt * 1e6, gt1 / g.nt * 1e6
     byts = (g.nx * 4 * 2 + g.n_med * D * 2) * 8
     return {"workload": f"three-level ladder, mu01 on E_z and mu12 on E_y, {g.nx} cells, {g.nt} steps",
-            "kernel": "fwd_pol2_tile_kernel (one thread per cell, 256-cell windows, 191 owned, "
-                      "32 steps per launch)",
+            "kernel": "fwd_pol2_quad_kernel (four lanes per cell, 128-cell windows, 79 owned, "
+                      "24 steps per launch)",
             "value": g.n_med * g.nt / t, "us_per_step": us, "dtype": "f64",
+            "one_lane_kernel": {"kernel": "fwd_pol2_tile_kernel (one thread per cell, 256-cell windows, "
+                                          "127 owned, 64 steps per launch)",
+                                "value": g.n_med * g.nt / tl, "us_per_step": usl},
             "one_step_kernel": {"kernel": "fwd_pol2_kernel (one launch per step)",
                                 "value": g.n_med * g.nt / t1, "us_per_step": us1,
                                 "alg_bytes_per_step": byts, "alg_GBps": byts / (us1 * 1e-6) / 1e9,
@@ -642,8 +647,9 @@ PROFILE_CASES = {
     "tmz_fp32": ("tmz", dict(nt=512), dict(precision="fp32")),
     "tmz_fp32c": ("tmz", dict(nt=512), dict(precision="fp32c")),
     # both transverse components (cross-polarised ladder, 20000 cells), 4000 steps
-    "pol2_fp64": ("pol2", dict(nt=4000, k=32), {}),
-    "pol2_fp64_one_step": ("pol2", dict(nt=4000, k=1), {}),
+    "pol2_fp64": ("pol2", dict(nt=4000, k=24, lanes=4), {}),
+    "pol2_fp64_one_lane": ("pol2", dict(nt=4000, k=64, lanes=1), {}),
+    "pol2_fp64_one_step": ("pol2", dict(nt=4000, k=1, lanes=1), {}),
     "pstd_n3_ring": ("pstd", dict(batch=1, med=True), dict(steps_per_launch=256)),
     "pstd_n3_ring_fields": ("pstd", dict(batch=1, med=False), dict(steps_per_launch=256)),
     "pstd_n3_ring_batch256": ("pstd", dict(batch=256, med=True), dict(steps_per_launch=256)),
@@ -725,12 +731,12 @@ def profile_tmz(name, nt, precision, steps, warmup):
                       "cell_updates_per_s": g.n_med * nt / t, "precision": precision}))
 
 
-def profile_pol2(name, nt, steps, warmup, k):
+def profile_pol2(name, nt, steps, warmup, k, lanes):
     import torch
     from paper_1710_09799_amd import mln
     from paper_1710_09799_amd import workloads as W
     p, muy, amp_y = W.cross_ladder(nt=nt)
-    s = mln.Pol2(p, muy, amp_y, record_pop=False, record_e=False, steps_per_launch=k)
+    s = mln.Pol2(p, muy, amp_y, record_pop=False, record_e=False, steps_per_launch=k, lanes_per_cell=lanes)
     ts = []
     for r in range(warmup + steps):
         s.reset()
@@ -744,7 +750,7 @@ def profile_pol2(name, nt, steps, warmup, k):
     t = _median(ts)
     g = p.grid
     print(json.dumps({"profile_case": name, "nx": g.nx, "nt": nt, "n_med": g.n_med, "steps_per_launch": k,
-                      "launches_per_run": (nt + k - 1) // k,
+                      "lanes_per_cell": lanes,
                       "ms_per_run": t * 1e3, "us_per_step": t / nt * 1e6, "cell_updates_per_s": g.n_med * nt / t}))
 
 
@@ -763,7 +769,7 @@ def profile_case(name, steps, warmup, calib):
         profile_pstd(name, pkw["batch"], pkw["med"], kw["steps_per_launch"], steps, warmup)
         return
     if wl == "pol2":
-        profile_pol2(name, pkw["nt"], steps, warmup, pkw["k"])
+        profile_pol2(name, pkw["nt"], steps, warmup, pkw["k"], pkw["lanes"])
         return
     if wl == "batch":
         profile_batch(name, pkw["nt"], kw, steps, warmup)

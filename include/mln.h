@@ -603,12 +603,13 @@ void mln_tmz_free(mln_tmz *t);
  *               steps 0..nt); snapshot s taken when step (s+1) snap_every - 1
  *               completes
  *   stream      hipStream_t for all device work, NULL = the default stream
- * FP64, one thread per cell; the step costs three D x D products.  By
- * default 32 steps per launch: a workgroup of 256 threads keeps both field
- * pairs of its window in LDS and the Bloch vectors in registers for the
- * launch's steps and recomputes a halo of 32 cells on its right and 33 on
- * its left (the Mur cell depends on two cells to its left), so 191 cells
- * are owned per workgroup (mln_pol2_configure).  Inputs are copied.
+ * FP64; the step costs three D x D products.  Temporal blocking: a
+ * workgroup keeps both field pairs of its window in LDS and the Bloch
+ * vectors in registers for K steps per launch and recomputes a halo of K
+ * cells on its right and K + 1 on its left (the Mur cell depends on two
+ * cells to its left).  Default: four lanes per cell, 128-cell windows, K
+ * the largest (8..48) whose workgroups fit one per compute unit, else 12
+ * (mln_pol2_configure).  Inputs are copied.
  * Errors: MLN_EINVAL,
  * MLN_ECOURANT, MLN_ENOTSUPPORTED, the medium errors of mln_init (also for
  * dipole_y), MLN_ENOMEM, MLN_EHIP; on error *out is set to NULL. */
@@ -620,14 +621,22 @@ typedef struct mln_pol2 mln_pol2;
 int mln_pol2_init(const mln_medium *medium, const double *dipole_y, const mln_grid *grid,
                   const mln_source *source, double amplitude_y, const mln_pol2_record *record, void *stream,
                   mln_pol2 **out);
-/* Steps per kernel launch, 1..64 (default 32).  1: one launch per step, one
- * thread per cell, every field and Bloch vector read from and written to
- * device memory each step; K > 1: the blocked kernel above with halos of K
- * and K + 1 cells, 256 - 2 K - 1 owned cells per workgroup.  The results do
- * not depend on K beyond rounding (the same arithmetic per cell).  Takes
- * effect with the next launch.  Errors: MLN_EINVAL (p NULL or K out of
- * range). */
-int mln_pol2_configure(mln_pol2 *p, int steps_per_launch);
+/* Kernel shape: steps per launch K and lanes per cell (default 0 and 4).
+ * K = 0: automatic, the largest K (at least 8) for which the workgroups fit
+ * one per compute unit, else 12 (four lanes) or 16 (one lane).
+ *   lanes_per_cell 1: K in 0..64, one thread per cell.  K = 1: one launch
+ *     per step, every field and Bloch vector read from and written to device
+ *     memory each step; K > 1: blocked, 256-cell windows, 256 - 2 K - 1
+ *     owned cells per workgroup.
+ *   lanes_per_cell 4: K in 0..48.  Blocked, 128-cell windows of four lanes
+ *     per cell (512 threads), 128 - 2 K - 1 owned cells: lane r holds
+ *     components 2r, 2r+1 of the Bloch vector, so each lane forms two rows
+ *     of each of the three products.
+ * The results do not depend on the shape beyond rounding (the same steps
+ * per cell; with four lanes dP/dt and the populations are summed in
+ * another order).  Takes effect with the next launch.  Errors: MLN_EINVAL
+ * (p NULL, lanes not 1 or 4, K out of range). */
+int mln_pol2_configure(mln_pol2 *p, int steps_per_launch, int lanes_per_cell);
 /* Advance min(n_steps, nt - current step) steps; asynchronous on the stream. */
 int mln_pol2_step(mln_pol2 *p, int64_t n_steps);
 /* The remaining steps, then synchronise. */

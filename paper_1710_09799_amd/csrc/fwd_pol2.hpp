@@ -32,16 +32,28 @@
 //   in registers; each workgroup owns kPol2TileW - 2 K - 1 cells and
 //   recomputes K cells on its right and K + 1 on its left (the stencil
 //   radius is one cell, two for the Mur cell), so neighbouring workgroups
-//   never wait for each other.
+//   never wait for each other;
+// * fwd_pol2_quad_kernel: the same blocking with four lanes per cell (the
+//   layout of the single-component quad kernel): lane r holds components
+//   2r, 2r+1 of the Bloch vector in each coordinate system, so each rotation
+//   is lane-local, and each of the three products is a gather of the other
+//   lanes' components (DPP) and two rows per lane, with its factor rows in
+//   registers for the whole launch; dP/dt is a quad sum.  A step then costs
+//   a quarter of the single-lane products per lane, and 128-cell windows
+//   spread a grid over more compute units.
 // FP64.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
+#include "fwd_quad.hpp"
+
 namespace mln {
 
 constexpr int kPol2TileW = 256;      // threads (cells) per workgroup of the tile kernel
 constexpr int kPol2MaxSteps = 64;    // steps per launch of the tile kernel: W - 2 K - 1 >= 127 owned cells
+constexpr int kPol2QuadCells = 128;  // cells per window of the quad kernel (512 lanes)
+constexpr int kPol2QuadMaxSteps = 48;  // C - 2 K - 1 >= 31 owned cells
 
 // factor block (doubles): B, K_u, c_u, w_z, w_y (in u-coordinates), the
 // rotation angles per unit field theta_y dt/2 and theta_z dt, population
@@ -343,6 +355,191 @@ __global__ void __launch_bounds__(kPol2TileW) fwd_pol2_tile_kernel(Pol2Args a) {
     if (med) {
 #pragma unroll
       for (int j = 0; j < D; ++j) a.uout[j * a.ld + c] = u[j];
+    }
+  }
+}
+
+// every lane of a quad receives the two components of lanes 0 .. NJ-1:
+// u[2J], u[2J+1] from lane J
+template <int NJ>
+__device__ __forceinline__ void pol2_gather(double x0, double x1, double (&u)[2 * NJ]) {
+  u[0] = quad_bcast<0>(x0);
+  u[1] = quad_bcast<0>(x1);
+  if constexpr (NJ > 1) {
+    u[2] = quad_bcast<1>(x0);
+    u[3] = quad_bcast<1>(x1);
+  }
+  if constexpr (NJ > 2) {
+    u[4] = quad_bcast<2>(x0);
+    u[5] = quad_bcast<2>(x1);
+  }
+  if constexpr (NJ > 3) {
+    u[6] = quad_bcast<3>(x0);
+    u[7] = quad_bcast<3>(x1);
+  }
+}
+
+// Window as in fwd_pol2_tile_kernel, kPol2QuadCells cells of four lanes.
+template <int N>
+__global__ void __launch_bounds__(4 * kPol2QuadCells) fwd_pol2_quad_kernel(Pol2Args a) {
+  using L = Pol2Layout<N>;
+  constexpr int D = L::D, Q = L::Q, C = kPol2QuadCells, S = C + 2, NJ = (D + 1) / 2;
+  static_assert(D <= 8 && Q <= 3, "four lanes of two components each");
+  __shared__ double sE[2][2][S];  // [buffer][E_z, E_y][slot]; slot k + 1 holds the window's cell k
+  __shared__ double sH[2][2][S];  // [buffer][H_y, G][slot]
+  __shared__ double sP[N * D + N];  // population rows in u-coordinates and their constants
+  const int lane = threadIdx.x & 3, k = threadIdx.x >> 2, q = k + 1;
+  const int r0 = 2 * lane, r1 = 2 * lane + 1;
+  const int64_t nx = a.nx;
+  const int64_t o0 = (int64_t)blockIdx.x * a.owned, o1 = o0 + a.owned < nx ? o0 + a.owned : nx;
+  const int64_t g = o0 - a.halo - 1 + k;
+  for (int t = threadIdx.x; t < N * D + N; t += 4 * C) sP[t] = a.fac[L::opop + t];
+  for (int t = threadIdx.x; t < 2 * 2 * S; t += 4 * C) {
+    (&sE[0][0][0])[t] = 0.0;
+    (&sH[0][0][0])[t] = 0.0;
+  }
+  // the lane's factor rows, held for the launch: columns r0, r1 of B (for
+  // B^T u), rows r0, r1 of B and of K_u, and its entries of c, w_z, w_y;
+  // zero for components beyond D
+  double bt0[D], bt1[D], b0[D], b1[D], k0[D], k1[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    bt0[j] = r0 < D ? a.fac[L::oB + j * D + r0] : 0.0;
+    bt1[j] = r1 < D ? a.fac[L::oB + j * D + r1] : 0.0;
+    b0[j] = r0 < D ? a.fac[L::oB + r0 * D + j] : 0.0;
+    b1[j] = r1 < D ? a.fac[L::oB + r1 * D + j] : 0.0;
+    k0[j] = r0 < D ? a.fac[L::oK + r0 * D + j] : 0.0;
+    k1[j] = r1 < D ? a.fac[L::oK + r1 * D + j] : 0.0;
+  }
+  const double c0 = r0 < D ? a.fac[L::oc + r0] : 0.0, c1 = r1 < D ? a.fac[L::oc + r1] : 0.0;
+  const double wz0 = r0 < D ? a.fac[L::owz + r0] : 0.0, wz1 = r1 < D ? a.fac[L::owz + r1] : 0.0;
+  const double wy0 = r0 < D ? a.fac[L::owy + r0] : 0.0, wy1 = r1 < D ? a.fac[L::owy + r1] : 0.0;
+  const double thy = lane < Q ? a.fac[L::othy + lane] : 0.0, thz = lane < Q ? a.fac[L::othz + lane] : 0.0;
+  const double p0z = a.fac[L::op0], p0y = a.fac[L::op0 + 1];
+  __syncthreads();
+  const bool act = g >= 0 && g < nx - 1;
+  const bool med = g >= a.mb && g < a.me;
+  const bool own = g >= o0 && g < o1;
+  const bool last = o1 == nx;
+  const int64_t c = g - a.mb, nmed = a.me - a.mb;
+  if (lane == 0 && g >= 0 && g < nx) {
+    sE[0][0][q] = a.Ezin[g];
+    sE[0][1][q] = a.Eyin[g];
+  }
+  if (lane == 0 && act) {
+    sH[0][0][q] = a.Hyin[g];
+    sH[0][1][q] = a.Gin[g];
+  }
+  double x0 = 0.0, x1 = 0.0;  // the lane's two components of u
+  if (med) {
+    if (r0 < D) x0 = a.uin[r0 * a.ld + c];
+    if (r1 < D) x1 = a.uin[r1 * a.ld + c];
+  }
+  __syncthreads();
+  int b = 0;
+  int64_t sn = a.snap_next, si = a.snap_i0;
+  for (int s = 0; s < a.nsteps; ++s) {
+    const int64_t n = a.n0 + s;
+    const bool snap = n == sn;
+    if (act) {
+      const double Ecz = sE[b][0][q], Erz = sE[b][0][q + 1], Elz = sE[b][0][q - 1];
+      const double Ecy = sE[b][1][q], Ery = sE[b][1][q + 1], Ely = sE[b][1][q - 1];
+      const Pol2Pair hz = pol2_faces(a, g, Elz, Ecz, Erz, sH[b][0][q - 1], sH[b][0][q]);
+      const Pol2Pair hy = pol2_faces(a, g, Ely, Ecy, Ery, sH[b][1][q - 1], sH[b][1][q]);
+      double Pz = 0.0, Py = 0.0;
+      if (med) {
+        double sy, cy, sz, cz;
+        pol2_sincm1(thy * Ecy, sy, cy);  // the same angles for both y half steps
+        double t0 = x0, t1 = x1;
+        x0 = t0 + (cy * t0 + sy * t1);  // exp(U_y E_y dt/2), lane-local
+        x1 = t1 + (cy * t1 - sy * t0);
+        double u[2 * NJ];  // gather: every lane receives the whole vector
+pol2_gather<NJ>(x0, x1, u);
+        double w0 = 0.0, w1 = 0.0;  // w = B^T u, components r0, r1
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          w0 += bt0[j] * u[j];
+          w1 += bt1[j] * u[j];
+        }
+        pol2_sincm1(thz * Ecz, sz, cz);
+        t0 = w0 + (cz * w0 + sz * w1);  // exp(U_z E_z dt)
+        t1 = w1 + (cz * w1 - sz * w0);
+pol2_gather<NJ>(t0, t1, u);
+        w0 = 0.0;  // u = B w
+        w1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          w0 += b0[j] * u[j];
+          w1 += b1[j] * u[j];
+        }
+        x0 = w0 + (cy * w0 + sy * w1);  // exp(U_y E_y dt/2): u = T_y^T d''
+        x1 = w1 + (cy * w1 - sy * w0);
+        Pz = p0z + quad_sum(wz0 * x0 + wz1 * x1);
+        Py = p0y + quad_sum(wy0 * x0 + wy1 * x1);
+        if (snap && own && a.pop_out) {
+#pragma unroll
+          for (int lv = 0; lv < N; ++lv) {
+            const double pr = (r0 < D ? sP[lv * D + r0] * x0 : 0.0) + (r1 < D ? sP[lv * D + r1] * x1 : 0.0);
+            const double p = sP[N * D + lv] + quad_sum(pr);
+            if (lane == 0) a.pop_out[(si * N + lv) * nmed + c] = p;
+          }
+        }
+pol2_gather<NJ>(x0, x1, u);
+        w0 = c0;  // the two half steps of this and the next step
+        w1 = c1;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          w0 += k0[j] * u[j];
+          w1 += k1[j] * u[j];
+        }
+        x0 = w0;
+        x1 = w1;
+      }
+      const double Ezn = pol2_e(a, g, a.amp_z, n, Ecz, hz, Pz);
+      const double Eyn = pol2_e(a, g, a.amp_y, n, Ecy, hy, Py);
+      if (lane == 0) {
+        sH[b ^ 1][0][q] = hz.Hr;
+        sH[b ^ 1][1][q] = hy.Hr;
+        sE[b ^ 1][0][q] = Ezn;
+        sE[b ^ 1][1][q] = Eyn;
+        if (snap && own) {
+          if (a.ez_out) a.ez_out[si * nx + g] = Ezn;
+          if (a.ey_out) a.ey_out[si * nx + g] = Eyn;
+        }
+        if (g == nx - 2) {  // first-order Mur boundary at cell nx - 1, both components
+          const double Ebz = Ecz + a.kmur * (Ezn - Erz), Eby = Ecy + a.kmur * (Eyn - Ery);
+          sE[b ^ 1][0][q + 1] = Ebz;
+          sE[b ^ 1][1][q + 1] = Eby;
+          if (last) {
+            if (a.probe_z) a.probe_z[n + 1] = Ebz;
+            if (a.probe_y) a.probe_y[n + 1] = Eby;
+            if (snap) {
+              if (a.ez_out) a.ez_out[si * nx + nx - 1] = Ebz;
+              if (a.ey_out) a.ey_out[si * nx + nx - 1] = Eby;
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    b ^= 1;
+    if (snap) {
+      sn += a.snap_every;
+      ++si;
+    }
+  }
+  if (own) {
+    if (lane == 0) {
+      a.Ezout[g] = sE[b][0][q];
+      a.Eyout[g] = sE[b][1][q];
+      if (g < nx - 1) {
+        a.Hyout[g] = sH[b][0][q];
+        a.Gout[g] = sH[b][1][q];
+      }
+    }
+    if (med) {
+      if (r0 < D) a.uout[r0 * a.ld + c] = x0;
+      if (r1 < D) a.uout[r1 * a.ld + c] = x1;
     }
   }
 }

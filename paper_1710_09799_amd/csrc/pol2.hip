@@ -21,7 +21,9 @@ struct mln_pol2 {
   mln_pol2_record rec{};
   hipStream_t stream = nullptr;
   int64_t nmed = 0, ld = 0, step = 0, nsnap = 0;
-  int K = 32;  // steps per launch: 1 = the one-step kernel, more = the tile kernel
+  int K = 0;      // steps per launch, 0: automatic (pol2_auto_steps)
+  int lanes = 4;  // lanes per cell: 1 (K = 1: the one-step kernel, else the tile kernel) or 4 (quad kernel)
+  int cus = 256;  // compute units of the device
   double amp_z = 0.0, amp_y = 0.0;
   double coef[5] = {0, 0, 0, 0, 0};  // ch, ca, cb, 1/dx, kmur
   std::vector<double> u0, src_host;
@@ -45,10 +47,37 @@ hipError_t launch_tile_n(const Pol2Args &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_pol2(int N, bool tile, const Pol2Args &a, hipStream_t st) {
+template <int N>
+hipError_t launch_quad_n(const Pol2Args &a, hipStream_t st) {
+  const unsigned nb = (unsigned)((a.nx + a.owned - 1) / a.owned);
+  hipLaunchKernelGGL((fwd_pol2_quad_kernel<N>), dim3(nb), dim3(4 * kPol2QuadCells), 0, st, a);
+  return hipGetLastError();
+}
+
+enum class Pol2Kernel { one_step, tile, quad };
+
+// The largest steps per launch (at least 8) whose workgroups, one per
+// compute unit, cover the grid: a step then lasts one workgroup's step on
+// every unit, and more steps per launch only spread the launch cost
+// further.  Grids larger than that: 12 (quad) or 16 steps per launch.
+int pol2_auto_steps(const mln_pol2 *p) {
+  const int w = p->lanes == 4 ? kPol2QuadCells : kPol2TileW;
+  const int kmax = p->lanes == 4 ? kPol2QuadMaxSteps : kPol2MaxSteps;
+  for (int k = kmax; k >= 8; --k) {
+    const int64_t owned = w - 2 * k - 1;
+    if ((p->grid.nx + owned - 1) / owned <= p->cus) return k;
+  }
+  return p->lanes == 4 ? 12 : 16;
+}
+
+hipError_t launch_pol2(int N, Pol2Kernel kind, const Pol2Args &a, hipStream_t st) {
   switch (N) {
-    case 2: return tile ? launch_tile_n<2>(a, st) : launch_n<2>(a, st);
-    case 3: return tile ? launch_tile_n<3>(a, st) : launch_n<3>(a, st);
+    case 2:
+      return kind == Pol2Kernel::quad ? launch_quad_n<2>(a, st)
+             : kind == Pol2Kernel::tile ? launch_tile_n<2>(a, st) : launch_n<2>(a, st);
+    case 3:
+      return kind == Pol2Kernel::quad ? launch_quad_n<3>(a, st)
+             : kind == Pol2Kernel::tile ? launch_tile_n<3>(a, st) : launch_n<3>(a, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -141,9 +170,10 @@ int pol2_reset(mln_pol2 *p) {
 }
 
 int pol2_steps(mln_pol2 *p, int64_t n) {
-  const bool tile = p->K > 1;
+  const int K = p->K > 0 ? p->K : pol2_auto_steps(p);
+  const Pol2Kernel kind = p->lanes == 4 ? Pol2Kernel::quad : K > 1 ? Pol2Kernel::tile : Pol2Kernel::one_step;
   for (int64_t s = 0; s < n;) {
-    const int k = (int)std::min<int64_t>(p->K, n - s);
+    const int k = (int)std::min<int64_t>(K, n - s);
     Pol2Args a{};
     const int in = p->cur, out = 1 - p->cur;
     a.fac = (const double *)p->fac.p;
@@ -164,8 +194,8 @@ int pol2_steps(mln_pol2 *p, int64_t n) {
     a.ld = p->ld;
     a.n0 = p->step;
     a.nsteps = k;
-    a.halo = p->K;
-    a.owned = kPol2TileW - 2 * p->K - 1;
+    a.halo = K;
+    a.owned = (kind == Pol2Kernel::quad ? kPol2QuadCells : kPol2TileW) - 2 * K - 1;
     a.amp_z = p->amp_z;
     a.amp_y = p->amp_y;
     a.ch = p->coef[0];
@@ -184,7 +214,7 @@ int pol2_steps(mln_pol2 *p, int64_t n) {
     a.pop_out = p->rec.pop_out;
     a.probe_z = p->rec.probe_z_out;
     a.probe_y = p->rec.probe_y_out;
-    const hipError_t e = launch_pol2(p->N, tile, a, p->stream);
+    const hipError_t e = launch_pol2(p->N, kind, a, p->stream);
     if (e != hipSuccess) return set_err(MLN_EHIP, std::string("two-component launch: ") + hipGetErrorString(e));
     p->cur = 1 - p->cur;
     p->step += k;
@@ -243,6 +273,12 @@ int mln_pol2_init(const mln_medium *medium, const double *dipole_y, const mln_gr
     p->rec.pop_out = nullptr;
   }
   p->stream = (hipStream_t)stream;
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      p->cus = cus;
+  }
   p->amp_z = source->amplitude;
   p->amp_y = amplitude_y;
   p->nmed = g.med_end - g.med_begin;
@@ -274,11 +310,15 @@ int mln_pol2_init(const mln_medium *medium, const double *dipole_y, const mln_gr
   return MLN_OK;
 }
 
-int mln_pol2_configure(mln_pol2 *p, int steps_per_launch) {
+int mln_pol2_configure(mln_pol2 *p, int steps_per_launch, int lanes_per_cell) {
   if (!p) return set_err(MLN_EINVAL, "null handle");
-  if (steps_per_launch < 1 || steps_per_launch > kPol2MaxSteps)
-    return set_err(MLN_EINVAL, "steps_per_launch must be in 1.." + std::to_string(kPol2MaxSteps));
+  if (lanes_per_cell != 1 && lanes_per_cell != 4) return set_err(MLN_EINVAL, "lanes_per_cell must be 1 or 4");
+  const int kmax = lanes_per_cell == 4 ? kPol2QuadMaxSteps : kPol2MaxSteps;
+  if (steps_per_launch < 0 || steps_per_launch > kmax)
+    return set_err(MLN_EINVAL, "steps_per_launch must be in 0.." + std::to_string(kmax) + " with " +
+                                   std::to_string(lanes_per_cell) + " lane(s) per cell");
   p->K = steps_per_launch;
+  p->lanes = lanes_per_cell;
   return MLN_OK;
 }
 

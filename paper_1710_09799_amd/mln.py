@@ -187,7 +187,7 @@ def load():
         "mln_tmz_free": ([P], None),
         "mln_pol2_init": ([ctypes.POINTER(_Medium), _dp, ctypes.POINTER(_Grid), ctypes.POINTER(_Source),
                            ctypes.c_double, ctypes.POINTER(_Pol2Record), P, ctypes.POINTER(P)], ctypes.c_int),
-        "mln_pol2_configure": ([P, ctypes.c_int], ctypes.c_int),
+        "mln_pol2_configure": ([P, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "mln_pol2_step": ([P, ctypes.c_int64], ctypes.c_int),
         "mln_pol2_run": ([P], ctypes.c_int),
         "mln_pol2_reset": ([P], ctypes.c_int),
@@ -668,10 +668,11 @@ class Pol2:
     drives E_z with the problem's amplitude and E_y with amplitude_y.  FP64,
     N = 2, 3.  Outputs (torch float64 device tensors) after run(): probe_z,
     probe_y (nt+1), ez_snap, ey_snap (nsnap, nx), pop (nsnap, N, n_med).
-    steps_per_launch: mln_pol2_configure (None: the library's default)."""
+    steps_per_launch, lanes_per_cell: mln_pol2_configure (None: the library's
+    defaults)."""
 
     def __init__(self, problem, dipole_y, amplitude_y, snap_every=0, record_probe=True, record_pop=True,
-                 record_e=True, steps_per_launch=None):
+                 record_e=True, steps_per_launch=None, lanes_per_cell=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("Pol2 needs a HIP device")
@@ -701,11 +702,12 @@ class Pol2:
                                float(amplitude_y), ctypes.byref(rs), ctypes.c_void_p(self.stream.cuda_stream),
                                ctypes.byref(h)))
         self._h = h
-        if steps_per_launch is not None:
-            self.configure(steps_per_launch)
+        if steps_per_launch is not None or lanes_per_cell is not None:
+            self.configure(0 if steps_per_launch is None else steps_per_launch,
+                           4 if lanes_per_cell is None else lanes_per_cell)
 
-    def configure(self, steps_per_launch):
-        _check(self._L.mln_pol2_configure(self._h, int(steps_per_launch)))
+    def configure(self, steps_per_launch=0, lanes_per_cell=4):
+        _check(self._L.mln_pol2_configure(self._h, int(steps_per_launch), int(lanes_per_cell)))
 
     def step(self, n):
         _check(self._L.mln_pol2_step(self._h, int(n)))

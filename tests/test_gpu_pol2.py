@@ -9,8 +9,9 @@ one; edge geometries; a lossy / dielectric host; the exact reductions (no
 second component: the one-component GPU run; equal dipoles and sources: the
 one-component run with sqrt(2) mu and sqrt(2) s, rotated by 45 degrees);
 reset and stepping in pieces; field read-back; errors.  Kernels: the
-blocked kernel at the default 32 steps per launch in every case, and each
-steps-per-launch setting against the oracle and against the one-step kernel
+blocked four-lanes-per-cell kernel at its default (automatic steps per
+launch) in every case, and each kernel shape against the oracle and against
+the one-step kernel
 (ragged last workgroups down to a single owned cell, run lengths and
 snapshot intervals that are not multiples of it).
 """
@@ -52,8 +53,8 @@ def _problem(n, seed, nx=600, nt=420, med=None, host=None):
     return p, muy
 
 
-def _run(p, muy, amp_y, snap, steps_per_launch=None):
-    s = mln.Pol2(p, muy, amp_y, snap_every=snap, steps_per_launch=steps_per_launch)
+def _run(p, muy, amp_y, snap, steps_per_launch=None, lanes_per_cell=None):
+    s = mln.Pol2(p, muy, amp_y, snap_every=snap, steps_per_launch=steps_per_launch, lanes_per_cell=lanes_per_cell)
     out = _np(s.run())
     s.close()
     return out
@@ -97,22 +98,27 @@ def test_pol2_host_media(orc, host):
     assert e["z"] < 1e-10 and e["y"] < 1e-10 and e["pop"] < 1e-10
 
 
-# nx against the 256 - 2 K - 1 cells a workgroup owns: 447 = 2 x 223 + 1 and
-# 448 leave one and two cells to the last workgroup at K = 16; 600 with K =
-# 64 gives four workgroups of 127 and a fifth of 92, 130 one of 127 and one of 3
-@pytest.mark.parametrize("k,nx,nt", [(1, 600, 420), (2, 600, 420), (7, 509, 333), (16, 447, 420),
-                                     (16, 448, 421), (64, 600, 420), (64, 130, 300)])
-def test_pol2_steps_per_launch(orc, k, nx, nt):
+# nx against the cells a workgroup owns, 256 - 2 K - 1 with one lane per
+# cell: 447 = 2 x 223 + 1 and 448 leave one and two cells to the last
+# workgroup at K = 16; 600 with K = 64 gives four workgroups of 127 and a
+# fifth of 92, 130 one of 127 and one of 3.  With four lanes 128 - 2 K - 1:
+# 191 = 2 x 95 + 1 at K = 16, 160 = 2 x 79 + 2 at K = 24, 600 at K = 48
+# gives nineteen of 31 and one of 11.
+@pytest.mark.parametrize("k,lanes,nx,nt", [(1, 1, 600, 420), (2, 1, 600, 420), (7, 1, 509, 333),
+                                           (16, 1, 447, 420), (16, 1, 448, 421), (64, 1, 600, 420),
+                                           (64, 1, 130, 300), (1, 4, 300, 200), (5, 4, 509, 333),
+                                           (16, 4, 191, 420), (24, 4, 160, 421), (48, 4, 600, 420)])
+def test_pol2_steps_per_launch(orc, k, lanes, nx, nt):
     p, muy = _problem(3, 9, nx=nx, nt=nt, med=(3, nx - 2))
     amp_y = 0.7 * p.source.amplitude
-    _case("pol2_steps_per_launch", k=k, nx=nx, nt=nt)
+    _case("pol2_steps_per_launch", k=k, lanes=lanes, nx=nx, nt=nt)
     ref = orc.run_pol2(p, muy, amp_y, snap_every=37)
-    got = _run(p, muy, amp_y, 37, steps_per_launch=k)
+    got = _run(p, muy, amp_y, 37, steps_per_launch=k, lanes_per_cell=lanes)
     e = _errs(got, ref)
     print(f"  err_Ez={e['z']:.2e} err_Ey={e['y']:.2e} err_pop={e['pop']:.2e}", flush=True)
     assert e["z"] < 1e-10 and e["y"] < 1e-10 and e["pop"] < 1e-10
-    if k > 1:  # the one-step kernel does the same arithmetic per cell
-        one = _run(p, muy, amp_y, 37, steps_per_launch=1)
+    if k > 1 or lanes > 1:  # the one-step kernel takes the same steps per cell
+        one = _run(p, muy, amp_y, 37, steps_per_launch=1, lanes_per_cell=1)
         d = _errs(got, one)
         print(f"  vs one-step kernel: {d['z']:.2e} {d['y']:.2e} {d['pop']:.2e}", flush=True)
         assert d["z"] < 1e-13 and d["y"] < 1e-13 and d["pop"] < 1e-13
@@ -125,14 +131,15 @@ def test_pol2_configure_between_steps(orc):
     amp_y = 0.9 * p.source.amplitude
     _case("pol2_configure_between_steps")
     s = mln.Pol2(p, muy, amp_y, snap_every=31)
-    for k, n in ((16, 5), (1, 3), (64, 70), (3, 11), (16, 1000)):
-        s.configure(k)
+    for k, lanes, n in ((16, 1, 5), (1, 1, 3), (12, 4, 40), (64, 1, 70), (3, 1, 11), (1, 4, 2), (48, 4, 60),
+                        (0, 1, 20), (0, 4, 1000)):
+        s.configure(k, lanes)
         s.step(n)
     assert s.current_step() == p.grid.nt
     got = _np(s.outputs())
-    for bad in (0, 65, -3):
+    for bad in ((65, 1), (-3, 1), (-1, 4), (49, 4), (16, 2), (16, 0)):
         with pytest.raises(mln.MLNError) as e:
-            s.configure(bad)
+            s.configure(*bad)
         assert e.value.code == -1
     s.close()
     ref = orc.run_pol2(p, muy, amp_y, snap_every=31)
