@@ -374,9 +374,9 @@ def variants(p3, ref64, pop64, headline):
                                                 "n6_bf16x3_mfma")}
     # N = 2: the two-level 2-pi sech workload (2000 cells x 10000 steps, FP64)
     p2 = W.two_level()
-    t, g, nl, _ = time_solver(p2, REPS, 1, 1000, precision="fp64", variant="quad", tile=128, steps_per_launch=16)
+    t, g, nl, _ = time_solver(p2, REPS, 1, 1000, precision="fp64", variant="quad", tile=128)
     var["n2_fp64_two_level"] = {"value": p2.grid.n_med * p2.grid.nt / t, "ms": t * 1e3,
-                                "launch_ms": g * 1e3 / nl}
+                                "launch_ms": g * 1e3 / nl, "shape": "quad, tile 128, automatic steps per launch"}
     var["n2_large"] = n2_large()
     # batched: 64 independent problems (N = 2 and 3 mixed, 1000..30000 cells,
     # 20000 steps), tiles autotuned on the compensated-FP32 batch, whole run
@@ -621,7 +621,7 @@ def calib_copy():
 # six-level cases run a 1600-step sample of the 200000-step run on the full
 # 50000-cell grid (every launch is alike).
 PROFILE_CASES = {
-    "n2_fp64": ("two_level", {}, dict(precision="fp64", variant="quad", tile=128, steps_per_launch=16)),
+    "n2_fp64": ("two_level", {}, dict(precision="fp64", variant="quad", tile=128)),
     "n3_fp64": ("three_level", dict(nt=20000), dict(precision="fp64", variant="quad", tile=128, steps_per_launch=20)),
     "n3_fp32c": ("three_level", dict(nt=20000), dict(precision="fp32c", variant="quad_mfma", tile=128,
                                                    steps_per_launch=24)),

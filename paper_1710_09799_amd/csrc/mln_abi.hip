@@ -362,18 +362,24 @@ int set_kernel(mln_handle *h, int variant_req, int tile, int steps_per_launch) {
   int K = steps_per_launch > 0
               ? steps_per_launch
               : (pade_wave ? 8 : (h->wave ? h->W / 8 : (h->mfma ? 16 : (h->quad ? h->W / 4 : 32))));
-  if (steps_per_launch <= 0 && (h->qmf || (h->mfma && h->quad))) {
-    // the matrix-core quad kernels: a step costs about the same with any
-    // number of tiles up to one per compute unit, and every launch has a
-    // fixed cost (prologue, epilogue, kernel boundary), so take the largest
-    // even step count (up to 24 at N = 3, 30 at N = 4, 6; measured optimum)
-    // that keeps the tiles within the compute units
+  if (steps_per_launch <= 0 && h->quad) {
+    // the quad kernels: a step costs about the same with any number of
+    // tiles up to about one per compute unit, and every launch has a fixed
+    // cost (prologue, epilogue, kernel boundary), so take the largest step
+    // count that keeps the tiles within the compute units.  Matrix-core
+    // forms: even counts up to 24 at N = 3, 30 at N = 4, 6, tiles up to the
+    // unit count; DPP form: up to 56, tiles up to 9/10 of the units (on
+    // 20000 cells 20 steps and 228 tiles beat 24 steps and 250 tiles by 7 %;
+    // on 2000 cells 56 steps run 1.3x faster than 16).  Larger grids keep
+    // the fixed default above.
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus <= 0)
       cus = 256;
-    const int kmax = std::min(h->qmf ? 24 : 30, (h->W - 1) / 2);
-    for (int k = kmax & ~1; k >= 8; k -= 2)
-      if ((h->grid.nx + (h->W - 2 * k) - 1) / (h->W - 2 * k) <= cus) {
+    const bool mf = h->qmf || h->mfma;
+    const int kmax = std::min(mf ? (h->qmf ? 24 : 30) : 56, (h->W - 1) / 2);
+    const int64_t maxtiles = mf ? cus : cus * 9 / 10;
+    for (int k = mf ? kmax & ~1 : kmax; k >= 8; k -= mf ? 2 : 1)
+      if ((h->grid.nx + (h->W - 2 * k) - 1) / (h->W - 2 * k) <= maxtiles) {
         K = k;
         break;
       }
