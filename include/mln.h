@@ -588,9 +588,7 @@ void mln_tmz_free(mln_tmz *t);
  * exponential routes (Sec. 4.2); second order like the step around it, and
  * exact when mu_y and mu_z commute.
  *
- *   medium      as mln_init; its dipole couples to E_z; N in {2, 3} (the
- *               step's three D x D products with their factors in LDS; at
- *               N = 4, 6 they would not fit the registers)
+ *   medium      as mln_init; its dipole couples to E_z; N in {2, 3, 4, 6}
  *   dipole_y    N*N complex Hermitian, couples to E_y (all zero: E_y is
  *               free vacuum propagation of its source)
  *   grid        as mln_init (both components share it, the host medium and
@@ -607,9 +605,10 @@ void mln_tmz_free(mln_tmz *t);
  * workgroup keeps both field pairs of its window in LDS and the Bloch
  * vectors in registers for K steps per launch and recomputes a halo of K
  * cells on its right and K + 1 on its left (the Mur cell depends on two
- * cells to its left).  Default: four lanes per cell, 128-cell windows, K
- * the largest (8..48) whose workgroups fit one per compute unit, else 12
- * (mln_pol2_configure).  Inputs are copied.
+ * cells to its left).  Default: four lanes per cell (N = 2, 3; one thread
+ * per cell for N = 4, 6, whose factors are read with scalar loads), K the
+ * largest whose workgroups fit one per compute unit (at least 8), else 12
+ * (four lanes) or 16 (mln_pol2_configure).  Inputs are copied.
  * Errors: MLN_EINVAL,
  * MLN_ECOURANT, MLN_ENOTSUPPORTED, the medium errors of mln_init (also for
  * dipole_y), MLN_ENOMEM, MLN_EHIP; on error *out is set to NULL. */
@@ -621,21 +620,23 @@ typedef struct mln_pol2 mln_pol2;
 int mln_pol2_init(const mln_medium *medium, const double *dipole_y, const mln_grid *grid,
                   const mln_source *source, double amplitude_y, const mln_pol2_record *record, void *stream,
                   mln_pol2 **out);
-/* Kernel shape: steps per launch K and lanes per cell (default 0 and 4).
+/* Kernel shape: steps per launch K and lanes per cell (default 0 and 4 for
+ * N <= 3, 0 and 1 for N = 4, 6).
  * K = 0: automatic, the largest K (at least 8) for which the workgroups fit
  * one per compute unit, else 12 (four lanes) or 16 (one lane).
  *   lanes_per_cell 1: K in 0..64, one thread per cell.  K = 1: one launch
  *     per step, every field and Bloch vector read from and written to device
  *     memory each step; K > 1: blocked, 256-cell windows, 256 - 2 K - 1
  *     owned cells per workgroup.
- *   lanes_per_cell 4: K in 0..48.  Blocked, 128-cell windows of four lanes
- *     per cell (512 threads), 128 - 2 K - 1 owned cells: lane r holds
+ *   lanes_per_cell 4 (N <= 3): K in 0..48.  Blocked, 128-cell windows of
+ *     four lanes per cell (512 threads), 128 - 2 K - 1 owned cells: lane r holds
  *     components 2r, 2r+1 of the Bloch vector, so each lane forms two rows
  *     of each of the three products.
  * The results do not depend on the shape beyond rounding (the same steps
  * per cell; with four lanes dP/dt and the populations are summed in
  * another order).  Takes effect with the next launch.  Errors: MLN_EINVAL
- * (p NULL, lanes not 1 or 4, K out of range). */
+ * (p NULL, lanes not 1 or 4, K out of range), MLN_ENOTSUPPORTED (four lanes
+ * with N = 4, 6). */
 int mln_pol2_configure(mln_pol2 *p, int steps_per_launch, int lanes_per_cell);
 /* Advance min(n_steps, nt - current step) steps; asynchronous on the stream. */
 int mln_pol2_step(mln_pol2 *p, int64_t n_steps);

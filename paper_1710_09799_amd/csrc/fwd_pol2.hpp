@@ -77,6 +77,7 @@ struct Pol2Args {
   int nsteps, halo;            // tile kernel: steps in this launch (<= halo), steps per launch of the handle
   int64_t owned;               // tile kernel: cells owned by a workgroup, kPol2TileW - 2 halo - 1
   double amp_z, amp_y, ch, ca, cb, inv_dx, kmur;
+  int64_t opaque0;             // always 0 (see Pol2FacSmem)
   int64_t snap_every, snap_next, snap_i0;  // first snapshot step >= n0 (-1: none) and its index
   double *ez_out, *ey_out, *pop_out, *probe_z, *probe_y;  // device records (NULL: not recorded)
 };
@@ -109,12 +110,31 @@ __device__ __forceinline__ void pol2_sincm1(double x, double &s, double &cm1) {
   }
 }
 
-// sin and cos - 1 of the angles th[p] e, and the 2x2 rotations of the pairs
-// (2p, 2p+1) by them
-template <int Q>
-__device__ __forceinline__ void pol2_angles(const double *th, double e, double (&s)[Q], double (&cm1)[Q]) {
+// Factor access: from LDS for N <= 3, or through scalar loads of the factor
+// block in device memory for N = 4, 6, whose D x D products (225 and 1225
+// entries) would otherwise hold their LDS reads in vector registers.  The
+// scalar loads' results live in scalar registers; p carries a zero offset
+// that changes every step (Pol2Args::opaque0 times the step) so that the
+// compiler keeps each load next to its use instead of hoisting all of them.
+struct Pol2FacLds {
+  const double *s;
+  __device__ double operator[](int i) const { return s[i]; }
+};
+struct Pol2FacSmem {
+  const double *p;
+  __device__ double operator[](int i) const { return cld(p, i); }
+};
+template <int N>
+constexpr bool pol2_smem() {
+  return N > 3;
+}
+
+// sin and cos - 1 of the angles F[off + p] e, and the 2x2 rotations of the
+// pairs (2p, 2p+1) by them
+template <int Q, class FA>
+__device__ __forceinline__ void pol2_angles(const FA &F, int off, double e, double (&s)[Q], double (&cm1)[Q]) {
 #pragma unroll
-  for (int p = 0; p < Q; ++p) pol2_sincm1(th[p] * e, s[p], cm1[p]);
+  for (int p = 0; p < Q; ++p) pol2_sincm1(F[off + p] * e, s[p], cm1[p]);
 }
 template <int D, int Q>
 __device__ __forceinline__ void pol2_rotate(double (&x)[D], const double (&s)[Q], const double (&cm1)[Q]) {
@@ -126,18 +146,38 @@ __device__ __forceinline__ void pol2_rotate(double (&x)[D], const double (&s)[Q]
   }
 }
 
+// the same rotations with each sin, cos - 1 formed where it is used
+template <int D, int Q, class FA>
+__device__ __forceinline__ void pol2_rotate_at(double (&x)[D], const FA &F, int off, double e) {
+#pragma unroll
+  for (int p = 0; p < Q; ++p) {
+    double s, cm1;
+    pol2_sincm1(F[off + p] * e, s, cm1);
+    const double a = x[2 * p], b = x[2 * p + 1];
+    x[2 * p] = a + (cm1 * a + s * b);
+    x[2 * p + 1] = b + (cm1 * b - s * a);
+  }
+}
+
 // The medium step of one cell: u (= T_y^T d') -> T_y^T d'' through the split
 // interaction factor, dP_z/dt and dP_y/dt from it, the populations of
 // d^{n+1/2} into pp[lv * pstride] (pp NULL: not recorded), and the two half
-// steps of this and the next step.
-template <int N>
-__device__ __forceinline__ void pol2_medium(const double *F, double (&u)[N * N - 1], double Ecz, double Ecy,
+// steps of this and the next step.  N <= 3 forms the y angles' sin and
+// cos - 1 once for both half steps; N = 4, 6 form them twice (fewer live
+// registers), with the same values.
+template <int N, class FA>
+__device__ __forceinline__ void pol2_medium(const FA &F, double (&u)[N * N - 1], double Ecz, double Ecy,
                                             double &Pz, double &Py, double *pp, int64_t pstride) {
   using L = Pol2Layout<N>;
   constexpr int D = L::D, Q = L::Q;
-  double w[D], sy[Q], cy[Q], sz[Q], cz[Q];
-  pol2_angles<Q>(F + L::othy, Ecy, sy, cy);  // the same angles for both y half steps
-  pol2_rotate<D, Q>(u, sy, cy);              // exp(U_y E_y dt/2)
+  constexpr bool reuse = N <= 3;
+  double w[D], sy[reuse ? Q : 1], cy[reuse ? Q : 1];
+  if constexpr (reuse) {
+    pol2_angles<Q>(F, L::othy, Ecy, sy, cy);
+    pol2_rotate<D, Q>(u, sy, cy);  // exp(U_y E_y dt/2)
+  } else {
+    pol2_rotate_at<D, Q>(u, F, L::othy, Ecy);
+  }
 #pragma unroll
   for (int i = 0; i < D; ++i) {  // to z-rotation coordinates: w = B^T u
     double t = 0.0;
@@ -145,8 +185,7 @@ __device__ __forceinline__ void pol2_medium(const double *F, double (&u)[N * N -
     for (int j = 0; j < D; ++j) t += F[L::oB + j * D + i] * u[j];
     w[i] = t;
   }
-  pol2_angles<Q>(F + L::othz, Ecz, sz, cz);
-  pol2_rotate<D, Q>(w, sz, cz);  // exp(U_z E_z dt)
+  pol2_rotate_at<D, Q>(w, F, L::othz, Ecz);  // exp(U_z E_z dt)
 #pragma unroll
   for (int i = 0; i < D; ++i) {  // back: u = B w
     double t = 0.0;
@@ -154,7 +193,11 @@ __device__ __forceinline__ void pol2_medium(const double *F, double (&u)[N * N -
     for (int j = 0; j < D; ++j) t += F[L::oB + i * D + j] * w[j];
     u[i] = t;
   }
-  pol2_rotate<D, Q>(u, sy, cy);  // exp(U_y E_y dt/2): u = T_y^T d''
+  if constexpr (reuse) {
+    pol2_rotate<D, Q>(u, sy, cy);  // exp(U_y E_y dt/2): u = T_y^T d''
+  } else {
+    pol2_rotate_at<D, Q>(u, F, L::othy, Ecy);
+  }
   Pz = F[L::op0];
   Py = F[L::op0 + 1];
 #pragma unroll
@@ -201,8 +244,8 @@ __device__ __forceinline__ double pol2_e(const Pol2Args &a, int64_t g, double am
   return g == 0 ? amp * a.src[n + 1] : a.ca * Ec + a.cb * (-P + (h.Hr - h.Hl) * a.inv_dx);
 }
 
-template <int N>
-__device__ __forceinline__ void pol2_cell(const Pol2Args &a, const double *F, int64_t g) {
+template <int N, class FA>
+__device__ __forceinline__ void pol2_cell(const Pol2Args &a, const FA &F, int64_t g) {
   constexpr int D = N * N - 1;
   const int64_t nx = a.nx, n = a.n0;
   const bool snap = n == a.snap_next;
@@ -249,11 +292,18 @@ __global__ void __launch_bounds__(256) fwd_pol2_kernel(Pol2Args a) {
   using L = Pol2Layout<N>;
   // the factor block in LDS (every lane reads the same element: broadcast);
   // read near its use instead of being held in registers across the step
-  __shared__ double sF[L::size];
-  for (int i = threadIdx.x; i < L::size; i += blockDim.x) sF[i] = a.fac[i];
-  __syncthreads();
+  __shared__ double sF[pol2_smem<N>() ? 1 : L::size];
+  if constexpr (!pol2_smem<N>()) {
+    for (int i = threadIdx.x; i < L::size; i += blockDim.x) sF[i] = a.fac[i];
+    __syncthreads();
+  }
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < a.nx - 1) pol2_cell<N>(a, sF, g);  // cell nx - 1 (Mur) is written by the thread of nx - 2
+  if (g >= a.nx - 1) return;  // cell nx - 1 (Mur) is written by the thread of nx - 2
+  if constexpr (pol2_smem<N>()) {
+    pol2_cell<N>(a, Pol2FacSmem{a.fac}, g);
+  } else {
+    pol2_cell<N>(a, Pol2FacLds{sF}, g);
+  }
 }
 
 // a.nsteps steps (at most a.halo) on the window of workgroup b: cells
@@ -267,14 +317,15 @@ template <int N>
 __global__ void __launch_bounds__(kPol2TileW) fwd_pol2_tile_kernel(Pol2Args a) {
   using L = Pol2Layout<N>;
   constexpr int D = L::D, S = kPol2TileW + 2;
-  __shared__ double sF[L::size];
+  __shared__ double sF[pol2_smem<N>() ? 1 : L::size];
   __shared__ double sE[2][2][S];  // [buffer][E_z, E_y][slot]; slot i + 1 holds thread i's cell
   __shared__ double sH[2][2][S];  // [buffer][H_y, G][slot]
   const int i = threadIdx.x, q = i + 1;
   const int64_t nx = a.nx;
   const int64_t o0 = (int64_t)blockIdx.x * a.owned, o1 = o0 + a.owned < nx ? o0 + a.owned : nx;
   const int64_t g = o0 - a.halo - 1 + i;
-  for (int k = i; k < L::size; k += kPol2TileW) sF[k] = a.fac[k];
+  if constexpr (!pol2_smem<N>())
+    for (int k = i; k < L::size; k += kPol2TileW) sF[k] = a.fac[k];
   for (int k = i; k < 2 * 2 * S; k += kPol2TileW) {
     (&sE[0][0][0])[k] = 0.0;
     (&sH[0][0][0])[k] = 0.0;
@@ -312,7 +363,11 @@ __global__ void __launch_bounds__(kPol2TileW) fwd_pol2_tile_kernel(Pol2Args a) {
       double Pz = 0.0, Py = 0.0;
       if (med) {
         double *pp = (snap && own && a.pop_out) ? a.pop_out + si * N * nmed + c : nullptr;
-        pol2_medium<N>(sF, u, Ecz, Ecy, Pz, Py, pp, nmed);
+        if constexpr (pol2_smem<N>()) {
+          pol2_medium<N>(Pol2FacSmem{a.fac + a.opaque0 * s}, u, Ecz, Ecy, Pz, Py, pp, nmed);
+        } else {
+          pol2_medium<N>(Pol2FacLds{sF}, u, Ecz, Ecy, Pz, Py, pp, nmed);
+        }
       }
       const double Ezn = pol2_e(a, g, a.amp_z, n, Ecz, hz, Pz);
       const double Eyn = pol2_e(a, g, a.amp_y, n, Ecy, hy, Py);

@@ -22,7 +22,8 @@ struct mln_pol2 {
   hipStream_t stream = nullptr;
   int64_t nmed = 0, ld = 0, step = 0, nsnap = 0;
   int K = 0;      // steps per launch, 0: automatic (pol2_auto_steps)
-  int lanes = 4;  // lanes per cell: 1 (K = 1: the one-step kernel, else the tile kernel) or 4 (quad kernel)
+  int lanes = 4;  // lanes per cell: 1 (K = 1: the one-step kernel, else the tile kernel) or 4 (quad
+                  // kernel, N <= 3; the default there, 1 for N = 4, 6)
   int cus = 256;  // compute units of the device
   double amp_z = 0.0, amp_y = 0.0;
   double coef[5] = {0, 0, 0, 0, 0};  // ch, ca, cb, 1/dx, kmur
@@ -70,6 +71,7 @@ int pol2_auto_steps(const mln_pol2 *p) {
   return p->lanes == 4 ? 12 : 16;
 }
 
+// four lanes per cell: N = 2, 3 only (two components per lane)
 hipError_t launch_pol2(int N, Pol2Kernel kind, const Pol2Args &a, hipStream_t st) {
   switch (N) {
     case 2:
@@ -78,6 +80,12 @@ hipError_t launch_pol2(int N, Pol2Kernel kind, const Pol2Args &a, hipStream_t st
     case 3:
       return kind == Pol2Kernel::quad ? launch_quad_n<3>(a, st)
              : kind == Pol2Kernel::tile ? launch_tile_n<3>(a, st) : launch_n<3>(a, st);
+    case 4:
+      return kind == Pol2Kernel::quad ? hipErrorInvalidValue
+             : kind == Pol2Kernel::tile ? launch_tile_n<4>(a, st) : launch_n<4>(a, st);
+    case 6:
+      return kind == Pol2Kernel::quad ? hipErrorInvalidValue
+             : kind == Pol2Kernel::tile ? launch_tile_n<6>(a, st) : launch_n<6>(a, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -86,6 +94,8 @@ size_t layout_size(int N) {
   switch (N) {
     case 2: return Pol2Layout<2>::size;
     case 3: return Pol2Layout<3>::size;
+    case 4: return Pol2Layout<4>::size;
+    case 6: return Pol2Layout<6>::size;
     default: return 0;
   }
 }
@@ -203,6 +213,7 @@ int pol2_steps(mln_pol2 *p, int64_t n) {
     a.cb = p->coef[2];
     a.inv_dx = p->coef[3];
     a.kmur = p->coef[4];
+    a.opaque0 = 0;
     // snapshot s is taken when step (s+1) snap_every - 1 completes
     const int64_t se = p->rec.snap_every;
     const int64_t m = se > 0 ? (p->step + se) / se : 0;  // the first snapshot at or after this step, plus one
@@ -262,7 +273,8 @@ int mln_pol2_init(const mln_medium *medium, const double *dipole_y, const mln_gr
   p->N = fz.N;
   p->D = fz.D;
   p->q = fz.q;
-  if (layout_size(p->N) == 0) return set_err(MLN_ENOTSUPPORTED, "the two-component kernel is built for N = 2 and 3");
+  if (layout_size(p->N) == 0) return set_err(MLN_ENOTSUPPORTED, "the two-component kernels are built for N = 2, 3, 4, 6");
+  p->lanes = p->N <= 3 ? 4 : 1;
   p->grid = g;
   p->rec = record ? *record : mln_pol2_record{};
   if (p->rec.snap_every < 0) return set_err(MLN_EINVAL, "snap_every must be >= 0");
@@ -313,6 +325,8 @@ int mln_pol2_init(const mln_medium *medium, const double *dipole_y, const mln_gr
 int mln_pol2_configure(mln_pol2 *p, int steps_per_launch, int lanes_per_cell) {
   if (!p) return set_err(MLN_EINVAL, "null handle");
   if (lanes_per_cell != 1 && lanes_per_cell != 4) return set_err(MLN_EINVAL, "lanes_per_cell must be 1 or 4");
+  if (lanes_per_cell == 4 && p->N > 3)
+    return set_err(MLN_ENOTSUPPORTED, "four lanes per cell hold the Bloch vector for N <= 3 only");
   const int kmax = lanes_per_cell == 4 ? kPol2QuadMaxSteps : kPol2MaxSteps;
   if (steps_per_launch < 0 || steps_per_launch > kmax)
     return set_err(MLN_EINVAL, "steps_per_launch must be in 0.." + std::to_string(kmax) + " with " +

@@ -666,7 +666,7 @@ class Pol2:
     """Both transverse field components (mln_pol2_init): the problem's dipole
     couples to E_z, dipole_y (N x N Hermitian) to E_y; the source waveform
     drives E_z with the problem's amplitude and E_y with amplitude_y.  FP64,
-    N = 2, 3.  Outputs (torch float64 device tensors) after run(): probe_z,
+    N = 2, 3, 4, 6.  Outputs (torch float64 device tensors) after run(): probe_z,
     probe_y (nt+1), ez_snap, ey_snap (nsnap, nx), pop (nsnap, N, n_med).
     steps_per_launch, lanes_per_cell: mln_pol2_configure (None: the library's
     defaults)."""
@@ -703,10 +703,13 @@ class Pol2:
                                ctypes.byref(h)))
         self._h = h
         if steps_per_launch is not None or lanes_per_cell is not None:
-            self.configure(0 if steps_per_launch is None else steps_per_launch,
-                           4 if lanes_per_cell is None else lanes_per_cell)
+            self.configure(0 if steps_per_launch is None else steps_per_launch, lanes_per_cell)
 
-    def configure(self, steps_per_launch=0, lanes_per_cell=4):
+    def configure(self, steps_per_launch=0, lanes_per_cell=None):
+        """mln_pol2_configure; lanes_per_cell None: the library's default for
+        the level count (4 for N <= 3, 1 for N = 4, 6)."""
+        if lanes_per_cell is None:
+            lanes_per_cell = 4 if self.problem.medium.n_levels <= 3 else 1
         _check(self._L.mln_pol2_configure(self._h, int(steps_per_launch), int(lanes_per_cell)))
 
     def step(self, n):

@@ -8,7 +8,8 @@ that does not commute with the first, several workgroups with a ragged last
 one; edge geometries; a lossy / dielectric host; the exact reductions (no
 second component: the one-component GPU run; equal dipoles and sources: the
 one-component run with sqrt(2) mu and sqrt(2) s, rotated by 45 degrees);
-reset and stepping in pieces; field read-back; errors.  Kernels: the
+reset and stepping in pieces; field read-back; errors; N = 4 and 6 (one
+thread per cell, factors through scalar loads).  Kernels: the
 blocked four-lanes-per-cell kernel at its default (automatic steps per
 launch) in every case, and each kernel shape against the oracle and against
 the one-step kernel
@@ -124,6 +125,24 @@ def test_pol2_steps_per_launch(orc, k, lanes, nx, nt):
         assert d["z"] < 1e-13 and d["y"] < 1e-13 and d["pop"] < 1e-13
 
 
+# N = 4, 6: one thread per cell, the factors read with scalar loads; the
+# one-step kernel, the blocked kernel at its default and at 7 steps per
+# launch over several workgroups (600 cells: 241 owned per workgroup)
+@pytest.mark.parametrize("n,seed", [(4, 11), (6, 12)])
+@pytest.mark.parametrize("k", [1, 0, 7])
+def test_pol2_four_and_six_levels(orc, n, seed, k):
+    p, muy = _problem(n, seed, nx=600, nt=260, med=(2, 590))
+    amp_y = 0.9 * p.source.amplitude
+    _case("pol2_n46", n=n, seed=seed, k=k)
+    ref = orc.run_pol2(p, muy, amp_y, snap_every=26)
+    got = _run(p, muy, amp_y, 26, steps_per_launch=k)
+    e = _errs(got, ref)
+    print(f"  err_Ez={e['z']:.2e} err_Ey={e['y']:.2e} err_pop={e['pop']:.2e}", flush=True)
+    assert e["z"] < 1e-10 and e["y"] < 1e-10 and e["pop"] < 1e-10
+    free = orc.run_pol2(p, np.zeros_like(muy), amp_y, snap_every=26)
+    assert np.max(np.abs(ref["ey_snap"] - free["ey_snap"])) > 1e-5 * np.max(np.abs(free["ey_snap"]))
+
+
 def test_pol2_configure_between_steps(orc):
     """Changing the steps per launch mid-run (and stepping in odd pieces)
     leaves the run as it was."""
@@ -207,10 +226,16 @@ def test_pol2_errors():
     with pytest.raises(mln.MLNError) as e:
         mln.Pol2(p, bad, 1.0)
     assert e.value.code == -2
-    p6 = W.random_problem(6, 3, nx=100, nt=50)
+    p5 = W.random_problem(5, 3, nx=100, nt=50)
     with pytest.raises(mln.MLNError) as e:
-        mln.Pol2(p6, W.random_dipole(6, 3, 1e-29), 1.0)
+        mln.Pol2(p5, W.random_dipole(5, 3, 1e-29), 1.0)
     assert e.value.code == -8
+    p4 = W.random_problem(4, 3, nx=100, nt=50)
+    s4 = mln.Pol2(p4, W.random_dipole(4, 3, 1e-29), 1.0)
+    with pytest.raises(mln.MLNError) as e:
+        s4.configure(16, 4)  # four lanes hold the Bloch vector for N <= 3 only
+    assert e.value.code == -8
+    s4.close()
     p.grid.dt *= 3.0  # Courant number above one
     with pytest.raises(mln.MLNError) as e:
         mln.Pol2(p, muy, 1.0)
