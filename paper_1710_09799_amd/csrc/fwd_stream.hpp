@@ -105,11 +105,8 @@ __device__ __forceinline__ void stream_cells(const FwdArgs<Real> &a, const Real 
 // (the launcher caps the grid at a few workgroups per compute unit), so the
 // staging is not repeated for every chunk of a large grid.
 template <int N, typename Real, bool COMP>
-__global__ void __launch_bounds__(kStreamThreads) fwd_stream_kernel(FwdArgs<Real> a) {
-  constexpr int D = N * N - 1;
+__device__ __forceinline__ void stream_grid(const FwdArgs<Real> &a, Real *sF, double *sP) {
   constexpr int CH = kStreamThreads * kStreamCells;
-  __shared__ Real sF[rot_smem<N>() ? 1 : RotLds<N, Real, COMP>::size];
-  __shared__ double sP[N * D + N];
   if constexpr (!rot_smem<N>()) RotLds<N, Real, COMP>::stage(a.fac, sF);
   RotLds<N, Real, COMP>::stage_pop(a.fac, sP);
   __syncthreads();
@@ -122,6 +119,29 @@ __global__ void __launch_bounds__(kStreamThreads) fwd_stream_kernel(FwdArgs<Real
     const int64_t g0 = ch * CH + (int64_t)threadIdx.x * kStreamCells;
     if (g0 < a.nx - 1) stream_cells<N, Real, COMP, kStreamCells>(a, sF, sP, g0, a.opaque0 * ch);
   }
+}
+
+// FP64, and FP32 for N = 4, 6
+template <int N, typename Real, bool COMP>
+__global__ void __launch_bounds__(kStreamThreads) fwd_stream_kernel(FwdArgs<Real> a) {
+  constexpr int D = N * N - 1;
+  __shared__ Real sF[rot_smem<N>() ? 1 : RotLds<N, Real, COMP>::size];
+  __shared__ double sP[N * D + N];
+  stream_grid<N, Real, COMP>(a, sF, sP);
+}
+
+// FP32 and compensated FP32 for N = 2, 3, compiled for eight wavefronts per
+// SIMD (measured on 2^24 two-level cells: 96.8 against 107-110 us per step
+// in FP32, 133.5 against 137 in compensated FP32; the FP64 instances gain
+// nothing, and they and the N = 4, 6 instances would spill, so they keep
+// the default register budget)
+template <int N, bool COMP>
+__global__ void __launch_bounds__(kStreamThreads) __attribute__((amdgpu_waves_per_eu(8, 8)))
+fwd_stream_kernel_f32(FwdArgs<float> a) {
+  constexpr int D = N * N - 1;
+  __shared__ float sF[rot_smem<N>() ? 1 : RotLds<N, float, COMP>::size];
+  __shared__ double sP[N * D + N];
+  stream_grid<N, float, COMP>(a, sF, sP);
 }
 
 }  // namespace mln

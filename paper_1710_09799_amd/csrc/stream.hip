@@ -28,7 +28,11 @@ template <int N, typename Real, bool COMP>
 hipError_t launch_n(const FwdArgs<Real> &a, hipStream_t st) {
   const int64_t nchunks = (a.nx + kStreamThreads * kStreamCells - 1) / (kStreamThreads * kStreamCells);
   const unsigned nb = (unsigned)std::min<int64_t>(nchunks, max_stream_blocks());
-  hipLaunchKernelGGL((fwd_stream_kernel<N, Real, COMP>), dim3(nb), dim3(kStreamThreads), 0, st, a);
+  if constexpr (std::is_same<Real, float>::value && N <= 3) {
+    hipLaunchKernelGGL((fwd_stream_kernel_f32<N, COMP>), dim3(nb), dim3(kStreamThreads), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((fwd_stream_kernel<N, Real, COMP>), dim3(nb), dim3(kStreamThreads), 0, st, a);
+  }
   return hipGetLastError();
 }
 
