@@ -65,11 +65,9 @@ __device__ __forceinline__ Real tmz_hx(Real hx, Real chy, Real e_up, Real e) {
 }
 
 template <int N, typename Real, bool COMP>
-__global__ void __launch_bounds__(kTmzTX * kTmzTY) fwd_tmz_kernel(TmzArgs<Real> a) {
+__device__ __forceinline__ void tmz_step(const TmzArgs<Real> &a, Real *sF, double *sP) {
   constexpr int D = N * N - 1;
   constexpr int DL = COMP ? D : 1;
-  __shared__ Real sF[rot_smem<N>() ? 1 : RotLds<N, Real, COMP>::size];
-  __shared__ double sP[N * D + N];
   if constexpr (!rot_smem<N>()) RotLds<N, Real, COMP>::stage(a.fac, sF);
   RotLds<N, Real, COMP>::stage_pop(a.fac, sP);
   __syncthreads();
@@ -131,6 +129,28 @@ __global__ void __launch_bounds__(kTmzTX * kTmzTY) fwd_tmz_kernel(TmzArgs<Real> 
     if (a.probe_out) a.probe_out[(a.n + 1) * a.ny + j] = (double)Eb;
     if (a.snap && a.e_out) a.e_out[a.snap_i * cells + g + 1] = (double)Eb;
   }
+}
+
+// N = 4, 6
+template <int N, typename Real, bool COMP>
+__global__ void __launch_bounds__(kTmzTX * kTmzTY) fwd_tmz_kernel(TmzArgs<Real> a) {
+  constexpr int D = N * N - 1;
+  __shared__ Real sF[rot_smem<N>() ? 1 : RotLds<N, Real, COMP>::size];
+  __shared__ double sP[N * D + N];
+  tmz_step<N, Real, COMP>(a, sF, sP);
+}
+
+// N = 2, 3, compiled for at least five wavefronts per SIMD (measured on the
+// 2048 x 512 three-level beam: FP64 26.9 against 27.9 us per step,
+// compensated FP32 25.0 against 25.8, plain FP32 unchanged, the same bits;
+// eight wavefronts spill and run 1.3-1.8x slower; N = 4, 6 would spill)
+template <int N, typename Real, bool COMP>
+__global__ void __launch_bounds__(kTmzTX * kTmzTY) __attribute__((amdgpu_waves_per_eu(5, 8)))
+fwd_tmz_kernel_w5(TmzArgs<Real> a) {
+  constexpr int D = N * N - 1;
+  __shared__ Real sF[rot_smem<N>() ? 1 : RotLds<N, Real, COMP>::size];
+  __shared__ double sP[N * D + N];
+  tmz_step<N, Real, COMP>(a, sF, sP);
 }
 
 }  // namespace mln

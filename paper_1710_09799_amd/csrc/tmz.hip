@@ -43,7 +43,11 @@ namespace {
 template <int N, typename Real, bool COMP>
 hipError_t launch_n(const TmzArgs<Real> &a, hipStream_t st) {
   const dim3 grid((unsigned)((a.nx + kTmzTX - 1) / kTmzTX), (unsigned)((a.ny + kTmzTY - 1) / kTmzTY));
-  hipLaunchKernelGGL((fwd_tmz_kernel<N, Real, COMP>), grid, dim3(kTmzTX * kTmzTY), 0, st, a);
+  if constexpr (N <= 3) {
+    hipLaunchKernelGGL((fwd_tmz_kernel_w5<N, Real, COMP>), grid, dim3(kTmzTX * kTmzTY), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((fwd_tmz_kernel<N, Real, COMP>), grid, dim3(kTmzTX * kTmzTY), 0, st, a);
+  }
   return hipGetLastError();
 }
 
