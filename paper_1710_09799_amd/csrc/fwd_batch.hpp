@@ -44,8 +44,17 @@ __global__ void __launch_bounds__(1024)
     quad_tile<3, Real, COMP, CF>(a, bt.tile);
 }
 
+// Compiled for seven wavefronts per SIMD: the default register budget held
+// 3-4 (115 to 135 VGPRs) and left the vector units half idle.  Measured on
+// the 64-problem sweep (tile 256, 16 steps per launch), cell-updates/s
+// against the default budget: FP64 1.04e11 / 8.78e10, FP32 1.64e11 /
+// 1.50e11, compensated state 9.27e10 / 8.58e10, compensated state and
+// fields 8.50e10 / 6.61e10, compensated fields 1.46e11 / 1.29e11; five, six
+// and eight wavefronts were slower than seven.  The budget costs spills
+// (12-156 B per lane, some inside the step loop); the added wavefronts
+// more than pay for them.
 template <typename Real, bool COMP, bool CF>
-__global__ void __launch_bounds__(kMaxTile)
+__global__ void __launch_bounds__(kMaxTile) __attribute__((amdgpu_waves_per_eu(7, 8)))
     fwd_block_batch_kernel(const BatchInst<Real> *__restrict__ inst, const BatchTile *__restrict__ tiles,
                            int64_t step0, int nsteps, int slot) {
   const BatchTile bt = tiles[blockIdx.x];
