@@ -16,14 +16,27 @@ using namespace mln;
 
 namespace mln {
 
+template <typename Real, bool COMP, bool CF>
+void launch_block_batch(bool many, dim3 grid, dim3 block, const BatchInst<Real> *inst, const BatchTile *tiles,
+                        int64_t step0, int nsteps, int slot, hipStream_t st) {
+  if (many)
+    hipLaunchKernelGGL((fwd_block_batch_kernel<Real, COMP, CF>), grid, block, 0, st, inst, tiles, step0, nsteps,
+                       slot);
+  else
+    hipLaunchKernelGGL((fwd_block_batch_kernel_few<Real, COMP, CF>), grid, block, 0, st, inst, tiles, step0,
+                       nsteps, slot);
+}
+
 // quad = true: four lanes per cell (4 W threads per workgroup); false: one
-// cell per thread (W threads).
+// cell per thread (W threads), compiled for seven wavefronts per SIMD when
+// the launch has many tiles (many_tiles).
 template <typename Real>
 hipError_t launch_fwd_batch(bool quad, bool comp, bool cf, int W, const BatchInst<Real> *inst,
                             const BatchTile *tiles, int64_t nblocks, int64_t step0, int nsteps, int slot,
                             hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
   const dim3 grid((unsigned)nblocks), block(quad ? 4 * W : W);
+  const bool many = many_tiles(nblocks);
   if (cf && !comp) {
     // plain single-precision state, float-float fields
     if constexpr (std::is_same<Real, float>::value) {
@@ -31,8 +44,7 @@ hipError_t launch_fwd_batch(bool quad, bool comp, bool cf, int W, const BatchIns
         hipLaunchKernelGGL((fwd_quad_batch_kernel<float, false, true>), grid, block, 0, st, inst, tiles, step0, nsteps,
                            slot);
       else
-        hipLaunchKernelGGL((fwd_block_batch_kernel<float, false, true>), grid, block, 0, st, inst, tiles, step0,
-                           nsteps, slot);
+        launch_block_batch<float, false, true>(many, grid, block, inst, tiles, step0, nsteps, slot, st);
       return hipGetLastError();
     }
     return hipErrorInvalidValue;
@@ -46,11 +58,9 @@ hipError_t launch_fwd_batch(bool quad, bool comp, bool cf, int W, const BatchIns
         hipLaunchKernelGGL((fwd_quad_batch_kernel<float, true, false>), grid, block, 0, st, inst, tiles, step0,
                            nsteps, slot);
       else if (cf)
-        hipLaunchKernelGGL((fwd_block_batch_kernel<float, true, true>), grid, block, 0, st, inst, tiles, step0,
-                           nsteps, slot);
+        launch_block_batch<float, true, true>(many, grid, block, inst, tiles, step0, nsteps, slot, st);
       else
-        hipLaunchKernelGGL((fwd_block_batch_kernel<float, true, false>), grid, block, 0, st, inst, tiles, step0,
-                           nsteps, slot);
+        launch_block_batch<float, true, false>(many, grid, block, inst, tiles, step0, nsteps, slot, st);
     } else {
       return hipErrorInvalidValue;
     }
@@ -58,8 +68,7 @@ hipError_t launch_fwd_batch(bool quad, bool comp, bool cf, int W, const BatchIns
     hipLaunchKernelGGL((fwd_quad_batch_kernel<Real, false, false>), grid, block, 0, st, inst, tiles, step0, nsteps,
                        slot);
   } else {
-    hipLaunchKernelGGL((fwd_block_batch_kernel<Real, false, false>), grid, block, 0, st, inst, tiles, step0, nsteps,
-                       slot);
+    launch_block_batch<Real, false, false>(many, grid, block, inst, tiles, step0, nsteps, slot, st);
   }
   return hipGetLastError();
 }

@@ -52,11 +52,11 @@ __global__ void __launch_bounds__(1024)
 // fields 8.50e10 / 6.61e10, compensated fields 1.46e11 / 1.29e11; five, six
 // and eight wavefronts were slower than seven.  The budget costs spills
 // (12-156 B per lane, some inside the step loop); the added wavefronts
-// more than pay for them.
+// more than pay for them when there are many tiles (many_tiles).
 template <typename Real, bool COMP, bool CF>
-__global__ void __launch_bounds__(kMaxTile) __attribute__((amdgpu_waves_per_eu(7, 8)))
-    fwd_block_batch_kernel(const BatchInst<Real> *__restrict__ inst, const BatchTile *__restrict__ tiles,
-                           int64_t step0, int nsteps, int slot) {
+__device__ __forceinline__ void block_batch_tile(const BatchInst<Real> *__restrict__ inst,
+                                                 const BatchTile *__restrict__ tiles, int64_t step0, int nsteps,
+                                                 int slot) {
   const BatchTile bt = tiles[blockIdx.x];
   const BatchInst<Real> &bi = inst[bt.inst];
   const FwdArgs<Real> a = batch_args(bi, step0, nsteps, slot);
@@ -64,6 +64,19 @@ __global__ void __launch_bounds__(kMaxTile) __attribute__((amdgpu_waves_per_eu(7
     block_tile<2, Real, ROUTE_ROT, COMP, CF>(a, bt.tile);
   else
     block_tile<3, Real, ROUTE_ROT, COMP, CF>(a, bt.tile);
+}
+template <typename Real, bool COMP, bool CF>
+__global__ void __launch_bounds__(kMaxTile) __attribute__((amdgpu_waves_per_eu(7, 8)))
+    fwd_block_batch_kernel(const BatchInst<Real> *__restrict__ inst, const BatchTile *__restrict__ tiles,
+                           int64_t step0, int nsteps, int slot) {
+  block_batch_tile<Real, COMP, CF>(inst, tiles, step0, nsteps, slot);
+}
+// the default register budget, for batches of few tiles
+template <typename Real, bool COMP, bool CF>
+__global__ void __launch_bounds__(kMaxTile)
+    fwd_block_batch_kernel_few(const BatchInst<Real> *__restrict__ inst, const BatchTile *__restrict__ tiles,
+                               int64_t step0, int nsteps, int slot) {
+  block_batch_tile<Real, COMP, CF>(inst, tiles, step0, nsteps, slot);
 }
 
 }  // namespace mln

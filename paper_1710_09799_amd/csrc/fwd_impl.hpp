@@ -662,6 +662,19 @@ __global__ void __launch_bounds__(kMaxTile) fwd_tile_kernel(FwdArgs<Real> a) {
   block_tile<N, Real, ROUTE, COMP, CF>(a, blockIdx.x);
 }
 
+// The rotation route compiled for seven wavefronts per SIMD, for launches of
+// many tiles (many_tiles).  Measured with tile 256 and 16 steps per launch,
+// cell-updates/s against the default build: two-level 2^24 cells FP64
+// 1.95e11 / 1.71e11, compensated FP32 2.04e11 / 1.90e11; three-level 2^20
+// cells FP64 9.69e10 / 9.24e10; but three-level 20000 cells (90 tiles) FP64
+// 1.14e10 / 1.28e10, compensated FP32 7.2e9 / 1.10e10.  The budget spills
+// 0-132 B per lane.
+template <int N, typename Real, bool COMP, bool CF = false>
+__global__ void __launch_bounds__(kMaxTile) __attribute__((amdgpu_waves_per_eu(7, 8)))
+fwd_tile_kernel_many(FwdArgs<Real> a) {
+  block_tile<N, Real, ROUTE_ROT, COMP, CF>(a, blockIdx.x);
+}
+
 // Prescribed-field mode: one thread per medium cell, no FDTD.
 template <int N, typename Real, int ROUTE, bool COMP>
 __global__ void __launch_bounds__(256) bloch_kernel(BlochArgs<Real> a) {

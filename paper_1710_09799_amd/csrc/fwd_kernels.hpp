@@ -19,6 +19,23 @@ constexpr int kStreamCells = 1;           // consecutive cells per thread of the
 constexpr int kPadeMax = 7;              // highest Pade degree of the per-step Pade route
 constexpr size_t kPadeMaxLds = 160 * 1024;  // LDS of one compute unit
 
+// Launches of the one-cell-per-thread tile kernels with at least four tiles
+// per compute unit fill the default register budget's occupancy (three to
+// five 256-thread workgroups per unit), so they take the builds compiled for
+// seven wavefronts per SIMD; launches with fewer tiles keep the default
+// build, whose step does not pay for the spills of the smaller budget.
+inline bool many_tiles(int64_t nblocks) {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
+  if (!cache[dev]) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    cache[dev] = cus;
+  }
+  return nblocks >= 4 * (int64_t)cache[dev];
+}
+
 // Device copies of the per-medium factors, in the precision of the state.
 // Indices are uniform across a wavefront, so the compiler reads them with
 // scalar loads.  Layouts are row-major.

@@ -12,7 +12,10 @@ hipError_t launch_fwd_n3(int route, bool comp, bool cf, const FwdArgs<Real> &a, 
     // plain single-precision state, float-float fields
     if constexpr (std::is_same<Real, float>::value) {
       if (route != ROUTE_ROT) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((fwd_tile_kernel<3, float, ROUTE_ROT, false, true>), dim3((unsigned)nblocks), dim3(W), 0, st, a);
+      if (many_tiles(nblocks))
+        hipLaunchKernelGGL((fwd_tile_kernel_many<3, float, false, true>), dim3((unsigned)nblocks), dim3(W), 0, st, a);
+      else
+        hipLaunchKernelGGL((fwd_tile_kernel<3, float, ROUTE_ROT, false, true>), dim3((unsigned)nblocks), dim3(W), 0, st, a);
       return hipGetLastError();
     }
     return hipErrorInvalidValue;
@@ -20,8 +23,13 @@ hipError_t launch_fwd_n3(int route, bool comp, bool cf, const FwdArgs<Real> &a, 
   if (comp) {
     if constexpr (std::is_same<Real, float>::value) {
       if (route != ROUTE_ROT) return hipErrorInvalidValue;
-      if (cf)
+      const bool many = many_tiles(nblocks);
+      if (cf && many)
+        hipLaunchKernelGGL((fwd_tile_kernel_many<3, float, true, true>), dim3((unsigned)nblocks), dim3(W), 0, st, a);
+      else if (cf)
         hipLaunchKernelGGL((fwd_tile_kernel<3, float, ROUTE_ROT, true, true>), dim3((unsigned)nblocks), dim3(W), 0, st, a);
+      else if (many)
+        hipLaunchKernelGGL((fwd_tile_kernel_many<3, float, true>), dim3((unsigned)nblocks), dim3(W), 0, st, a);
       else
         hipLaunchKernelGGL((fwd_tile_kernel<3, float, ROUTE_ROT, true>), dim3((unsigned)nblocks), dim3(W), 0, st, a);
       return hipGetLastError();
@@ -29,7 +37,12 @@ hipError_t launch_fwd_n3(int route, bool comp, bool cf, const FwdArgs<Real> &a, 
     return hipErrorInvalidValue;
   }
   switch (route) {
-    case ROUTE_ROT: hipLaunchKernelGGL((fwd_tile_kernel<3, Real, ROUTE_ROT, false>), dim3((unsigned)nblocks), dim3(W), 0, st, a); break;
+    case ROUTE_ROT:
+      if (many_tiles(nblocks))
+        hipLaunchKernelGGL((fwd_tile_kernel_many<3, Real, false>), dim3((unsigned)nblocks), dim3(W), 0, st, a);
+      else
+        hipLaunchKernelGGL((fwd_tile_kernel<3, Real, ROUTE_ROT, false>), dim3((unsigned)nblocks), dim3(W), 0, st, a);
+      break;
     case ROUTE_DIAG: hipLaunchKernelGGL((fwd_tile_kernel<3, Real, ROUTE_DIAG, false>), dim3((unsigned)nblocks), dim3(W), 0, st, a); break;
     case ROUTE_RODR: hipLaunchKernelGGL((fwd_tile_kernel<3, Real, ROUTE_RODR, false>), dim3((unsigned)nblocks), dim3(W), 0, st, a); break;
     case ROUTE_PADE: hipLaunchKernelGGL((fwd_tile_kernel<3, Real, ROUTE_PADE, false>), dim3((unsigned)nblocks), dim3(W), 0, st, a); break;

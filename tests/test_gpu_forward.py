@@ -79,6 +79,28 @@ def test_coupled_rotation_variants(ref_cache, n, seed, variant, tile, k, precisi
     assert ee < tol and ep < tol, (ee, ep)
 
 
+# One cell per thread on a grid of more tiles than four per compute unit:
+# the launcher takes the build compiled for seven wavefronts per SIMD there
+# (240000 cells, tile 256 with 16 steps per launch: 1072 tiles).  The random
+# initial density matrix radiates from every cell from the first step.
+@pytest.mark.parametrize("n,seed", [(2, 21), (3, 22)])
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL64), ("fp32c", 1e-5), ("fp32cf", 1e-5)])
+def test_block_kernel_many_tiles(orc, n, seed, precision, tol):
+    p = W.random_problem(n, seed, nx=240000, nt=40)
+    _print_case("block_many_tiles", n=n, seed=seed, precision=precision)
+    key = ("many", n, seed)
+    if key not in _MANY_REF:
+        _MANY_REF[key] = orc.run(p, snap_every=20)
+    got = mln.run(p, precision=precision, snap_every=20, variant="block", tile=256, steps_per_launch=16)
+    got = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in got.items()}
+    err_e, err_p = _errs(got, _MANY_REF[key])
+    print(f"  err_E={err_e:.2e} err_pop={err_p:.2e}", flush=True)
+    assert err_e < tol and err_p < tol
+
+
+_MANY_REF = {}
+
+
 def test_two_level_full_fp64(orc):
     """Two-level self-induced transparency set-up at full size: 2000 cells,
     10000 steps, 2 pi sech pulse through a medium filling the central half."""
