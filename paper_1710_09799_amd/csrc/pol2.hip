@@ -136,8 +136,12 @@ std::vector<double> pol2_factors(const Factors &fz, const Factors &fy, double dt
   std::vector<double> K = tmul(D, Ty, ATy);  // T_y^T A T_y
   std::vector<double> c = tvec(D, Ty, fz.c), wz = tvec(D, Ty, fz.w), wy = tvec(D, Ty, fy.w);
   u0 = tvec(D, Ty, fz.dprime0);
+  std::vector<double> Bt((size_t)D * D);
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < D; ++j) Bt[(size_t)i * D + j] = B[(size_t)j * D + i];
   std::vector<double> blk;
   blk.insert(blk.end(), B.begin(), B.end());
+  blk.insert(blk.end(), Bt.begin(), Bt.end());
   blk.insert(blk.end(), K.begin(), K.end());
   blk.insert(blk.end(), c.begin(), c.end());
   blk.insert(blk.end(), wz.begin(), wz.end());
