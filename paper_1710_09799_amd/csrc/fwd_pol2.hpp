@@ -55,15 +55,17 @@ constexpr int kPol2MaxSteps = 64;    // steps per launch of the tile kernel: W -
 constexpr int kPol2QuadCells = 128;  // cells per window of the quad kernel (512 lanes)
 constexpr int kPol2QuadMaxSteps = 48;  // C - 2 K - 1 >= 31 owned cells
 
-// factor block (doubles): B, B^T (so that every product reads rows, which
-// the scalar loads of N = 4, 6 fetch in wide contiguous pieces), K_u, c_u,
+// factor block (doubles): B, for N = 4, 6 also B^T (so that every product
+// reads rows, which their scalar loads fetch in wide contiguous pieces; the
+// N <= 3 kernels read B's columns from LDS, measured faster), K_u, c_u,
 // w_z, w_y (in u-coordinates), the rotation angles per unit field
 // theta_y dt/2 and theta_z dt, population rows in u-coordinates and their
 // constants, p0_z, p0_y
 template <int N>
 struct Pol2Layout {
   static constexpr int D = N * N - 1, Q = N * (N - 1) / 2;
-  static constexpr int oB = 0, oBt = D * D, oK = 2 * D * D, oc = 3 * D * D, owz = oc + D, owy = owz + D;
+  static constexpr int nBt = N > 3 ? D * D : 0;
+  static constexpr int oB = 0, oBt = D * D, oK = D * D + nBt, oc = oK + D * D, owz = oc + D, owy = owz + D;
   static constexpr int othy = owy + D, othz = othy + Q, opop = othz + Q, opopc = opop + N * D;
   static constexpr int op0 = opopc + N, size = op0 + 2;
 };
@@ -184,7 +186,7 @@ __device__ __forceinline__ void pol2_medium(const FA &F, double (&u)[N * N - 1],
   for (int i = 0; i < D; ++i) {  // to z-rotation coordinates: w = B^T u
     double t = 0.0;
 #pragma unroll
-    for (int j = 0; j < D; ++j) t += F[L::oBt + i * D + j] * u[j];
+    for (int j = 0; j < D; ++j) t += (L::nBt ? F[L::oBt + i * D + j] : F[L::oB + j * D + i]) * u[j];
     w[i] = t;
   }
   pol2_rotate_at<D, Q>(w, F, L::othz, Ecz);  // exp(U_z E_z dt)

@@ -141,7 +141,7 @@ std::vector<double> pol2_factors(const Factors &fz, const Factors &fy, double dt
     for (int j = 0; j < D; ++j) Bt[(size_t)i * D + j] = B[(size_t)j * D + i];
   std::vector<double> blk;
   blk.insert(blk.end(), B.begin(), B.end());
-  blk.insert(blk.end(), Bt.begin(), Bt.end());
+  if (N > 3) blk.insert(blk.end(), Bt.begin(), Bt.end());
   blk.insert(blk.end(), K.begin(), K.end());
   blk.insert(blk.end(), c.begin(), c.end());
   blk.insert(blk.end(), wz.begin(), wz.end());
