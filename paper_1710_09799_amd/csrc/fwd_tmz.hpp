@@ -140,10 +140,11 @@ __global__ void __launch_bounds__(kTmzTX * kTmzTY) fwd_tmz_kernel(TmzArgs<Real> 
   tmz_step<N, Real, COMP>(a, sF, sP);
 }
 
-// N = 2, 3, compiled for at least five wavefronts per SIMD (measured on the
-// 2048 x 512 three-level beam: FP64 26.9 against 27.9 us per step,
-// compensated FP32 25.0 against 25.8, plain FP32 unchanged, the same bits;
-// eight wavefronts spill and run 1.3-1.8x slower; N = 4, 6 would spill)
+// N = 2, 3 in FP64 and compensated FP32, compiled for at least five
+// wavefronts per SIMD (measured on the 2048 x 512 three-level beam: FP64
+// 26.9 against 27.9 us per step, compensated FP32 25.0 against 25.8, the
+// same bits; seven or eight wavefronts spill and run 1.3-1.8x slower; N = 4,
+// 6 would spill)
 template <int N, typename Real, bool COMP>
 __global__ void __launch_bounds__(kTmzTX * kTmzTY) __attribute__((amdgpu_waves_per_eu(5, 8)))
 fwd_tmz_kernel_w5(TmzArgs<Real> a) {
@@ -151,6 +152,17 @@ fwd_tmz_kernel_w5(TmzArgs<Real> a) {
   __shared__ Real sF[rot_smem<N>() ? 1 : RotLds<N, Real, COMP>::size];
   __shared__ double sP[N * D + N];
   tmz_step<N, Real, COMP>(a, sF, sP);
+}
+
+// N = 2, 3 in plain FP32, compiled for seven wavefronts per SIMD (71 VGPRs,
+// no spills; 15.6 against 16.2 us per step on the same beam)
+template <int N>
+__global__ void __launch_bounds__(kTmzTX * kTmzTY) __attribute__((amdgpu_waves_per_eu(7, 8)))
+fwd_tmz_kernel_w7(TmzArgs<float> a) {
+  constexpr int D = N * N - 1;
+  __shared__ float sF[rot_smem<N>() ? 1 : RotLds<N, float, false>::size];
+  __shared__ double sP[N * D + N];
+  tmz_step<N, float, false>(a, sF, sP);
 }
 
 }  // namespace mln

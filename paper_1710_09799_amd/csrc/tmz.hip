@@ -7,6 +7,7 @@
 #include <cmath>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "fwd_tmz.hpp"
@@ -43,7 +44,9 @@ namespace {
 template <int N, typename Real, bool COMP>
 hipError_t launch_n(const TmzArgs<Real> &a, hipStream_t st) {
   const dim3 grid((unsigned)((a.nx + kTmzTX - 1) / kTmzTX), (unsigned)((a.ny + kTmzTY - 1) / kTmzTY));
-  if constexpr (N <= 3) {
+  if constexpr (N <= 3 && std::is_same<Real, float>::value && !COMP) {
+    hipLaunchKernelGGL((fwd_tmz_kernel_w7<N>), grid, dim3(kTmzTX * kTmzTY), 0, st, a);
+  } else if constexpr (N <= 3) {
     hipLaunchKernelGGL((fwd_tmz_kernel_w5<N, Real, COMP>), grid, dim3(kTmzTX * kTmzTY), 0, st, a);
   } else {
     hipLaunchKernelGGL((fwd_tmz_kernel<N, Real, COMP>), grid, dim3(kTmzTX * kTmzTY), 0, st, a);
