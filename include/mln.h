@@ -608,10 +608,10 @@ void mln_tmz_free(mln_tmz *t);
  * cells to its left).  Default: four lanes per cell (N = 2, 3; one thread
  * per cell for N = 4, 6, whose factors are read with scalar loads), K the
  * largest whose workgroups fit one per compute unit (at least 8), else 12
- * (four lanes) or 16 (mln_pol2_configure).  Inputs are copied.
- * Errors: MLN_EINVAL,
- * MLN_ECOURANT, MLN_ENOTSUPPORTED, the medium errors of mln_init (also for
- * dipole_y), MLN_ENOMEM, MLN_EHIP; on error *out is set to NULL. */
+ * (four lanes) or 16 (mln_pol2_configure).  Inputs are copied.  Errors:
+ * MLN_EINVAL, MLN_ECOURANT, MLN_ENOTSUPPORTED (N not in {2, 3, 4, 6}), the
+ * medium errors of mln_init (also for dipole_y), MLN_ENOMEM, MLN_EHIP; on
+ * error *out is set to NULL. */
 typedef struct {
   int64_t snap_every;
   double *ez_out, *ey_out, *pop_out, *probe_z_out, *probe_y_out;
@@ -629,9 +629,9 @@ int mln_pol2_init(const mln_medium *medium, const double *dipole_y, const mln_gr
  *     memory each step; K > 1: blocked, 256-cell windows, 256 - 2 K - 1
  *     owned cells per workgroup.
  *   lanes_per_cell 4 (N <= 3): K in 0..48.  Blocked, 128-cell windows of
- *     four lanes per cell (512 threads), 128 - 2 K - 1 owned cells: lane r holds
- *     components 2r, 2r+1 of the Bloch vector, so each lane forms two rows
- *     of each of the three products.
+ *     four lanes per cell (512 threads), 128 - 2 K - 1 owned cells: lane r
+ *     holds components 2r, 2r+1 of the Bloch vector, so each lane forms two
+ *     rows of each of the three products.
  * The results do not depend on the shape beyond rounding (the same steps
  * per cell; with four lanes dP/dt and the populations are summed in
  * another order).  Takes effect with the next launch.  Errors: MLN_EINVAL
